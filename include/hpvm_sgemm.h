@@ -1,0 +1,223 @@
+/*
+ * hpvm_sgemm.h -- C ABI of the MI355X (gfx950) lowering of the HPVM sgemm
+ * dataflow graph (HPVM technical report, arXiv:1611.00860).
+ *
+ * The graph (Sec. 6.1, listing "SGEMM in HPVM"; drawing in Fig. "Dataflow
+ * graph of sgemm") has a single-instance root node SgemmRoot, a 2-D grid of
+ * SgemmInternal instances, and inside each of them an Allocation leaf and a
+ * 2-D grid of SgemmLeaf instances.  Sec. 3.4 lowers that hierarchy onto a GPU
+ * as tiles: leaf instances form one tile (a workgroup), the parent's
+ * instances form the grid of tiles, and memory the Allocation node obtains
+ * with llvm.hpvm.malloc lives in the scratchpad.  This library is that
+ * lowering written by hand for CDNA4:
+ *
+ *   SgemmRoot          -> one kernel launch (hpvm_sgemm, hpvm_launch_root)
+ *   SgemmInternal grid -> workgroups, one per tile_m x tile_n block of C
+ *   SgemmLeaf grid     -> lanes; in the MFMA lowerings each wavefront owns a
+ *                         leaf_m x leaf_n sub-tile held as MFMA accumulators
+ *   Allocation         -> LDS, sized on the host before the launch (the
+ *                         backend's rewritten Allocation1 of Sec. 6.3)
+ *
+ * Storage: every matrix is row-major.  A is m x k with leading dimension
+ * lda >= k, B is k x n with ldb >= n, C is m x n with ldc >= n.  All device
+ * pointers are owned by the caller; the library never allocates, frees or
+ * copies them (the paper's runtime free calls are no-ops as well, Sec. 6.3).
+ * C is updated in place: A and B are `in`, C is `in out` (Sec. 2.3).
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Every launch is asynchronous on that stream, like the paper's
+ * llvm.hpvm.launch (Table 1); hpvm_wait is its llvm.hpvm.wait.
+ *
+ * Errors: every entry point returns an hpvm_status.  Argument checks run in
+ * argument order before any HIP call, so a rejected call touches no device
+ * state; hpvm_last_error() then names the first offending argument.  No C++
+ * exception crosses this interface.  The library keeps no per-call state
+ * other than a thread-local error message and the explicit plan / graph
+ * handles below.
+ */
+#ifndef HPVM_SGEMM_H
+#define HPVM_SGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+typedef enum hpvm_status {
+  HPVM_OK = 0,
+  HPVM_INVALID_ARG = -1,      /* a size, leading dimension or pointer is bad */
+  HPVM_UNSUPPORTED = -2,      /* tile not in the compiled menu, misalignment */
+  HPVM_HIP_ERROR = -3,        /* the HIP runtime reported an error           */
+  HPVM_WORKSPACE_TOO_SMALL = -4,
+  HPVM_BAD_HANDLE = -5        /* plan or graph handle unknown or destroyed   */
+} hpvm_status;
+
+/* ---- arithmetic of the bulk products ------------------------------------ */
+/* The paper's sgemm is single precision throughout (Sec. 5.1).  The two other
+ * precisions keep FP32 storage and FP32 accumulation and change only the
+ * product operands:
+ *   HPVM_PREC_BF16   : A and B rounded to bfloat16 (nearest-even) on load.
+ *   HPVM_PREC_BF16X3 : each element split as hi = bf16(x), lo = bf16(x - hi);
+ *                      the product uses hi*hi + hi*lo + lo*hi.              */
+typedef enum hpvm_precision {
+  HPVM_PREC_FP32 = 0,
+  HPVM_PREC_BF16 = 1,
+  HPVM_PREC_BF16X3 = 2
+} hpvm_precision;
+
+/* ---- tile: the shape of the two-level hierarchy ------------------------- */
+/* tile_m x tile_n : the block of C one SgemmInternal instance (workgroup)
+ *                   owns; grid = ceil(n / tile_n) x ceil(m / tile_m).
+ * tile_k          : depth of the K-slab of A and B the Allocation node
+ *                   stages in LDS per step.
+ * leaf_m x leaf_n : outputs per leaf unit.  1 x 1 selects the literal
+ *                   lowering: one lane per SgemmLeaf instance, one output
+ *                   each, tile_n x tile_m lanes per workgroup, and an
+ *                   Allocation of tile_m * tile_n floats holding a tile_k
+ *                   (= tile_m) x tile_n slab of B, as in Sec. 6.1-6.3.
+ *                   Larger values select an MFMA lowering in which every
+ *                   wavefront owns a leaf_m x leaf_n sub-tile of C.
+ * stages          : LDS buffers per operand (1, or 2 for double buffering).
+ * hpvm_tile_menu lists the combinations compiled into this library.       */
+typedef struct hpvm_tile {
+  int32_t tile_m;
+  int32_t tile_n;
+  int32_t tile_k;
+  int32_t leaf_m;
+  int32_t leaf_n;
+  int32_t stages;
+} hpvm_tile;
+
+/* ---- the root node's packed argument block ------------------------------ */
+/* Byte-compatible with the paper's %struct.RootIn (Sec. 6.1): packed, 88
+ * bytes, fields in this order.  bytesX give the extent of each array in
+ * bytes; the grid and block fields are the SgemmInternal and SgemmLeaf
+ * instance counts, so m = grid_y * block_y and n = grid_x * block_x (the
+ * paper passes no m or n).                                                 */
+#pragma pack(push, 1)
+typedef struct hpvm_root_in {
+  const float* A;
+  int64_t bytesA;
+  int32_t lda;
+  const float* B;
+  int64_t bytesB;
+  int32_t ldb;
+  float* C;
+  int64_t bytesC;
+  int32_t ldc;
+  int32_t k;
+  float alpha;
+  float beta;
+  int32_t block_x;
+  int32_t block_y;
+  int32_t grid_x;
+  int32_t grid_y;
+} hpvm_root_in;
+#pragma pack(pop)
+
+/* ---- structural description of one lowered graph instance -------------- */
+typedef struct hpvm_dfg {
+  int32_t root_instances; /* always 1: the root has one dynamic instance   */
+  int32_t grid_x;         /* SgemmInternal instances along n (columns)     */
+  int32_t grid_y;         /* SgemmInternal instances along m (rows)        */
+  int32_t block_x;        /* lanes per workgroup along x                   */
+  int32_t block_y;        /* lanes per workgroup along y                   */
+  int32_t waves;          /* 64-lane wavefronts per workgroup              */
+  int64_t alloc_bytes;    /* LDS bytes the Allocation node provides        */
+  int32_t k_slabs;        /* ceil(k / tile_k): trips of the staging loop   */
+  int32_t lowering;       /* 0 literal, 1 FP32 MFMA, 2 BF16 MFMA,
+                             3 bf16x3 MFMA                                 */
+} hpvm_dfg;
+
+/* One edge or binding of the static graph (Sec. 2.1, Table 1 createEdge,
+ * bind.input).  Nodes: 0 SgemmRoot, 1 SgemmInternal, 2 Allocation,
+ * 3 SgemmLeaf.  kind 0 = dataflow edge (src output port -> dst input port),
+ * kind 1 = input binding (parent input port -> child input port).          */
+typedef struct hpvm_edge {
+  int32_t kind;
+  int32_t src_node;
+  int32_t dst_node;
+  int32_t src_port;
+  int32_t dst_port;
+  int32_t all_to_all; /* edges: 1 all-to-all replication, 0 one-to-one */
+} hpvm_edge;
+
+/* ======================================================================== */
+/* Single sgemm                                                             */
+/* ======================================================================== */
+
+/* C <- alpha * A B + beta * C  (the sgemm node of Sec. 6.1; operand order as
+ * SgemmLeaf's with m and n made explicit).
+ *   m, n, k      : sizes, >= 0.  m == 0 or n == 0 returns HPVM_OK without a
+ *                  launch.  k == 0 or alpha == 0 gives C <- beta * C.
+ *   alpha, beta  : scalars.  beta == 0 never reads C (NaN in C is
+ *                  overwritten); alpha == 0 never reads A or B.
+ *   A, B, C      : device pointers (row-major, see above); may be NULL only
+ *                  when the matrix is not read or written.
+ *   prec         : hpvm_precision.
+ *   tile         : hierarchy shape, or NULL to take the autotuned choice for
+ *                  this shape class (the built-in default until
+ *                  hpvm_autotune has run).  Must be in hpvm_tile_menu for
+ *                  prec.
+ *   stream       : hipStream_t or NULL.
+ * Returns HPVM_OK once the work is enqueued.  The MFMA lowerings use 16-byte
+ * vector loads where A, B, C and their leading dimensions allow and scalar
+ * loads elsewhere; any alignment is accepted.                              */
+int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A,
+               int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+               int64_t ldc, int32_t prec, const hpvm_tile* tile, void* stream);
+
+/* The paper's launch of the root node with its packed argument block
+ * (Sec. 6.3, LaunchDataflowGraph unpacking the 88-byte block and calling the
+ * generated SgemmRoot2).  Uses the literal lowering: block_x x block_y lanes
+ * per workgroup, one output each, grid_x x grid_y workgroups, Allocation =
+ * block_x * block_y floats of LDS.  Every byte extent is checked against the
+ * sizes it implies; block_x * block_y must be a multiple of 64 and at most
+ * 1024.                                                                     */
+int hpvm_launch_root(const hpvm_root_in* args, void* stream);
+
+/* Completes all work enqueued on `stream` (llvm.hpvm.wait, Table 1) and
+ * reports an asynchronous HIP error if one occurred.                       */
+int hpvm_wait(void* stream);
+
+/* ======================================================================== */
+/* Graph structure queries (host only, no device access)                    */
+/* ======================================================================== */
+
+/* The Allocation node: LDS bytes one SgemmInternal instance needs for
+ * `tile` at precision `prec`.  For the literal lowering this is
+ * (tile_m * tile_n) << 2, the formula of the Allocation node function in
+ * Sec. 6.1.                                                                 */
+int hpvm_alloc_bytes(const hpvm_tile* tile, int32_t prec, int64_t* bytes);
+
+/* Grid, block, LDS and lowering that hpvm_sgemm would use for these sizes. */
+int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec,
+                  const hpvm_tile* tile, hpvm_dfg* out);
+
+/* The static edge and binding table of the sgemm graph.  Writes at most
+ * `capacity` entries to `out` (which may be NULL when capacity is 0) and
+ * the total count to *count.                                               */
+int hpvm_dfg_edges(hpvm_edge* out, int32_t capacity, int32_t* count);
+
+/* Compiled tiles for `prec`: writes at most `capacity` entries, total count
+ * to *count.  Entry 0 is the default when no tile is given.                */
+int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity,
+                   int32_t* count);
+
+/* ======================================================================== */
+/* Diagnostics                                                               */
+/* ======================================================================== */
+
+/* Static text for a status code. */
+const char* hpvm_status_string(int status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* hpvm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPVM_SGEMM_H */

@@ -1,0 +1,169 @@
+"""MI355X (gfx950) lowering of the HPVM sgemm dataflow graph -- Python binding.
+
+Thin marshalling over the C ABI in ``include/hpvm_sgemm.h``: every call here
+checks tensor types, takes device pointers and torch's current HIP stream, and
+calls the library of the same name.  All arithmetic runs in the library's HIP
+kernels; there is no CPU fallback, and a missing library raises ImportError.
+
+HPVM technical report (arXiv:1611.00860): the sgemm graph of Sec. 6.1, its GPU
+lowering of Sec. 3.4 and 6.2-6.3.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+LOWERINGS = {0: "literal", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_bf16x3"}
+
+
+class HpvmError(RuntimeError):
+    """A non-zero status from the library, with its detail text."""
+
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        super().__init__(f"{status_string(status)} ({status}): {detail}")
+
+
+def load():
+    """Load the HIP library (binding it to torch's HIP runtime)."""
+    return _lib.load()
+
+
+def status_string(status: int) -> str:
+    return load().hpvm_status_string(status).decode()
+
+
+def last_error() -> str:
+    return load().hpvm_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise HpvmError(rc, last_error())
+
+
+def _prec(prec) -> int:
+    if isinstance(prec, str):
+        return PREC[prec]
+    return int(prec)
+
+
+def _tile(tile):
+    if tile is None:
+        return None
+    if isinstance(tile, _lib.Tile):
+        return ctypes.byref(tile)
+    return ctypes.byref(_lib.Tile(*[int(v) for v in tile]))
+
+
+def _stream(stream=None):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mat(t, name, rows=None, cols=None):
+    """(pointer, leading dimension) of a 2-D row-major float32 device tensor."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32 or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float32 tensor")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must live on the GPU")
+    if t.numel() and t.stride(1) != 1 and t.shape[1] > 1:
+        raise ValueError(f"{name} must have unit column stride (row-major)")
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), max(ld, 1)
+
+
+def sgemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None, stream=None):
+    """C <- alpha * A @ B + beta * C in place (hpvm_sgemm); returns C.
+
+    A (m x k), B (k x n), C (m x n): float32 CUDA tensors, row-major, any
+    leading dimension.  ``prec`` is 'fp32', 'bf16' or 'bf16x3'; ``tile`` is
+    None (default / autotuned) or (tile_m, tile_n, tile_k, leaf_m, leaf_n,
+    stages).
+    """
+    lib = load()
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    _check(lib.hpvm_sgemm(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
+                          _prec(prec), _tile(tile), _stream(stream)))
+    return C
+
+
+def launch_root(A, B, C, k: int, alpha: float, beta: float, block, grid, stream=None,
+                bytes_override=None):
+    """The root node's launch with the paper's packed 88-byte argument block.
+
+    ``block`` = (block_x, block_y) leaf instances per internal instance and
+    ``grid`` = (grid_x, grid_y) internal instances; m = grid_y * block_y and
+    n = grid_x * block_x.  Byte extents are those of the tensors' storage
+    unless ``bytes_override`` = (bytesA, bytesB, bytesC) is given.
+    """
+    lib = load()
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+
+    def nbytes(t):
+        return (t.untyped_storage().nbytes() - t.storage_offset() * 4) if t.numel() else 0
+
+    bA, bB, bC = bytes_override or (nbytes(A), nbytes(B), nbytes(C))
+    r = _lib.RootIn(pa.value, bA, lda, pb.value, bB, ldb, pc.value, bC, ldc, int(k),
+                    float(alpha), float(beta), int(block[0]), int(block[1]), int(grid[0]),
+                    int(grid[1]))
+    _check(lib.hpvm_launch_root(ctypes.byref(r), _stream(stream)))
+    return C
+
+
+def wait(stream=None):
+    """Complete all work on the stream (hpvm_wait)."""
+    _check(load().hpvm_wait(_stream(stream)))
+
+
+def alloc_bytes(tile, prec="fp32") -> int:
+    """The Allocation node: LDS bytes per SgemmInternal instance."""
+    out = ctypes.c_int64(0)
+    _check(load().hpvm_alloc_bytes(_tile(tile), _prec(prec), ctypes.byref(out)))
+    return out.value
+
+
+def describe(m: int, n: int, k: int, prec="fp32", tile=None) -> dict:
+    """Grid / block / LDS / lowering of one launch (hpvm_describe)."""
+    d = _lib.Dfg()
+    _check(load().hpvm_describe(m, n, k, _prec(prec), _tile(tile), ctypes.byref(d)))
+    out = {f: getattr(d, f) for f, _ in _lib.Dfg._fields_}
+    out["lowering_name"] = LOWERINGS.get(d.lowering, "?")
+    return out
+
+
+def dfg_edges() -> list:
+    """The static edge / binding table of the sgemm graph."""
+    lib = load()
+    count = ctypes.c_int32(0)
+    _check(lib.hpvm_dfg_edges(None, 0, ctypes.byref(count)))
+    arr = (_lib.Edge * count.value)()
+    _check(lib.hpvm_dfg_edges(arr, count.value, ctypes.byref(count)))
+    return [{f: getattr(e, f) for f, _ in _lib.Edge._fields_} for e in arr]
+
+
+def tile_menu(prec="fp32") -> list:
+    """Compiled tiles for a precision; entry 0 is the default."""
+    lib = load()
+    count = ctypes.c_int32(0)
+    _check(lib.hpvm_tile_menu(_prec(prec), None, 0, ctypes.byref(count)))
+    arr = (_lib.Tile * count.value)()
+    _check(lib.hpvm_tile_menu(_prec(prec), arr, count.value, ctypes.byref(count)))
+    return [t.as_tuple() for t in arr]

@@ -1,0 +1,83 @@
+"""ctypes loader for libhpvm_sgemm.so.
+
+torch is imported first so that its HIP runtime (soname libamdhip64.so.7) is
+the one the library binds to; torch's device pointers and streams are then
+valid inside the library.  There is no fallback: if the library is missing
+the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libhpvm_sgemm.so")
+
+i32 = ctypes.c_int32
+i64 = ctypes.c_int64
+f32 = ctypes.c_float
+vp = ctypes.c_void_p
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("tile_m", i32), ("tile_n", i32), ("tile_k", i32),
+                ("leaf_m", i32), ("leaf_n", i32), ("stages", i32)]
+
+    def as_tuple(self):
+        return (self.tile_m, self.tile_n, self.tile_k, self.leaf_m, self.leaf_n, self.stages)
+
+
+class RootIn(ctypes.Structure):
+    _pack_ = 1
+    _fields_ = [("A", vp), ("bytesA", i64), ("lda", i32),
+                ("B", vp), ("bytesB", i64), ("ldb", i32),
+                ("C", vp), ("bytesC", i64), ("ldc", i32),
+                ("k", i32), ("alpha", f32), ("beta", f32),
+                ("block_x", i32), ("block_y", i32), ("grid_x", i32), ("grid_y", i32)]
+
+
+class Dfg(ctypes.Structure):
+    _fields_ = [("root_instances", i32), ("grid_x", i32), ("grid_y", i32),
+                ("block_x", i32), ("block_y", i32), ("waves", i32),
+                ("alloc_bytes", i64), ("k_slabs", i32), ("lowering", i32)]
+
+
+class Edge(ctypes.Structure):
+    _fields_ = [("kind", i32), ("src_node", i32), ("dst_node", i32),
+                ("src_port", i32), ("dst_port", i32), ("all_to_all", i32)]
+
+
+# name -> (restype, argtypes); the same list the header declares.
+SIGNATURES = {
+    "hpvm_sgemm": (ctypes.c_int, [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32,
+                                  ctypes.POINTER(Tile), vp]),
+    "hpvm_launch_root": (ctypes.c_int, [ctypes.POINTER(RootIn), vp]),
+    "hpvm_wait": (ctypes.c_int, [vp]),
+    "hpvm_alloc_bytes": (ctypes.c_int, [ctypes.POINTER(Tile), i32, ctypes.POINTER(i64)]),
+    "hpvm_describe": (ctypes.c_int, [i64, i64, i64, i32, ctypes.POINTER(Tile), ctypes.POINTER(Dfg)]),
+    "hpvm_dfg_edges": (ctypes.c_int, [ctypes.POINTER(Edge), i32, ctypes.POINTER(i32)]),
+    "hpvm_tile_menu": (ctypes.c_int, [i32, ctypes.POINTER(Tile), i32, ctypes.POINTER(i32)]),
+    "hpvm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "hpvm_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load (once) and return the ctypes library handle."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  -- binds the library to torch's HIP runtime
+
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,306 @@
+// C-ABI layer of the sgemm dataflow-graph library: argument checks, the
+// Allocation-size function, structural queries and the root launch.
+//
+// This file plays the role of the host code the paper's GPU backend emits
+// (HPVM report, Sec. 6.3): it unpacks the root node's arguments, computes the
+// Allocation node's size before the launch, sets the launch geometry from the
+// SgemmInternal / SgemmLeaf instance counts, and enqueues the kernel.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "device_common.hpp"
+#include "hpvm_sgemm.h"
+#include "internal.hpp"
+
+namespace {
+
+thread_local char g_error[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_error, sizeof g_error, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int ok() {
+  g_error[0] = '\0';
+  return HPVM_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(HPVM_HIP_ERROR, "%s: %s", what, hipGetErrorString(e));
+}
+
+// HPVM_FAULT_INJECT=launch makes every launch report a HIP failure after the
+// argument checks, so that error propagation can be exercised without a GPU.
+bool inject(const char* site) {
+  const char* v = std::getenv("HPVM_FAULT_INJECT");
+  return v && std::strcmp(v, site) == 0;
+}
+
+bool valid_prec(int32_t prec) {
+  return prec == HPVM_PREC_FP32 || prec == HPVM_PREC_BF16 || prec == HPVM_PREC_BF16X3;
+}
+
+bool is_literal(const hpvm_tile& t) { return t.leaf_m == 1 && t.leaf_n == 1; }
+
+// Literal lowering: tile_n x tile_m lanes (block_x = tile_n, block_y =
+// tile_m), a whole number of wavefronts, at most 1024 lanes; the staged B
+// slab is tile_m deep and one buffer.
+bool literal_ok(const hpvm_tile& t) {
+  const int64_t lanes = (int64_t)t.tile_m * t.tile_n;
+  return t.tile_m > 0 && t.tile_n > 0 && lanes >= hpvm::kWave && lanes <= 1024 &&
+         lanes % hpvm::kWave == 0 && t.tile_k == t.tile_m && t.stages == 1;
+}
+
+bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
+  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k &&
+         a.leaf_m == b.leaf_m && a.leaf_n == b.leaf_n && a.stages == b.stages;
+}
+
+const hpvm::MfmaEntry* find_entry(int32_t prec, const hpvm_tile* tile) {
+  const hpvm::MfmaEntry* menu;
+  const int count = hpvm::mfma_menu(prec, &menu);
+  if (count == 0) return nullptr;
+  if (!tile) return &menu[0];
+  for (int i = 0; i < count; ++i)
+    if (same_tile(menu[i].tile, *tile)) return &menu[i];
+  return nullptr;
+}
+
+// Resolves the lowering for (prec, tile); *entry is null for the literal one.
+int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, int argno) {
+  *entry = nullptr;
+  if (tile && is_literal(*tile)) {
+    if (prec != HPVM_PREC_FP32)
+      return fail(HPVM_UNSUPPORTED, "argument %d: the literal lowering (leaf 1x1) is FP32 only", argno);
+    if (!literal_ok(*tile))
+      return fail(HPVM_UNSUPPORTED,
+                  "argument %d: literal tile %dx%d (k %d, stages %d) needs 64..1024 lanes in whole "
+                  "wavefronts, tile_k == tile_m and one stage",
+                  argno, tile->tile_m, tile->tile_n, tile->tile_k, tile->stages);
+    return HPVM_OK;
+  }
+  *entry = find_entry(prec, tile);
+  if (!*entry) {
+    if (tile)
+      return fail(HPVM_UNSUPPORTED, "argument %d: tile %dx%dx%d leaf %dx%d stages %d is not compiled for precision %d",
+                  argno, tile->tile_m, tile->tile_n, tile->tile_k, tile->leaf_m, tile->leaf_n,
+                  tile->stages, prec);
+    return fail(HPVM_UNSUPPORTED, "no compiled tile for precision %d", prec);
+  }
+  return HPVM_OK;
+}
+
+// Byte range [lo, hi) a row-major rows x cols matrix with leading dimension
+// ld occupies.
+void extent(const void* p, int64_t rows, int64_t cols, int64_t ld, uintptr_t* lo, uintptr_t* hi) {
+  *lo = (uintptr_t)p;
+  *hi = (uintptr_t)p + (uintptr_t)(((rows - 1) * ld + cols) * (int64_t)sizeof(float));
+}
+
+bool overlaps(const void* a, int64_t ar, int64_t ac, int64_t alda, const void* b, int64_t br,
+              int64_t bc, int64_t bld) {
+  uintptr_t a0, a1, b0, b1;
+  extent(a, ar, ac, alda, &a0, &a1);
+  extent(b, br, bc, bld, &b0, &b1);
+  return a0 < b1 && b0 < a1;
+}
+
+bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
+
+}  // namespace
+
+extern "C" {
+
+const char* hpvm_status_string(int status) {
+  switch (status) {
+    case HPVM_OK: return "HPVM_OK";
+    case HPVM_INVALID_ARG: return "HPVM_INVALID_ARG";
+    case HPVM_UNSUPPORTED: return "HPVM_UNSUPPORTED";
+    case HPVM_HIP_ERROR: return "HPVM_HIP_ERROR";
+    case HPVM_WORKSPACE_TOO_SMALL: return "HPVM_WORKSPACE_TOO_SMALL";
+    case HPVM_BAD_HANDLE: return "HPVM_BAD_HANDLE";
+    default: return "HPVM_UNKNOWN_STATUS";
+  }
+}
+
+const char* hpvm_last_error(void) { return g_error; }
+
+int hpvm_alloc_bytes(const hpvm_tile* tile, int32_t prec, int64_t* bytes) {
+  if (!tile) return fail(HPVM_INVALID_ARG, "argument 1: tile is NULL");
+  if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 2: unknown precision %d", prec);
+  if (!bytes) return fail(HPVM_INVALID_ARG, "argument 3: bytes is NULL");
+  const hpvm::MfmaEntry* e;
+  int rc = resolve(prec, tile, &e, 1);
+  if (rc != HPVM_OK) return rc;
+  *bytes = e ? e->lds_bytes : hpvm::literal_alloc_bytes(tile->tile_n, tile->tile_m);
+  return ok();
+}
+
+int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity, int32_t* count) {
+  if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 1: unknown precision %d", prec);
+  if (capacity < 0 || (capacity > 0 && !out))
+    return fail(HPVM_INVALID_ARG, "argument 3: bad capacity or NULL output");
+  if (!count) return fail(HPVM_INVALID_ARG, "argument 4: count is NULL");
+  const hpvm::MfmaEntry* menu;
+  const int n = hpvm::mfma_menu(prec, &menu);
+  for (int i = 0; i < n && i < capacity; ++i) out[i] = menu[i].tile;
+  *count = n;
+  return ok();
+}
+
+int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile, hpvm_dfg* out) {
+  if (m < 0) return fail(HPVM_INVALID_ARG, "argument 1: m = %lld < 0", (long long)m);
+  if (n < 0) return fail(HPVM_INVALID_ARG, "argument 2: n = %lld < 0", (long long)n);
+  if (k < 0) return fail(HPVM_INVALID_ARG, "argument 3: k = %lld < 0", (long long)k);
+  if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
+  if (!out) return fail(HPVM_INVALID_ARG, "argument 6: out is NULL");
+  const hpvm::MfmaEntry* e;
+  int rc = resolve(prec, tile, &e, 5);
+  if (rc != HPVM_OK) return rc;
+  const hpvm_tile t = e ? e->tile : *tile;
+  out->root_instances = 1;
+  out->grid_x = (int32_t)((n + t.tile_n - 1) / t.tile_n);
+  out->grid_y = (int32_t)((m + t.tile_m - 1) / t.tile_m);
+  out->k_slabs = (int32_t)((k + t.tile_k - 1) / t.tile_k);
+  if (e) {
+    out->block_x = e->threads;
+    out->block_y = 1;
+    out->waves = e->threads / hpvm::kWave;
+    out->alloc_bytes = e->lds_bytes;
+    out->lowering = prec == HPVM_PREC_FP32 ? hpvm::kMfmaF32
+                    : prec == HPVM_PREC_BF16 ? hpvm::kMfmaBf16
+                                              : hpvm::kMfmaBf16x3;
+  } else {
+    out->block_x = t.tile_n;
+    out->block_y = t.tile_m;
+    out->waves = t.tile_m * t.tile_n / hpvm::kWave;
+    out->alloc_bytes = hpvm::literal_alloc_bytes(t.tile_n, t.tile_m);
+    out->lowering = hpvm::kLiteral;
+  }
+  return ok();
+}
+
+// The sgemm graph of Sec. 6.1: SgemmRoot (0) creates a 2-D SgemmInternal (1)
+// and binds its inputs 0..13 through; SgemmInternal creates Allocation (2)
+// and a 2-D SgemmLeaf (3), wires Allocation's outputs 0 and 1 (pointer,
+// bytes) to the leaf's inputs 12 and 13 with all-to-all replication (one
+// Allocation instance feeds every leaf instance), binds its own inputs 0..11
+// to the leaf's 0..11 and its inputs 12, 13 (block_x, block_y) to
+// Allocation's 0, 1.
+int hpvm_dfg_edges(hpvm_edge* out, int32_t capacity, int32_t* count) {
+  if (capacity < 0 || (capacity > 0 && !out))
+    return fail(HPVM_INVALID_ARG, "argument 2: bad capacity or NULL output");
+  if (!count) return fail(HPVM_INVALID_ARG, "argument 3: count is NULL");
+  hpvm_edge table[64];
+  int n = 0;
+  table[n++] = hpvm_edge{0, 2, 3, 0, 12, 1};
+  table[n++] = hpvm_edge{0, 2, 3, 1, 13, 1};
+  for (int port = 0; port < 12; ++port) table[n++] = hpvm_edge{1, 1, 3, port, port, 0};
+  table[n++] = hpvm_edge{1, 1, 2, 12, 0, 0};
+  table[n++] = hpvm_edge{1, 1, 2, 13, 1, 0};
+  for (int port = 0; port < 14; ++port) table[n++] = hpvm_edge{1, 0, 1, port, port, 0};
+  for (int i = 0; i < n && i < capacity; ++i) out[i] = table[i];
+  *count = n;
+  return ok();
+}
+
+int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
+               const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
+               const hpvm_tile* tile, void* stream) {
+  // Checks in argument order; nothing below touches the device until all pass.
+  if (m < 0) return fail(HPVM_INVALID_ARG, "argument 1: m = %lld < 0", (long long)m);
+  if (n < 0) return fail(HPVM_INVALID_ARG, "argument 2: n = %lld < 0", (long long)n);
+  if (k < 0) return fail(HPVM_INVALID_ARG, "argument 3: k = %lld < 0", (long long)k);
+  if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX)
+    return fail(HPVM_UNSUPPORTED, "sizes above 2^31 - 1 are not supported");
+  const bool empty = (m == 0 || n == 0);
+  const bool reads_ab = !empty && k > 0 && alpha != 0.0f;
+  if (reads_ab && !A) return fail(HPVM_INVALID_ARG, "argument 5: A is NULL");
+  if (lda < (k > 1 ? k : 1))
+    return fail(HPVM_INVALID_ARG, "argument 6: lda = %lld < max(1, k)", (long long)lda);
+  if (reads_ab && !B) return fail(HPVM_INVALID_ARG, "argument 7: B is NULL");
+  if (ldb < (n > 1 ? n : 1))
+    return fail(HPVM_INVALID_ARG, "argument 8: ldb = %lld < max(1, n)", (long long)ldb);
+  if (!empty && !C) return fail(HPVM_INVALID_ARG, "argument 10: C is NULL");
+  if (ldc < (n > 1 ? n : 1))
+    return fail(HPVM_INVALID_ARG, "argument 11: ldc = %lld < max(1, n)", (long long)ldc);
+  if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 12: unknown precision %d", prec);
+  const hpvm::MfmaEntry* entry;
+  int rc = resolve(prec, tile, &entry, 13);
+  if (rc != HPVM_OK) return rc;
+  if (reads_ab && (overlaps(C, m, n, ldc, A, m, k, lda) || overlaps(C, m, n, ldc, B, k, n, ldb)))
+    return fail(HPVM_INVALID_ARG, "argument 10: C overlaps A or B");
+  if (empty) return ok();
+  if (inject("launch")) return fail(HPVM_HIP_ERROR, "injected launch failure (HPVM_FAULT_INJECT)");
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (!reads_ab) {
+    e = hpvm::launch_scale(C, ldc, m, n, beta, s);
+    return e == hipSuccess ? ok() : hip_fail(e, "scale launch");
+  }
+  hpvm::GemmArgs a{};
+  a.A = A;
+  a.B = B;
+  a.C = C;
+  a.lda = lda;
+  a.ldb = ldb;
+  a.ldc = ldc;
+  a.m = (int32_t)m;
+  a.n = (int32_t)n;
+  a.k = (int32_t)k;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.vec_a = aligned16(A, lda);
+  a.vec_b = aligned16(B, ldb);
+  if (entry)
+    e = entry->launch(a, false, false, s);
+  else
+    e = hpvm::launch_literal(a, tile->tile_n, tile->tile_m, s);
+  return e == hipSuccess ? ok() : hip_fail(e, "sgemm launch");
+}
+
+int hpvm_launch_root(const hpvm_root_in* r, void* stream) {
+  if (!r) return fail(HPVM_INVALID_ARG, "argument 1: args is NULL");
+  if (r->block_x <= 0 || r->block_y <= 0 || r->grid_x < 0 || r->grid_y < 0)
+    return fail(HPVM_INVALID_ARG, "block and grid counts must be positive");
+  const int64_t lanes = (int64_t)r->block_x * r->block_y;
+  if (lanes > 1024 || lanes % hpvm::kWave)
+    return fail(HPVM_UNSUPPORTED, "block_x * block_y = %lld must be a multiple of 64, at most 1024",
+                (long long)lanes);
+  const int64_t m = (int64_t)r->grid_y * r->block_y;
+  const int64_t n = (int64_t)r->grid_x * r->block_x;
+  const int64_t k = r->k;
+  if (k < 0) return fail(HPVM_INVALID_ARG, "k = %lld < 0", (long long)k);
+  // The byte extents stand in for the sizes the paper's runtime copies.
+  const int64_t f = (int64_t)sizeof(float);
+  if (m > 0 && n > 0) {
+    if (k > 0 && r->alpha != 0.0f) {
+      if (r->lda < (k > 1 ? k : 1) || r->bytesA < ((m - 1) * r->lda + k) * f)
+        return fail(HPVM_INVALID_ARG, "bytesA / lda too small for %lld x %lld", (long long)m, (long long)k);
+      if (r->ldb < (n > 1 ? n : 1) || r->bytesB < ((k - 1) * r->ldb + n) * f)
+        return fail(HPVM_INVALID_ARG, "bytesB / ldb too small for %lld x %lld", (long long)k, (long long)n);
+    }
+    if (r->ldc < (n > 1 ? n : 1) || r->bytesC < ((m - 1) * r->ldc + n) * f)
+      return fail(HPVM_INVALID_ARG, "bytesC / ldc too small for %lld x %lld", (long long)m, (long long)n);
+  }
+  hpvm_tile t{r->block_y, r->block_x, r->block_y, 1, 1, 1};
+  return hpvm_sgemm(m, n, k, r->alpha, r->A, r->lda > 0 ? r->lda : 1, r->B, r->ldb > 0 ? r->ldb : 1,
+                    r->beta, r->C, r->ldc > 0 ? r->ldc : 1, HPVM_PREC_FP32, &t, stream);
+}
+
+int hpvm_wait(void* stream) {
+  if (inject("wait")) return fail(HPVM_HIP_ERROR, "injected wait failure (HPVM_FAULT_INJECT)");
+  hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ok() : hip_fail(e, "stream synchronize");
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Device-side building blocks shared by the sgemm lowerings (gfx950 only).
+//
+// The hierarchy of the sgemm dataflow graph (HPVM report, Sec. 3.4 and 6.1)
+// maps onto CDNA4 as: one SgemmInternal instance = one workgroup tile of C,
+// the Allocation node = the LDS staging buffers of that workgroup, and the
+// SgemmLeaf instances = lanes whose outputs sit in MFMA accumulators.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hpvm {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// Arguments of one sgemm as every kernel sees them.  A is addressed as
+// element (i, p) = A[i * lda + p], or A[p * lda + i] when a_trans; B as
+// (p, j) = B[p * ldb + j], or B[j * ldb + p] when b_trans (the backward pass
+// needs the transposed forms; the forward entry point is row-major only).
+struct GemmArgs {
+  const float* A;
+  const float* B;
+  float* C;
+  int64_t lda, ldb, ldc;
+  int32_t m, n, k;
+  float alpha, beta;
+  int32_t vec_a, vec_b;  // 16-byte vector loads allowed for this operand
+  int32_t tiles_m, tiles_n;
+};
+
+// --------------------------------------------------------------------------
+// Tile of a row-major global matrix -> registers -> LDS.
+// R x Cc elements starting at `base` (already offset to the tile corner);
+// rows >= rlim or columns >= clim read as zero (edge tiles, K tail).
+// Each thread moves U float4 units; consecutive threads take consecutive
+// units along a row, so a wavefront reads whole 128-byte row segments.
+// --------------------------------------------------------------------------
+template <int R, int Cc, int NT>
+struct GlobalTile {
+  static_assert(Cc % 4 == 0, "tile width must be a multiple of 4");
+  static constexpr int kUnitsPerRow = Cc / 4;
+  static constexpr int kUnits = R * kUnitsPerRow;
+  static_assert(kUnits % NT == 0, "tile must split evenly over the workgroup");
+  static constexpr int U = kUnits / NT;
+
+  f32x4 v[U];
+
+  __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld,
+                                       int rlim, int clim, bool vec, int tid) {
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int u = tid + j * NT;
+      const int r = u / kUnitsPerRow;
+      const int c = (u % kUnitsPerRow) * 4;
+      const float* p = base + (int64_t)r * ld + c;
+      if (vec && r < rlim && c + 4 <= clim) {
+        v[j] = *reinterpret_cast<const f32x4*>(p);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[j][e] = (r < rlim && c + e < clim) ? p[e] : 0.0f;
+      }
+    }
+  }
+
+  // FP32 staging with the global layout kept: LDS row stride S floats.
+  template <int S>
+  __device__ __forceinline__ void store_f32(float* lds, int tid) const {
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int u = tid + j * NT;
+      const int r = u / kUnitsPerRow;
+      const int c = (u % kUnitsPerRow) * 4;
+      *reinterpret_cast<f32x4*>(lds + r * S + c) = v[j];
+    }
+  }
+};
+
+}  // namespace hpvm

@@ -1,0 +1,37 @@
+// Host-side interface between the C-ABI layer (api.hip) and the kernel
+// translation units.  Not installed, not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hpvm_sgemm.h"
+
+namespace hpvm {
+
+struct GemmArgs;
+
+// Lowering ids (hpvm_dfg.lowering).
+enum Lowering { kLiteral = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kMfmaBf16x3 = 3 };
+
+// One compiled MFMA configuration.
+struct MfmaEntry {
+  hpvm_tile tile;
+  int32_t prec;
+  int32_t threads;
+  int64_t lds_bytes;
+  // Launch with the given operand forms (a_trans / b_trans, see GemmArgs).
+  hipError_t (*launch)(const GemmArgs& args, bool a_trans, bool b_trans, hipStream_t s);
+};
+
+// The compiled menu for `prec` (FP32, BF16, BF16X3); returns the count.
+int mfma_menu(int32_t prec, const MfmaEntry** entries);
+
+// Literal lowering: block_x x block_y lanes, one output each.
+hipError_t launch_literal(const GemmArgs& args, int block_x, int block_y, hipStream_t s);
+int64_t literal_alloc_bytes(int block_x, int block_y);
+
+// C <- beta * C (beta == 0 writes zeros without reading C).
+hipError_t launch_scale(float* C, int64_t ldc, int64_t m, int64_t n, float beta, hipStream_t s);
+
+}  // namespace hpvm

@@ -1,0 +1,269 @@
+// MFMA lowerings of the sgemm dataflow graph for CDNA4 (gfx950).
+//
+// Hierarchy (HPVM report, Sec. 3.4: leaf instances form one tile, the parent's
+// instances the grid of tiles, allocation-node memory goes to the scratchpad):
+//   SgemmInternal instance -> one workgroup owning a TM x TN tile of C;
+//   Allocation node        -> two LDS stages, each a TM x TK slab of A and a
+//                             TK x TN slab of B, filled from HBM with
+//                             coalesced 16-byte loads while the other stage
+//                             feeds the matrix cores;
+//   SgemmLeaf instances    -> the TM x TN outputs, held as MFMA accumulators:
+//                             each 64-lane wavefront owns a WM x WN sub-tile,
+//                             i.e. (WM/32) x (WN/32) blocks of 32 x 32.
+// The dynamic instances of SgemmInternal are independent (Sec. 2.1), so the
+// tiles may run in any order; the order chosen keeps the tiles in flight on
+// one XCD close together so that they share that XCD's L2.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace hpvm {
+
+// ---------------------------------------------------------------------------
+// Tile order.  Workgroup w is placed on XCD (w mod 8); renumber so that each
+// XCD works through one contiguous run of tiles, then walk that run in
+// groups of kGroupM tile-rows so that concurrently resident tiles share
+// A row-panels and B column-panels.
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+constexpr int kGroupM = 8;
+
+__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int w, int& tm, int& tn) {
+  const int total = tiles_m * tiles_n;
+  const int q = total / kXcds, rem = total % kXcds;
+  const int x = w % kXcds;
+  const int t = x * q + (x < rem ? x : rem) + w / kXcds;
+  const int per_group = kGroupM * tiles_n;
+  const int group = t / per_group;
+  const int first_m = group * kGroupM;
+  const int gsize = (tiles_m - first_m) < kGroupM ? (tiles_m - first_m) : kGroupM;
+  const int in_group = t - group * per_group;
+  tm = first_m + in_group % gsize;
+  tn = in_group / gsize;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 operand staging.  KC: rows are m (or n) indices with k contiguous,
+// row stride TK + 4 floats; otherwise rows are k indices with m (or n)
+// contiguous, row stride MN + 8 floats.  Both keep the global layout, so no
+// transposition happens on the way into LDS; the paddings spread one
+// fragment read over all LDS banks.
+//
+// v_mfma_f32_32x32x2f32 takes, in lane l, A(row l%32, k-slot l/32) and
+// B(k-slot l/32, col l%32).  Within a group of 8 k values the slot h of
+// step t is k = 4h + t, so a k-contiguous operand is read with one 16-byte
+// LDS read per group and an m/n-contiguous one with four 4-byte reads.
+// ---------------------------------------------------------------------------
+template <int MN, int TK, bool KC>
+struct F32Operand {
+  static constexpr int kRows = KC ? MN : TK;
+  static constexpr int kCols = KC ? TK : MN;
+  static constexpr int kStride = KC ? TK + 4 : MN + 8;
+  static constexpr int kFloats = kRows * kStride;
+
+  __device__ __forceinline__ static f32x4 frag(const float* lds, int mn0, int kg, int lane) {
+    const int r32 = lane & 31, h = lane >> 5;
+    if constexpr (KC) {
+      return *reinterpret_cast<const f32x4*>(lds + (mn0 + r32) * kStride + kg * 8 + 4 * h);
+    } else {
+      const float* q = lds + (kg * 8 + 4 * h) * kStride + mn0 + r32;
+      f32x4 v;
+      v[0] = q[0];
+      v[1] = q[kStride];
+      v[2] = q[2 * kStride];
+      v[3] = q[3 * kStride];
+      return v;
+    }
+  }
+};
+
+// Global-memory corner of the slab at k0 for each operand form.
+template <bool AT>
+__device__ __forceinline__ void slab_a(const GemmArgs& p, int m0, int k0, const float*& base,
+                                       int& rlim, int& clim) {
+  if constexpr (!AT) {
+    base = p.A + (int64_t)m0 * p.lda + k0;
+    rlim = p.m - m0;
+    clim = p.k - k0;
+  } else {
+    base = p.A + (int64_t)k0 * p.lda + m0;
+    rlim = p.k - k0;
+    clim = p.m - m0;
+  }
+}
+template <bool BT>
+__device__ __forceinline__ void slab_b(const GemmArgs& p, int n0, int k0, const float*& base,
+                                       int& rlim, int& clim) {
+  if constexpr (!BT) {
+    base = p.B + (int64_t)k0 * p.ldb + n0;
+    rlim = p.k - k0;
+    clim = p.n - n0;
+  } else {
+    base = p.B + (int64_t)n0 * p.ldb + k0;
+    rlim = p.n - n0;
+    clim = p.k - k0;
+  }
+}
+
+// Epilogue: C <- alpha * acc + beta * C, element-wise, masked at the edges.
+// Output (i, j) of a 32 x 32 block lives in lane j + 32 * ((i / 4) % 2),
+// register (i % 4) + 4 * (i / 8).
+template <int BM, int BN>
+__device__ __forceinline__ void store_c(const GemmArgs& p, const f32x16 (&acc)[BM][BN], int row0,
+                                        int col0, int lane) {
+  const int r32 = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BN; ++bj) {
+      const int j = col0 + 32 * bj + r32;
+      if (j >= p.n) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = row0 + 32 * bi + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (i < p.m) {
+          float* c = p.C + (int64_t)i * p.ldc + j;
+          float v = p.alpha * acc[bi][bj][r];
+          if (p.beta != 0.0f) v = fmaf(p.beta, *c, v);
+          *c = v;
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 kernel: v_mfma_f32_32x32x2f32, FP32 operands and accumulation.
+// ---------------------------------------------------------------------------
+template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT>
+__global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
+    sgemm_mfma_f32(GemmArgs p) {
+  constexpr int kWavesN = TN / WN;
+  constexpr int NT = (TM / WM) * kWavesN * kWave;
+  constexpr int BM = WM / 32, BN = WN / 32;
+  static_assert(TK % 8 == 0, "K slab must hold whole groups of 8");
+  using OpA = F32Operand<TM, TK, !AT>;
+  using OpB = F32Operand<TN, TK, BT>;
+
+  extern __shared__ __align__(16) float lds[];
+  float* As0 = lds;
+  float* As1 = lds + OpA::kFloats;
+  float* Bs0 = lds + 2 * OpA::kFloats;
+  float* Bs1 = Bs0 + OpB::kFloats;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int wm0 = (wave / kWavesN) * WM, wn0 = (wave % kWavesN) * WN;
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, blockIdx.x, tm, tn);
+  const int m0 = tm * TM, n0 = tn * TN;
+
+  GlobalTile<OpA::kRows, OpA::kCols, NT> ga;
+  GlobalTile<OpB::kRows, OpB::kCols, NT> gb;
+  auto fetch = [&](int k0) {
+    const float* base;
+    int rl, cl;
+    slab_a<AT>(p, m0, k0, base, rl, cl);
+    ga.load(base, p.lda, rl, cl, p.vec_a, tid);
+    slab_b<BT>(p, n0, k0, base, rl, cl);
+    gb.load(base, p.ldb, rl, cl, p.vec_b, tid);
+  };
+
+  f32x16 acc[BM][BN];
+#pragma unroll
+  for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BN; ++bj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0.0f;
+
+  const int slabs = (p.k + TK - 1) / TK;
+  fetch(0);
+  ga.template store_f32<OpA::kStride>(As0, tid);
+  gb.template store_f32<OpB::kStride>(Bs0, tid);
+  __syncthreads();
+
+  for (int s = 0; s < slabs; ++s) {
+    const float* As = (s & 1) ? As1 : As0;
+    const float* Bs = (s & 1) ? Bs1 : Bs0;
+    const bool more = s + 1 < slabs;
+    if (more) fetch((s + 1) * TK);
+#pragma unroll
+    for (int kg = 0; kg < TK / 8; ++kg) {
+      f32x4 a[BM], b[BN];
+#pragma unroll
+      for (int bi = 0; bi < BM; ++bi) a[bi] = OpA::frag(As, wm0 + 32 * bi, kg, lane);
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj) b[bj] = OpB::frag(Bs, wn0 + 32 * bj, kg, lane);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < BN; ++bj)
+            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bi][t], b[bj][t], acc[bi][bj], 0, 0, 0);
+    }
+    if (more) {
+      ga.template store_f32<OpA::kStride>((s & 1) ? As0 : As1, tid);
+      gb.template store_f32<OpB::kStride>((s & 1) ? Bs0 : Bs1, tid);
+    }
+    __syncthreads();
+  }
+  store_c<BM, BN>(p, acc, m0 + wm0, n0 + wn0, lane);
+}
+
+// Dynamic LDS beyond 64 KiB must be enabled per kernel before its launch.
+template <typename Kernel>
+static hipError_t allow_lds(Kernel* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int TM, int TN, int TK, int WM, int WN>
+struct F32Config {
+  static constexpr int kThreads = (TM / WM) * (TN / WN) * kWave;
+  // LDS bytes for the given operand forms (the Allocation node's size).
+  static constexpr int64_t lds(bool at, bool bt) {
+    const int64_t a = at ? F32Operand<TM, TK, false>::kFloats : F32Operand<TM, TK, true>::kFloats;
+    const int64_t b = bt ? F32Operand<TN, TK, true>::kFloats : F32Operand<TN, TK, false>::kFloats;
+    return 2 * (a + b) * (int64_t)sizeof(float);
+  }
+  static hipError_t launch(const GemmArgs& args, bool at, bool bt, hipStream_t s) {
+    GemmArgs a = args;
+    a.tiles_m = (a.m + TM - 1) / TM;
+    a.tiles_n = (a.n + TN - 1) / TN;
+    const dim3 grid((unsigned)(a.tiles_m * a.tiles_n));
+    void* kargs[] = {&a};
+    void (*fn)(GemmArgs);
+    if (!at && !bt) fn = &sgemm_mfma_f32<TM, TN, TK, WM, WN, false, false>;
+    else if (at && !bt) fn = &sgemm_mfma_f32<TM, TN, TK, WM, WN, true, false>;
+    else if (!at && bt) fn = &sgemm_mfma_f32<TM, TN, TK, WM, WN, false, true>;
+    else return hipErrorInvalidValue;
+    const size_t bytes = (size_t)lds(at, bt);
+    hipError_t e = allow_lds(fn, bytes);
+    if (e != hipSuccess) return e;
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), grid, dim3(kThreads), kargs, bytes, s);
+  }
+};
+
+#define HPVM_F32_ENTRY(TM, TN, TK, WM, WN)                                               \
+  {{TM, TN, TK, WM, WN, 2}, HPVM_PREC_FP32, F32Config<TM, TN, TK, WM, WN>::kThreads,     \
+   F32Config<TM, TN, TK, WM, WN>::lds(false, false), &F32Config<TM, TN, TK, WM, WN>::launch}
+
+static const MfmaEntry kF32Menu[] = {
+    HPVM_F32_ENTRY(128, 128, 16, 64, 64),
+    HPVM_F32_ENTRY(256, 128, 16, 128, 64),
+    HPVM_F32_ENTRY(128, 128, 32, 64, 64),
+    HPVM_F32_ENTRY(64, 64, 16, 32, 32),
+    HPVM_F32_ENTRY(128, 64, 16, 64, 32),
+};
+
+int mfma_menu(int32_t prec, const MfmaEntry** entries) {
+  if (prec == HPVM_PREC_FP32) {
+    *entries = kF32Menu;
+    return (int)(sizeof(kF32Menu) / sizeof(kF32Menu[0]));
+  }
+  *entries = nullptr;
+  return 0;
+}
+
+}  // namespace hpvm

@@ -1,0 +1,183 @@
+"""C-ABI checks that need no GPU: exports, argument validation, graph structure.
+
+No test here launches a kernel: argument checks return before any HIP call,
+and the fault-injection switch stops a valid call right after them.
+"""
+import ctypes
+import json
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1611_00860_amd as hp
+from paper_1611_00860_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hpvm_sgemm.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "sgemm_dfg_structure.json")
+FAKE = 0x10000  # never dereferenced: validation or injection stops first
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return hp.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpvm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_functions()
+    assert names, "no declarations found"
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (hpvm_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    # and the binding declares a signature for every one of them
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(_lib.RootIn) == 88
+    assert ctypes.sizeof(_lib.Tile) == 24
+    assert ctypes.sizeof(_lib.Edge) == 24
+
+
+def test_root_in_matches_paper_listing():
+    g = json.load(open(GOLDEN))
+    assert ctypes.sizeof(_lib.RootIn) == g["root_in_bytes"]
+    assert [f for f, _ in _lib.RootIn._fields_] == g["root_in_field_names"]
+    kinds = {ctypes.c_void_p: "ptr", ctypes.c_int64: "i64", ctypes.c_int32: "i32",
+             ctypes.c_float: "float"}
+    assert [kinds[t] for _, t in _lib.RootIn._fields_] == g["root_in_field_types"]
+
+
+def test_allocation_size_formula():
+    g = json.load(open(GOLDEN))
+    for bx, by, expect in g["allocation_bytes"]:
+        tile = (by, bx, by, 1, 1, 1)
+        assert hp.alloc_bytes(tile) == expect
+
+
+def test_edges_match_paper_listing():
+    g = json.load(open(GOLDEN))
+    ids = g["nodes"]
+    edges = hp.dfg_edges()
+    flows = [e for e in edges if e["kind"] == 0]
+    binds = [e for e in edges if e["kind"] == 1]
+    for e in g["edges_printed"]:
+        assert {"kind": 0, "src_node": ids[e["src"]], "dst_node": ids[e["dst"]],
+                "src_port": e["src_port"], "dst_port": e["dst_port"],
+                "all_to_all": int(e["all_to_all"])} in flows
+    assert len(flows) == len(g["edges_printed"])
+    for b in g["binds_printed"]:
+        assert any(x["src_node"] == ids[b["parent"]] and x["dst_node"] == ids[b["child"]] and
+                   x["src_port"] == b["parent_port"] and x["dst_port"] == b["child_port"]
+                   for x in binds), b
+    lo, hi = g["binds_implied"]["SgemmInternal->SgemmLeaf"]
+    leaf = sorted(x["src_port"] for x in binds if x["src_node"] == 1 and x["dst_node"] == 3)
+    assert leaf == list(range(lo, hi + 1))
+    lo, hi = g["binds_implied"]["SgemmRoot->SgemmInternal"]
+    root = sorted(x["src_port"] for x in binds if x["src_node"] == 0 and x["dst_node"] == 1)
+    assert root == list(range(lo, hi + 1))
+    # every leaf input (0..13) is fed exactly once, by a bind or an edge
+    fed = sorted([x["dst_port"] for x in binds if x["dst_node"] == 3] +
+                 [x["dst_port"] for x in flows if x["dst_node"] == 3])
+    assert fed == list(range(14))
+
+
+def test_describe_literal_config():
+    g = json.load(open(GOLDEN))
+    d = hp.describe(128, 128, 128, "fp32", (32, 32, 32, 1, 1, 1))
+    assert d["root_instances"] == g["root_instances"] == 1
+    assert (d["grid_x"], d["grid_y"], d["block_x"], d["block_y"]) == (4, 4, 32, 32)
+    assert d["alloc_bytes"] == 4096 and d["lowering_name"] == "literal" and d["k_slabs"] == 4
+    assert d["waves"] == 16
+
+
+def test_describe_mfma_grids():
+    menu = hp.tile_menu("fp32")
+    assert menu, "no FP32 MFMA tile compiled"
+    for tile in menu:
+        tm, tn, tk, lm, ln, st = tile
+        d = hp.describe(4096, 4096, 4096, "fp32", tile)
+        assert d["grid_x"] == -(-4096 // tn) and d["grid_y"] == -(-4096 // tm)
+        assert d["waves"] == (tm // lm) * (tn // ln)
+        assert d["k_slabs"] == -(-4096 // tk)
+        assert d["alloc_bytes"] == hp.alloc_bytes(tile, "fp32") <= 160 * 1024
+        assert d["lowering_name"] == "mfma_f32"
+    d = hp.describe(8192, 4096, 2048, "fp32", None)
+    assert d["lowering_name"] == "mfma_f32"
+
+
+def call(lib, m=4, n=4, k=4, alpha=1.0, A=FAKE, lda=4, B=FAKE * 2, ldb=4, beta=0.0, C=FAKE * 4,
+         ldc=4, prec=0, tile=None):
+    t = ctypes.byref(_lib.Tile(*tile)) if tile else None
+    return lib.hpvm_sgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec, t, None)
+
+
+@pytest.mark.parametrize("kw,argno", [
+    ({"m": -1}, 1), ({"n": -1}, 2), ({"k": -2}, 3), ({"A": None}, 5), ({"lda": 3}, 6),
+    ({"B": None}, 7), ({"ldb": 2}, 8), ({"C": None}, 10), ({"ldc": 1}, 11), ({"prec": 9}, 12),
+])
+def test_invalid_arguments_name_the_first_bad_one(lib, kw, argno):
+    rc = call(lib, **kw)
+    assert rc == -1
+    assert hp.last_error().startswith(f"argument {argno}:"), hp.last_error()
+
+
+def test_checks_run_in_argument_order(lib):
+    rc = call(lib, m=-1, lda=0, C=None)
+    assert rc == -1 and hp.last_error().startswith("argument 1:")
+
+
+def test_unsupported_tile_and_literal_precision(lib):
+    assert call(lib, tile=(48, 48, 16, 16, 16, 2)) == -2
+    assert "argument 13" in hp.last_error()
+    assert call(lib, tile=(32, 32, 32, 1, 1, 1), prec=1) == -2
+    assert call(lib, tile=(32, 32, 16, 1, 1, 1)) == -2  # literal needs tile_k == tile_m
+    assert call(lib, tile=(4, 4, 4, 1, 1, 1)) == -2     # fewer lanes than a wavefront
+
+
+def test_overlap_of_c_with_inputs_is_refused(lib):
+    assert call(lib, A=FAKE, C=FAKE + 8) == -1
+    assert "overlaps" in hp.last_error()
+
+
+def test_quick_returns_without_device(lib):
+    assert call(lib, m=0, A=None, B=None, C=None) == 0
+    assert call(lib, n=0, A=None, B=None, C=None) == 0
+
+
+def test_fault_injection_reports_hip_error(lib, monkeypatch):
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    rc = call(lib)
+    assert rc == -3 and "injected" in hp.last_error()
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "wait")
+    assert lib.hpvm_wait(None) == -3
+    with pytest.raises(hp.HpvmError) as ei:
+        hp._check(-3)
+    assert ei.value.status == -3
+
+
+def test_status_strings(lib):
+    for code, name in [(0, "HPVM_OK"), (-1, "HPVM_INVALID_ARG"), (-2, "HPVM_UNSUPPORTED"),
+                       (-3, "HPVM_HIP_ERROR"), (-4, "HPVM_WORKSPACE_TOO_SMALL"), (-5, "HPVM_BAD_HANDLE")]:
+        assert hp.status_string(code) == name
+
+
+def test_root_launch_validation(lib):
+    r = _lib.RootIn(FAKE, 16 * 16 * 4, 16, FAKE * 2, 16 * 16 * 4, 16, FAKE * 4, 16 * 16 * 4, 16,
+                    16, 1.0, 0.0, 16, 16, 1, 1)
+    r.bytesC = 100
+    assert lib.hpvm_launch_root(ctypes.byref(r), None) == -1 and "bytesC" in hp.last_error()
+    r.bytesC = 16 * 16 * 4
+    r.block_x = 3
+    assert lib.hpvm_launch_root(ctypes.byref(r), None) == -2
+    assert lib.hpvm_launch_root(None, None) == -1

@@ -1,0 +1,167 @@
+"""GPU parity of the sgemm lowerings against the FP64 oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1611_00860_amd import inputs
+from gpu_util import componentwise_bound, normwise, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+LITERAL = (32, 32, 32, 1, 1, 1)
+
+
+def run(hp, A, B, C, alpha, beta, prec="fp32", tile=None, pad=0, misalign=False):
+    import torch
+
+    dA, dB, dC = (to_dev(x, pad, misalign) for x in (A, B, C))
+    hp.sgemm(dA, dB, dC, alpha, beta, prec=prec, tile=tile)
+    torch.cuda.synchronize()
+    return to_host(dC)
+
+
+# ---------------------------------------------------------------------------
+# Literal lowering: 128^3, alpha = 1, beta = 0.5, internal tile 32 x 32, one
+# output per leaf instance.
+# ---------------------------------------------------------------------------
+def test_literal_small_config(gpu):
+    print("case: literal 128^3 seed 0", flush=True)
+    A, B, C = inputs.sgemm_operands(128, 128, 128, seed=0)
+    ref = oracle.sgemm(A, B, C, 1.0, 0.5)
+    got = run(gpu, A, B, C, 1.0, 0.5, tile=LITERAL)
+    assert normwise(got, ref) <= 1e-5
+    assert np.all(np.abs(got - ref) <= componentwise_bound(A, B, C, 1.0, 0.5, 128))
+
+
+def test_literal_integers_bit_exact(gpu):
+    A, B, C = inputs.sgemm_operands(128, 128, 128, seed=0, dist="int")
+    ref = oracle.sgemm(A, B, C, 1.0, 0.5)
+    got = run(gpu, A, B, C, 1.0, 0.5, tile=LITERAL)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("m,n,k,tile", [(100, 70, 45, LITERAL), (65, 130, 33, (16, 16, 16, 1, 1, 1)),
+                                        (33, 64, 17, (8, 32, 8, 1, 1, 1))])
+def test_literal_ragged(gpu, m, n, k, tile):
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=1, dist="int")
+    ref = oracle.sgemm(A, B, C, 2.0, -1.0)
+    got = run(gpu, A, B, C, 2.0, -1.0, tile=tile, pad=3)
+    assert np.array_equal(got, ref)
+
+
+def test_root_launch_packed_args(gpu):
+    """The paper's 88-byte root argument block drives the same lowering."""
+    import torch
+
+    A, B, C = inputs.sgemm_operands(128, 128, 128, seed=0)
+    ref = oracle.sgemm(A, B, C, 1.0, 0.5)
+    dA, dB, dC = (to_dev(x) for x in (A, B, C))
+    gpu.launch_root(dA, dB, dC, 128, 1.0, 0.5, block=(32, 32), grid=(4, 4))
+    gpu.wait()
+    got = to_host(dC)
+    assert normwise(got, ref) <= 1e-5
+    # the same call with too small a byte extent for C is refused, C untouched
+    before = dC.clone()
+    with pytest.raises(gpu.HpvmError):
+        gpu.launch_root(dA, dB, dC, 128, 1.0, 0.5, block=(32, 32), grid=(4, 4),
+                        bytes_override=(128 * 128 * 4, 128 * 128 * 4, 100))
+    torch.cuda.synchronize()
+    assert torch.equal(before, dC)
+
+
+# ---------------------------------------------------------------------------
+# MFMA lowerings, every compiled tile
+# ---------------------------------------------------------------------------
+def _menu(prec):
+    import paper_1611_00860_amd as hp
+
+    return hp.tile_menu(prec)
+
+
+SHAPES = [(300, 260, 200), (128, 128, 16), (1, 1, 1), (257, 129, 77), (64, 520, 36)]
+
+
+@pytest.mark.parametrize("m,n,k", SHAPES)
+def test_f32_mfma_integers_bit_exact_all_tiles(gpu, m, n, k):
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=m + n + k, dist="int")
+    ref = oracle.sgemm(A, B, C, 1.0, 1.0)
+    for tile in _menu("fp32"):
+        print(f"case: fp32 int {m}x{n}x{k} tile {tile}", flush=True)
+        got = run(gpu, A, B, C, 1.0, 1.0, tile=tile, pad=4)
+        assert np.array_equal(got, ref), tile
+
+
+@pytest.mark.parametrize("m,n,k", SHAPES[:2])
+def test_f32_mfma_uniform_within_bound_all_tiles(gpu, m, n, k):
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=5)
+    alpha, beta = 1.0, 0.5
+    ref = oracle.sgemm(A, B, C, alpha, beta)
+    bound = componentwise_bound(A, B, C, alpha, beta, k)
+    for tile in _menu("fp32"):
+        got = run(gpu, A, B, C, alpha, beta, tile=tile)
+        assert normwise(got, ref) <= 1e-5, tile
+        assert np.all(np.abs(got - ref) <= bound), tile
+
+
+def test_f32_mfma_unaligned_operands(gpu):
+    """Pointers off 16-byte alignment and odd leading dimensions take scalar loads."""
+    A, B, C = inputs.sgemm_operands(190, 150, 130, seed=9, dist="int")
+    ref = oracle.sgemm(A, B, C, 1.0, -2.0)
+    got = run(gpu, A, B, C, 1.0, -2.0, pad=1, misalign=True)
+    assert np.array_equal(got, ref)
+
+
+def test_edge_cases(gpu):
+    import torch
+
+    A, B, C = inputs.sgemm_operands(70, 90, 50, seed=2)
+    # alpha = 0: C <- beta C, A and B never read (NaN there must not leak)
+    An = A.copy()
+    An[0, 0] = np.nan
+    got = run(gpu, An, B, C, 0.0, 0.25)
+    assert np.array_equal(got, (np.float32(0.25) * C).astype(np.float64))
+    # beta = 0: C never read (NaN in C is overwritten)
+    Cn = np.full_like(C, np.nan)
+    got = run(gpu, A, B, Cn, 1.0, 0.0)
+    ref = oracle.sgemm(A, B, None, 1.0, 0.0)
+    assert np.all(np.isfinite(got)) and normwise(got, ref) <= 1e-5
+    # beta = 0 and alpha = 0: zeros
+    got = run(gpu, A, B, Cn, 0.0, 0.0)
+    assert np.array_equal(got, np.zeros_like(got))
+    # k = 0: C <- beta C
+    dA = torch.zeros((70, 0), device="cuda")
+    dB = torch.zeros((0, 90), device="cuda")
+    dC = to_dev(C)
+    gpu.sgemm(dA, dB, dC, 1.0, 3.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(dC), (np.float32(3.0) * C).astype(np.float64))
+    # m = 0 / n = 0: nothing happens
+    e = torch.zeros((0, 5), device="cuda")
+    gpu.sgemm(e, torch.zeros((5, 7), device="cuda"), torch.zeros((0, 7), device="cuda"), 1.0, 1.0)
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# Full sizes of the FP32 workload, in the launch configuration the benchmark
+# times: sampled entries against the oracle's element-wise definition.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,k", [(4096, 4096, 4096), (8192, 4096, 2048)])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_f32_full_size_sampled(gpu, m, n, k, beta):
+    import torch
+
+    print(f"case: fp32 full {m}x{n}x{k} beta {beta}", flush=True)
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=1)
+    dA, dB, dC = (to_dev(x) for x in (A, B, C))
+    gpu.sgemm(dA, dB, dC, 1.0, beta)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy()
+    rng = np.random.default_rng(123)
+    rows = np.concatenate([rng.integers(0, m, 1500), [0, m - 1, m - 1, 0]])
+    cols = np.concatenate([rng.integers(0, n, 1500), [0, n - 1, 0, n - 1]])
+    ref = oracle.sgemm_entries(A, B, C, 1.0, beta, rows, cols)
+    g = got[rows, cols].astype(np.float64)
+    assert normwise(g, ref) <= 1e-5
+    ab = np.abs(A[rows].astype(np.float64)) * np.abs(B[:, cols].T.astype(np.float64))
+    bound = 2 * (k + 2) * 2.0 ** -24 * ab.sum(axis=1) + 4 * 2.0 ** -24 * abs(beta) * np.abs(C[rows, cols])
+    assert np.all(np.abs(g - ref) <= bound)
