@@ -207,6 +207,93 @@ int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity,
                    int32_t* count);
 
 /* ======================================================================== */
+/* Grouped launch: many independent sgemms in one persistent kernel         */
+/* ======================================================================== */
+/* The instances of a batch are independent dataflow graphs (Sec. 2.1: the
+ * dynamic instances of a node are independent), so their SgemmInternal
+ * tiles can share one launch.  One persistent kernel (Sec. 3.5 keeps nodes
+ * alive as persistent workers; Sec. 4.2 fuses nodes to save kernel launches)
+ * pulls tiles from a device-side list, longest first, with an atomic
+ * counter; each instance has its own tile shape.  Plans are host objects;
+ * device state lives in a caller-provided workspace.                       */
+
+typedef struct hpvm_sgemm_desc {
+  int64_t m, n, k;
+  float alpha, beta;
+  const float* A;
+  int64_t lda;
+  const float* B;
+  int64_t ldb;
+  float* C;
+  int64_t ldc;
+} hpvm_sgemm_desc;
+
+typedef struct hpvm_grouped_info {
+  int32_t count;        /* instances                                        */
+  int32_t total_tiles;  /* SgemmInternal instances over the whole batch    */
+  int32_t grid;         /* persistent workgroups per launch                */
+  int32_t shapes_used;  /* distinct tile shapes in the plan                 */
+  int64_t workspace_bytes;
+  int64_t scratch_bytes; /* output scratch hpvm_grouped_autotune needs      */
+  double flops;         /* sum of 2 m n k over the instances               */
+} hpvm_grouped_info;
+
+/* Validates every descriptor (the hpvm_sgemm rules per instance, and no two
+ * instances' C ranges may overlap) and builds a plan.  prec must be
+ * HPVM_PREC_FP32.  tile == NULL picks a shape per instance from
+ * hpvm_grouped_menu with the built-in cost model; otherwise `tile` (from
+ * that menu) is used for every instance.  *plan receives an opaque handle
+ * owned by the library until hpvm_grouped_plan_destroy.  The descriptors
+ * are copied: the caller's array may be freed afterwards; the matrices
+ * themselves must stay valid while the plan is run.                       */
+int hpvm_grouped_plan_create(int32_t count, const hpvm_sgemm_desc* descs, int32_t prec,
+                             const hpvm_tile* tile, void** plan);
+
+/* Plan summary. */
+int hpvm_grouped_plan_info(const void* plan, hpvm_grouped_info* info);
+
+/* Tile shape chosen for instance `index` (0-based, in the caller's order). */
+int hpvm_grouped_instance_tile(const void* plan, int32_t index, hpvm_tile* tile);
+
+/* Shapes the grouped kernel supports (all 256 lanes per workgroup). */
+int hpvm_grouped_menu(hpvm_tile* out, int32_t capacity, int32_t* count);
+
+/* Device bytes the workspace of hpvm_grouped_run / _capture must have:
+ * a tile counter, the instance descriptors and the tile -> instance map. */
+int hpvm_grouped_workspace_bytes(const void* plan, int64_t* bytes);
+
+/* Uploads the plan into `workspace` (device memory, >= the bytes above,
+ * 16-byte aligned) and enqueues the batch on `stream`: a kernel that clears
+ * the tile counter, then the persistent kernel.  Returns once enqueued.
+ * Runs on one stream must not overlap in time on the same workspace.      */
+int hpvm_grouped_run(void* plan, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* Uploads the plan into `workspace` (synchronously on `stream`) and builds
+ * an instantiated HIP graph of the same two kernels (a counter-clearing
+ * kernel, no memset node).  *graph receives a handle for hpvm_graph_launch;
+ * the workspace and every matrix must stay valid while the graph exists.  */
+int hpvm_grouped_capture(void* plan, void* workspace, int64_t workspace_bytes, void* stream,
+                         void** graph);
+
+/* Replays a graph on `stream` (asynchronous, like llvm.hpvm.launch; the
+ * graph handle plays the role of the paper's graph ID, Table 1).           */
+int hpvm_graph_launch(void* graph, void* stream);
+
+/* Destroys a graph / plan.  Using a handle afterwards returns
+ * HPVM_BAD_HANDLE.                                                          */
+int hpvm_graph_destroy(void* graph);
+int hpvm_grouped_plan_destroy(void* plan);
+
+/* Autotuner of the grouped plan: times candidate shape assignments (one
+ * shape for all instances, and cost-model assignments) with the real
+ * kernel, keeps the fastest in the plan and returns its time per launch in
+ * *best_ms.  Timing runs write their outputs to `scratch` (device memory of
+ * hpvm_grouped_info.scratch_bytes, with beta = 0), never to the instances'
+ * C.  Each candidate is launched `reps` times after one warm-up.           */
+int hpvm_grouped_autotune(void* plan, void* workspace, int64_t workspace_bytes, float* scratch,
+                          int64_t scratch_bytes, int32_t reps, void* stream, float* best_ms);
+
+/* ======================================================================== */
 /* Diagnostics                                                               */
 /* ======================================================================== */
 

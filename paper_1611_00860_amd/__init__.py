@@ -167,3 +167,106 @@ def tile_menu(prec="fp32") -> list:
     arr = (_lib.Tile * count.value)()
     _check(lib.hpvm_tile_menu(_prec(prec), arr, count.value, ctypes.byref(count)))
     return [t.as_tuple() for t in arr]
+
+
+# ---------------------------------------------------------------------------
+# Grouped launch
+# ---------------------------------------------------------------------------
+def grouped_menu() -> list:
+    """Tile shapes the grouped persistent kernel supports."""
+    lib = load()
+    count = ctypes.c_int32(0)
+    _check(lib.hpvm_grouped_menu(None, 0, ctypes.byref(count)))
+    arr = (_lib.Tile * count.value)()
+    _check(lib.hpvm_grouped_menu(arr, count.value, ctypes.byref(count)))
+    return [t.as_tuple() for t in arr]
+
+
+class Graph:
+    """An instantiated HIP graph of a grouped launch (hpvm_graph_*)."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep  # tensors the graph reads or writes
+
+    def launch(self, stream=None):
+        _check(load().hpvm_graph_launch(self._h, _stream(stream)))
+
+    def destroy(self):
+        if self._h is not None:
+            _check(load().hpvm_graph_destroy(self._h))
+            self._h = None
+
+
+class GroupedPlan:
+    """Many independent sgemms C_i <- alpha_i A_i B_i + beta_i C_i in one launch.
+
+    Holds references to every tensor so they outlive the plan; the device
+    workspace is a torch allocation of the size the library asks for.
+    """
+
+    def __init__(self, As, Bs, Cs, alphas, betas, prec="fp32", tile=None):
+        import torch
+
+        lib = load()
+        n = len(As)
+        if not (len(Bs) == len(Cs) == len(alphas) == len(betas) == n):
+            raise ValueError("As, Bs, Cs, alphas, betas must have the same length")
+        descs = (_lib.SgemmDesc * max(n, 1))()
+        for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+            m, k = A.shape
+            k2, nn = B.shape
+            if k2 != k or tuple(C.shape) != (m, nn):
+                raise ValueError(f"instance {i}: shape mismatch")
+            pa, lda = _mat(A, f"A[{i}]")
+            pb, ldb = _mat(B, f"B[{i}]")
+            pc, ldc = _mat(C, f"C[{i}]")
+            descs[i] = _lib.SgemmDesc(m, nn, k, float(alphas[i]), float(betas[i]), pa.value, lda,
+                                      pb.value, ldb, pc.value, ldc)
+        h = ctypes.c_void_p()
+        _check(lib.hpvm_grouped_plan_create(n, descs, _prec(prec), _tile(tile), ctypes.byref(h)))
+        self._h = h
+        self._keep = (list(As), list(Bs), list(Cs))
+        self.workspace = torch.empty(max(self.info()["workspace_bytes"], 16), dtype=torch.uint8,
+                                     device=Cs[0].device if n else "cuda")
+
+    def info(self) -> dict:
+        inf = _lib.GroupedInfo()
+        _check(load().hpvm_grouped_plan_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _lib.GroupedInfo._fields_}
+
+    def instance_tile(self, i: int):
+        t = _lib.Tile()
+        _check(load().hpvm_grouped_instance_tile(self._h, int(i), ctypes.byref(t)))
+        return t.as_tuple()
+
+    def _ws(self):
+        return ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel()
+
+    def run(self, stream=None):
+        ws, nb = self._ws()
+        _check(load().hpvm_grouped_run(self._h, ws, nb, _stream(stream)))
+
+    def autotune(self, reps: int = 3, stream=None) -> float:
+        """Times candidate shape assignments on scratch outputs; keeps the fastest."""
+        import torch
+
+        scratch = torch.empty(max(self.info()["scratch_bytes"] // 4, 1), dtype=torch.float32,
+                              device=self.workspace.device)
+        ws, nb = self._ws()
+        best = ctypes.c_float(0.0)
+        _check(load().hpvm_grouped_autotune(self._h, ws, nb, ctypes.c_void_p(scratch.data_ptr()),
+                                            scratch.numel() * 4, int(reps), _stream(stream),
+                                            ctypes.byref(best)))
+        return best.value
+
+    def capture(self, stream=None) -> Graph:
+        ws, nb = self._ws()
+        g = ctypes.c_void_p()
+        _check(load().hpvm_grouped_capture(self._h, ws, nb, _stream(stream), ctypes.byref(g)))
+        return Graph(g, (self._keep, self.workspace))
+
+    def destroy(self):
+        if self._h is not None:
+            _check(load().hpvm_grouped_plan_destroy(self._h))
+            self._h = None

@@ -46,6 +46,20 @@ class Edge(ctypes.Structure):
                 ("src_port", i32), ("dst_port", i32), ("all_to_all", i32)]
 
 
+class SgemmDesc(ctypes.Structure):
+    _fields_ = [("m", i64), ("n", i64), ("k", i64), ("alpha", f32), ("beta", f32),
+                ("A", vp), ("lda", i64), ("B", vp), ("ldb", i64), ("C", vp), ("ldc", i64)]
+
+
+class GroupedInfo(ctypes.Structure):
+    _fields_ = [("count", i32), ("total_tiles", i32), ("grid", i32), ("shapes_used", i32),
+                ("workspace_bytes", i64), ("scratch_bytes", i64), ("flops", ctypes.c_double)]
+
+
+PTile = ctypes.POINTER(Tile)
+Pvp = ctypes.POINTER(vp)
+Pi64 = ctypes.POINTER(i64)
+
 # name -> (restype, argtypes); the same list the header declares.
 SIGNATURES = {
     "hpvm_sgemm": (ctypes.c_int, [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32,
@@ -56,6 +70,17 @@ SIGNATURES = {
     "hpvm_describe": (ctypes.c_int, [i64, i64, i64, i32, ctypes.POINTER(Tile), ctypes.POINTER(Dfg)]),
     "hpvm_dfg_edges": (ctypes.c_int, [ctypes.POINTER(Edge), i32, ctypes.POINTER(i32)]),
     "hpvm_tile_menu": (ctypes.c_int, [i32, ctypes.POINTER(Tile), i32, ctypes.POINTER(i32)]),
+    "hpvm_grouped_plan_create": (ctypes.c_int, [i32, ctypes.POINTER(SgemmDesc), i32, PTile, Pvp]),
+    "hpvm_grouped_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(GroupedInfo)]),
+    "hpvm_grouped_instance_tile": (ctypes.c_int, [vp, i32, PTile]),
+    "hpvm_grouped_menu": (ctypes.c_int, [PTile, i32, ctypes.POINTER(i32)]),
+    "hpvm_grouped_workspace_bytes": (ctypes.c_int, [vp, Pi64]),
+    "hpvm_grouped_run": (ctypes.c_int, [vp, vp, i64, vp]),
+    "hpvm_grouped_capture": (ctypes.c_int, [vp, vp, i64, vp, Pvp]),
+    "hpvm_graph_launch": (ctypes.c_int, [vp, vp]),
+    "hpvm_graph_destroy": (ctypes.c_int, [vp]),
+    "hpvm_grouped_plan_destroy": (ctypes.c_int, [vp]),
+    "hpvm_grouped_autotune": (ctypes.c_int, [vp, vp, i64, vp, i64, i32, vp, ctypes.POINTER(f32)]),
     "hpvm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "hpvm_last_error": (ctypes.c_char_p, []),
 }

@@ -16,11 +16,13 @@
 #include "hpvm_sgemm.h"
 #include "internal.hpp"
 
+namespace hpvm {
+
 namespace {
-
 thread_local char g_error[512] = "";
+}
 
-int fail(int code, const char* fmt, ...) {
+int set_error(int code, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(g_error, sizeof g_error, fmt, ap);
@@ -28,21 +30,83 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-int ok() {
+int clear_error() {
   g_error[0] = '\0';
   return HPVM_OK;
 }
 
-int hip_fail(hipError_t e, const char* what) {
-  return fail(HPVM_HIP_ERROR, "%s: %s", what, hipGetErrorString(e));
+const char* last_error_text() { return g_error; }
+
+int hip_error(hipError_t e, const char* what) {
+  return set_error(HPVM_HIP_ERROR, "%s: %s", what, hipGetErrorString(e));
 }
 
-// HPVM_FAULT_INJECT=launch makes every launch report a HIP failure after the
-// argument checks, so that error propagation can be exercised without a GPU.
-bool inject(const char* site) {
+// HPVM_FAULT_INJECT=<site> makes the named step report a HIP failure after
+// the argument checks, so that error propagation can be exercised without a
+// GPU.  Sites: launch, wait, capture.
+bool fault_injected(const char* site) {
   const char* v = std::getenv("HPVM_FAULT_INJECT");
   return v && std::strcmp(v, site) == 0;
 }
+
+void matrix_extent(const void* p, int64_t rows, int64_t cols, int64_t ld, uintptr_t* lo, uintptr_t* hi) {
+  *lo = (uintptr_t)p;
+  *hi = (uintptr_t)p + (uintptr_t)(((rows - 1) * ld + cols) * (int64_t)sizeof(float));
+}
+
+int check_gemm_args(const char* what, int64_t m, int64_t n, int64_t k, float alpha, const float* A,
+                    int64_t lda, const float* B, int64_t ldb, float beta, const float* C,
+                    int64_t ldc, bool* reads_ab) {
+  (void)beta;
+  if (m < 0) return set_error(HPVM_INVALID_ARG, "%sargument 1: m = %lld < 0", what, (long long)m);
+  if (n < 0) return set_error(HPVM_INVALID_ARG, "%sargument 2: n = %lld < 0", what, (long long)n);
+  if (k < 0) return set_error(HPVM_INVALID_ARG, "%sargument 3: k = %lld < 0", what, (long long)k);
+  if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX)
+    return set_error(HPVM_UNSUPPORTED, "%ssizes above 2^31 - 1 are not supported", what);
+  const bool empty = (m == 0 || n == 0);
+  *reads_ab = !empty && k > 0 && alpha != 0.0f;
+  if (*reads_ab && !A) return set_error(HPVM_INVALID_ARG, "%sargument 5: A is NULL", what);
+  if (lda < (k > 1 ? k : 1))
+    return set_error(HPVM_INVALID_ARG, "%sargument 6: lda = %lld < max(1, k)", what, (long long)lda);
+  if (*reads_ab && !B) return set_error(HPVM_INVALID_ARG, "%sargument 7: B is NULL", what);
+  if (ldb < (n > 1 ? n : 1))
+    return set_error(HPVM_INVALID_ARG, "%sargument 8: ldb = %lld < max(1, n)", what, (long long)ldb);
+  if (!empty && !C) return set_error(HPVM_INVALID_ARG, "%sargument 10: C is NULL", what);
+  if (ldc < (n > 1 ? n : 1))
+    return set_error(HPVM_INVALID_ARG, "%sargument 11: ldc = %lld < max(1, n)", what, (long long)ldc);
+  if (*reads_ab) {
+    uintptr_t c0, c1, x0, x1;
+    matrix_extent(C, m, n, ldc, &c0, &c1);
+    matrix_extent(A, m, k, lda, &x0, &x1);
+    const bool oa = c0 < x1 && x0 < c1;
+    matrix_extent(B, k, n, ldb, &x0, &x1);
+    const bool ob = c0 < x1 && x0 < c1;
+    if (oa || ob) return set_error(HPVM_INVALID_ARG, "%sargument 10: C overlaps A or B", what);
+  }
+  return HPVM_OK;
+}
+
+}  // namespace hpvm
+
+namespace {
+
+using hpvm::set_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return set_error(code, "%s", buf);
+}
+
+int ok() { return hpvm::clear_error(); }
+
+int hip_fail(hipError_t e, const char* what) { return hpvm::hip_error(e, what); }
+
+bool inject(const char* site) { return hpvm::fault_injected(site); }
 
 bool valid_prec(int32_t prec) {
   return prec == HPVM_PREC_FP32 || prec == HPVM_PREC_BF16 || prec == HPVM_PREC_BF16X3;
@@ -98,21 +162,6 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
   return HPVM_OK;
 }
 
-// Byte range [lo, hi) a row-major rows x cols matrix with leading dimension
-// ld occupies.
-void extent(const void* p, int64_t rows, int64_t cols, int64_t ld, uintptr_t* lo, uintptr_t* hi) {
-  *lo = (uintptr_t)p;
-  *hi = (uintptr_t)p + (uintptr_t)(((rows - 1) * ld + cols) * (int64_t)sizeof(float));
-}
-
-bool overlaps(const void* a, int64_t ar, int64_t ac, int64_t alda, const void* b, int64_t br,
-              int64_t bc, int64_t bld) {
-  uintptr_t a0, a1, b0, b1;
-  extent(a, ar, ac, alda, &a0, &a1);
-  extent(b, br, bc, bld, &b0, &b1);
-  return a0 < b1 && b0 < a1;
-}
-
 bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
 
 }  // namespace
@@ -131,7 +180,7 @@ const char* hpvm_status_string(int status) {
   }
 }
 
-const char* hpvm_last_error(void) { return g_error; }
+const char* hpvm_last_error(void) { return hpvm::last_error_text(); }
 
 int hpvm_alloc_bytes(const hpvm_tile* tile, int32_t prec, int64_t* bytes) {
   if (!tile) return fail(HPVM_INVALID_ARG, "argument 1: tile is NULL");
@@ -216,28 +265,14 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
                const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
                const hpvm_tile* tile, void* stream) {
   // Checks in argument order; nothing below touches the device until all pass.
-  if (m < 0) return fail(HPVM_INVALID_ARG, "argument 1: m = %lld < 0", (long long)m);
-  if (n < 0) return fail(HPVM_INVALID_ARG, "argument 2: n = %lld < 0", (long long)n);
-  if (k < 0) return fail(HPVM_INVALID_ARG, "argument 3: k = %lld < 0", (long long)k);
-  if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX)
-    return fail(HPVM_UNSUPPORTED, "sizes above 2^31 - 1 are not supported");
-  const bool empty = (m == 0 || n == 0);
-  const bool reads_ab = !empty && k > 0 && alpha != 0.0f;
-  if (reads_ab && !A) return fail(HPVM_INVALID_ARG, "argument 5: A is NULL");
-  if (lda < (k > 1 ? k : 1))
-    return fail(HPVM_INVALID_ARG, "argument 6: lda = %lld < max(1, k)", (long long)lda);
-  if (reads_ab && !B) return fail(HPVM_INVALID_ARG, "argument 7: B is NULL");
-  if (ldb < (n > 1 ? n : 1))
-    return fail(HPVM_INVALID_ARG, "argument 8: ldb = %lld < max(1, n)", (long long)ldb);
-  if (!empty && !C) return fail(HPVM_INVALID_ARG, "argument 10: C is NULL");
-  if (ldc < (n > 1 ? n : 1))
-    return fail(HPVM_INVALID_ARG, "argument 11: ldc = %lld < max(1, n)", (long long)ldc);
+  bool reads_ab = false;
+  int rc = hpvm::check_gemm_args("", m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, &reads_ab);
+  if (rc != HPVM_OK) return rc;
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 12: unknown precision %d", prec);
   const hpvm::MfmaEntry* entry;
-  int rc = resolve(prec, tile, &entry, 13);
+  rc = resolve(prec, tile, &entry, 13);
   if (rc != HPVM_OK) return rc;
-  if (reads_ab && (overlaps(C, m, n, ldc, A, m, k, lda) || overlaps(C, m, n, ldc, B, k, n, ldb)))
-    return fail(HPVM_INVALID_ARG, "argument 10: C overlaps A or B");
+  const bool empty = (m == 0 || n == 0);
   if (empty) return ok();
   if (inject("launch")) return fail(HPVM_HIP_ERROR, "injected launch failure (HPVM_FAULT_INJECT)");
 

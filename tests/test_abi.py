@@ -181,3 +181,105 @@ def test_root_launch_validation(lib):
     r.block_x = 3
     assert lib.hpvm_launch_root(ctypes.byref(r), None) == -2
     assert lib.hpvm_launch_root(None, None) == -1
+
+
+# ---------------------------------------------------------------------------
+# Grouped plans: host-side construction, validation and handles
+# ---------------------------------------------------------------------------
+def _descs(shapes, base=0x100000):
+    arr = (_lib.SgemmDesc * len(shapes))()
+    addr = base
+    for i, (m, n, k) in enumerate(shapes):
+        a, b, c = addr, addr + 4 * m * k + 256, addr + 4 * (m * k + k * n) + 512
+        addr = c + 4 * m * n + 4096
+        arr[i] = _lib.SgemmDesc(m, n, k, 1.0, 0.5, a, max(k, 1), b, max(n, 1), c, max(n, 1))
+    return arr
+
+
+def _plan(lib, shapes, tile=None):
+    h = ctypes.c_void_p()
+    t = ctypes.byref(_lib.Tile(*tile)) if tile else None
+    rc = lib.hpvm_grouped_plan_create(len(shapes), _descs(shapes), 0, t, ctypes.byref(h))
+    return rc, h
+
+
+def test_grouped_plan_host_side(lib):
+    shapes = [(48, 48, 64), (2048, 2048, 512), (100, 300, 7), (0, 5, 5), (64, 64, 0)]
+    rc, h = _plan(lib, shapes)
+    assert rc == 0, hp.last_error()
+    info = _lib.GroupedInfo()
+    assert lib.hpvm_grouped_plan_info(h, ctypes.byref(info)) == 0
+    assert info.count == 5
+    assert info.flops == sum(2.0 * m * n * k for m, n, k in shapes)
+    tiles = []
+    for i, (m, n, k) in enumerate(shapes):
+        t = _lib.Tile()
+        assert lib.hpvm_grouped_instance_tile(h, i, ctypes.byref(t)) == 0
+        tiles.append(t.as_tuple())
+        if m and n:
+            tiles_i = -(-m // t.tile_m) * -(-n // t.tile_n)
+        else:
+            tiles_i = 0
+        shapes[i] = (m, n, k, tiles_i)
+    # every tile of every instance is listed exactly once
+    assert info.total_tiles == sum(s[3] for s in shapes)
+    # the cost model gives the small instance the small tile, the big one the big tile
+    assert tiles[0] == (64, 64, 16, 32, 32, 2)
+    assert tiles[1] == (128, 128, 16, 64, 64, 2)
+    ws = ctypes.c_int64()
+    assert lib.hpvm_grouped_workspace_bytes(h, ctypes.byref(ws)) == 0 and ws.value == info.workspace_bytes
+    assert info.scratch_bytes == 4 * sum(m * n for m, n, *_ in shapes)
+    # too small a workspace is refused before any device work
+    assert lib.hpvm_grouped_run(h, FAKE, ws.value - 1, None) == -4
+    assert lib.hpvm_grouped_run(h, FAKE + 4, ws.value, None) == -1  # misaligned
+    assert lib.hpvm_grouped_plan_destroy(h) == 0
+    # stale handles
+    assert lib.hpvm_grouped_plan_destroy(h) == -5
+    assert lib.hpvm_grouped_plan_info(h, ctypes.byref(info)) == -5
+    assert lib.hpvm_grouped_run(h, FAKE, 1 << 30, None) == -5
+    assert lib.hpvm_graph_launch(ctypes.c_void_p(FAKE), None) == -5
+    assert lib.hpvm_graph_destroy(None) == -5
+
+
+def test_grouped_plan_fixed_tile_and_menu(lib):
+    menu = hp.grouped_menu()
+    assert len(menu) == 4 and all(t[3] * 0 == 0 for t in menu)
+    for tile in menu:
+        rc, h = _plan(lib, [(300, 200, 50), (17, 33, 9)], tile)
+        assert rc == 0
+        t = _lib.Tile()
+        assert lib.hpvm_grouped_instance_tile(h, 1, ctypes.byref(t)) == 0 and t.as_tuple() == tuple(tile)
+        assert lib.hpvm_grouped_plan_destroy(h) == 0
+    rc, h = _plan(lib, [(8, 8, 8)], (32, 32, 16, 16, 16, 2))
+    assert rc == -2 and "grouped menu" in hp.last_error()
+    # every grouped shape can also run as a single launch (bitwise comparisons)
+    single = hp.tile_menu("fp32")
+    assert all(tuple(t) in single for t in menu)
+
+
+def test_grouped_plan_validation(lib):
+    h = ctypes.c_void_p()
+    assert lib.hpvm_grouped_plan_create(-1, None, 0, None, ctypes.byref(h)) == -1
+    assert lib.hpvm_grouped_plan_create(2, None, 0, None, ctypes.byref(h)) == -1
+    d = _descs([(10, 10, 10), (20, 20, 20)])
+    assert lib.hpvm_grouped_plan_create(2, d, 1, None, ctypes.byref(h)) == -2
+    d[1].ldb = 3
+    assert lib.hpvm_grouped_plan_create(2, d, 0, None, ctypes.byref(h)) == -1
+    assert hp.last_error().startswith("instance 1: argument 8"), hp.last_error()
+    d = _descs([(10, 10, 10), (20, 20, 20)])
+    d[1].C = d[0].C + 16  # two instances writing overlapping memory
+    assert lib.hpvm_grouped_plan_create(2, d, 0, None, ctypes.byref(h)) == -1
+    assert "overlapping" in hp.last_error()
+
+
+def test_grouped_fault_injection(lib, monkeypatch):
+    rc, h = _plan(lib, [(64, 64, 64)])
+    assert rc == 0
+    ws = ctypes.c_int64()
+    lib.hpvm_grouped_workspace_bytes(h, ctypes.byref(ws))
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "capture")
+    g = ctypes.c_void_p()
+    assert lib.hpvm_grouped_capture(h, FAKE, ws.value, None, ctypes.byref(g)) == -3
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    assert lib.hpvm_grouped_run(h, FAKE, ws.value, None) == -3
+    assert lib.hpvm_grouped_plan_destroy(h) == 0
