@@ -2,13 +2,18 @@
 
 One step = the FP32 tiled sgemm workload: C = alpha*A*B + beta*C at
 M=N=K=4096 and M=8192, N=4096, K=2048, each with beta = 0 and beta = 1
-(alpha = 1, A, B, C uniform on [-1, 1], seed 1), i.e. four launches.  Inputs
-are resident in HBM before the timed region.  Prints ONE JSON line.
+(alpha = 1, A, B, C uniform on [-1, 1], seed 1), i.e. four launches of the
+FP32 MFMA lowering with autotuned tiles.  Inputs are resident in HBM before
+the timed region.  Prints ONE JSON line on stdout (progress goes to stderr).
 
-The other forms of the path (BF16 / bf16x3 at 8192^3, the grouped launch,
-the backward pass) are measured after the timed region and reported under
-"variants", each with its TFLOP/s, fraction of the matching MFMA peak and
-normwise error against the FP64 oracle on sampled entries.
+After the timed region the other forms of the path are measured and reported
+under "variants", each with TFLOP/s, the fraction of the matching MFMA peak
+and its error against the FP64 oracle:
+  * BF16 and bf16x3 at M=N=K=8192 (uniform and log-uniform inputs, seed 2);
+  * the grouped persistent launch of 512 uneven sgemms, replayed from a HIP
+    graph (seed 3);
+  * forward + backward at M=N=4096, K=1024, alpha=0.7, beta=0.3 (seed 4), in
+    FP32 and BF16.
 """
 from __future__ import annotations
 
@@ -23,7 +28,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6}  # MI355X dense MFMA peaks
+# MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
+PEAK = {"fp32": 157.3, "bf16": 2516.6}
+PEAK["bf16x3_fp32_equiv"] = PEAK["bf16"] / 3.0
 HBM_PEAK_GBS = 8000.0
 
 WORKLOAD = [  # (m, n, k, beta)
@@ -35,58 +42,207 @@ WORKLOAD = [  # (m, n, k, beta)
 
 
 def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def sampled_error(A, B, C_in, alpha, beta, got, seed=7, count=256, mode="fp32"):
-    """Normwise error of `got` against the oracle on `count` sampled entries."""
+def sampled_error(A, B, C_in, alpha, beta, got_fn, m, n, seed=7, count=256, mode="fp32"):
+    """Normwise error against the oracle on `count` sampled entries.
+
+    got_fn(rows, cols) returns the GPU values at those positions.
+    """
     import oracle
 
-    m, n = got.shape
     rng = np.random.default_rng(seed)
     rows = rng.integers(0, m, count)
     cols = rng.integers(0, n, count)
     ref = oracle.sgemm_entries(A, B, C_in, alpha, beta, rows, cols, mode=mode)
-    g = got[rows, cols].astype(np.float64)
+    g = np.asarray(got_fn(rows, cols), dtype=np.float64)
     return float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
 
 
-def time_launches(fn, stream, reps):
-    """Per-launch durations (ms) from HIP events recorded on `stream`."""
+def gather(t, rows, cols):
     import torch
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(reps)]
-    with torch.cuda.stream(stream):
-        for a, b in evs:
-            a.record(stream)
-            fn()
-            b.record(stream)
+    return t[torch.from_numpy(rows).to(t.device), torch.from_numpy(cols).to(t.device)].cpu().numpy()
+
+
+def event_time(fn, reps, stream):
+    """Milliseconds per call of fn() from HIP events recorded on `stream`."""
+    import torch
+
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    return [a.elapsed_time(b) for a, b in evs]
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
 
 
-def cpu_baseline(target_s=15.0):
-    """The FP64 oracle on a row sample of the 4096^3 product, all host threads."""
+def cpu_baseline(host, target_s=30.0):
+    """The FP64 oracle over the FP32 step's products (all host threads).
+
+    Runs the whole step when it fits in about `target_s` seconds, otherwise a
+    row sample of it, and scales to TFLOP/s.
+    """
     import oracle
-    from paper_1611_00860_amd import inputs
 
-    m = n = k = 4096
-    A, B, _ = inputs.sgemm_operands(m, n, k, seed=1)
     threads = oracle.default_threads()
-    rows = max(threads, 8)
+    (A, B, _), (m, n, k, _) = host[0], WORKLOAD[0]
+    rows = max(threads, 16)
     t0 = time.perf_counter()
     oracle.sgemm(A[:rows], B, None, 1.0, 0.0, threads=threads)
-    dt = time.perf_counter() - t0
-    rows2 = int(min(m, max(rows, rows * target_s / max(dt, 1e-3))))
-    rows2 -= rows2 % threads if rows2 >= threads else 0
+    per_row = (time.perf_counter() - t0) / rows  # seconds per row of a 4096^3 product
+    step_flops = sum(2.0 * mm * nn * kk for (mm, nn, kk, _) in WORKLOAD)
+    est = per_row * step_flops / (2.0 * n * k)
+    flops = 0.0
     t0 = time.perf_counter()
-    oracle.sgemm(A[:rows2], B, None, 1.0, 0.0, threads=threads)
-    dt2 = time.perf_counter() - t0
-    flops = 2.0 * rows2 * n * k
-    return {"value": flops / dt2 / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows2} of {m} rows of the 4096^3 FP32 product (beta=0), "
-                      f"{flops / 1e9:.1f} GFLOP in {dt2:.1f} s"}
+    if est <= target_s:
+        for (A, B, C), (mm, nn, kk, beta) in zip(host, WORKLOAD):
+            oracle.sgemm(A, B, C, 1.0, beta, threads=threads)
+            flops += 2.0 * mm * nn * kk
+        sample = "the whole FP32 step (4 products)"
+    else:
+        r = max(threads, int(target_s / per_row) // threads * threads)
+        oracle.sgemm(A[:r], B, None, 1.0, 0.0, threads=threads)
+        flops = 2.0 * r * n * k
+        sample = f"{r} of {m} rows of the 4096^3 product"
+    dt = time.perf_counter() - t0
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample}: {flops / 1e9:.1f} GFLOP in {dt:.1f} s"}
+
+
+# --------------------------------------------------------------------------- #
+# Variants                                                                     #
+# --------------------------------------------------------------------------- #
+def variant_precision(hp, inputs, dev, stream, reps):
+    import torch
+
+    out = {}
+    n = 8192
+    for dist in ("uniform", "loguniform"):
+        rng = np.random.default_rng(2)  # A then B, as inputs.sgemm_operands draws them
+        A = inputs.draw(rng, (n, n), dist)
+        B = inputs.draw(rng, (n, n), dist)
+        dA = torch.from_numpy(A).to(dev)
+        dB = torch.from_numpy(B).to(dev)
+        dC = torch.empty((n, n), dtype=torch.float32, device=dev)
+        for prec in ("bf16", "bf16x3"):
+            key = f"{prec}_8192^3_{dist}"
+            if dist == "uniform":
+                tile, _ = hp.autotune(dA, dB, prec=prec, reps=2, scratch=dC)
+                ms = event_time(lambda: hp.sgemm(dA, dB, dC, 1.0, 0.0, prec=prec), reps, stream)
+                tf = 2.0 * n ** 3 / (ms / 1e3) / 1e12
+                peak = PEAK["bf16"] if prec == "bf16" else PEAK["bf16x3_fp32_equiv"]
+                rec = {"tflops": round(tf, 2), "ms": round(ms, 4), "tile": list(tile),
+                       "frac_of_peak": round(tf / peak, 4),
+                       "peak": peak, "peak_note": "BF16 dense MFMA" if prec == "bf16" else
+                       "BF16 dense MFMA / 3 (three bf16 products per FP32 product)"}
+            else:
+                hp.sgemm(dA, dB, dC, 1.0, 0.0, prec=prec)
+                rec = {}
+            torch.cuda.synchronize()
+            rec["normwise_rel_error_vs_fp64"] = sampled_error(
+                A, B, None, 1.0, 0.0, lambda r, c: gather(dC, r, c), n, n, count=192)
+            rec["normwise_rel_error_vs_split_aware"] = sampled_error(
+                A, B, None, 1.0, 0.0, lambda r, c: gather(dC, r, c), n, n, count=192, mode=prec)
+            rec["bar"] = 1e-2 if prec == "bf16" else 1e-5
+            out[key] = rec
+        del dA, dB, dC
+        torch.cuda.empty_cache()
+    return out
+
+
+def variant_grouped(hp, inputs, dev, reps):
+    import torch
+
+    import oracle
+
+    dims, alphas, betas, rng = inputs.grouped_problem(512, seed=3)
+    As_h, Bs_h, Cs_h = inputs.grouped_operands(dims, rng)
+    As = [torch.from_numpy(x).to(dev) for x in As_h]
+    Bs = [torch.from_numpy(x).to(dev) for x in Bs_h]
+    Cs = [torch.from_numpy(x).to(dev) for x in Cs_h]
+    plan = hp.GroupedPlan(As, Bs, Cs, alphas.tolist(), betas.tolist())
+    tuned_ms = plan.autotune(reps=3)
+    info = plan.info()
+    stream = torch.cuda.Stream()
+    graph = plan.capture(stream=stream)
+    graph.launch(stream=stream)  # warm-up; results checked below after one fresh launch
+    stream.synchronize()
+    ms = event_time(lambda: graph.launch(stream=stream), reps, stream)
+    # correctness of one launch from the original C
+    for c, c0 in zip(Cs, Cs_h):
+        c.copy_(torch.from_numpy(c0))
+    torch.cuda.synchronize()
+    graph.launch(stream=stream)
+    stream.synchronize()
+    worst = 0.0
+    rs = np.random.default_rng(5)
+    for i in range(512):
+        m, n, k = (int(v) for v in dims[i])
+        rows, cols = rs.integers(0, m, 8), rs.integers(0, n, 8)
+        ref = oracle.sgemm_entries(As_h[i], Bs_h[i], Cs_h[i], float(alphas[i]), float(betas[i]), rows, cols)
+        g = gather(Cs[i], rows, cols).astype(np.float64)
+        worst = max(worst, float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
+    tf = info["flops"] / (ms / 1e3) / 1e12
+    graph.destroy()
+    plan.destroy()
+    return {"grouped_512_hipgraph": {
+        "tflops": round(tf, 2), "ms": round(ms, 4), "frac_of_peak": round(tf / PEAK["fp32"], 4),
+        "peak": PEAK["fp32"], "gflop": round(info["flops"] / 1e9, 2), "tiles": info["total_tiles"],
+        "persistent_workgroups": info["grid"], "shapes_used": info["shapes_used"],
+        "autotuned_ms": round(tuned_ms, 4), "max_instance_normwise_rel_error_sampled": worst, "bar": 1e-5}}
+
+
+def variant_backward(hp, inputs, dev, stream, reps):
+    import torch
+
+    import oracle
+
+    m, n, k = 4096, 4096, 1024
+    A, B, C, G = inputs.backward_operands(m, n, k, seed=4)
+    dA_, dB_, dC_, dG_ = (torch.from_numpy(x).to(dev) for x in (A, B, C, G))
+    AB = oracle.sgemm(A, B, None, 1.0, 0.0)
+    dalpha_ref = float(np.sum(G.astype(np.float64) * AB))
+    dbeta_ref = float(np.sum(G.astype(np.float64) * C.astype(np.float64)))
+    out = {}
+    for prec in ("fp32", "bf16"):
+        peak = PEAK[prec]
+        fwd_out = torch.empty_like(dC_)
+
+        def fwd():
+            fwd_out.copy_(dC_)
+            hp.sgemm(dA_, dB_, fwd_out, 0.7, 0.3, prec=prec)
+
+        fwd()
+        ms_f = event_time(lambda: hp.sgemm(dA_, dB_, fwd_out, 0.7, 0.3, prec=prec), reps, stream)
+        g = hp.sgemm_backward(dA_, dB_, dC_, dG_, 0.7, 0.3, prec=prec)
+        ms_b = event_time(lambda: hp.sgemm_backward(dA_, dB_, dC_, dG_, 0.7, 0.3, prec=prec), reps, stream)
+        torch.cuda.synchronize()
+        rs = np.random.default_rng(8)
+        ra, ca = rs.integers(0, m, 200), rs.integers(0, k, 200)
+        rb, cb = rs.integers(0, k, 200), rs.integers(0, n, 200)
+        ea = oracle.grad_entries("dA", A, B, G, 0.7, ra, ca)
+        eb = oracle.grad_entries("dB", A, B, G, 0.7, rb, cb)
+        err_a = float(np.linalg.norm(gather(g["dA"], ra, ca) - ea) / np.linalg.norm(ea))
+        err_b = float(np.linalg.norm(gather(g["dB"], rb, cb) - eb) / np.linalg.norm(eb))
+        fwd()
+        torch.cuda.synchronize()
+        err_f = sampled_error(A, B, C, 0.7, 0.3, lambda r, c: gather(fwd_out, r, c), m, n, count=192)
+        tf_f = 2.0 * m * n * k / (ms_f / 1e3) / 1e12
+        tf_b = 4.0 * m * n * k / (ms_b / 1e3) / 1e12
+        out[f"fwd_bwd_{prec}_4096x4096x1024"] = {
+            "forward_tflops": round(tf_f, 2), "forward_ms": round(ms_f, 4),
+            "backward_tflops": round(tf_b, 2), "backward_ms": round(ms_b, 4),
+            "backward_frac_of_peak": round(tf_b / peak, 4), "peak": peak,
+            "forward_normwise_rel_error_sampled": err_f,
+            "dA_normwise_rel_error_sampled": err_a, "dB_normwise_rel_error_sampled": err_b,
+            "dalpha_rel_error": abs(float(g["dalpha"]) - dalpha_ref) / abs(dalpha_ref),
+            "dbeta_rel_error": abs(float(g["dbeta"]) - dbeta_ref) / abs(dbeta_ref),
+            "bar": 1e-5 if prec == "fp32" else 1e-2}
+    return out
 
 
 def main():
@@ -96,6 +252,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -113,29 +270,33 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---- inputs resident in HBM ----
-    log("bench: generating inputs")
+    log("generating inputs")
     host, devs = [], []
     for (m, n, k, beta) in WORKLOAD:
         A, B, C = inputs.sgemm_operands(m, n, k, seed=1)
         host.append((A, B, C))
         devs.append(tuple(torch.from_numpy(x).to(dev) for x in (A, B, C)))
-    outs = [torch.empty_like(d[2]) for d in devs]
+    outs = [d[2].clone() for d in devs]
     flops_step = sum(2.0 * m * n * k for (m, n, k, _) in WORKLOAD)
+
+    tiles = {}
+    if not args.no_autotune:
+        log("autotuning the FP32 tiles (outside the timed region)")
+        for (m, n, k, beta), (dA, dB, dC) in zip(WORKLOAD, devs):
+            if (m, n, k) not in tiles:
+                tiles[(m, n, k)] = hp.autotune(dA, dB, prec="fp32", reps=3, scratch=torch.empty_like(dC))
 
     def step():
         for (m, n, k, beta), (dA, dB, dC), out in zip(WORKLOAD, devs, outs):
-            if beta != 0.0:
-                out.copy_(dC)  # C is in-out: restore its input value (not timed below)
             hp.sgemm(dA, dB, out, 1.0, beta)
 
-    log("bench: warmup")
+    log("warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
     # ---- timed region: K steps ----
-    log(f"bench: timing {args.steps} steps")
-    launch_ms = []
+    log(f"timing {args.steps} steps")
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     per_launch = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(args.steps * len(WORKLOAD))]
@@ -145,10 +306,9 @@ def main():
     idx = 0
     for _ in range(args.steps):
         for (m, n, k, beta), (dA, dB, dC), out in zip(WORKLOAD, devs, outs):
-            # beta = 1 reads C: accumulate onto the previous output (same work)
             a, b = per_launch[idx]
             a.record(stream)
-            hp.sgemm(dA, dB, out, 1.0, beta)
+            hp.sgemm(dA, dB, out, 1.0, beta)  # beta = 1 accumulates onto the previous output
             b.record(stream)
             idx += 1
     end.record(stream)
@@ -161,19 +321,19 @@ def main():
     achieved = flops_step * args.steps / (kernel_ms / 1e3) / 1e12
 
     # ---- correctness of one fresh step (not timed) ----
+    for out, (_, _, dC) in zip(outs, devs):
+        out.copy_(dC)
     step()
     torch.cuda.synchronize()
-    errors = {}
-    for (m, n, k, beta), (A, B, C), out in zip(WORKLOAD, host, outs):
-        errors[f"{m}x{n}x{k}_beta{beta:g}"] = sampled_error(A, B, C, 1.0, beta, out.cpu().numpy())
-
-    per_shape = {}
-    for j, (m, n, k, beta) in enumerate(WORKLOAD):
+    errors, per_shape = {}, {}
+    for j, ((m, n, k, beta), (A, B, C), out) in enumerate(zip(WORKLOAD, host, outs)):
+        key = f"{m}x{n}x{k}_beta{beta:g}"
+        errors[key] = sampled_error(A, B, C, 1.0, beta, lambda r, c: gather(out, r, c), m, n)
         ms = launch_ms[j::len(WORKLOAD)]
-        per_shape[f"{m}x{n}x{k}_beta{beta:g}"] = {
-            "tflops": 2.0 * m * n * k / (np.median(ms) / 1e3) / 1e12, "median_ms": float(np.median(ms))}
+        per_shape[key] = {"tflops": round(2.0 * m * n * k / (np.median(ms) / 1e3) / 1e12, 2),
+                          "median_ms": round(float(np.median(ms)), 4),
+                          "tile": list(hp.autotune_lookup(m, n, k, "fp32")[0])}
 
-    default_tile = hp.tile_menu("fp32")[0]
     result = {
         "metric": "sgemm TFLOP/s & % MFMA peak: FP32 tiled vs BF16/bf16x3 at stated rel. error",
         "value": round(value, 3),
@@ -189,19 +349,30 @@ def main():
         "data": "synthetic",
         "config": {"workload": "FP32 hierarchical-tiled sgemm C=alpha*A*B+beta*C, row-major, "
                                "uniform[-1,1] seed 1, alpha=1: 4096^3 and 8192x4096x2048, "
-                               "each with beta=0 and beta=1 (4 launches per step)",
-                   "tile": list(default_tile), "frac_of_fp32_peak": round(value / PEAK_TFLOPS["fp32"], 4),
-                   "normwise_rel_error_sampled": errors, "per_shape": per_shape,
-                   "wall_s": round(wall, 3)},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4),
+                               "each with beta=0 and beta=1 (4 launches per step, autotuned tiles)",
+                   "frac_of_fp32_peak": round(value / PEAK["fp32"], 4),
+                   "normwise_rel_error_sampled": errors, "error_bar": 1e-5,
+                   "per_shape": per_shape, "wall_s": round(wall, 3)},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp32"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 4),
                      "traffic": None,
-                     "kernel": "sgemm_mfma_f32", "avg_launch_ms": kernel_ms / len(launch_ms)},
+                     "kernel": "sgemm_mfma_f32", "avg_launch_ms": round(kernel_ms / len(launch_ms), 5),
+                     "flops_per_launch_avg": flops_step / len(WORKLOAD)},
     }
 
+    if not args.no_variants:
+        variants = {}
+        log("variant: BF16 / bf16x3 at 8192^3")
+        variants.update(variant_precision(hp, inputs, dev, stream, reps=10))
+        log("variant: grouped 512 from a HIP graph")
+        variants.update(variant_grouped(hp, inputs, dev, reps=10))
+        log("variant: forward + backward 4096x4096x1024")
+        variants.update(variant_backward(hp, inputs, dev, stream, reps=5))
+        result["variants"] = variants
+
     if not args.no_cpu_baseline:
-        log("bench: timing the CPU oracle baseline")
-        result["cpu_baseline"] = cpu_baseline()
+        log("timing the CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(host)
     print(json.dumps(result), flush=True)
 
 

@@ -207,6 +207,73 @@ int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity,
                    int32_t* count);
 
 /* ======================================================================== */
+/* Backward pass                                                            */
+/* ======================================================================== */
+/* Gradient of a scalar loss L through C_out = alpha A B + beta C_in, given
+ * the upstream gradient G = dL/dC_out (m x n).  The paper defines no
+ * backward; these are the closed forms of the same definition:
+ *   dA     = alpha G B^T                 (m x k)
+ *   dB     = alpha A^T G                 (k x n)
+ *   dalpha = sum_ij G_ij (A B)_ij        (= <A, G B^T>, fused into dA's pass)
+ *   dbeta  = sum_ij G_ij C_in_ij
+ *   dC_in  = beta G                      (zeros when beta == 0: C_out then
+ *                                         does not depend on C_in)
+ * dA and dB run on the MFMA lowering of `prec` (FP32, BF16 or bf16x3
+ * products, FP32 accumulation); the two scalars are reduced in FP32 with
+ * fixed-order tree sums, so repeated calls give identical bits.
+ * Any of dA, dB, dC_in, dalpha, dbeta may be NULL to skip that output.
+ * dalpha and dbeta are single device floats.  A, B, C_in and G are device
+ * matrices with the row-major layouts of hpvm_sgemm (G and dC_in like C,
+ * dA like A, dB like B); C_in is only read when dbeta is requested.
+ * `workspace` (device, >= hpvm_sgemm_backward_workspace_bytes) holds the
+ * partial sums of the scalars.                                             */
+int hpvm_sgemm_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, int64_t* bytes);
+
+int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta, const float* A,
+                        int64_t lda, const float* B, int64_t ldb, const float* C_in, int64_t ldci,
+                        const float* G, int64_t ldg, float* dA, int64_t ldda, float* dB,
+                        int64_t lddb, float* dC_in, int64_t lddci, float* dalpha, float* dbeta,
+                        int32_t prec, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* ======================================================================== */
+/* Autotuner of single launches                                             */
+/* ======================================================================== */
+/* The paper leaves tile sizes to the programmer and expects them to come
+ * from "upstream optimization passes or autotuning tools" (Sec. 3.4).  This
+ * tuner times every compiled tile of hpvm_tile_menu(prec) for one problem
+ * with HIP events and records the fastest in a process-wide cache keyed by
+ * (prec, m, n, k); the same entry also serves as the fallback for the shape
+ * class (prec, ceil(log2 m), ceil(log2 n), ceil(log2 k)).  hpvm_sgemm with
+ * tile == NULL takes the exact entry, else the class entry, else menu
+ * entry 0.                                                                  */
+
+/* Times the menu on A, B (device, read only) writing C_scratch (device,
+ * m x n, leading dimension ldc; overwritten with beta = 0, never read).
+ * Each tile runs once to warm up, then `reps` times.  Writes the winner to
+ * *best (may be NULL) and its time per launch to *best_ms (may be NULL).  */
+int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A, int64_t lda,
+                  const float* B, int64_t ldb, float* C_scratch, int64_t ldc, int32_t reps,
+                  void* stream, hpvm_tile* best, float* best_ms);
+
+/* Cache lookup: *found = 2 for an exact entry, 1 for a shape-class entry,
+ * 0 when hpvm_sgemm would use the default (then *tile is that default).   */
+int hpvm_autotune_lookup(int64_t m, int64_t n, int64_t k, int32_t prec, hpvm_tile* tile,
+                         int32_t* found);
+
+/* Records a choice without timing (e.g. from another process). */
+int hpvm_autotune_record(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile,
+                         float ms);
+
+/* Empties the cache. */
+int hpvm_autotune_clear(void);
+
+/* Writes / merges the cache as text, one entry per line:
+ * "prec m n k tile_m tile_n tile_k leaf_m leaf_n stages ms".  Loading skips
+ * entries whose tile is not compiled into this library.                   */
+int hpvm_autotune_save(const char* path);
+int hpvm_autotune_load(const char* path);
+
+/* ======================================================================== */
 /* Grouped launch: many independent sgemms in one persistent kernel         */
 /* ======================================================================== */
 /* The instances of a batch are independent dataflow graphs (Sec. 2.1: the

@@ -170,6 +170,112 @@ def tile_menu(prec="fp32") -> list:
 
 
 # ---------------------------------------------------------------------------
+# Backward pass
+# ---------------------------------------------------------------------------
+def backward_workspace_bytes(m: int, n: int, k: int, prec="fp32") -> int:
+    out = ctypes.c_int64(0)
+    _check(load().hpvm_sgemm_backward_workspace_bytes(m, n, k, _prec(prec), ctypes.byref(out)))
+    return out.value
+
+
+def sgemm_backward(A, B, C_in, G, alpha: float, beta: float, prec="fp32", need=("dA", "dB", "dC_in",
+                   "dalpha", "dbeta"), stream=None) -> dict:
+    """Gradients of <G, alpha A B + beta C_in> (hpvm_sgemm_backward).
+
+    Returns a dict with the requested entries of dA, dB, dC_in (tensors) and
+    dalpha, dbeta (0-dim device tensors).
+    """
+    import torch
+
+    lib = load()
+    m, k = A.shape
+    n = B.shape[1]
+    dev = G.device
+    out = {}
+    if "dA" in need:
+        out["dA"] = torch.empty((m, k), dtype=torch.float32, device=dev)
+    if "dB" in need:
+        out["dB"] = torch.empty((k, n), dtype=torch.float32, device=dev)
+    if "dC_in" in need:
+        out["dC_in"] = torch.empty((m, n), dtype=torch.float32, device=dev)
+    scal = torch.zeros(2, dtype=torch.float32, device=dev)
+    ws = torch.empty(max(backward_workspace_bytes(m, n, k, prec) // 4, 4), dtype=torch.float32, device=dev)
+
+    def mat(name, t, rows, cols):
+        if t is None:
+            return ctypes.c_void_p(0), max(cols, 1)
+        return _mat(t, name)
+
+    pa, lda = mat("A", A, m, k)
+    pb, ldb = mat("B", B, k, n)
+    pci, ldci = mat("C_in", C_in if "dbeta" in need else None, m, n)
+    pg, ldg = mat("G", G, m, n)
+    pda, ldda = mat("dA", out.get("dA"), m, k)
+    pdb, lddb = mat("dB", out.get("dB"), k, n)
+    pdc, lddc = mat("dC_in", out.get("dC_in"), m, n)
+    base = scal.data_ptr()
+    da = ctypes.c_void_p(base) if "dalpha" in need else ctypes.c_void_p(0)
+    db = ctypes.c_void_p(base + 4) if "dbeta" in need else ctypes.c_void_p(0)
+    _check(lib.hpvm_sgemm_backward(m, n, k, float(alpha), float(beta), pa, lda, pb, ldb, pci, ldci,
+                                   pg, ldg, pda, ldda, pdb, lddb, pdc, lddc, da, db, _prec(prec),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel() * 4, _stream(stream)))
+    if "dalpha" in need:
+        out["dalpha"] = scal[0]
+    if "dbeta" in need:
+        out["dbeta"] = scal[1]
+    out["_keep"] = ws
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Autotuner of single launches
+# ---------------------------------------------------------------------------
+def autotune(A, B, prec="fp32", reps: int = 5, scratch=None, stream=None):
+    """Times every compiled tile for A @ B at `prec`; caches and returns (tile, ms).
+
+    ``scratch`` (m x n float32, overwritten) is allocated when not given.
+    """
+    import torch
+
+    m, k = A.shape
+    n = B.shape[1]
+    if scratch is None:
+        scratch = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(scratch, "scratch")
+    best = _lib.Tile()
+    ms = ctypes.c_float(0.0)
+    _check(load().hpvm_autotune(m, n, k, _prec(prec), pa, lda, pb, ldb, pc, ldc, int(reps),
+                                _stream(stream), ctypes.byref(best), ctypes.byref(ms)))
+    return best.as_tuple(), ms.value
+
+
+def autotune_lookup(m: int, n: int, k: int, prec="fp32"):
+    """(tile, found): found = 2 exact, 1 shape class, 0 default."""
+    t = _lib.Tile()
+    found = ctypes.c_int32(0)
+    _check(load().hpvm_autotune_lookup(m, n, k, _prec(prec), ctypes.byref(t), ctypes.byref(found)))
+    return t.as_tuple(), found.value
+
+
+def autotune_record(m: int, n: int, k: int, tile, prec="fp32", ms: float = 0.0):
+    _check(load().hpvm_autotune_record(m, n, k, _prec(prec), _tile(tile), float(ms)))
+
+
+def autotune_clear():
+    _check(load().hpvm_autotune_clear())
+
+
+def autotune_save(path: str):
+    _check(load().hpvm_autotune_save(str(path).encode()))
+
+
+def autotune_load(path: str):
+    _check(load().hpvm_autotune_load(str(path).encode()))
+
+
+# ---------------------------------------------------------------------------
 # Grouped launch
 # ---------------------------------------------------------------------------
 def grouped_menu() -> list:

@@ -269,6 +269,8 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   int rc = hpvm::check_gemm_args("", m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, &reads_ab);
   if (rc != HPVM_OK) return rc;
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 12: unknown precision %d", prec);
+  hpvm_tile tuned;
+  if (!tile && hpvm::tuned_tile(prec, m, n, k, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   rc = resolve(prec, tile, &entry, 13);
   if (rc != HPVM_OK) return rc;

@@ -1,0 +1,191 @@
+// Autotuner of single sgemm launches: times the compiled tiles of one
+// precision on a problem and caches the fastest (HPVM report, Sec. 3.4
+// leaves tile sizes to autotuning tools).  Host code only.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "device_common.hpp"
+#include "hpvm_sgemm.h"
+#include "internal.hpp"
+
+namespace hpvm {
+namespace {
+
+struct Choice {
+  hpvm_tile tile;
+  float ms;
+};
+
+using Key = std::tuple<int32_t, int64_t, int64_t, int64_t, int32_t>;  // prec, m|cls, n|cls, k|cls, is_class
+
+std::mutex g_mu;
+std::map<Key, Choice> g_cache;
+
+int32_t clog2(int64_t v) {
+  int32_t c = 0;
+  while ((int64_t(1) << c) < v) ++c;
+  return c;
+}
+
+Key exact_key(int32_t prec, int64_t m, int64_t n, int64_t k) { return Key{prec, m, n, k, 0}; }
+Key class_key(int32_t prec, int64_t m, int64_t n, int64_t k) {
+  return Key{prec, clog2(m), clog2(n), clog2(k), 1};
+}
+
+bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
+  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k && a.leaf_m == b.leaf_m &&
+         a.leaf_n == b.leaf_n && a.stages == b.stages;
+}
+
+bool in_menu(int32_t prec, const hpvm_tile& t) {
+  const MfmaEntry* menu;
+  const int n = mfma_menu(prec, &menu);
+  for (int i = 0; i < n; ++i)
+    if (same_tile(menu[i].tile, t)) return true;
+  return false;
+}
+
+void record(int32_t prec, int64_t m, int64_t n, int64_t k, const hpvm_tile& t, float ms) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[exact_key(prec, m, n, k)] = Choice{t, ms};
+  g_cache[class_key(prec, m, n, k)] = Choice{t, ms};
+}
+
+}  // namespace
+
+// Used by hpvm_sgemm when no tile is given: 2 exact, 1 class, 0 none.
+int tuned_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_cache.find(exact_key(prec, m, n, k));
+  if (it != g_cache.end()) {
+    *out = it->second.tile;
+    return 2;
+  }
+  it = g_cache.find(class_key(prec, m, n, k));
+  if (it != g_cache.end()) {
+    *out = it->second.tile;
+    return 1;
+  }
+  return 0;
+}
+
+}  // namespace hpvm
+
+using namespace hpvm;
+
+extern "C" {
+
+int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A, int64_t lda, const float* B,
+                  int64_t ldb, float* C_scratch, int64_t ldc, int32_t reps, void* stream, hpvm_tile* best,
+                  float* best_ms) {
+  bool reads_ab = false;
+  int rc = check_gemm_args("", m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, &reads_ab);
+  if (rc != HPVM_OK) return rc;
+  const MfmaEntry* menu;
+  const int count = mfma_menu(prec, &menu);
+  if (count == 0) return set_error(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
+  if (reps < 1) return set_error(HPVM_INVALID_ARG, "argument 11: reps = %d < 1", reps);
+  if (!reads_ab) return set_error(HPVM_INVALID_ARG, "nothing to time: m, n and k must be positive");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best_t = -1.0f;
+  int best_i = 0;
+  for (int i = 0; i < count && e == hipSuccess; ++i) {
+    rc = hpvm_sgemm(m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, prec, &menu[i].tile, stream);
+    if (rc != HPVM_OK) break;
+    e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess && rc == HPVM_OK; ++r)
+      rc = hpvm_sgemm(m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, prec, &menu[i].tile, stream);
+    if (rc != HPVM_OK) break;
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (best_t < 0.0f || ms < best_t)) {
+      best_t = ms;
+      best_i = i;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc != HPVM_OK) return rc;
+  if (e != hipSuccess) return hip_error(e, "autotune timing");
+  record(prec, m, n, k, menu[best_i].tile, best_t / (float)reps);
+  if (best) *best = menu[best_i].tile;
+  if (best_ms) *best_ms = best_t / (float)reps;
+  return clear_error();
+}
+
+int hpvm_autotune_lookup(int64_t m, int64_t n, int64_t k, int32_t prec, hpvm_tile* tile, int32_t* found) {
+  if (m < 0 || n < 0 || k < 0) return set_error(HPVM_INVALID_ARG, "sizes must be >= 0");
+  const MfmaEntry* menu;
+  if (mfma_menu(prec, &menu) == 0) return set_error(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
+  if (!tile || !found) return set_error(HPVM_INVALID_ARG, "NULL output");
+  *found = tuned_tile(prec, m, n, k, tile);
+  if (*found == 0) *tile = menu[0].tile;
+  return clear_error();
+}
+
+int hpvm_autotune_record(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile, float ms) {
+  if (m < 0 || n < 0 || k < 0) return set_error(HPVM_INVALID_ARG, "sizes must be >= 0");
+  if (!tile) return set_error(HPVM_INVALID_ARG, "argument 5: tile is NULL");
+  if (!in_menu(prec, *tile)) return set_error(HPVM_UNSUPPORTED, "argument 5: tile not compiled for precision %d", prec);
+  record(prec, m, n, k, *tile, ms);
+  return clear_error();
+}
+
+int hpvm_autotune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache.clear();
+  return clear_error();
+}
+
+int hpvm_autotune_save(const char* path) {
+  if (!path) return set_error(HPVM_INVALID_ARG, "argument 1: path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return set_error(HPVM_INVALID_ARG, "cannot open %s for writing", path);
+  std::fprintf(f, "# hpvm_sgemm autotune cache v1: prec m n k tile_m tile_n tile_k leaf_m leaf_n stages ms\n");
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : g_cache) {
+      if (std::get<4>(kv.first)) continue;  // class entries are rebuilt on load
+      const hpvm_tile& t = kv.second.tile;
+      std::fprintf(f, "%d %lld %lld %lld %d %d %d %d %d %d %.6f\n", std::get<0>(kv.first),
+                   (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
+                   (long long)std::get<3>(kv.first), t.tile_m, t.tile_n, t.tile_k, t.leaf_m, t.leaf_n, t.stages,
+                   kv.second.ms);
+    }
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok ? clear_error() : set_error(HPVM_INVALID_ARG, "write to %s failed", path);
+}
+
+int hpvm_autotune_load(const char* path) {
+  if (!path) return set_error(HPVM_INVALID_ARG, "argument 1: path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return set_error(HPVM_INVALID_ARG, "cannot open %s", path);
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    int prec;
+    long long m, n, k;
+    hpvm_tile t;
+    float ms;
+    if (std::sscanf(line, "%d %lld %lld %lld %d %d %d %d %d %d %f", &prec, &m, &n, &k, &t.tile_m, &t.tile_n,
+                    &t.tile_k, &t.leaf_m, &t.leaf_n, &t.stages, &ms) != 11)
+      continue;
+    if (m < 0 || n < 0 || k < 0 || !in_menu(prec, t)) continue;
+    record(prec, m, n, k, t, ms);
+  }
+  std::fclose(f);
+  return clear_error();
+}
+
+}  // extern "C"

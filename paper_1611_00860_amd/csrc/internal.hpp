@@ -48,6 +48,9 @@ int check_gemm_args(const char* what, int64_t m, int64_t n, int64_t k, float alp
                     int64_t lda, const float* B, int64_t ldb, float beta, const float* C,
                     int64_t ldc, bool* reads_ab);
 
+// Autotuned tile for a problem: 2 exact entry, 1 shape-class entry, 0 none.
+int tuned_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out);
+
 // Byte range [lo, hi) of a row-major rows x cols float matrix.
 void matrix_extent(const void* p, int64_t rows, int64_t cols, int64_t ld, uintptr_t* lo, uintptr_t* hi);
 

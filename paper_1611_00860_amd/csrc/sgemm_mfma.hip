@@ -12,29 +12,6 @@
 
 namespace hpvm {
 
-// ---------------------------------------------------------------------------
-// Tile order.  Workgroup w is placed on XCD (w mod 8); renumber so that each
-// XCD works through one contiguous run of tiles, then walk that run in
-// groups of kGroupM tile-rows so that concurrently resident tiles share
-// A row-panels and B column-panels.
-// ---------------------------------------------------------------------------
-constexpr int kXcds = 8;
-constexpr int kGroupM = 8;
-
-__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int w, int& tm, int& tn) {
-  const int total = tiles_m * tiles_n;
-  const int q = total / kXcds, rem = total % kXcds;
-  const int x = w % kXcds;
-  const int t = x * q + (x < rem ? x : rem) + w / kXcds;
-  const int per_group = kGroupM * tiles_n;
-  const int group = t / per_group;
-  const int first_m = group * kGroupM;
-  const int gsize = (tiles_m - first_m) < kGroupM ? (tiles_m - first_m) : kGroupM;
-  const int in_group = t - group * per_group;
-  tm = first_m + in_group % gsize;
-  tn = in_group / gsize;
-}
-
 // FP32 kernel: v_mfma_f32_32x32x2f32, FP32 operands and accumulation.
 template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT>
 __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)

@@ -283,3 +283,65 @@ def test_grouped_fault_injection(lib, monkeypatch):
     monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
     assert lib.hpvm_grouped_run(h, FAKE, ws.value, None) == -3
     assert lib.hpvm_grouped_plan_destroy(h) == 0
+
+
+def test_autotune_cache_host_side(lib, tmp_path):
+    hp.autotune_clear()
+    menu = hp.tile_menu("fp32")
+    tile, found = hp.autotune_lookup(4096, 4096, 4096, "fp32")
+    assert found == 0 and tile == menu[0]
+    hp.autotune_record(4096, 4096, 4096, menu[2], "fp32", 1.25)
+    assert hp.autotune_lookup(4096, 4096, 4096, "fp32") == (menu[2], 2)
+    # same shape class (ceil log2 of each size) falls back to the class entry
+    assert hp.autotune_lookup(3000, 4000, 2500, "fp32") == (menu[2], 1)
+    assert hp.autotune_lookup(5000, 4096, 4096, "fp32")[1] == 0
+    assert hp.autotune_lookup(4096, 4096, 4096, "bf16")[1] == 0
+    path = tmp_path / "cache.txt"
+    hp.autotune_save(path)
+    hp.autotune_clear()
+    assert hp.autotune_lookup(4096, 4096, 4096, "fp32")[1] == 0
+    with open(path, "a") as f:
+        f.write("0 10 10 10 48 48 16 16 16 2 1.0\n")  # not compiled: skipped
+        f.write("garbage line\n")
+    hp.autotune_load(path)
+    assert hp.autotune_lookup(4096, 4096, 4096, "fp32") == (menu[2], 2)
+    assert hp.autotune_lookup(10, 10, 10, "fp32")[1] == 0
+    with pytest.raises(hp.HpvmError):
+        hp.autotune_record(8, 8, 8, (48, 48, 16, 16, 16, 2), "fp32")
+    hp.autotune_clear()
+
+
+def test_backward_validation(lib):
+    ws = ctypes.c_int64()
+    assert lib.hpvm_sgemm_backward_workspace_bytes(4096, 4096, 1024, 0, ctypes.byref(ws)) == 0
+    assert ws.value >= 4 * 256
+    args = dict(m=16, n=16, k=16, alpha=0.7, beta=0.3, A=FAKE, lda=16, B=FAKE * 2, ldb=16, C_in=FAKE * 3,
+                ldci=16, G=FAKE * 4, ldg=16, dA=FAKE * 5, ldda=16, dB=FAKE * 6, lddb=16, dC_in=FAKE * 7,
+                lddci=16, dalpha=FAKE * 8, dbeta=FAKE * 8 + 4, prec=0, ws=FAKE * 9, wsb=1 << 20)
+
+    def call_bw(**kw):
+        a = dict(args)
+        a.update(kw)
+        return lib.hpvm_sgemm_backward(a["m"], a["n"], a["k"], a["alpha"], a["beta"], a["A"], a["lda"],
+                                       a["B"], a["ldb"], a["C_in"], a["ldci"], a["G"], a["ldg"], a["dA"],
+                                       a["ldda"], a["dB"], a["lddb"], a["dC_in"], a["lddci"], a["dalpha"],
+                                       a["dbeta"], a["prec"], a["ws"], a["wsb"], None)
+
+    assert call_bw(m=-1) == -1 and hp.last_error().startswith("argument 1")
+    assert call_bw(A=None) == -1 and hp.last_error().startswith("argument 6")
+    assert call_bw(B=None) == -1 and hp.last_error().startswith("argument 8")
+    assert call_bw(C_in=None) == -1 and hp.last_error().startswith("argument 10")
+    assert call_bw(G=None) == -1 and hp.last_error().startswith("argument 12")
+    assert call_bw(lddb=3) == -1 and hp.last_error().startswith("argument 17")
+    assert call_bw(prec=7) == -1
+    assert call_bw(wsb=8) == -4
+    assert call_bw(ws=FAKE + 4) == -1
+    # C_in is not needed without dbeta, B not needed for dB alone: the checks
+    # pass and the (injected) launch is reached
+    import os
+    os.environ["HPVM_FAULT_INJECT"] = "launch"
+    try:
+        rc = call_bw(C_in=None, dbeta=None, wsb=0, ws=None, dalpha=None, B=None, dA=None, dC_in=None)
+        assert rc == -3 and "injected" in hp.last_error()
+    finally:
+        del os.environ["HPVM_FAULT_INJECT"]

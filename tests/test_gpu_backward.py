@@ -1,0 +1,150 @@
+"""GPU parity of the hand-written backward pass (needs an MI355X).
+
+The oracle's closed-form gradient is pinned by exact FP64 central differences
+(tests/test_oracle_pins.py); here the GPU backward is compared with it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1611_00860_amd import inputs
+from gpu_util import normwise, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+BAR = {"fp32": 1e-5, "bf16": 1e-2, "bf16x3": 1e-5}
+
+
+def dev_all(*xs):
+    return [to_dev(x) for x in xs]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+def test_backward_16_against_oracle_gradient(gpu, prec):
+    import torch
+
+    A, B, C, G = inputs.backward_operands(16, 16, 16, seed=4, dist="dyadic")
+    alpha, beta = 0.7, 0.3
+    ref = oracle.sgemm_grad(A, B, C, G, alpha, beta)
+    dA_, dB_, dC_, dG_ = dev_all(A, B, C, G)
+    g = gpu.sgemm_backward(dA_, dB_, dC_, dG_, alpha, beta, prec=prec)
+    torch.cuda.synchronize()
+    tol = BAR[prec]
+    for key in ("dA", "dB", "dC_in"):
+        assert normwise(to_host(g[key]), ref[key]) <= tol, key
+    assert abs(float(g["dalpha"]) - ref["dalpha"]) <= tol * abs(ref["dalpha"])
+    assert abs(float(g["dbeta"]) - ref["dbeta"]) <= tol * abs(ref["dbeta"])
+    if prec != "bf16":
+        # dyadic inputs: the products are exact, only FP32 accumulation rounds
+        bound = 2 * 18 * U32 * (np.abs(G.astype(np.float64)) @ np.abs(B.astype(np.float64)).T) * alpha
+        assert np.all(np.abs(to_host(g["dA"]) - ref["dA"]) <= bound + 1e-30)
+
+
+def test_backward_integers_exact_scalars(gpu):
+    """Integer inputs: every partial sum is an exact FP32 integer."""
+    import torch
+
+    A, B, C, G = inputs.backward_operands(100, 90, 70, seed=8, dist="int")
+    ref = oracle.sgemm_grad(A, B, C, G, 1.0, 2.0)
+    g = gpu.sgemm_backward(*dev_all(A, B, C, G), 1.0, 2.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(g["dA"]), ref["dA"])
+    assert np.array_equal(to_host(g["dB"]), ref["dB"])
+    assert np.array_equal(to_host(g["dC_in"]), ref["dC_in"])
+    assert float(g["dalpha"]) == ref["dalpha"] and float(g["dbeta"]) == ref["dbeta"]
+
+
+def test_backward_deterministic_and_partial_outputs(gpu):
+    import torch
+
+    A, B, C, G = inputs.backward_operands(300, 260, 200, seed=5)
+    d = dev_all(A, B, C, G)
+    g1 = gpu.sgemm_backward(*d, 0.7, 0.3)
+    g2 = gpu.sgemm_backward(*d, 0.7, 0.3)
+    only = gpu.sgemm_backward(*d, 0.7, 0.3, need=("dalpha",))
+    only_b = gpu.sgemm_backward(*d, 0.7, 0.3, need=("dB", "dbeta"))
+    torch.cuda.synchronize()
+    for key in ("dA", "dB", "dC_in", "dalpha", "dbeta"):
+        assert torch.equal(g1[key], g2[key]), key
+    assert torch.equal(only["dalpha"], g1["dalpha"])
+    assert torch.equal(only_b["dB"], g1["dB"]) and torch.equal(only_b["dbeta"], g1["dbeta"])
+
+
+def test_backward_edge_cases(gpu):
+    import torch
+
+    A, B, C, G = inputs.backward_operands(40, 30, 20, seed=6)
+    # beta = 0: dC_in is exactly zero, dbeta still <G, C_in>
+    g = gpu.sgemm_backward(*dev_all(A, B, C, G), 1.5, 0.0)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(g["dC_in"]) == 0
+    ref = oracle.sgemm_grad(A, B, C, G, 1.5, 0.0)
+    assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-5)
+    # alpha = 0: dA = dB = 0 but dalpha = <G, A B>
+    g = gpu.sgemm_backward(*dev_all(A, B, C, G), 0.0, 1.0)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(g["dA"]) == 0 and torch.count_nonzero(g["dB"]) == 0
+    assert math.isclose(float(g["dalpha"]), ref["dalpha"], rel_tol=1e-5)
+    # k = 0: no products; dalpha = 0
+    A0 = np.zeros((40, 0), dtype=np.float32)
+    B0 = np.zeros((0, 30), dtype=np.float32)
+    dA0 = torch.zeros((40, 0), device="cuda")
+    dB0 = torch.zeros((0, 30), device="cuda")
+    g = gpu.sgemm_backward(dA0, dB0, to_dev(C), to_dev(G), 1.0, 1.0)
+    torch.cuda.synchronize()
+    assert float(g["dalpha"]) == 0.0
+    assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-5)
+    del A0, B0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_backward_full_size_sampled(gpu, prec):
+    """M = N = 4096, K = 1024, alpha = 0.7, beta = 0.3, G uniform, seed 4."""
+    import torch
+
+    m, n, k = 4096, 4096, 1024
+    print(f"case: backward {prec} {m}x{n}x{k}", flush=True)
+    A, B, C, G = inputs.backward_operands(m, n, k, seed=4)
+    g = gpu.sgemm_backward(*dev_all(A, B, C, G), 0.7, 0.3, prec=prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(31)
+    ra, ca = rng.integers(0, m, 400), rng.integers(0, k, 400)
+    rb, cb = rng.integers(0, k, 400), rng.integers(0, n, 400)
+    ref_a = oracle.grad_entries("dA", A, B, G, 0.7, ra, ca)
+    ref_b = oracle.grad_entries("dB", A, B, G, 0.7, rb, cb)
+    got_a = g["dA"][torch.from_numpy(ra).cuda(), torch.from_numpy(ca).cuda()].cpu().numpy()
+    got_b = g["dB"][torch.from_numpy(rb).cuda(), torch.from_numpy(cb).cuda()].cpu().numpy()
+    assert normwise(got_a, ref_a) <= BAR[prec]
+    assert normwise(got_b, ref_b) <= BAR[prec]
+    AB = oracle.sgemm(A, B, None, 1.0, 0.0)
+    dalpha = float(np.sum(G.astype(np.float64) * AB))
+    dbeta = float(np.sum(G.astype(np.float64) * C.astype(np.float64)))
+    assert abs(float(g["dalpha"]) - dalpha) <= BAR[prec] * abs(dalpha)
+    assert abs(float(g["dbeta"]) - dbeta) <= 1e-5 * abs(dbeta)
+    assert torch.equal(g["dC_in"], 0.3 * to_dev(G)) or normwise(to_host(g["dC_in"]), 0.3 * G.astype(np.float64)) <= 1e-7
+
+
+def test_autograd_function(gpu):
+    import torch
+
+    from paper_1611_00860_amd.autograd import SgemmFn
+
+    A, B, C, G = inputs.backward_operands(70, 50, 40, seed=12)
+    tA, tB, tC = (to_dev(x).contiguous().requires_grad_(True) for x in (A, B, C))
+    alpha = torch.tensor(0.7, device="cuda", requires_grad=True)
+    beta = torch.tensor(0.3, device="cuda", requires_grad=True)
+    out = SgemmFn.apply(tA, tB, tC, alpha, beta, "fp32")
+    fwd = oracle.sgemm(A, B, C, float(np.float32(0.7)), float(np.float32(0.3)))
+    assert normwise(to_host(out), fwd) <= 1e-5
+    out.backward(to_dev(G).contiguous())
+    ref = oracle.sgemm_grad(A, B, C, G, float(np.float32(0.7)), float(np.float32(0.3)))
+    assert normwise(to_host(tA.grad), ref["dA"]) <= 1e-5
+    assert normwise(to_host(tB.grad), ref["dB"]) <= 1e-5
+    assert normwise(to_host(tC.grad), ref["dC_in"]) <= 1e-6
+    assert math.isclose(float(alpha.grad), ref["dalpha"], rel_tol=1e-5)
+    assert math.isclose(float(beta.grad), ref["dbeta"], rel_tol=1e-5)
+    # input C_in is left untouched by the forward (out of place)
+    assert torch.equal(tC.detach(), to_dev(C))
