@@ -45,6 +45,95 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+# --------------------------------------------------------------------------- #
+# HBM traffic of the FP32 kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs  #
+# --------------------------------------------------------------------------- #
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "sgemm_mfma_f32_traffic.txt")
+KERNEL_SOURCES = ("device_common.hpp", "mfma_f32.hpp", "sgemm_mfma.hip")
+COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read, 1 GiB written
+
+
+def kernel_source_sha():
+    """Hash of the FP32 kernel's sources: traffic figures are void once it changes."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1611_00860_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _tile_key(tile, m, n, k, beta):
+    return f"{'x'.join(str(v) for v in tile)}|{m}x{n}x{k}|beta{beta:g}"
+
+
+def load_traffic_table():
+    """{key: (fetch_bytes, write_bytes)} if the table matches the current sources."""
+    if not os.path.exists(TRAFFIC_TABLE):
+        return None
+    table, sha = {}, None
+    with open(TRAFFIC_TABLE) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("source_sha256_16:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.startswith("entry:"):
+                key, fb, wb = line.split(":", 1)[1].split()
+                table[key] = (float(fb), float(wb))
+    return table if sha == kernel_source_sha() else None
+
+
+def build_traffic_table(fetch_csv, write_csv, tiles_json, steps, warmup, command):
+    """Per-(tile, shape, beta) HBM bytes from two counter runs of this script.
+
+    The counter runs use --tiles-from, so their FP32 dispatches are exactly
+    warmup + steps + 1 passes over WORKLOAD in order.  Each counter is scaled
+    by what it reads for the calibration copy of COPY_BYTES.
+    """
+    import csv
+
+    def rows(path, counter):
+        out = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        return sorted(out, key=lambda r: int(r["Dispatch_Id"]))
+
+    with open(tiles_json) as f:
+        per_shape = json.loads(f.read().strip().splitlines()[-1])["config"]["per_shape"]
+    result = {}
+    factors = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rs = rows(path, counter)
+        copies = [float(r["Counter_Value"]) * 1024 for r in rs if "copyBuffer" in r["Kernel_Name"]][-3:]
+        factor = COPY_BYTES / (sum(copies) / len(copies))
+        factors[counter] = factor
+        gemm = [r for r in rs if "sgemm_mfma_f32<" in r["Kernel_Name"]]
+        expect = (warmup + steps + 1) * len(WORKLOAD)
+        if len(gemm) != expect:
+            raise SystemExit(f"{path}: {len(gemm)} FP32 dispatches, expected {expect}")
+        for i, r in enumerate(gemm):
+            m, n, k, beta = WORKLOAD[i % len(WORKLOAD)]
+            tile = per_shape[f"{m}x{n}x{k}_beta{beta:g}"]["tile"]
+            key = _tile_key(tile, m, n, k, beta)
+            result.setdefault(key, {}).setdefault(counter, []).append(float(r["Counter_Value"]) * 1024 * factor)
+    lines = ["# HBM traffic of sgemm_mfma_f32 per launch (bytes), from rocprofv3 counters",
+             "# counter runs (GPU, repository root), once with FETCH_SIZE and once with WRITE_SIZE:",
+             "#   rocprofv3 --pmc <COUNTER> --output-format csv -d <dir> -o pmc -- python3 bench.py --steps 2"
+             " --warmup 1 --no-variants --no-cpu-baseline --calibrate-copy --tiles-from <bench.json>",
+             "#   (<bench.json> = the JSON line of a default bench.py run, whose tuned tiles are reused)",
+             f"# table: python3 {command}",
+             "# entry: <tile>|<m>x<n>x<k>|beta<b> <fetch bytes> <write bytes> (median over the dispatches)",
+             f"# FETCH_SIZE factor {factors['FETCH_SIZE']:.4f}, WRITE_SIZE factor {factors['WRITE_SIZE']:.4f} "
+             f"(bytes of a plain {COPY_BYTES >> 30} GiB device copy / what the counter reads for it)",
+             f"source_sha256_16: {kernel_source_sha()}"]
+    for key, d in sorted(result.items()):
+        fb = float(np.median(d["FETCH_SIZE"]))
+        wb = float(np.median(d["WRITE_SIZE"]))
+        lines.append(f"entry: {key} {fb:.0f} {wb:.0f}")
+    with open(TRAFFIC_TABLE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def sampled_error(A, B, C_in, alpha, beta, got_fn, m, n, seed=7, count=256, mode="fp32"):
     """Normwise error against the oracle on `count` sampled entries.
 
@@ -83,32 +172,25 @@ def event_time(fn, reps, stream):
 def cpu_baseline(host, target_s=30.0):
     """The FP64 oracle over the FP32 step's products (all host threads).
 
-    Runs the whole step when it fits in about `target_s` seconds, otherwise a
-    row sample of it, and scales to TFLOP/s.
+    Times the first product (4096^3) in full; if the whole step would take
+    about `target_s` seconds or less, times all four products, otherwise
+    reports that first product alone.  Scaled to TFLOP/s.
     """
     import oracle
 
     threads = oracle.default_threads()
-    (A, B, _), (m, n, k, _) = host[0], WORKLOAD[0]
-    rows = max(threads, 16)
     t0 = time.perf_counter()
-    oracle.sgemm(A[:rows], B, None, 1.0, 0.0, threads=threads)
-    per_row = (time.perf_counter() - t0) / rows  # seconds per row of a 4096^3 product
+    (A, B, C), (m, n, k, beta) = host[0], WORKLOAD[0]
+    oracle.sgemm(A, B, C, 1.0, beta, threads=threads)
+    t1 = time.perf_counter() - t0
     step_flops = sum(2.0 * mm * nn * kk for (mm, nn, kk, _) in WORKLOAD)
-    est = per_row * step_flops / (2.0 * n * k)
-    flops = 0.0
-    t0 = time.perf_counter()
-    if est <= target_s:
+    if t1 * step_flops / (2.0 * m * n * k) <= target_s:
+        t0 = time.perf_counter()
         for (A, B, C), (mm, nn, kk, beta) in zip(host, WORKLOAD):
             oracle.sgemm(A, B, C, 1.0, beta, threads=threads)
-            flops += 2.0 * mm * nn * kk
-        sample = "the whole FP32 step (4 products)"
+        dt, flops, sample = time.perf_counter() - t0, step_flops, "the whole FP32 step (4 products)"
     else:
-        r = max(threads, int(target_s / per_row) // threads * threads)
-        oracle.sgemm(A[:r], B, None, 1.0, 0.0, threads=threads)
-        flops = 2.0 * r * n * k
-        sample = f"{r} of {m} rows of the 4096^3 product"
-    dt = time.perf_counter() - t0
+        dt, flops, sample = t1, 2.0 * m * n * k, f"the first product of the step ({m}x{n}x{k}, beta=0)"
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{sample}: {flops / 1e9:.1f} GFLOP in {dt:.1f} s"}
 
@@ -253,7 +335,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with three plain 1 GiB device-to-device copies (HBM counter calibration)")
+    ap.add_argument("--tiles-from", help="take the FP32 tiles from a previous bench JSON line instead of tuning")
+    ap.add_argument("--traffic-table", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="build profiles/sgemm_mfma_f32_traffic.txt from two counter runs and exit")
     args = ap.parse_args()
+    if args.traffic_table:
+        build_traffic_table(*args.traffic_table, steps=args.steps, warmup=args.warmup,
+                            command=" ".join(sys.argv))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the sgemm path has no multi-GPU mode)", file=sys.stderr)
@@ -280,7 +371,12 @@ def main():
     flops_step = sum(2.0 * m * n * k for (m, n, k, _) in WORKLOAD)
 
     tiles = {}
-    if not args.no_autotune:
+    if args.tiles_from:
+        with open(args.tiles_from) as f:
+            per_shape = json.loads(f.read().strip().splitlines()[-1])["config"]["per_shape"]
+        for (m, n, k, beta) in WORKLOAD:
+            hp.autotune_record(m, n, k, per_shape[f"{m}x{n}x{k}_beta{beta:g}"]["tile"], "fp32")
+    elif not args.no_autotune:
         log("autotuning the FP32 tiles (outside the timed region)")
         for (m, n, k, beta), (dA, dB, dC) in zip(WORKLOAD, devs):
             if (m, n, k) not in tiles:
@@ -334,6 +430,14 @@ def main():
                           "median_ms": round(float(np.median(ms)), 4),
                           "tile": list(hp.autotune_lookup(m, n, k, "fp32")[0])}
 
+    traffic = None
+    table = load_traffic_table()
+    if table is not None:
+        keys = [_tile_key(per_shape[f"{m}x{n}x{k}_beta{beta:g}"]["tile"], m, n, k, beta)
+                for (m, n, k, beta) in WORKLOAD]
+        if all(key in table for key in keys):
+            traffic = float(np.mean([sum(table[key]) for key in keys]))
+
     result = {
         "metric": "sgemm TFLOP/s & % MFMA peak: FP32 tiled vs BF16/bf16x3 at stated rel. error",
         "value": round(value, 3),
@@ -355,7 +459,10 @@ def main():
                    "per_shape": per_shape, "wall_s": round(wall, 3)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp32"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 4),
-                     "traffic": None,
+                     "traffic": traffic,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     "algorithmic_bytes_per_launch": float(np.mean(
+                         [4.0 * (m * k + k * n + m * n * (2 if beta else 1)) for (m, n, k, beta) in WORKLOAD])),
                      "kernel": "sgemm_mfma_f32", "avg_launch_ms": round(kernel_ms / len(launch_ms), 5),
                      "flops_per_launch_avg": flops_step / len(WORKLOAD)},
     }
@@ -369,6 +476,16 @@ def main():
         log("variant: forward + backward 4096x4096x1024")
         variants.update(variant_backward(hp, inputs, dev, stream, reps=5))
         result["variants"] = variants
+
+    if args.calibrate_copy:
+        log("calibration: three 1 GiB device copies")
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")

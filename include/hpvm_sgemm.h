@@ -249,7 +249,8 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
 
 /* Times the menu on A, B (device, read only) writing C_scratch (device,
  * m x n, leading dimension ldc; overwritten with beta = 0, never read).
- * Each tile runs once to warm up, then `reps` times.  Writes the winner to
+ * Two rounds over the menu; in each, a tile runs once to warm up, then
+ * `reps` times, and it keeps its faster round.  Writes the winner to
  * *best (may be NULL) and its time per launch to *best_ms (may be NULL).  */
 int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A, int64_t lda,
                   const float* B, int64_t ldb, float* C_scratch, int64_t ldc, int32_t reps,

@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "device_common.hpp"
 #include "hpvm_sgemm.h"
@@ -95,24 +96,31 @@ int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A,
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  float best_t = -1.0f;
-  int best_i = 0;
-  for (int i = 0; i < count && e == hipSuccess; ++i) {
-    rc = hpvm_sgemm(m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, prec, &menu[i].tile, stream);
-    if (rc != HPVM_OK) break;
-    e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && e == hipSuccess && rc == HPVM_OK; ++r)
+  // Two interleaved rounds over the menu; each tile keeps its faster round,
+  // so a clock ramp or a one-off stall does not decide the choice.
+  std::vector<float> best_of(count, -1.0f);
+  for (int round = 0; round < 2 && e == hipSuccess && rc == HPVM_OK; ++round) {
+    for (int i = 0; i < count && e == hipSuccess; ++i) {
       rc = hpvm_sgemm(m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, prec, &menu[i].tile, stream);
-    if (rc != HPVM_OK) break;
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e == hipSuccess && (best_t < 0.0f || ms < best_t)) {
-      best_t = ms;
-      best_i = i;
+      if (rc != HPVM_OK) break;
+      e = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && e == hipSuccess && rc == HPVM_OK; ++r)
+        rc = hpvm_sgemm(m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, prec, &menu[i].tile, stream);
+      if (rc != HPVM_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && (best_of[i] < 0.0f || ms < best_of[i])) best_of[i] = ms;
     }
   }
+  float best_t = -1.0f;
+  int best_i = 0;
+  for (int i = 0; i < count; ++i)
+    if (best_of[i] >= 0.0f && (best_t < 0.0f || best_of[i] < best_t)) {
+      best_t = best_of[i];
+      best_i = i;
+    }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (rc != HPVM_OK) return rc;
