@@ -79,7 +79,12 @@ typedef enum hpvm_precision {
  *                   (= tile_m) x tile_n slab of B, as in Sec. 6.1-6.3.
  *                   Larger values select an MFMA lowering in which every
  *                   wavefront owns a leaf_m x leaf_n sub-tile of C.
- * stages          : LDS buffers per operand (1, or 2 for double buffering).
+ * stages          : 1 = one LDS buffer (literal lowering); 2 = two LDS
+ *                   stages, conversion to bfloat16 (if any) fused into the
+ *                   HBM -> LDS copy; 3 = staged BF16 / bf16x3 lowering:
+ *                   operands converted into a workspace by a separate pass,
+ *                   two K-slabs in flight in registers ahead of two LDS
+ *                   stages (hpvm_sgemm_ws only).
  * hpvm_tile_menu lists the combinations compiled into this library.       */
 typedef struct hpvm_tile {
   int32_t tile_m;
@@ -128,7 +133,7 @@ typedef struct hpvm_dfg {
   int64_t alloc_bytes;    /* LDS bytes the Allocation node provides        */
   int32_t k_slabs;        /* ceil(k / tile_k): trips of the staging loop   */
   int32_t lowering;       /* 0 literal, 1 FP32 MFMA, 2 BF16 MFMA,
-                             3 bf16x3 MFMA                                 */
+                             3 bf16x3 MFMA, 4 staged BF16, 5 staged bf16x3 */
 } hpvm_dfg;
 
 /* One edge or binding of the static graph (Sec. 2.1, Table 1 createEdge,
@@ -160,7 +165,7 @@ typedef struct hpvm_edge {
  *   tile         : hierarchy shape, or NULL to take the autotuned choice for
  *                  this shape class (the built-in default until
  *                  hpvm_autotune has run).  Must be in hpvm_tile_menu for
- *                  prec.
+ *                  prec and not need a workspace (stages != 3).
  *   stream       : hipStream_t or NULL.
  * Returns HPVM_OK once the work is enqueued.  The MFMA lowerings use 16-byte
  * vector loads where A, B, C and their leading dimensions allow and scalar
@@ -168,6 +173,23 @@ typedef struct hpvm_edge {
 int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A,
                int64_t lda, const float* B, int64_t ldb, float beta, float* C,
                int64_t ldc, int32_t prec, const hpvm_tile* tile, void* stream);
+
+/* hpvm_sgemm with a workspace: the only way to run the staged BF16 / bf16x3
+ * lowering (tiles with stages == 3), which first rewrites A and B as
+ * zero-padded bfloat16 planes (B transposed so k is contiguous; hi and lo
+ * planes for bf16x3) in `workspace` and then runs a GEMM over them.
+ * workspace: device memory, 16-byte aligned, at least
+ * hpvm_sgemm_workspace_bytes(m, n, k, prec, tile) bytes (may be NULL when
+ * that is 0); its contents are scratch.  tile == NULL takes the autotuned
+ * overall winner.  Every other argument and rule is hpvm_sgemm's.          */
+int hpvm_sgemm_ws(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
+                  const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
+                  const hpvm_tile* tile, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* Workspace bytes hpvm_sgemm_ws needs for these sizes and tile (NULL = the
+ * tile it would pick); 0 for every lowering except the staged one.        */
+int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec,
+                               const hpvm_tile* tile, int64_t* bytes);
 
 /* The paper's launch of the root node with its packed argument block
  * (Sec. 6.3, LaunchDataflowGraph unpacking the 88-byte block and calling the
@@ -249,28 +271,37 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
 
 /* Times the menu on A, B (device, read only) writing C_scratch (device,
  * m x n, leading dimension ldc; overwritten with beta = 0, never read).
+ * Tiles of the staged lowering (stages == 3) are timed only when
+ * `workspace` (device, 16-byte aligned) holds at least
+ * hpvm_sgemm_workspace_bytes for them; workspace may be NULL with 0 bytes.
  * Two rounds over the menu; in each, a tile runs once to warm up, then
- * `reps` times, and it keeps its faster round.  Writes the winner to
- * *best (may be NULL) and its time per launch to *best_ms (may be NULL).  */
+ * `reps` times, and it keeps its faster round.  The cache records the
+ * fastest tile (used by hpvm_sgemm_ws with tile == NULL) and the fastest
+ * tile needing no workspace (used by hpvm_sgemm with tile == NULL).  Writes
+ * the overall winner to *best (may be NULL) and its time per launch to
+ * *best_ms (may be NULL).                                                   */
 int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A, int64_t lda,
-                  const float* B, int64_t ldb, float* C_scratch, int64_t ldc, int32_t reps,
-                  void* stream, hpvm_tile* best, float* best_ms);
+                  const float* B, int64_t ldb, float* C_scratch, int64_t ldc, void* workspace,
+                  int64_t workspace_bytes, int32_t reps, void* stream, hpvm_tile* best,
+                  float* best_ms);
 
-/* Cache lookup: *found = 2 for an exact entry, 1 for a shape-class entry,
- * 0 when hpvm_sgemm would use the default (then *tile is that default).   */
+/* Cache lookup of the overall winner: *found = 2 for an exact entry, 1 for
+ * a shape-class entry, 0 when none is cached (then *tile is menu entry 0). */
 int hpvm_autotune_lookup(int64_t m, int64_t n, int64_t k, int32_t prec, hpvm_tile* tile,
                          int32_t* found);
 
-/* Records a choice without timing (e.g. from another process). */
+/* Records a choice without timing (e.g. from another process).  When the
+ * tile needs a workspace, the no-workspace choice becomes menu entry 0.     */
 int hpvm_autotune_record(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile,
                          float ms);
 
 /* Empties the cache. */
 int hpvm_autotune_clear(void);
 
-/* Writes / merges the cache as text, one entry per line:
- * "prec m n k tile_m tile_n tile_k leaf_m leaf_n stages ms".  Loading skips
- * entries whose tile is not compiled into this library.                   */
+/* Writes / merges the cache as text, one entry per line: "prec m n k", the
+ * overall winner (tile_m tile_n tile_k leaf_m leaf_n stages ms), then the
+ * no-workspace winner in the same form.  Loading skips entries whose tiles
+ * are not compiled into this library.                                       */
 int hpvm_autotune_save(const char* path);
 int hpvm_autotune_load(const char* path);
 

@@ -15,7 +15,8 @@ import ctypes
 from . import _lib
 
 PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
-LOWERINGS = {0: "literal", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_bf16x3"}
+LOWERINGS = {0: "literal", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_bf16x3", 4: "staged_bf16",
+             5: "staged_bf16x3"}
 
 
 class HpvmError(RuntimeError):
@@ -82,14 +83,26 @@ def _mat(t, name, rows=None, cols=None):
     return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), max(ld, 1)
 
 
-def sgemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None, stream=None):
-    """C <- alpha * A @ B + beta * C in place (hpvm_sgemm); returns C.
+def workspace_bytes(m: int, n: int, k: int, prec="fp32", tile=None) -> int:
+    """Workspace hpvm_sgemm_ws needs (0 except for the staged lowering)."""
+    out = ctypes.c_int64(0)
+    _check(load().hpvm_sgemm_workspace_bytes(m, n, k, _prec(prec), _tile(tile), ctypes.byref(out)))
+    return out.value
+
+
+def sgemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None, stream=None,
+          workspace=None):
+    """C <- alpha * A @ B + beta * C in place; returns C.
 
     A (m x k), B (k x n), C (m x n): float32 CUDA tensors, row-major, any
     leading dimension.  ``prec`` is 'fp32', 'bf16' or 'bf16x3'; ``tile`` is
-    None (default / autotuned) or (tile_m, tile_n, tile_k, leaf_m, leaf_n,
-    stages).
+    None (autotuned or default) or (tile_m, tile_n, tile_k, leaf_m, leaf_n,
+    stages).  Tiles of the staged lowering (stages = 3) need a workspace:
+    ``workspace`` (a CUDA tensor) is used when given, else one is allocated
+    from torch's caching allocator for the call (hpvm_sgemm_ws).
     """
+    import torch
+
     lib = load()
     m, k = A.shape
     k2, n = B.shape
@@ -98,8 +111,16 @@ def sgemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(C, "C")
-    _check(lib.hpvm_sgemm(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
-                          _prec(prec), _tile(tile), _stream(stream)))
+    need = workspace_bytes(m, n, k, prec, tile)
+    if need == 0:
+        _check(lib.hpvm_sgemm(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
+                              _prec(prec), _tile(tile), _stream(stream)))
+        return C
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=C.device)
+    _check(lib.hpvm_sgemm_ws(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
+                             _prec(prec), _tile(tile), ctypes.c_void_p(workspace.data_ptr()),
+                             workspace.numel() * workspace.element_size(), _stream(stream)))
     return C
 
 
@@ -230,10 +251,12 @@ def sgemm_backward(A, B, C_in, G, alpha: float, beta: float, prec="fp32", need=(
 # ---------------------------------------------------------------------------
 # Autotuner of single launches
 # ---------------------------------------------------------------------------
-def autotune(A, B, prec="fp32", reps: int = 5, scratch=None, stream=None):
+def autotune(A, B, prec="fp32", reps: int = 5, scratch=None, stream=None, allow_workspace=True):
     """Times every compiled tile for A @ B at `prec`; caches and returns (tile, ms).
 
-    ``scratch`` (m x n float32, overwritten) is allocated when not given.
+    ``scratch`` (m x n float32, overwritten) is allocated when not given;
+    with ``allow_workspace`` the staged tiles are timed too, on a workspace
+    allocated for the call.
     """
     import torch
 
@@ -241,13 +264,18 @@ def autotune(A, B, prec="fp32", reps: int = 5, scratch=None, stream=None):
     n = B.shape[1]
     if scratch is None:
         scratch = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    need = 0
+    if allow_workspace:
+        need = max([workspace_bytes(m, n, k, prec, t) for t in tile_menu(prec)] + [0])
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(scratch, "scratch")
     best = _lib.Tile()
     ms = ctypes.c_float(0.0)
-    _check(load().hpvm_autotune(m, n, k, _prec(prec), pa, lda, pb, ldb, pc, ldc, int(reps),
-                                _stream(stream), ctypes.byref(best), ctypes.byref(ms)))
+    _check(load().hpvm_autotune(m, n, k, _prec(prec), pa, lda, pb, ldb, pc, ldc,
+                                ctypes.c_void_p(ws.data_ptr()), need, int(reps), _stream(stream),
+                                ctypes.byref(best), ctypes.byref(ms)))
     return best.as_tuple(), ms.value
 
 

@@ -129,13 +129,8 @@ bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
 }
 
 const hpvm::MfmaEntry* find_entry(int32_t prec, const hpvm_tile* tile) {
-  const hpvm::MfmaEntry* menu;
-  const int count = hpvm::mfma_menu(prec, &menu);
-  if (count == 0) return nullptr;
-  if (!tile) return &menu[0];
-  for (int i = 0; i < count; ++i)
-    if (same_tile(menu[i].tile, *tile)) return &menu[i];
-  return nullptr;
+  if (!tile) return hpvm::menu_entry_at(prec, 0);
+  return hpvm::find_menu_entry(prec, *tile);
 }
 
 // Resolves the lowering for (prec, tile); *entry is null for the literal one.
@@ -198,9 +193,8 @@ int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity, int32_t* coun
   if (capacity < 0 || (capacity > 0 && !out))
     return fail(HPVM_INVALID_ARG, "argument 3: bad capacity or NULL output");
   if (!count) return fail(HPVM_INVALID_ARG, "argument 4: count is NULL");
-  const hpvm::MfmaEntry* menu;
-  const int n = hpvm::mfma_menu(prec, &menu);
-  for (int i = 0; i < n && i < capacity; ++i) out[i] = menu[i].tile;
+  const int n = hpvm::menu_size(prec);
+  for (int i = 0; i < n && i < capacity; ++i) out[i] = hpvm::menu_entry_at(prec, i)->tile;
   *count = n;
   return ok();
 }
@@ -224,9 +218,12 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile
     out->block_y = 1;
     out->waves = e->threads / hpvm::kWave;
     out->alloc_bytes = e->lds_bytes;
-    out->lowering = prec == HPVM_PREC_FP32 ? hpvm::kMfmaF32
-                    : prec == HPVM_PREC_BF16 ? hpvm::kMfmaBf16
-                                              : hpvm::kMfmaBf16x3;
+    if (e->launch_staged)
+      out->lowering = prec == HPVM_PREC_BF16 ? hpvm::kStagedBf16 : hpvm::kStagedBf16x3;
+    else
+      out->lowering = prec == HPVM_PREC_FP32 ? hpvm::kMfmaF32
+                      : prec == HPVM_PREC_BF16 ? hpvm::kMfmaBf16
+                                                : hpvm::kMfmaBf16x3;
   } else {
     out->block_x = t.tile_n;
     out->block_y = t.tile_m;
@@ -261,19 +258,35 @@ int hpvm_dfg_edges(hpvm_edge* out, int32_t capacity, int32_t* count) {
   return ok();
 }
 
-int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
-               const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
-               const hpvm_tile* tile, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// hpvm_sgemm and hpvm_sgemm_ws: `ws_ok` tells whether a workspace argument
+// exists (it is argument 14/15 of hpvm_sgemm_ws).
+int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda, const float* B,
+               int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec, const hpvm_tile* tile, bool ws_ok,
+               void* workspace, int64_t workspace_bytes, void* stream) {
   // Checks in argument order; nothing below touches the device until all pass.
   bool reads_ab = false;
   int rc = hpvm::check_gemm_args("", m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, &reads_ab);
   if (rc != HPVM_OK) return rc;
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 12: unknown precision %d", prec);
   hpvm_tile tuned;
-  if (!tile && hpvm::tuned_tile(prec, m, n, k, &tuned)) tile = &tuned;
+  if (!tile && hpvm::tuned_tile(prec, m, n, k, ws_ok, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   rc = resolve(prec, tile, &entry, 13);
   if (rc != HPVM_OK) return rc;
+  const int64_t need = hpvm::entry_workspace_bytes(entry, m, n, k);
+  if (need > 0 && reads_ab) {
+    if (!ws_ok)
+      return fail(HPVM_UNSUPPORTED, "argument 13: tile with stages = 3 needs a workspace (use hpvm_sgemm_ws)");
+    if (!workspace) return fail(HPVM_INVALID_ARG, "argument 14: workspace is NULL");
+    if ((uintptr_t)workspace % 16) return fail(HPVM_INVALID_ARG, "argument 14: workspace is not 16-byte aligned");
+    if (workspace_bytes < need)
+      return fail(HPVM_WORKSPACE_TOO_SMALL, "argument 15: workspace has %lld bytes, needs %lld",
+                  (long long)workspace_bytes, (long long)need);
+  }
   const bool empty = (m == 0 || n == 0);
   if (empty) return ok();
   if (inject("launch")) return fail(HPVM_HIP_ERROR, "injected launch failure (HPVM_FAULT_INJECT)");
@@ -298,11 +311,43 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   a.beta = beta;
   a.vec_a = aligned16(A, lda);
   a.vec_b = aligned16(B, ldb);
-  if (entry)
+  if (entry && entry->launch_staged)
+    e = entry->launch_staged(a, workspace, s);
+  else if (entry)
     e = entry->launch(a, false, false, s);
   else
     e = hpvm::launch_literal(a, tile->tile_n, tile->tile_m, s);
   return e == hipSuccess ? ok() : hip_fail(e, "sgemm launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda, const float* B,
+               int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec, const hpvm_tile* tile, void* stream) {
+  return sgemm_impl(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec, tile, false, nullptr, 0, stream);
+}
+
+int hpvm_sgemm_ws(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda, const float* B,
+                  int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec, const hpvm_tile* tile,
+                  void* workspace, int64_t workspace_bytes, void* stream) {
+  return sgemm_impl(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec, tile, true, workspace, workspace_bytes,
+                    stream);
+}
+
+int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile,
+                               int64_t* bytes) {
+  if (m < 0 || n < 0 || k < 0) return fail(HPVM_INVALID_ARG, "sizes must be >= 0");
+  if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
+  if (!bytes) return fail(HPVM_INVALID_ARG, "argument 6: bytes is NULL");
+  hpvm_tile tuned;
+  if (!tile && hpvm::tuned_tile(prec, m, n, k, true, &tuned)) tile = &tuned;
+  const hpvm::MfmaEntry* entry;
+  int rc = resolve(prec, tile, &entry, 5);
+  if (rc != HPVM_OK) return rc;
+  *bytes = hpvm::entry_workspace_bytes(entry, m, n, k);
+  return ok();
 }
 
 int hpvm_launch_root(const hpvm_root_in* r, void* stream) {

@@ -18,8 +18,10 @@ namespace hpvm {
 namespace {
 
 struct Choice {
-  hpvm_tile tile;
+  hpvm_tile tile;  // fastest tile overall
   float ms;
+  hpvm_tile fused;  // fastest tile that needs no workspace
+  float fused_ms;
 };
 
 using Key = std::tuple<int32_t, int64_t, int64_t, int64_t, int32_t>;  // prec, m|cls, n|cls, k|cls, is_class
@@ -43,36 +45,45 @@ bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
          a.leaf_n == b.leaf_n && a.stages == b.stages;
 }
 
-bool in_menu(int32_t prec, const hpvm_tile& t) {
-  const MfmaEntry* menu;
-  const int n = mfma_menu(prec, &menu);
-  for (int i = 0; i < n; ++i)
-    if (same_tile(menu[i].tile, t)) return true;
-  return false;
+bool in_menu(int32_t prec, const hpvm_tile& t) { return find_menu_entry(prec, t) != nullptr; }
+
+bool needs_workspace(int32_t prec, const hpvm_tile& t) {
+  const MfmaEntry* e = find_menu_entry(prec, t);
+  return e && e->launch_staged;
 }
 
-void record(int32_t prec, int64_t m, int64_t n, int64_t k, const hpvm_tile& t, float ms) {
+void record(int32_t prec, int64_t m, int64_t n, int64_t k, const Choice& c) {
   std::lock_guard<std::mutex> lk(g_mu);
-  g_cache[exact_key(prec, m, n, k)] = Choice{t, ms};
-  g_cache[class_key(prec, m, n, k)] = Choice{t, ms};
+  g_cache[exact_key(prec, m, n, k)] = c;
+  g_cache[class_key(prec, m, n, k)] = c;
+}
+
+// A choice from one tile: its no-workspace fallback is menu entry 0 unless
+// the tile itself needs none.
+Choice single_choice(int32_t prec, const hpvm_tile& t, float ms) {
+  Choice c{t, ms, t, ms};
+  if (needs_workspace(prec, t)) {
+    c.fused = menu_entry_at(prec, 0)->tile;
+    c.fused_ms = -1.0f;
+  }
+  return c;
 }
 
 }  // namespace
 
-// Used by hpvm_sgemm when no tile is given: 2 exact, 1 class, 0 none.
-int tuned_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
+// Used by hpvm_sgemm / hpvm_sgemm_ws when no tile is given: 2 exact, 1
+// class, 0 none.
+int tuned_tile(int32_t prec, int64_t m, int64_t n, int64_t k, bool allow_workspace, hpvm_tile* out) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_cache.find(exact_key(prec, m, n, k));
-  if (it != g_cache.end()) {
-    *out = it->second.tile;
-    return 2;
+  int found = 2;
+  if (it == g_cache.end()) {
+    it = g_cache.find(class_key(prec, m, n, k));
+    found = 1;
   }
-  it = g_cache.find(class_key(prec, m, n, k));
-  if (it != g_cache.end()) {
-    *out = it->second.tile;
-    return 1;
-  }
-  return 0;
+  if (it == g_cache.end()) return 0;
+  *out = allow_workspace ? it->second.tile : it->second.fused;
+  return found;
 }
 
 }  // namespace hpvm
@@ -82,30 +93,37 @@ using namespace hpvm;
 extern "C" {
 
 int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A, int64_t lda, const float* B,
-                  int64_t ldb, float* C_scratch, int64_t ldc, int32_t reps, void* stream, hpvm_tile* best,
-                  float* best_ms) {
+                  int64_t ldb, float* C_scratch, int64_t ldc, void* workspace, int64_t workspace_bytes, int32_t reps,
+                  void* stream, hpvm_tile* best, float* best_ms) {
   bool reads_ab = false;
   int rc = check_gemm_args("", m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, &reads_ab);
   if (rc != HPVM_OK) return rc;
-  const MfmaEntry* menu;
-  const int count = mfma_menu(prec, &menu);
+  const int count = menu_size(prec);
   if (count == 0) return set_error(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
-  if (reps < 1) return set_error(HPVM_INVALID_ARG, "argument 11: reps = %d < 1", reps);
+  if (workspace_bytes < 0 || (workspace_bytes > 0 && !workspace))
+    return set_error(HPVM_INVALID_ARG, "argument 11/12: bad workspace");
+  if (reps < 1) return set_error(HPVM_INVALID_ARG, "argument 13: reps = %d < 1", reps);
   if (!reads_ab) return set_error(HPVM_INVALID_ARG, "nothing to time: m, n and k must be positive");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto run = [&](const MfmaEntry* me) {
+    return hpvm_sgemm_ws(m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, prec, &me->tile, workspace,
+                         workspace_bytes, stream);
+  };
   // Two interleaved rounds over the menu; each tile keeps its faster round,
-  // so a clock ramp or a one-off stall does not decide the choice.
+  // so a clock ramp or a one-off stall does not decide the choice.  Tiles
+  // needing more workspace than given are skipped.
   std::vector<float> best_of(count, -1.0f);
   for (int round = 0; round < 2 && e == hipSuccess && rc == HPVM_OK; ++round) {
     for (int i = 0; i < count && e == hipSuccess; ++i) {
-      rc = hpvm_sgemm(m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, prec, &menu[i].tile, stream);
+      const MfmaEntry* me = menu_entry_at(prec, i);
+      if (entry_workspace_bytes(me, m, n, k) > workspace_bytes) continue;
+      rc = run(me);
       if (rc != HPVM_OK) break;
       e = hipEventRecord(e0, s);
-      for (int r = 0; r < reps && e == hipSuccess && rc == HPVM_OK; ++r)
-        rc = hpvm_sgemm(m, n, k, 1.0f, A, lda, B, ldb, 0.0f, C_scratch, ldc, prec, &menu[i].tile, stream);
+      for (int r = 0; r < reps && e == hipSuccess && rc == HPVM_OK; ++r) rc = run(me);
       if (rc != HPVM_OK) break;
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -114,20 +132,22 @@ int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A,
       if (e == hipSuccess && (best_of[i] < 0.0f || ms < best_of[i])) best_of[i] = ms;
     }
   }
-  float best_t = -1.0f;
-  int best_i = 0;
-  for (int i = 0; i < count; ++i)
-    if (best_of[i] >= 0.0f && (best_t < 0.0f || best_of[i] < best_t)) {
-      best_t = best_of[i];
-      best_i = i;
-    }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (rc != HPVM_OK) return rc;
   if (e != hipSuccess) return hip_error(e, "autotune timing");
-  record(prec, m, n, k, menu[best_i].tile, best_t / (float)reps);
-  if (best) *best = menu[best_i].tile;
-  if (best_ms) *best_ms = best_t / (float)reps;
+  int bi = -1, bf = -1;
+  for (int i = 0; i < count; ++i) {
+    if (best_of[i] < 0.0f) continue;
+    if (bi < 0 || best_of[i] < best_of[bi]) bi = i;
+    if (!menu_entry_at(prec, i)->launch_staged && (bf < 0 || best_of[i] < best_of[bf])) bf = i;
+  }
+  if (bi < 0 || bf < 0) return set_error(HPVM_INVALID_ARG, "no tile could be timed");
+  Choice c{menu_entry_at(prec, bi)->tile, best_of[bi] / (float)reps, menu_entry_at(prec, bf)->tile,
+           best_of[bf] / (float)reps};
+  record(prec, m, n, k, c);
+  if (best) *best = c.tile;
+  if (best_ms) *best_ms = c.ms;
   return clear_error();
 }
 
@@ -136,7 +156,7 @@ int hpvm_autotune_lookup(int64_t m, int64_t n, int64_t k, int32_t prec, hpvm_til
   const MfmaEntry* menu;
   if (mfma_menu(prec, &menu) == 0) return set_error(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
   if (!tile || !found) return set_error(HPVM_INVALID_ARG, "NULL output");
-  *found = tuned_tile(prec, m, n, k, tile);
+  *found = tuned_tile(prec, m, n, k, true, tile);
   if (*found == 0) *tile = menu[0].tile;
   return clear_error();
 }
@@ -145,7 +165,7 @@ int hpvm_autotune_record(int64_t m, int64_t n, int64_t k, int32_t prec, const hp
   if (m < 0 || n < 0 || k < 0) return set_error(HPVM_INVALID_ARG, "sizes must be >= 0");
   if (!tile) return set_error(HPVM_INVALID_ARG, "argument 5: tile is NULL");
   if (!in_menu(prec, *tile)) return set_error(HPVM_UNSUPPORTED, "argument 5: tile not compiled for precision %d", prec);
-  record(prec, m, n, k, *tile, ms);
+  record(prec, m, n, k, single_choice(prec, *tile, ms));
   return clear_error();
 }
 
@@ -159,16 +179,19 @@ int hpvm_autotune_save(const char* path) {
   if (!path) return set_error(HPVM_INVALID_ARG, "argument 1: path is NULL");
   FILE* f = std::fopen(path, "w");
   if (!f) return set_error(HPVM_INVALID_ARG, "cannot open %s for writing", path);
-  std::fprintf(f, "# hpvm_sgemm autotune cache v1: prec m n k tile_m tile_n tile_k leaf_m leaf_n stages ms\n");
+  std::fprintf(f,
+               "# hpvm_sgemm autotune cache v2: prec m n k | best tile (m n k leaf_m leaf_n stages) ms | "
+               "best tile without workspace, ms\n");
   {
     std::lock_guard<std::mutex> lk(g_mu);
     for (const auto& kv : g_cache) {
       if (std::get<4>(kv.first)) continue;  // class entries are rebuilt on load
       const hpvm_tile& t = kv.second.tile;
-      std::fprintf(f, "%d %lld %lld %lld %d %d %d %d %d %d %.6f\n", std::get<0>(kv.first),
+      const hpvm_tile& u = kv.second.fused;
+      std::fprintf(f, "%d %lld %lld %lld %d %d %d %d %d %d %.6f %d %d %d %d %d %d %.6f\n", std::get<0>(kv.first),
                    (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
                    (long long)std::get<3>(kv.first), t.tile_m, t.tile_n, t.tile_k, t.leaf_m, t.leaf_n, t.stages,
-                   kv.second.ms);
+                   kv.second.ms, u.tile_m, u.tile_n, u.tile_k, u.leaf_m, u.leaf_n, u.stages, kv.second.fused_ms);
     }
   }
   const bool ok = std::fclose(f) == 0;
@@ -184,13 +207,14 @@ int hpvm_autotune_load(const char* path) {
     if (line[0] == '#') continue;
     int prec;
     long long m, n, k;
-    hpvm_tile t;
-    float ms;
-    if (std::sscanf(line, "%d %lld %lld %lld %d %d %d %d %d %d %f", &prec, &m, &n, &k, &t.tile_m, &t.tile_n,
-                    &t.tile_k, &t.leaf_m, &t.leaf_n, &t.stages, &ms) != 11)
+    hpvm_tile t, u;
+    float ms, ums;
+    if (std::sscanf(line, "%d %lld %lld %lld %d %d %d %d %d %d %f %d %d %d %d %d %d %f", &prec, &m, &n, &k,
+                    &t.tile_m, &t.tile_n, &t.tile_k, &t.leaf_m, &t.leaf_n, &t.stages, &ms, &u.tile_m, &u.tile_n,
+                    &u.tile_k, &u.leaf_m, &u.leaf_n, &u.stages, &ums) != 18)
       continue;
-    if (m < 0 || n < 0 || k < 0 || !in_menu(prec, t)) continue;
-    record(prec, m, n, k, t, ms);
+    if (m < 0 || n < 0 || k < 0 || !in_menu(prec, t) || !in_menu(prec, u) || needs_workspace(prec, u)) continue;
+    record(prec, m, n, k, Choice{t, ms, u, ums});
   }
   std::fclose(f);
   return clear_error();

@@ -12,7 +12,7 @@ namespace hpvm {
 struct GemmArgs;
 
 // Lowering ids (hpvm_dfg.lowering).
-enum Lowering { kLiteral = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kMfmaBf16x3 = 3 };
+enum Lowering { kLiteral = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kMfmaBf16x3 = 3, kStagedBf16 = 4, kStagedBf16x3 = 5 };
 
 // One compiled MFMA configuration.
 struct MfmaEntry {
@@ -20,12 +20,31 @@ struct MfmaEntry {
   int32_t prec;
   int32_t threads;
   int64_t lds_bytes;
-  // Launch with the given operand forms (a_trans / b_trans, see GemmArgs).
+  // Fused lowerings: launch with the given operand forms (a_trans / b_trans,
+  // see GemmArgs).  Null for staged entries.
   hipError_t (*launch)(const GemmArgs& args, bool a_trans, bool b_trans, hipStream_t s);
+  // Staged lowering (tile.stages == 3): operands converted into `workspace`
+  // first, then the GEMM.  Null for fused entries.
+  hipError_t (*launch_staged)(const GemmArgs& args, void* workspace, hipStream_t s) = nullptr;
 };
 
-// The compiled menu for `prec` (FP32, BF16, BF16X3); returns the count.
+// The compiled fused menu for `prec` (FP32, BF16, BF16X3); returns the count.
 int mfma_menu(int32_t prec, const MfmaEntry** entries);
+
+// The staged menu for `prec` (BF16, BF16X3); returns the count.
+int staged_menu(int32_t prec, const MfmaEntry** entries);
+
+// Workspace bytes the staged lowering needs for one m x n x k product.
+int64_t staged_workspace_bytes(int32_t prec, int64_t m, int64_t n, int64_t k);
+
+// Every compiled entry of a precision: fused first (entry 0 is the default),
+// then staged.  Returns nullptr past the end.
+const MfmaEntry* menu_entry_at(int32_t prec, int index);
+int menu_size(int32_t prec);
+const MfmaEntry* find_menu_entry(int32_t prec, const hpvm_tile& tile);
+
+// Workspace bytes an entry needs for m x n x k (0 for fused entries).
+int64_t entry_workspace_bytes(const MfmaEntry* e, int64_t m, int64_t n, int64_t k);
 
 // Literal lowering: block_x x block_y lanes, one output each.
 hipError_t launch_literal(const GemmArgs& args, int block_x, int block_y, hipStream_t s);
@@ -49,7 +68,9 @@ int check_gemm_args(const char* what, int64_t m, int64_t n, int64_t k, float alp
                     int64_t ldc, bool* reads_ab);
 
 // Autotuned tile for a problem: 2 exact entry, 1 shape-class entry, 0 none.
-int tuned_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out);
+// With allow_workspace the overall winner is returned, otherwise the best
+// tile that needs no workspace.
+int tuned_tile(int32_t prec, int64_t m, int64_t n, int64_t k, bool allow_workspace, hpvm_tile* out);
 
 // Byte range [lo, hi) of a row-major rows x cols float matrix.
 void matrix_extent(const void* p, int64_t rows, int64_t cols, int64_t ld, uintptr_t* lo, uintptr_t* hi);

@@ -182,13 +182,49 @@ struct Bf16TileShape {
   static_assert(TK % 16 == 0, "K slab must hold whole MFMA steps of 16");
 };
 
+// The MFMAs of one LDS stage: TK/16 steps of 16 k over the wave's
+// (WM/32) x (WN/32) blocks.  a_lo / b_lo are read only with X3.
+template <int TK, int BM, int BN, bool X3>
+__device__ __forceinline__ void bf16_stage_mfma(const char* a_hi, const char* a_lo, const char* b_hi,
+                                                const char* b_lo, int wm0, int wn0, int lane,
+                                                f32x16 (&acc)[BM][BN]) {
+  constexpr int RB = Bf16Rows<TK>::kRowBytes;
+#pragma unroll
+  for (int ks = 0; ks < TK / 16; ++ks) {
+    bf16x8 ah[BM], bh[BN];
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi) ah[bi] = frag_bf16(a_hi, wm0 + 32 * bi, ks, lane, RB);
+#pragma unroll
+    for (int bj = 0; bj < BN; ++bj) bh[bj] = frag_bf16(b_hi, wn0 + 32 * bj, ks, lane, RB);
+    if constexpr (X3) {
+      bf16x8 al[BM], bl[BN];
+#pragma unroll
+      for (int bi = 0; bi < BM; ++bi) al[bi] = frag_bf16(a_lo, wm0 + 32 * bi, ks, lane, RB);
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj) bl[bj] = frag_bf16(b_lo, wn0 + 32 * bj, ks, lane, RB);
+#pragma unroll
+      for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BN; ++bj) {
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+  }
+}
+
 // Accumulates the TM x TN tile at (m0, n0) of op(A) op(B) into acc with
 // bf16 products (X3: lo*hi + hi*lo + hi*hi).  Ends with a barrier.
 template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, bool X3>
 __device__ __forceinline__ void bf16_mainloop(const GemmArgs& p, int m0, int n0, char* smem,
                                               f32x16 (&acc)[WM / 32][WN / 32]) {
   using T = Bf16TileShape<TM, TN, TK, WM, WN, X3>;
-  constexpr int NT = T::NT, BM = T::BM, BN = T::BN, RB = T::RB;
+  constexpr int NT = T::NT, BM = T::BM, BN = T::BN;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid / kWave;
   const int wm0 = (wave / T::kWavesN) * WM, wn0 = (wave % T::kWavesN) * WN;
@@ -223,33 +259,7 @@ __device__ __forceinline__ void bf16_mainloop(const GemmArgs& p, int m0, int n0,
     const int st = s & 1;
     const bool more = s + 1 < slabs;
     if (more) fetch((s + 1) * TK);
-#pragma unroll
-    for (int ks = 0; ks < TK / 16; ++ks) {
-      bf16x8 ah[BM], bh[BN];
-#pragma unroll
-      for (int bi = 0; bi < BM; ++bi) ah[bi] = frag_bf16(a_hi(st), wm0 + 32 * bi, ks, lane, RB);
-#pragma unroll
-      for (int bj = 0; bj < BN; ++bj) bh[bj] = frag_bf16(b_hi(st), wn0 + 32 * bj, ks, lane, RB);
-      if constexpr (X3) {
-        bf16x8 al[BM], bl[BN];
-#pragma unroll
-        for (int bi = 0; bi < BM; ++bi) al[bi] = frag_bf16(a_lo(st), wm0 + 32 * bi, ks, lane, RB);
-#pragma unroll
-        for (int bj = 0; bj < BN; ++bj) bl[bj] = frag_bf16(b_lo(st), wn0 + 32 * bj, ks, lane, RB);
-#pragma unroll
-        for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < BN; ++bj) {
-            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
-          }
-      }
-#pragma unroll
-      for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < BN; ++bj)
-          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-    }
+    bf16_stage_mfma<TK, BM, BN, X3>(a_hi(st), a_lo(st), b_hi(st), b_lo(st), wm0, wn0, lane, acc);
     if (more) stash(st ^ 1);
     __syncthreads();
   }

@@ -345,3 +345,36 @@ def test_backward_validation(lib):
         assert rc == -3 and "injected" in hp.last_error()
     finally:
         del os.environ["HPVM_FAULT_INJECT"]
+
+
+def test_staged_workspace_rules(lib):
+    BIG = 1 << 24  # far enough apart that no two matrices overlap
+    for prec, planes in (("bf16", 1), ("bf16x3", 2)):
+        menu = hp.tile_menu(prec)
+        staged = [t for t in menu if t[5] == 3]
+        fused = [t for t in menu if t[5] != 3]
+        assert staged and fused and menu[0][5] != 3  # the default needs no workspace
+        m, n, k = 300, 520, 100
+        need = hp.workspace_bytes(m, n, k, prec, staged[0])
+        assert need == planes * 2 * (512 + 768) * 128  # padded to 256 x 256 x 64 blocks
+        assert hp.workspace_bytes(m, n, k, prec, fused[0]) == 0
+        assert hp.describe(m, n, k, prec, staged[0])["lowering_name"] == f"staged_{prec}"
+        t = ctypes.byref(_lib.Tile(*staged[0]))
+        rc = lib.hpvm_sgemm(m, n, k, 1.0, BIG, k, BIG * 2, n, 0.0, BIG * 4, n, hp.PREC[prec], t, None)
+        assert rc == -2 and "workspace" in hp.last_error()
+        rc = lib.hpvm_sgemm_ws(m, n, k, 1.0, BIG, k, BIG * 2, n, 0.0, BIG * 4, n, hp.PREC[prec], t,
+                               BIG * 8, need - 16, None)
+        assert rc == -4
+        rc = lib.hpvm_sgemm_ws(m, n, k, 1.0, BIG, k, BIG * 2, n, 0.0, BIG * 4, n, hp.PREC[prec], t,
+                               BIG * 8 + 4, need, None)
+        assert rc == -1 and "aligned" in hp.last_error()
+        # alpha = 0 needs no workspace: nothing is converted
+        import os
+        os.environ["HPVM_FAULT_INJECT"] = "launch"
+        try:
+            rc = lib.hpvm_sgemm_ws(m, n, k, 0.0, None, k, None, n, 1.0, BIG * 4, n, hp.PREC[prec], t, None, 0,
+                                   None)
+            assert rc == -3
+        finally:
+            del os.environ["HPVM_FAULT_INJECT"]
+    assert all(t[5] != 3 for t in hp.tile_menu("fp32"))

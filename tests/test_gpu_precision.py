@@ -62,8 +62,27 @@ def test_random_against_exact_and_split_aware(gpu, prec, dist):
 def test_unaligned_and_padded(gpu, prec):
     A, B, C = inputs.sgemm_operands(190, 150, 130, seed=9, dist="int")
     ref = oracle.sgemm(A, B, C, 1.0, -2.0)
-    got = run(gpu, A, B, C, 1.0, -2.0, prec, pad=1, misalign=True)
-    assert np.array_equal(got, ref)
+    for tile in gpu.tile_menu(prec):
+        got = run(gpu, A, B, C, 1.0, -2.0, prec, tile=tile, pad=1, misalign=True)
+        assert np.array_equal(got, ref), tile
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_staged_equals_fused_bitwise(gpu, prec):
+    """Same tile shape, same bf16 operands, same MFMA order: identical bits."""
+    import torch
+
+    A, B, C = inputs.sgemm_operands(700, 600, 333, seed=21)
+    menu = gpu.tile_menu(prec)
+    pairs = [(f, s) for f in menu for s in menu if f[5] == 2 and s[5] == 3 and f[:5] == s[:5]]
+    assert pairs
+    for fused, staged in pairs:
+        dA, dB = to_dev(A), to_dev(B)
+        c1, c2 = to_dev(C), to_dev(C)
+        gpu.sgemm(dA, dB, c1, 1.5, 0.5, prec=prec, tile=fused)
+        gpu.sgemm(dA, dB, c2, 1.5, 0.5, prec=prec, tile=staged)
+        torch.cuda.synchronize()
+        assert torch.equal(c1, c2), (fused, staged)
 
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
