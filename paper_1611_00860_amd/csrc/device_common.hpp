@@ -34,6 +34,14 @@ struct GemmArgs {
   int32_t tiles_m, tiles_n;
 };
 
+// True when the TM x TN tile at (m0, n0) and every K-slab of depth TK lie
+// inside the matrices and both operands allow 16-byte loads: the main loop
+// then needs no per-element checks.  Uniform across the workgroup.
+template <int TM, int TN, int TK>
+__device__ __forceinline__ bool interior_tile(const GemmArgs& p, int m0, int n0) {
+  return p.vec_a && p.vec_b && m0 + TM <= p.m && n0 + TN <= p.n && p.k % TK == 0;
+}
+
 // --------------------------------------------------------------------------
 // Tile of a row-major global matrix -> registers -> LDS.
 // R x Cc elements starting at `base` (already offset to the tile corner);
@@ -51,15 +59,21 @@ struct GlobalTile {
 
   f32x4 v[U];
 
-  __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld,
-                                       int rlim, int clim, bool vec, int tid) {
+  // MASKED = false: the caller guarantees the whole tile is inside the
+  // matrix and 16-byte aligned, so every unit is one unconditional vector
+  // load (no divergent branches between the loads of a slab).
+  template <bool MASKED>
+  __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld, int rlim, int clim,
+                                       bool vec, int tid) {
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int u = tid + j * NT;
       const int r = u / kUnitsPerRow;
       const int c = (u % kUnitsPerRow) * 4;
       const float* p = base + (int64_t)r * ld + c;
-      if (vec && r < rlim && c + 4 <= clim) {
+      if constexpr (!MASKED) {
+        v[j] = *reinterpret_cast<const f32x4*>(p);
+      } else if (vec && r < rlim && c + 4 <= clim) {
         v[j] = *reinterpret_cast<const f32x4*>(p);
       } else {
 #pragma unroll

@@ -59,6 +59,7 @@ struct KcTile {
   static constexpr int U = kUnits / NT;
   f32x4 v[U][2];
 
+  template <bool MASKED>
   __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld, int rlim,
                                        int clim, bool vec, int tid) {
 #pragma unroll
@@ -67,7 +68,7 @@ struct KcTile {
       const int r = u / kUnitsPerRow;
       const int c = (u % kUnitsPerRow) * 8;
       const float* p = base + (int64_t)r * ld + c;
-      if (vec && r < rlim && c + 8 <= clim) {
+      if (!MASKED || (vec && r < rlim && c + 8 <= clim)) {
         v[j][0] = *reinterpret_cast<const f32x4*>(p);
         v[j][1] = *reinterpret_cast<const f32x4*>(p + 4);
       } else {
@@ -116,6 +117,7 @@ struct MnTile {
   static constexpr int U = kUnits / NT;
   f32x4 v[U][2];
 
+  template <bool MASKED>
   __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld, int rlim,
                                        int clim, bool vec, int tid) {
 #pragma unroll
@@ -127,7 +129,7 @@ struct MnTile {
       for (int h = 0; h < 2; ++h) {
         const int r = 2 * kp + h;
         const float* p = base + (int64_t)r * ld + c;
-        if (vec && r < rlim && c + 4 <= clim) {
+        if (!MASKED || (vec && r < rlim && c + 4 <= clim)) {
           v[j][h] = *reinterpret_cast<const f32x4*>(p);
         } else {
 #pragma unroll
@@ -220,9 +222,9 @@ __device__ __forceinline__ void bf16_stage_mfma(const char* a_hi, const char* a_
 
 // Accumulates the TM x TN tile at (m0, n0) of op(A) op(B) into acc with
 // bf16 products (X3: lo*hi + hi*lo + hi*hi).  Ends with a barrier.
-template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, bool X3>
-__device__ __forceinline__ void bf16_mainloop(const GemmArgs& p, int m0, int n0, char* smem,
-                                              f32x16 (&acc)[WM / 32][WN / 32]) {
+template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, bool X3, bool MASKED>
+__device__ __forceinline__ void bf16_mainloop_impl(const GemmArgs& p, int m0, int n0, char* smem,
+                                                   f32x16 (&acc)[WM / 32][WN / 32]) {
   using T = Bf16TileShape<TM, TN, TK, WM, WN, X3>;
   constexpr int NT = T::NT, BM = T::BM, BN = T::BN;
   const int tid = threadIdx.x;
@@ -241,9 +243,9 @@ __device__ __forceinline__ void bf16_mainloop(const GemmArgs& p, int m0, int n0,
     const float* base;
     int rl, cl;
     slab_a<AT>(p, m0, k0, base, rl, cl);
-    ga.load(base, p.lda, rl, cl, p.vec_a, tid);
+    ga.template load<MASKED>(base, p.lda, rl, cl, p.vec_a, tid);
     slab_b<BT>(p, n0, k0, base, rl, cl);
-    gb.load(base, p.ldb, rl, cl, p.vec_b, tid);
+    gb.template load<MASKED>(base, p.ldb, rl, cl, p.vec_b, tid);
   };
   auto stash = [&](int st) {
     ga.template store<X3>(a_hi(st), a_lo(st), tid);
@@ -263,6 +265,15 @@ __device__ __forceinline__ void bf16_mainloop(const GemmArgs& p, int m0, int n0,
     if (more) stash(st ^ 1);
     __syncthreads();
   }
+}
+
+template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, bool X3>
+__device__ __forceinline__ void bf16_mainloop(const GemmArgs& p, int m0, int n0, char* smem,
+                                              f32x16 (&acc)[WM / 32][WN / 32]) {
+  if (interior_tile<TM, TN, TK>(p, m0, n0))
+    bf16_mainloop_impl<TM, TN, TK, WM, WN, AT, BT, X3, false>(p, m0, n0, smem, acc);
+  else
+    bf16_mainloop_impl<TM, TN, TK, WM, WN, AT, BT, X3, true>(p, m0, n0, smem, acc);
 }
 
 }  // namespace hpvm

@@ -131,10 +131,8 @@ struct F32Tile {
   static_assert(TK % 8 == 0, "K slab must hold whole groups of 8");
 };
 
-// Accumulates the TM x TN tile at (m0, n0) of op(A) op(B) into acc.  Ends
-// with a barrier, so the caller may reuse `lds` right away.
-template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT>
-__device__ __forceinline__ void f32_mainloop(
+template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, bool MASKED>
+__device__ __forceinline__ void f32_mainloop_impl(
     const GemmArgs& p, int m0, int n0, float* lds, f32x16 (&acc)[WM / 32][WN / 32]) {
   using T = F32Tile<TM, TN, TK, WM, WN, AT, BT>;
   using OpA = typename T::OpA;
@@ -155,9 +153,9 @@ __device__ __forceinline__ void f32_mainloop(
     const float* base;
     int rl, cl;
     slab_a<AT>(p, m0, k0, base, rl, cl);
-    ga.load(base, p.lda, rl, cl, p.vec_a, tid);
+    ga.template load<MASKED>(base, p.lda, rl, cl, p.vec_a, tid);
     slab_b<BT>(p, n0, k0, base, rl, cl);
-    gb.load(base, p.ldb, rl, cl, p.vec_b, tid);
+    gb.template load<MASKED>(base, p.ldb, rl, cl, p.vec_b, tid);
   };
 
   zero_acc(acc);
@@ -193,6 +191,18 @@ __device__ __forceinline__ void f32_mainloop(
     }
     __syncthreads();
   }
+}
+
+// Accumulates the TM x TN tile at (m0, n0) of op(A) op(B) into acc.  Ends
+// with a barrier, so the caller may reuse `lds` right away.  Interior tiles
+// take the unmasked loop.
+template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT>
+__device__ __forceinline__ void f32_mainloop(const GemmArgs& p, int m0, int n0, float* lds,
+                                             f32x16 (&acc)[WM / 32][WN / 32]) {
+  if (interior_tile<TM, TN, TK>(p, m0, n0))
+    f32_mainloop_impl<TM, TN, TK, WM, WN, AT, BT, false>(p, m0, n0, lds, acc);
+  else
+    f32_mainloop_impl<TM, TN, TK, WM, WN, AT, BT, true>(p, m0, n0, lds, acc);
 }
 
 }  // namespace hpvm
