@@ -185,38 +185,60 @@ struct Bf16TileShape {
 };
 
 // The MFMAs of one LDS stage: TK/16 steps of 16 k over the wave's
-// (WM/32) x (WN/32) blocks.  a_lo / b_lo are read only with X3.
-template <int TK, int BM, int BN, bool X3>
+// (WM/32) x (WN/32) blocks.  a_lo / b_lo are read only with X3.  With
+// PIPE, the fragments of step ks + 1 are read from LDS before the MFMAs of
+// step ks are issued (two fragment buffers), so LDS latency overlaps the
+// matrix-core work instead of preceding it.
+template <int TK, int BM, int BN, bool X3, bool PIPE = false>
 __device__ __forceinline__ void bf16_stage_mfma(const char* a_hi, const char* a_lo, const char* b_hi,
                                                 const char* b_lo, int wm0, int wn0, int lane,
                                                 f32x16 (&acc)[BM][BN]) {
   constexpr int RB = Bf16Rows<TK>::kRowBytes;
+  constexpr int KS = TK / 16;
+  constexpr int NB = PIPE ? 2 : 1;
+  bf16x8 ah[NB][BM], bh[NB][BN], al[NB][X3 ? BM : 1], bl[NB][X3 ? BN : 1];
+  auto read = [&](int buf, int ks) {
 #pragma unroll
-  for (int ks = 0; ks < TK / 16; ++ks) {
-    bf16x8 ah[BM], bh[BN];
+    for (int bi = 0; bi < BM; ++bi) ah[buf][bi] = frag_bf16(a_hi, wm0 + 32 * bi, ks, lane, RB);
 #pragma unroll
-    for (int bi = 0; bi < BM; ++bi) ah[bi] = frag_bf16(a_hi, wm0 + 32 * bi, ks, lane, RB);
-#pragma unroll
-    for (int bj = 0; bj < BN; ++bj) bh[bj] = frag_bf16(b_hi, wn0 + 32 * bj, ks, lane, RB);
+    for (int bj = 0; bj < BN; ++bj) bh[buf][bj] = frag_bf16(b_hi, wn0 + 32 * bj, ks, lane, RB);
     if constexpr (X3) {
-      bf16x8 al[BM], bl[BN];
 #pragma unroll
-      for (int bi = 0; bi < BM; ++bi) al[bi] = frag_bf16(a_lo, wm0 + 32 * bi, ks, lane, RB);
+      for (int bi = 0; bi < BM; ++bi) al[buf][bi] = frag_bf16(a_lo, wm0 + 32 * bi, ks, lane, RB);
 #pragma unroll
-      for (int bj = 0; bj < BN; ++bj) bl[bj] = frag_bf16(b_lo, wn0 + 32 * bj, ks, lane, RB);
+      for (int bj = 0; bj < BN; ++bj) bl[buf][bj] = frag_bf16(b_lo, wn0 + 32 * bj, ks, lane, RB);
+    }
+  };
+  auto mfma = [&](int buf) {
+    if constexpr (X3) {
 #pragma unroll
       for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
         for (int bj = 0; bj < BN; ++bj) {
-          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[buf][bi], bh[buf][bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[buf][bi], bl[buf][bj], acc[bi][bj], 0, 0, 0);
         }
     }
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
       for (int bj = 0; bj < BN; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[buf][bi], bh[buf][bj], acc[bi][bj], 0, 0, 0);
+  };
+  if constexpr (PIPE) {
+    read(0, 0);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (ks + 1 < KS) read((ks + 1) & 1, ks + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma(ks & 1);
+    }
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      read(0, ks);
+      mfma(0);
+    }
   }
 }
 

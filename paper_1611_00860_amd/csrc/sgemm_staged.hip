@@ -147,10 +147,14 @@ struct StagedArgs {
   float alpha, beta;
 };
 
-// The GEMM over staged planes.  Slab j is loaded into register buffer j % 2
-// two slabs before it is written to LDS stage j % 2, so two slabs of MFMA
-// work cover each load.
-template <int TM, int TN, int TK, int WM, int WN, bool X3>
+// The GEMM over staged planes.  DEPTH = 1: each K-slab is loaded into
+// registers while the previous one, already in LDS, feeds the matrix cores,
+// and is written to the other LDS stage after those MFMAs.  DEPTH = 2: slab j
+// is loaded into register buffer j % 2 two slabs before it is written to LDS,
+// so two slabs of MFMA work cover each load.  One barrier per slab either
+// way.  PIPE reads the fragments of the next 16-k step ahead of the current
+// MFMAs.
+template <int TM, int TN, int TK, int WM, int WN, bool X3, int DEPTH, bool PIPE>
 __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
     sgemm_bf16_staged(StagedArgs p) {
   using T = Bf16TileShape<TM, TN, TK, WM, WN, X3>;
@@ -158,6 +162,7 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
   constexpr int kUnitsPerRow = TK / 8;
   constexpr int UA = TM * kUnitsPerRow / NT, UB = TN * kUnitsPerRow / NT;
   static_assert(UA * NT == TM * kUnitsPerRow && UB * NT == TN * kUnitsPerRow, "even split");
+  static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
   extern __shared__ __align__(16) char smem[];
 
   const int tid = threadIdx.x;
@@ -172,7 +177,7 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
   auto a_st = [&](int st, int pl) { return smem + st * T::kStageBytes + pl * T::kABytes; };
   auto b_st = [&](int st, int pl) { return smem + st * T::kStageBytes + P * T::kABytes + pl * T::kBBytes; };
 
-  u32x4 ra[2][P * UA], rb[2][P * UB];
+  u32x4 ra[DEPTH][P * UA], rb[DEPTH][P * UB];
   auto load = [&](u32x4(&a)[P * UA], u32x4(&b)[P * UB], int slab) {
     const int64_t k0 = (int64_t)slab * TK;
 #pragma unroll
@@ -204,29 +209,44 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
       }
     }
   };
-
   f32x16 acc[BM][BN];
   zero_acc(acc);
-  const int S = p.slabs;
-  load(ra[0], rb[0], 0);
-  if (S > 1) load(ra[1], rb[1], 1);
-  store(ra[0], rb[0], 0);
-  __syncthreads();
-  if (S > 2) load(ra[0], rb[0], 2);
-
-  // One slab: multiply stage B, move slab s + 1 (register buffer B ^ 1) into
-  // stage B ^ 1, refill that buffer with slab s + 3.
-  auto step = [&](auto parity, int s) {
-    constexpr int B = decltype(parity)::value;
-    bf16_stage_mfma<TK, BM, BN, X3>(a_st(B, 0), a_st(B, X3 ? 1 : 0), b_st(B, 0), b_st(B, X3 ? 1 : 0), wm0,
-                                    wn0, lane, acc);
-    if (s + 1 < S) store(ra[B ^ 1], rb[B ^ 1], B ^ 1);
-    if (s + 3 < S) load(ra[B ^ 1], rb[B ^ 1], s + 3);
-    __syncthreads();
+  auto mfma_stage = [&](int st) {
+    bf16_stage_mfma<TK, BM, BN, X3, PIPE>(a_st(st, 0), a_st(st, X3 ? 1 : 0), b_st(st, 0), b_st(st, X3 ? 1 : 0),
+                                          wm0, wn0, lane, acc);
   };
-  for (int s = 0; s < S; s += 2) {
-    step(std::integral_constant<int, 0>{}, s);
-    if (s + 1 < S) step(std::integral_constant<int, 1>{}, s + 1);
+  const int S = p.slabs;
+  if constexpr (DEPTH == 1) {
+    load(ra[0], rb[0], 0);
+    store(ra[0], rb[0], 0);
+    __syncthreads();
+    for (int s = 0; s < S; ++s) {
+      const int st = s & 1;
+      const bool more = s + 1 < S;
+      if (more) load(ra[0], rb[0], s + 1);
+      mfma_stage(st);
+      if (more) store(ra[0], rb[0], st ^ 1);
+      __syncthreads();
+    }
+  } else {
+    load(ra[0], rb[0], 0);
+    if (S > 1) load(ra[1], rb[1], 1);
+    store(ra[0], rb[0], 0);
+    __syncthreads();
+    if (S > 2) load(ra[0], rb[0], 2);
+    // One slab: multiply stage B, move slab s + 1 (register buffer B ^ 1)
+    // into stage B ^ 1, refill that buffer with slab s + 3.
+    auto step = [&](auto parity, int s) {
+      constexpr int B = decltype(parity)::value;
+      mfma_stage(B);
+      if (s + 1 < S) store(ra[B ^ 1], rb[B ^ 1], B ^ 1);
+      if (s + 3 < S) load(ra[B ^ 1], rb[B ^ 1], s + 3);
+      __syncthreads();
+    };
+    for (int s = 0; s < S; s += 2) {
+      step(std::integral_constant<int, 0>{}, s);
+      if (s + 1 < S) step(std::integral_constant<int, 1>{}, s + 1);
+    }
   }
 
   GemmArgs e{};
@@ -275,7 +295,7 @@ hipError_t stage_operands(const GemmArgs& a, const StagedLayout& L, char* ws, hi
   }
 }
 
-template <int TM, int TN, int TK, int WM, int WN, bool X3>
+template <int TM, int TN, int TK, int WM, int WN, bool X3, int DEPTH, bool PIPE>
 struct StagedConfig {
   using T = Bf16TileShape<TM, TN, TK, WM, WN, X3>;
   static constexpr int kThreads = T::NT;
@@ -302,7 +322,7 @@ struct StagedConfig {
     p.tiles_n = (a.n + TN - 1) / TN;
     p.alpha = a.alpha;
     p.beta = a.beta;
-    auto* fn = &sgemm_bf16_staged<TM, TN, TK, WM, WN, X3>;
+    auto* fn = &sgemm_bf16_staged<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>;
     e = allow_lds_staged(fn, (size_t)T::kLdsBytes);
     if (e != hipSuccess) return e;
     void* kargs[] = {&p};
@@ -311,20 +331,21 @@ struct StagedConfig {
   }
 };
 
-#define HPVM_STAGED_ENTRY(PREC, X3, TM, TN, TK, WM, WN)                                           \
-  {{TM, TN, TK, WM, WN, 3}, PREC, StagedConfig<TM, TN, TK, WM, WN, X3>::kThreads,                  \
-   Bf16TileShape<TM, TN, TK, WM, WN, X3>::kLdsBytes, nullptr, &StagedConfig<TM, TN, TK, WM, WN, X3>::launch}
+#define HPVM_STAGED_ENTRY(PREC, X3, DEPTH, PIPE, TM, TN, TK, WM, WN)                                     \
+  {{TM, TN, TK, WM, WN, 3}, PREC, StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::kThreads,           \
+   Bf16TileShape<TM, TN, TK, WM, WN, X3>::kLdsBytes, nullptr,                                             \
+   &StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::launch}
 
 const MfmaEntry kStagedMenuBf16[] = {
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 256, 256, 32, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 256, 256, 64, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 256, 128, 32, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 128, 128, 32, 64, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 2, false, 256, 256, 64, 128, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 1, true, 256, 256, 32, 128, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 1, true, 256, 128, 64, 128, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 1, true, 128, 128, 64, 64, 64),
 };
-// (256 x 256 x 32 with two planes exceeds the register file: not compiled.)
 const MfmaEntry kStagedMenuBf16x3[] = {
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, 256, 128, 32, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, 128, 128, 32, 64, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, 1, false, 256, 256, 32, 128, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, 1, true, 256, 128, 32, 128, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, 1, true, 128, 128, 64, 64, 64),
 };
 
 }  // namespace
