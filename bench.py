@@ -298,6 +298,8 @@ def variant_backward(hp, inputs, dev, stream, reps):
             fwd_out.copy_(dC_)
             hp.sgemm(dA_, dB_, fwd_out, 0.7, 0.3, prec=prec)
 
+        hp.autotune(dA_, dB_, prec=prec, reps=3)
+        bwd_tile, _ = hp.autotune_backward(dA_, dB_, dG_, prec=prec, reps=3)
         fwd()
         ms_f = event_time(lambda: hp.sgemm(dA_, dB_, fwd_out, 0.7, 0.3, prec=prec), reps, stream)
         g = hp.sgemm_backward(dA_, dB_, dC_, dG_, 0.7, 0.3, prec=prec)
@@ -319,6 +321,7 @@ def variant_backward(hp, inputs, dev, stream, reps):
             "forward_tflops": round(tf_f, 2), "forward_ms": round(ms_f, 4),
             "backward_tflops": round(tf_b, 2), "backward_ms": round(ms_b, 4),
             "backward_frac_of_peak": round(tf_b / peak, 4), "peak": peak,
+            "forward_tile": list(hp.autotune_lookup(m, n, k, prec)[0]), "backward_tile": list(bwd_tile),
             "forward_normwise_rel_error_sampled": err_f,
             "dA_normwise_rel_error_sampled": err_a, "dB_normwise_rel_error_sampled": err_b,
             "dalpha_rel_error": abs(float(g["dalpha"]) - dalpha_ref) / abs(dalpha_ref),

@@ -240,22 +240,44 @@ int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity,
  *   dbeta  = sum_ij G_ij C_in_ij
  *   dC_in  = beta G                      (zeros when beta == 0: C_out then
  *                                         does not depend on C_in)
- * dA and dB run on the MFMA lowering of `prec` (FP32, BF16 or bf16x3
- * products, FP32 accumulation); the two scalars are reduced in FP32 with
- * fixed-order tree sums, so repeated calls give identical bits.
+ * dA and dB run on an MFMA lowering of `prec` (FP32, BF16 or bf16x3
+ * products, FP32 accumulation): the fused one reads B (for dA) and A (for
+ * dB) in transposed form; the staged one (tiles with stages == 3) folds
+ * that transposition into its conversion pass.  The two scalars are reduced
+ * in FP32 with fixed-order tree sums, so repeated calls give identical bits.
  * Any of dA, dB, dC_in, dalpha, dbeta may be NULL to skip that output.
  * dalpha and dbeta are single device floats.  A, B, C_in and G are device
  * matrices with the row-major layouts of hpvm_sgemm (G and dC_in like C,
  * dA like A, dB like B); C_in is only read when dbeta is requested.
- * `workspace` (device, >= hpvm_sgemm_backward_workspace_bytes) holds the
- * partial sums of the scalars.                                             */
-int hpvm_sgemm_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, int64_t* bytes);
+ * tile: an entry of hpvm_sgemm_backward_menu(prec), or NULL for the
+ * hpvm_autotune_backward choice for these sizes (else a built-in rule).
+ * `workspace` (device, 16-byte aligned, >= hpvm_sgemm_backward_workspace_bytes
+ * for the same sizes, prec and tile) holds the partial sums of the scalars
+ * and, for staged tiles, the bfloat16 planes.                              */
+int hpvm_sgemm_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec,
+                                        const hpvm_tile* tile, int64_t* bytes);
 
 int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta, const float* A,
                         int64_t lda, const float* B, int64_t ldb, const float* C_in, int64_t ldci,
                         const float* G, int64_t ldg, float* dA, int64_t ldda, float* dB,
                         int64_t lddb, float* dC_in, int64_t lddci, float* dalpha, float* dbeta,
-                        int32_t prec, void* workspace, int64_t workspace_bytes, void* stream);
+                        int32_t prec, const hpvm_tile* tile, void* workspace,
+                        int64_t workspace_bytes, void* stream);
+
+/* Tiles the backward can use at `prec` (writes at most `capacity`, total
+ * count to *count).                                                         */
+int hpvm_sgemm_backward_menu(int32_t prec, hpvm_tile* out, int32_t capacity, int32_t* count);
+
+/* Autotuner of the backward: times dA + dB + dalpha (alpha = 1) for every
+ * backward tile whose workspace fits (the last 256 bytes of `workspace` are
+ * kept for a scratch dalpha), two rounds, `reps` calls each after a warm-up;
+ * dA (m x k, ldda) and dB (k x n, lddb) are scratch outputs.  Records the
+ * fastest for (prec, m, n, k), used when hpvm_sgemm_backward gets no tile.  */
+int hpvm_autotune_backward(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A,
+                           int64_t lda, const float* B, int64_t ldb, const float* G, int64_t ldg,
+                           float* dA, int64_t ldda, float* dB, int64_t lddb, void* workspace,
+                           int64_t workspace_bytes, int32_t reps, void* stream, hpvm_tile* best,
+                           float* best_ms);
 
 /* ======================================================================== */
 /* Autotuner of single launches                                             */

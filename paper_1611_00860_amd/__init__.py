@@ -193,14 +193,24 @@ def tile_menu(prec="fp32") -> list:
 # ---------------------------------------------------------------------------
 # Backward pass
 # ---------------------------------------------------------------------------
-def backward_workspace_bytes(m: int, n: int, k: int, prec="fp32") -> int:
+def backward_workspace_bytes(m: int, n: int, k: int, prec="fp32", tile=None) -> int:
     out = ctypes.c_int64(0)
-    _check(load().hpvm_sgemm_backward_workspace_bytes(m, n, k, _prec(prec), ctypes.byref(out)))
+    _check(load().hpvm_sgemm_backward_workspace_bytes(m, n, k, _prec(prec), _tile(tile), ctypes.byref(out)))
     return out.value
 
 
+def backward_menu(prec="fp32") -> list:
+    """Tiles the backward can use at `prec`."""
+    lib = load()
+    count = ctypes.c_int32(0)
+    _check(lib.hpvm_sgemm_backward_menu(_prec(prec), None, 0, ctypes.byref(count)))
+    arr = (_lib.Tile * count.value)()
+    _check(lib.hpvm_sgemm_backward_menu(_prec(prec), arr, count.value, ctypes.byref(count)))
+    return [t.as_tuple() for t in arr]
+
+
 def sgemm_backward(A, B, C_in, G, alpha: float, beta: float, prec="fp32", need=("dA", "dB", "dC_in",
-                   "dalpha", "dbeta"), stream=None) -> dict:
+                   "dalpha", "dbeta"), tile=None, stream=None) -> dict:
     """Gradients of <G, alpha A B + beta C_in> (hpvm_sgemm_backward).
 
     Returns a dict with the requested entries of dA, dB, dC_in (tensors) and
@@ -220,7 +230,8 @@ def sgemm_backward(A, B, C_in, G, alpha: float, beta: float, prec="fp32", need=(
     if "dC_in" in need:
         out["dC_in"] = torch.empty((m, n), dtype=torch.float32, device=dev)
     scal = torch.zeros(2, dtype=torch.float32, device=dev)
-    ws = torch.empty(max(backward_workspace_bytes(m, n, k, prec) // 4, 4), dtype=torch.float32, device=dev)
+    nbytes = backward_workspace_bytes(m, n, k, prec, tile)
+    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=dev)
 
     def mat(name, t, rows, cols):
         if t is None:
@@ -239,13 +250,38 @@ def sgemm_backward(A, B, C_in, G, alpha: float, beta: float, prec="fp32", need=(
     db = ctypes.c_void_p(base + 4) if "dbeta" in need else ctypes.c_void_p(0)
     _check(lib.hpvm_sgemm_backward(m, n, k, float(alpha), float(beta), pa, lda, pb, ldb, pci, ldci,
                                    pg, ldg, pda, ldda, pdb, lddb, pdc, lddc, da, db, _prec(prec),
-                                   ctypes.c_void_p(ws.data_ptr()), ws.numel() * 4, _stream(stream)))
+                                   _tile(tile), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream(stream)))
     if "dalpha" in need:
         out["dalpha"] = scal[0]
     if "dbeta" in need:
         out["dbeta"] = scal[1]
     out["_keep"] = ws
     return out
+
+
+def autotune_backward(A, B, G, prec="fp32", reps: int = 3, stream=None):
+    """Times every backward tile for these operands; caches and returns (tile, ms)."""
+    import torch
+
+    lib = load()
+    m, k = A.shape
+    n = B.shape[1]
+    dev = G.device
+    need = max(backward_workspace_bytes(m, n, k, prec, t) for t in backward_menu(prec)) + 256
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    dA = torch.empty((m, k), dtype=torch.float32, device=dev)
+    dB = torch.empty((k, n), dtype=torch.float32, device=dev)
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pg, ldg = _mat(G, "G")
+    best = _lib.Tile()
+    ms = ctypes.c_float(0.0)
+    _check(lib.hpvm_autotune_backward(m, n, k, _prec(prec), pa, lda, pb, ldb, pg, ldg,
+                                      ctypes.c_void_p(dA.data_ptr()), k, ctypes.c_void_p(dB.data_ptr()), n,
+                                      ctypes.c_void_p(ws.data_ptr()), need, int(reps), _stream(stream),
+                                      ctypes.byref(best), ctypes.byref(ms)))
+    return best.as_tuple(), ms.value
 
 
 # ---------------------------------------------------------------------------

@@ -91,9 +91,12 @@ SIGNATURES = {
     "hpvm_autotune_clear": (ctypes.c_int, []),
     "hpvm_autotune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "hpvm_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
-    "hpvm_sgemm_backward_workspace_bytes": (ctypes.c_int, [i64, i64, i64, i32, Pi64]),
+    "hpvm_sgemm_backward_workspace_bytes": (ctypes.c_int, [i64, i64, i64, i32, PTile, Pi64]),
     "hpvm_sgemm_backward": (ctypes.c_int, [i64, i64, i64, f32, f32, vp, i64, vp, i64, vp, i64, vp, i64,
-                                           vp, i64, vp, i64, vp, i64, vp, vp, i32, vp, i64, vp]),
+                                           vp, i64, vp, i64, vp, i64, vp, vp, i32, PTile, vp, i64, vp]),
+    "hpvm_sgemm_backward_menu": (ctypes.c_int, [i32, PTile, i32, ctypes.POINTER(i32)]),
+    "hpvm_autotune_backward": (ctypes.c_int, [i64, i64, i64, i32, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                                              vp, i64, i32, vp, PTile, ctypes.POINTER(f32)]),
     "hpvm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "hpvm_last_error": (ctypes.c_char_p, []),
 }

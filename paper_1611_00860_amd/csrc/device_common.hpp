@@ -118,4 +118,26 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int w, int
   tn = in_group / gsize;
 }
 
+// Sum over a wavefront with a fixed butterfly.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over the workgroup; the result is valid in thread 0.  `red` holds one
+// float per wavefront.  Ends with every thread past a barrier.
+__device__ __forceinline__ float block_sum(float v, float* red) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  float t = 0.0f;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
 }  // namespace hpvm

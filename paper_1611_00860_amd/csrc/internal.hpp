@@ -26,6 +26,11 @@ struct MfmaEntry {
   // Staged lowering (tile.stages == 3): operands converted into `workspace`
   // first, then the GEMM.  Null for fused entries.
   hipError_t (*launch_staged)(const GemmArgs& args, void* workspace, hipStream_t s) = nullptr;
+  // Staged, any operand form; with `partial` the epilogue is the backward's
+  // dA one (C <- alpha acc when C is set; partial[tile] = sum aorig .* acc).
+  hipError_t (*launch_staged_form)(const GemmArgs& args, bool a_trans, bool b_trans, void* workspace,
+                                   const float* aorig, int64_t lda_orig, float* partial,
+                                   hipStream_t s) = nullptr;
 };
 
 // The compiled fused menu for `prec` (FP32, BF16, BF16X3); returns the count.
@@ -45,6 +50,10 @@ const MfmaEntry* find_menu_entry(int32_t prec, const hpvm_tile& tile);
 
 // Workspace bytes an entry needs for m x n x k (0 for fused entries).
 int64_t entry_workspace_bytes(const MfmaEntry* e, int64_t m, int64_t n, int64_t k);
+
+// Backward tile cache (see hpvm_autotune_backward): 1 when found.
+int tuned_backward_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out);
+void record_backward_tile(int32_t prec, int64_t m, int64_t n, int64_t k, const hpvm_tile& t);
 
 // Literal lowering: block_x x block_y lanes, one output each.
 hipError_t launch_literal(const GemmArgs& args, int block_x, int block_y, hipStream_t s);

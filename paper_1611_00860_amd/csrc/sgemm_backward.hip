@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "device_common.hpp"
 #include "hpvm_sgemm.h"
@@ -18,28 +21,6 @@
 #include "mfma_f32.hpp"
 
 namespace hpvm {
-
-// Sum over a wavefront with a fixed butterfly.
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
-// Sum over the workgroup; the result is valid in thread 0.  `red` holds one
-// float per wavefront.  Ends with every thread past a barrier.
-__device__ __forceinline__ float block_sum(float v, float* red) {
-  v = wave_sum(v);
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  float t = 0.0f;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
-  __syncthreads();
-  return t;
-}
 
 // dA tile: acc = (G B^T) tile; dA = alpha acc; partial = sum A .* acc.
 // p: A = G (m x n_g), B = B (read transposed), m = m, n = k, k = n.
@@ -119,100 +100,178 @@ __global__ void __launch_bounds__(kElemThreads)
 
 namespace {
 
-struct BwdConfig {
-  hpvm_tile tile;  // also the dB launch's tile (must be in the menu)
+// One candidate tile of the backward.  Fused entries run dA through
+// sgemm_grad_a and dB through the fused menu entry's launch; staged entries
+// run both through the staged lowering (conversion pass into the workspace,
+// with the transposition of each operand folded into it).
+struct BwdEntry {
+  hpvm_tile tile;
   int32_t prec;
   int32_t threads;
   int64_t lds;
-  void (*grad_a)(GemmArgs, const float*, int64_t, float*);
+  void (*grad_a)(GemmArgs, const float*, int64_t, float*);  // null for staged entries
 };
 
 template <int TM, int TN, int TK, int WM, int WN, int PREC>
-constexpr BwdConfig bwd_entry() {
+constexpr BwdEntry fused_entry() {
   constexpr int64_t lds = PREC == HPVM_PREC_FP32
                               ? F32Tile<TM, TN, TK, WM, WN, false, true>::kLdsBytes
                               : Bf16TileShape<TM, TN, TK, WM, WN, PREC == HPVM_PREC_BF16X3>::kLdsBytes;
-  return BwdConfig{{TM, TN, TK, WM, WN, 2}, PREC, (TM / WM) * (TN / WN) * kWave, lds,
-                   &sgemm_grad_a<TM, TN, TK, WM, WN, PREC>};
+  return BwdEntry{{TM, TN, TK, WM, WN, 2}, PREC, (TM / WM) * (TN / WN) * kWave, lds,
+                  &sgemm_grad_a<TM, TN, TK, WM, WN, PREC>};
+}
+constexpr BwdEntry staged_entry(int tm, int tn, int tk, int wm, int wn, int prec) {
+  return BwdEntry{{tm, tn, tk, wm, wn, 3}, prec, 0, 0, nullptr};
 }
 
-// Preference order per precision: largest tile first.
-const BwdConfig kBwd[] = {
-    bwd_entry<128, 128, 16, 64, 64, HPVM_PREC_FP32>(),
-    bwd_entry<128, 64, 16, 64, 32, HPVM_PREC_FP32>(),
-    bwd_entry<64, 64, 16, 32, 32, HPVM_PREC_FP32>(),
-    bwd_entry<128, 128, 32, 64, 64, HPVM_PREC_BF16>(),
-    bwd_entry<64, 64, 32, 32, 32, HPVM_PREC_BF16>(),
-    bwd_entry<128, 128, 32, 64, 64, HPVM_PREC_BF16X3>(),
-    bwd_entry<64, 64, 32, 32, 32, HPVM_PREC_BF16X3>(),
+// Per precision, in the order the built-in choice tries them.
+const BwdEntry kBwd[] = {
+    fused_entry<128, 128, 32, 64, 64, HPVM_PREC_FP32>(),
+    fused_entry<128, 128, 16, 64, 64, HPVM_PREC_FP32>(),
+    fused_entry<128, 64, 16, 64, 32, HPVM_PREC_FP32>(),
+    fused_entry<64, 128, 16, 32, 64, HPVM_PREC_FP32>(),
+    fused_entry<64, 64, 16, 32, 32, HPVM_PREC_FP32>(),
+    staged_entry(128, 128, 64, 64, 64, HPVM_PREC_BF16),
+    staged_entry(256, 256, 64, 128, 64, HPVM_PREC_BF16),
+    staged_entry(256, 128, 64, 128, 64, HPVM_PREC_BF16),
+    fused_entry<128, 128, 32, 64, 64, HPVM_PREC_BF16>(),
+    fused_entry<64, 64, 32, 32, 32, HPVM_PREC_BF16>(),
+    staged_entry(128, 128, 64, 64, 64, HPVM_PREC_BF16X3),
+    staged_entry(256, 256, 32, 128, 64, HPVM_PREC_BF16X3),
+    staged_entry(256, 128, 32, 128, 64, HPVM_PREC_BF16X3),
+    fused_entry<128, 128, 32, 64, 64, HPVM_PREC_BF16X3>(),
+    fused_entry<64, 64, 32, 32, 32, HPVM_PREC_BF16X3>(),
 };
 constexpr int kNumBwd = sizeof(kBwd) / sizeof(kBwd[0]);
 
-// Enough tiles to give every CU of a 256-CU part two workgroups, else the
-// smallest tile.
-constexpr int64_t kTargetTiles = 512;
+bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
+  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k && a.leaf_m == b.leaf_m &&
+         a.leaf_n == b.leaf_n && a.stages == b.stages;
+}
 
 int64_t tiles_for(const hpvm_tile& t, int64_t rows, int64_t cols) {
   return ((rows + t.tile_m - 1) / t.tile_m) * ((cols + t.tile_n - 1) / t.tile_n);
 }
 
-const BwdConfig* pick(int32_t prec, int64_t rows, int64_t cols) {
-  const BwdConfig* last = nullptr;
-  for (int i = 0; i < kNumBwd; ++i) {
-    if (kBwd[i].prec != prec) continue;
-    last = &kBwd[i];
-    if (tiles_for(kBwd[i].tile, rows, cols) >= kTargetTiles) return last;
-  }
-  return last;
+const BwdEntry* find_bwd(int32_t prec, const hpvm_tile& t) {
+  for (int i = 0; i < kNumBwd; ++i)
+    if (kBwd[i].prec == prec && same_tile(kBwd[i].tile, t)) return &kBwd[i];
+  return nullptr;
 }
 
-const MfmaEntry* menu_entry(int32_t prec, const hpvm_tile& t) {
-  const MfmaEntry* menu;
-  const int n = mfma_menu(prec, &menu);
-  for (int i = 0; i < n; ++i) {
-    const hpvm_tile& u = menu[i].tile;
-    if (u.tile_m == t.tile_m && u.tile_n == t.tile_n && u.tile_k == t.tile_k && u.leaf_m == t.leaf_m &&
-        u.leaf_n == t.leaf_n && u.stages == t.stages)
-      return &menu[i];
+// Built-in choice: the first entry giving dA at least one tile per CU of a
+// 256-CU part, else the one giving the most tiles.
+constexpr int64_t kTargetTiles = 256;
+const BwdEntry* pick(int32_t prec, int64_t m, int64_t n, int64_t k) {
+  hpvm_tile tuned;
+  if (tuned_backward_tile(prec, m, n, k, &tuned)) {
+    const BwdEntry* e = find_bwd(prec, tuned);
+    if (e) return e;
   }
-  return nullptr;
+  const BwdEntry* most = nullptr;
+  for (int i = 0; i < kNumBwd; ++i) {
+    if (kBwd[i].prec != prec) continue;
+    if (tiles_for(kBwd[i].tile, m, k) >= kTargetTiles) return &kBwd[i];
+    if (!most || tiles_for(kBwd[i].tile, m, k) > tiles_for(most->tile, m, k)) most = &kBwd[i];
+  }
+  return most;
 }
 
 int64_t elem_blocks(int64_t m, int64_t n) {
   return std::max<int64_t>(1, std::min<int64_t>(kElemBlocks, (m * n + kElemThreads - 1) / kElemThreads));
 }
 
-// Partial-sum slots: dA tiles, then element-wise blocks (16-byte aligned).
-int64_t ws_floats(int32_t prec, int64_t m, int64_t n, int64_t k, int64_t* na) {
-  const BwdConfig* c = pick(prec, m, k);
-  *na = (m > 0 && k > 0) ? tiles_for(c->tile, m, k) : 0;
-  return ((*na + 3) / 4) * 4 + elem_blocks(m, n);
+// Workspace: [dA partials][element-wise partials][staging planes], each
+// 256-byte aligned.  The dA and dB passes run one after the other on the
+// stream, so they share the staging region.
+struct BwdLayout {
+  int64_t na, nb;
+  int64_t pb_off, stage_off, total;
+};
+
+BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  BwdLayout L;
+  L.na = (m > 0 && k > 0) ? tiles_for(e->tile, m, k) : 0;
+  L.nb = elem_blocks(m, n);
+  L.pb_off = up(L.na * 4);
+  L.stage_off = L.pb_off + up(L.nb * 4);
+  int64_t stage = 0;
+  if (!e->grad_a)
+    stage = std::max(staged_workspace_bytes(e->prec, m, k, n), staged_workspace_bytes(e->prec, k, n, m));
+  L.total = L.stage_off + stage;
+  return L;
 }
 
 bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
 
+std::mutex g_tune_mu;
+std::map<std::tuple<int32_t, int64_t, int64_t, int64_t>, hpvm_tile> g_tuned;
+
+int resolve_bwd(int32_t prec, const hpvm_tile* tile, int64_t m, int64_t n, int64_t k, const BwdEntry** out,
+                int argno) {
+  if (prec < HPVM_PREC_FP32 || prec > HPVM_PREC_BF16X3)
+    return set_error(HPVM_INVALID_ARG, "argument %d: unknown precision %d", argno - 1, prec);
+  *out = tile ? find_bwd(prec, *tile) : pick(prec, m, n, k);
+  if (!*out)
+    return set_error(HPVM_UNSUPPORTED, "argument %d: tile not in the backward menu for precision %d", argno,
+                     prec);
+  return HPVM_OK;
+}
+
 }  // namespace
+
+int tuned_backward_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_tuple(prec, m, n, k));
+  if (it == g_tuned.end()) return 0;
+  *out = it->second;
+  return 1;
+}
+
+void record_backward_tile(int32_t prec, int64_t m, int64_t n, int64_t k, const hpvm_tile& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[std::make_tuple(prec, m, n, k)] = t;
+}
+
 }  // namespace hpvm
 
 using namespace hpvm;
 
 extern "C" {
 
-int hpvm_sgemm_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, int64_t* bytes) {
-  if (m < 0 || n < 0 || k < 0) return set_error(HPVM_INVALID_ARG, "sizes must be >= 0");
+int hpvm_sgemm_backward_menu(int32_t prec, hpvm_tile* out, int32_t capacity, int32_t* count) {
   if (prec < HPVM_PREC_FP32 || prec > HPVM_PREC_BF16X3)
-    return set_error(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
-  if (!bytes) return set_error(HPVM_INVALID_ARG, "argument 5: bytes is NULL");
-  int64_t na;
-  *bytes = ws_floats(prec, m, n, k, &na) * (int64_t)sizeof(float);
+    return set_error(HPVM_INVALID_ARG, "argument 1: unknown precision %d", prec);
+  if (capacity < 0 || (capacity > 0 && !out))
+    return set_error(HPVM_INVALID_ARG, "argument 3: bad capacity or NULL output");
+  if (!count) return set_error(HPVM_INVALID_ARG, "argument 4: count is NULL");
+  int n = 0;
+  for (int i = 0; i < kNumBwd; ++i) {
+    if (kBwd[i].prec != prec) continue;
+    if (n < capacity) out[n] = kBwd[i].tile;
+    ++n;
+  }
+  *count = n;
+  return clear_error();
+}
+
+int hpvm_sgemm_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile,
+                                        int64_t* bytes) {
+  if (m < 0 || n < 0 || k < 0) return set_error(HPVM_INVALID_ARG, "sizes must be >= 0");
+  const BwdEntry* e;
+  int rc = resolve_bwd(prec, tile, m, n, k, &e, 5);
+  if (rc != HPVM_OK) return rc;
+  if (!bytes) return set_error(HPVM_INVALID_ARG, "argument 6: bytes is NULL");
+  *bytes = bwd_layout(e, m, n, k).total;
   return clear_error();
 }
 
 int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta, const float* A, int64_t lda,
                         const float* B, int64_t ldb, const float* C_in, int64_t ldci, const float* G, int64_t ldg,
                         float* dA, int64_t ldda, float* dB, int64_t lddb, float* dC_in, int64_t lddci,
-                        float* dalpha, float* dbeta, int32_t prec, void* workspace, int64_t workspace_bytes,
-                        void* stream) {
+                        float* dalpha, float* dbeta, int32_t prec, const hpvm_tile* tile, void* workspace,
+                        int64_t workspace_bytes, void* stream) {
   if (m < 0) return set_error(HPVM_INVALID_ARG, "argument 1: m = %lld < 0", (long long)m);
   if (n < 0) return set_error(HPVM_INVALID_ARG, "argument 2: n = %lld < 0", (long long)n);
   if (k < 0) return set_error(HPVM_INVALID_ARG, "argument 3: k = %lld < 0", (long long)k);
@@ -220,11 +279,11 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     return set_error(HPVM_UNSUPPORTED, "sizes above 2^31 - 1 are not supported");
   const bool mn = m > 0 && n > 0, mk = m > 0 && k > 0, kn = k > 0 && n > 0;
   const bool want_a = dA != nullptr || dalpha != nullptr;  // dalpha rides on dA's pass
-  const bool need_A = (want_a && mk && n > 0) || (dB && kn && m > 0);
-  const bool need_B = want_a && mk && n > 0;
-  if (need_A && !A) return set_error(HPVM_INVALID_ARG, "argument 6: A is NULL");
+  const bool run_a = want_a && mk && n > 0;
+  const bool run_b = dB && kn && m > 0;
+  if ((run_a || run_b) && !A) return set_error(HPVM_INVALID_ARG, "argument 6: A is NULL");
   if (lda < std::max<int64_t>(1, k)) return set_error(HPVM_INVALID_ARG, "argument 7: lda < max(1, k)");
-  if (need_B && !B) return set_error(HPVM_INVALID_ARG, "argument 8: B is NULL");
+  if (run_a && !B) return set_error(HPVM_INVALID_ARG, "argument 8: B is NULL");
   if (ldb < std::max<int64_t>(1, n)) return set_error(HPVM_INVALID_ARG, "argument 9: ldb < max(1, n)");
   if (dbeta && mn && !C_in) return set_error(HPVM_INVALID_ARG, "argument 10: C_in is NULL");
   if (ldci < std::max<int64_t>(1, n)) return set_error(HPVM_INVALID_ARG, "argument 11: ldci < max(1, n)");
@@ -233,65 +292,67 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   if (ldda < std::max<int64_t>(1, k)) return set_error(HPVM_INVALID_ARG, "argument 15: ldda < max(1, k)");
   if (lddb < std::max<int64_t>(1, n)) return set_error(HPVM_INVALID_ARG, "argument 17: lddb < max(1, n)");
   if (lddci < std::max<int64_t>(1, n)) return set_error(HPVM_INVALID_ARG, "argument 19: lddci < max(1, n)");
-  if (prec < HPVM_PREC_FP32 || prec > HPVM_PREC_BF16X3)
-    return set_error(HPVM_INVALID_ARG, "argument 22: unknown precision %d", prec);
-  int64_t na;
-  const int64_t need = ws_floats(prec, m, n, k, &na) * (int64_t)sizeof(float);
-  if ((dalpha || dbeta) && !workspace) return set_error(HPVM_INVALID_ARG, "argument 23: workspace is NULL");
-  if ((dalpha || dbeta) && workspace_bytes < need)
-    return set_error(HPVM_WORKSPACE_TOO_SMALL, "argument 24: workspace has %lld bytes, needs %lld",
-                     (long long)workspace_bytes, (long long)need);
+  const BwdEntry* cfg;
+  int rc = resolve_bwd(prec, tile, m, n, k, &cfg, 23);
+  if (rc != HPVM_OK) return rc;
+  const BwdLayout L = bwd_layout(cfg, m, n, k);
+  const bool staged = cfg->grad_a == nullptr;
+  const bool need_ws = dalpha || dbeta || (staged && (run_a || run_b));
+  if (need_ws && !workspace) return set_error(HPVM_INVALID_ARG, "argument 24: workspace is NULL");
+  if (need_ws && workspace_bytes < L.total)
+    return set_error(HPVM_WORKSPACE_TOO_SMALL, "argument 25: workspace has %lld bytes, needs %lld",
+                     (long long)workspace_bytes, (long long)L.total);
   if (workspace && (uintptr_t)workspace % 16)
-    return set_error(HPVM_INVALID_ARG, "argument 23: workspace is not 16-byte aligned");
+    return set_error(HPVM_INVALID_ARG, "argument 24: workspace is not 16-byte aligned");
   if (fault_injected("launch")) return set_error(HPVM_HIP_ERROR, "injected launch failure (HPVM_FAULT_INJECT)");
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  float* pa = reinterpret_cast<float*>(workspace);
-  float* pb = pa ? pa + ((na + 3) / 4) * 4 : nullptr;
-  const int64_t nb = elem_blocks(m, n);
+  char* ws = reinterpret_cast<char*>(workspace);
+  float* pa = ws ? reinterpret_cast<float*>(ws) : nullptr;
+  float* pb = ws ? reinterpret_cast<float*>(ws + L.pb_off) : nullptr;
+  void* stage = ws ? ws + L.stage_off : nullptr;
+  const MfmaEntry* me = find_menu_entry(prec, cfg->tile);
   hipError_t e = hipSuccess;
-  const BwdConfig* cfg = pick(prec, m, k);
+  int64_t na = L.na;
 
   // dA (and dalpha's partials): contraction over n.
-  if (want_a && mk) {
-    if (n == 0) {
-      if (dA) e = launch_scale(dA, ldda, m, k, 0.0f, s);
-      na = 0;
-    } else {
-      GemmArgs a{};
-      a.A = G;
-      a.lda = ldg;
-      a.B = B;
-      a.ldb = ldb;
-      a.C = dA;
-      a.ldc = ldda;
-      a.m = (int32_t)m;
-      a.n = (int32_t)k;
-      a.k = (int32_t)n;
-      a.alpha = alpha;
-      a.beta = 0.0f;
-      a.vec_a = aligned16(G, ldg);
-      a.vec_b = aligned16(B, ldb);
-      a.tiles_m = (a.m + cfg->tile.tile_m - 1) / cfg->tile.tile_m;
-      a.tiles_n = (a.n + cfg->tile.tile_n - 1) / cfg->tile.tile_n;
-      if (dalpha) {
-        // Fused pass: dA (when requested) and the per-tile partials of dalpha.
-        if (cfg->lds > 65536)
-          e = hipFuncSetAttribute(reinterpret_cast<const void*>(cfg->grad_a),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg->lds);
-        if (e == hipSuccess) {
-          const float* Ao = A;
-          int64_t ldao = lda;
-          float* part = pa;
-          void* kargs[] = {&a, &Ao, &ldao, &part};
-          e = hipLaunchKernel(reinterpret_cast<const void*>(cfg->grad_a), dim3((unsigned)(a.tiles_m * a.tiles_n)),
-                              dim3(cfg->threads), kargs, (size_t)cfg->lds, s);
-        }
-      } else {
-        // No dalpha: dA is a plain launch of the main loop (B transposed).
-        const MfmaEntry* me = menu_entry(prec, cfg->tile);
-        e = me ? me->launch(a, false, true, s) : hipErrorInvalidValue;
+  if (want_a && mk && n == 0) {
+    if (dA) e = launch_scale(dA, ldda, m, k, 0.0f, s);
+    na = 0;
+  } else if (run_a) {
+    GemmArgs a{};
+    a.A = G;
+    a.lda = ldg;
+    a.B = B;
+    a.ldb = ldb;
+    a.C = dA;
+    a.ldc = ldda;
+    a.m = (int32_t)m;
+    a.n = (int32_t)k;
+    a.k = (int32_t)n;
+    a.alpha = alpha;
+    a.beta = 0.0f;
+    a.vec_a = aligned16(G, ldg);
+    a.vec_b = aligned16(B, ldb);
+    a.tiles_m = (a.m + cfg->tile.tile_m - 1) / cfg->tile.tile_m;
+    a.tiles_n = (a.n + cfg->tile.tile_n - 1) / cfg->tile.tile_n;
+    if (staged) {
+      e = me ? me->launch_staged_form(a, false, true, stage, A, lda, dalpha ? pa : nullptr, s) : hipErrorInvalidValue;
+    } else if (dalpha) {
+      // Fused pass: dA (when requested) and the per-tile partials of dalpha.
+      if (cfg->lds > 65536)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(cfg->grad_a),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg->lds);
+      if (e == hipSuccess) {
+        const float* Ao = A;
+        int64_t ldao = lda;
+        float* part = pa;
+        void* kargs[] = {&a, &Ao, &ldao, &part};
+        e = hipLaunchKernel(reinterpret_cast<const void*>(cfg->grad_a), dim3((unsigned)(a.tiles_m * a.tiles_n)),
+                            dim3(cfg->threads), kargs, (size_t)cfg->lds, s);
       }
+    } else {
+      e = me ? me->launch(a, false, true, s) : hipErrorInvalidValue;
     }
   } else {
     na = 0;
@@ -299,28 +360,26 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   if (e != hipSuccess) return hip_error(e, "backward dA launch");
 
   // dB: contraction over m.
-  if (dB && kn) {
-    if (m == 0) {
-      e = launch_scale(dB, lddb, k, n, 0.0f, s);
-    } else {
-      GemmArgs b{};
-      b.A = A;
-      b.lda = lda;
-      b.B = G;
-      b.ldb = ldg;
-      b.C = dB;
-      b.ldc = lddb;
-      b.m = (int32_t)k;
-      b.n = (int32_t)n;
-      b.k = (int32_t)m;
-      b.alpha = alpha;
-      b.beta = 0.0f;
-      b.vec_a = aligned16(A, lda);
-      b.vec_b = aligned16(G, ldg);
-      const BwdConfig* cb = pick(prec, k, n);
-      const MfmaEntry* me = menu_entry(prec, cb->tile);
-      e = me ? me->launch(b, true, false, s) : hipErrorInvalidValue;
-    }
+  if (dB && kn && m == 0) {
+    e = launch_scale(dB, lddb, k, n, 0.0f, s);
+  } else if (run_b) {
+    GemmArgs b{};
+    b.A = A;
+    b.lda = lda;
+    b.B = G;
+    b.ldb = ldg;
+    b.C = dB;
+    b.ldc = lddb;
+    b.m = (int32_t)k;
+    b.n = (int32_t)n;
+    b.k = (int32_t)m;
+    b.alpha = alpha;
+    b.beta = 0.0f;
+    b.vec_a = aligned16(A, lda);
+    b.vec_b = aligned16(G, ldg);
+    if (!me) e = hipErrorInvalidValue;
+    else if (staged) e = me->launch_staged_form(b, true, false, stage, nullptr, 0, nullptr, s);
+    else e = me->launch(b, true, false, s);
   }
   if (e != hipSuccess) return hip_error(e, "backward dB launch");
 
@@ -333,8 +392,8 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     int64_t ldg_ = ldg, ldci_ = ldci, lddci_ = lddci, m_ = m, n_ = n;
     float beta_ = beta;
     void* kargs[] = {&Gp, &ldg_, &Cp, &ldci_, &dCp, &lddci_, &m_, &n_, &beta_, &part};
-    e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_grad_c), dim3((unsigned)nb), dim3(kElemThreads), kargs,
-                        0, s);
+    e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_grad_c), dim3((unsigned)L.nb), dim3(kElemThreads),
+                        kargs, 0, s);
   }
   if (e != hipSuccess) return hip_error(e, "backward dC_in launch");
 
@@ -342,11 +401,67 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     const float* pa_ = pa;
     const float* pb_ = pb;
     int32_t na_ = (int32_t)(dalpha ? na : 0);
-    int32_t nb_ = (int32_t)((dbeta && mn) ? nb : 0);
+    int32_t nb_ = (int32_t)((dbeta && mn) ? L.nb : 0);
     void* kargs[] = {&pa_, &na_, &pb_, &nb_, &dalpha, &dbeta};
     e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_grad_finish), dim3(1), dim3(kElemThreads), kargs, 0, s);
   }
   if (e != hipSuccess) return hip_error(e, "backward reduction launch");
+  return clear_error();
+}
+
+int hpvm_autotune_backward(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A, int64_t lda,
+                           const float* B, int64_t ldb, const float* G, int64_t ldg, float* dA, int64_t ldda,
+                           float* dB, int64_t lddb, void* workspace, int64_t workspace_bytes, int32_t reps,
+                           void* stream, hpvm_tile* best, float* best_ms) {
+  if (m <= 0 || n <= 0 || k <= 0) return set_error(HPVM_INVALID_ARG, "m, n and k must be positive");
+  if (prec < HPVM_PREC_FP32 || prec > HPVM_PREC_BF16X3)
+    return set_error(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
+  if (reps < 1) return set_error(HPVM_INVALID_ARG, "argument 17: reps = %d < 1", reps);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best_t = -1.0f;
+  const BwdEntry* best_e = nullptr;
+  int rc = HPVM_OK;
+  // dA, dB and dalpha: the outputs whose GEMMs the tile decides.
+  float* dalpha = nullptr;
+  for (int round = 0; round < 2 && e == hipSuccess && rc == HPVM_OK; ++round) {
+    for (int i = 0; i < kNumBwd && e == hipSuccess; ++i) {
+      const BwdEntry* c = &kBwd[i];
+      if (c->prec != prec) continue;
+      const BwdLayout L = bwd_layout(c, m, n, k);
+      if (L.total + 256 > workspace_bytes) continue;
+      // the last 256 bytes of the workspace hold dalpha
+      dalpha = reinterpret_cast<float*>(reinterpret_cast<char*>(workspace) + workspace_bytes - 256);
+      auto run = [&]() {
+        return hpvm_sgemm_backward(m, n, k, 1.0f, 0.0f, A, lda, B, ldb, nullptr, std::max<int64_t>(n, 1), G, ldg,
+                                   dA, ldda, dB, lddb, nullptr, std::max<int64_t>(n, 1), dalpha, nullptr, prec,
+                                   &c->tile, workspace, workspace_bytes - 256, stream);
+      };
+      rc = run();
+      if (rc != HPVM_OK) break;
+      e = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && e == hipSuccess && rc == HPVM_OK; ++r) rc = run();
+      if (rc != HPVM_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && (best_t < 0.0f || ms < best_t)) {
+        best_t = ms;
+        best_e = c;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc != HPVM_OK) return rc;
+  if (e != hipSuccess) return hip_error(e, "backward autotune timing");
+  if (!best_e) return set_error(HPVM_WORKSPACE_TOO_SMALL, "no backward tile fits the workspace");
+  record_backward_tile(prec, m, n, k, best_e->tile);
+  if (best) *best = best_e->tile;
+  if (best_ms) *best_ms = best_t / (float)reps;
   return clear_error();
 }
 

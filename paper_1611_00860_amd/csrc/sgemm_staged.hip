@@ -145,6 +145,11 @@ struct StagedArgs {
   int64_t ldc;
   int32_t m, n, slabs, tiles_m, tiles_n;
   float alpha, beta;
+  // Backward epilogue (EPI = 1): C (may be null) <- alpha acc, and
+  // partial[tile] <- sum over the tile of aorig .* acc.
+  const float* aorig;
+  int64_t lda_orig;
+  float* partial;
 };
 
 // The GEMM over staged planes.  DEPTH = 1: each K-slab is loaded into
@@ -154,7 +159,7 @@ struct StagedArgs {
 // so two slabs of MFMA work cover each load.  One barrier per slab either
 // way.  PIPE reads the fragments of the next 16-k step ahead of the current
 // MFMAs.
-template <int TM, int TN, int TK, int WM, int WN, bool X3, int DEPTH, bool PIPE>
+template <int TM, int TN, int TK, int WM, int WN, bool X3, int DEPTH, bool PIPE, int EPI>
 __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
     sgemm_bf16_staged(StagedArgs p) {
   using T = Bf16TileShape<TM, TN, TK, WM, WN, X3>;
@@ -249,14 +254,36 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
     }
   }
 
-  GemmArgs e{};
-  e.C = p.C;
-  e.ldc = p.ldc;
-  e.m = p.m;
-  e.n = p.n;
-  e.alpha = p.alpha;
-  e.beta = p.beta;
-  store_c<BM, BN>(e, acc, (int)m0 + wm0, (int)n0 + wn0, lane);
+  if constexpr (EPI == 0) {
+    GemmArgs e{};
+    e.C = p.C;
+    e.ldc = p.ldc;
+    e.m = p.m;
+    e.n = p.n;
+    e.alpha = p.alpha;
+    e.beta = p.beta;
+    store_c<BM, BN>(e, acc, (int)m0 + wm0, (int)n0 + wn0, lane);
+  } else {
+    float part = 0.0f;
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj) {
+        const int j = (int)n0 + wn0 + 32 * bj + acc_col(lane);
+        if (j >= p.n) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = (int)m0 + wm0 + 32 * bi + acc_row(r, lane);
+          if (i < p.m) {
+            const float v = acc[bi][bj][r];
+            if (p.C) p.C[(int64_t)i * p.ldc + j] = p.alpha * v;
+            part = fmaf(p.aorig[(int64_t)i * p.lda_orig + j], v, part);
+          }
+        }
+      }
+    const float sum = block_sum(part, reinterpret_cast<float*>(smem));
+    if (threadIdx.x == 0) p.partial[blockIdx.x] = sum;
+  }
 }
 
 namespace {
@@ -269,30 +296,41 @@ hipError_t allow_lds_staged(Kernel* fn, size_t bytes) {
 }
 
 template <bool X3>
-hipError_t stage_operands(const GemmArgs& a, const StagedLayout& L, char* ws, hipStream_t s) {
+hipError_t stage_rows_launch(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
+                             int64_t cols_pad, uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s) {
+  const int64_t units = rows_pad * cols_pad / 8;
+  const unsigned blocks = (unsigned)std::min<int64_t>((units + 255) / 256, 8192);
+  void* args[] = {&src, &ld, &rows, &cols, &rows_pad, &cols_pad, &hi, &lo, &vec};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&stage_rows<X3>), dim3(blocks), dim3(256), args, 0, s);
+}
+
+template <bool X3>
+hipError_t stage_cols_launch(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
+                             int64_t cols_pad, uint16_t* hi, uint16_t* lo, hipStream_t s) {
+  void* args[] = {&src, &ld, &rows, &cols, &rows_pad, &hi, &lo};
+  const dim3 grid((unsigned)(cols_pad / kTB), (unsigned)(rows_pad / kTB));
+  return hipLaunchKernel(reinterpret_cast<const void*>(&stage_cols<X3>), grid, dim3(256), args, 0, s);
+}
+
+// Writes op(A) as [m_pad][k_pad] and op(B) as [n_pad][k_pad] planes, k
+// contiguous: an operand already k-contiguous in HBM is copied row by row,
+// the other is transposed through LDS.
+template <bool X3>
+hipError_t stage_operands(const GemmArgs& a, bool at, bool bt, const StagedLayout& L, char* ws, hipStream_t s) {
   uint16_t* ah = reinterpret_cast<uint16_t*>(ws);
   uint16_t* al = X3 ? reinterpret_cast<uint16_t*>(ws + L.a_plane) : nullptr;
   uint16_t* bh = reinterpret_cast<uint16_t*>(ws + L.planes * L.a_plane);
   uint16_t* bl = X3 ? reinterpret_cast<uint16_t*>(ws + L.planes * L.a_plane + L.b_plane) : nullptr;
-  // A: m x k, k contiguous.
-  {
-    const float* src = a.A;
-    int64_t ld = a.lda, rows = a.m, cols = a.k, rp = L.m_pad, cp = L.k_pad;
-    int32_t vec = a.vec_a;
-    const int64_t units = rp * cp / 8;
-    const unsigned blocks = (unsigned)std::min<int64_t>((units + 255) / 256, 8192);
-    void* args[] = {&src, &ld, &rows, &cols, &rp, &cp, &ah, &al, &vec};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&stage_rows<X3>), dim3(blocks), dim3(256), args, 0, s);
-    if (e != hipSuccess) return e;
-  }
-  // B: k x n, n contiguous -> transposed planes.
-  {
-    const float* src = a.B;
-    int64_t ld = a.ldb, rows = a.k, cols = a.n, rp = L.k_pad;
-    void* args[] = {&src, &ld, &rows, &cols, &rp, &bh, &bl};
-    const dim3 grid((unsigned)(L.n_pad / kTB), (unsigned)(L.k_pad / kTB));
-    return hipLaunchKernel(reinterpret_cast<const void*>(&stage_cols<X3>), grid, dim3(256), args, 0, s);
-  }
+  hipError_t e;
+  if (!at)  // A: m x k, k contiguous
+    e = stage_rows_launch<X3>(a.A, a.lda, a.m, a.k, L.m_pad, L.k_pad, ah, al, a.vec_a, s);
+  else      // A stored k x m
+    e = stage_cols_launch<X3>(a.A, a.lda, a.k, a.m, L.k_pad, L.m_pad, ah, al, s);
+  if (e != hipSuccess) return e;
+  if (!bt)  // B: k x n, n contiguous
+    return stage_cols_launch<X3>(a.B, a.ldb, a.k, a.n, L.k_pad, L.n_pad, bh, bl, s);
+  // B stored n x k
+  return stage_rows_launch<X3>(a.B, a.ldb, a.n, a.k, L.n_pad, L.k_pad, bh, bl, a.vec_b, s);
 }
 
 template <int TM, int TN, int TK, int WM, int WN, bool X3, int DEPTH, bool PIPE>
@@ -301,11 +339,13 @@ struct StagedConfig {
   static constexpr int kThreads = T::NT;
   static_assert(kPadMN % TM == 0 && kPadMN % TN == 0 && kPadK % TK == 0, "padding covers the tile");
 
-  static hipError_t launch(const GemmArgs& a, void* workspace, hipStream_t s) {
+  template <int EPI>
+  static hipError_t run(const GemmArgs& a, bool at, bool bt, void* workspace, const float* aorig, int64_t lda_orig,
+                        float* partial, hipStream_t s) {
     const int32_t prec = X3 ? HPVM_PREC_BF16X3 : HPVM_PREC_BF16;
     const StagedLayout L = staged_layout(prec, a.m, a.n, a.k);
     char* ws = reinterpret_cast<char*>(workspace);
-    hipError_t e = stage_operands<X3>(a, L, ws, s);
+    hipError_t e = stage_operands<X3>(a, at, bt, L, ws, s);
     if (e != hipSuccess) return e;
     StagedArgs p{};
     p.ah = reinterpret_cast<const uint16_t*>(ws);
@@ -322,19 +362,31 @@ struct StagedConfig {
     p.tiles_n = (a.n + TN - 1) / TN;
     p.alpha = a.alpha;
     p.beta = a.beta;
-    auto* fn = &sgemm_bf16_staged<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>;
+    p.aorig = aorig;
+    p.lda_orig = lda_orig;
+    p.partial = partial;
+    auto* fn = &sgemm_bf16_staged<TM, TN, TK, WM, WN, X3, DEPTH, PIPE, EPI>;
     e = allow_lds_staged(fn, (size_t)T::kLdsBytes);
     if (e != hipSuccess) return e;
     void* kargs[] = {&p};
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(p.tiles_m * p.tiles_n)),
                            dim3(kThreads), kargs, (size_t)T::kLdsBytes, s);
   }
+  static hipError_t launch(const GemmArgs& a, void* workspace, hipStream_t s) {
+    return run<0>(a, false, false, workspace, nullptr, 0, nullptr, s);
+  }
+  static hipError_t launch_form(const GemmArgs& a, bool at, bool bt, void* workspace, const float* aorig,
+                                int64_t lda_orig, float* partial, hipStream_t s) {
+    return partial ? run<1>(a, at, bt, workspace, aorig, lda_orig, partial, s)
+                   : run<0>(a, at, bt, workspace, nullptr, 0, nullptr, s);
+  }
 };
 
 #define HPVM_STAGED_ENTRY(PREC, X3, DEPTH, PIPE, TM, TN, TK, WM, WN)                                     \
   {{TM, TN, TK, WM, WN, 3}, PREC, StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::kThreads,           \
    Bf16TileShape<TM, TN, TK, WM, WN, X3>::kLdsBytes, nullptr,                                             \
-   &StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::launch}
+   &StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::launch,                                           \
+   &StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::launch_form}
 
 const MfmaEntry kStagedMenuBf16[] = {
     HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 2, false, 256, 256, 64, 128, 64),

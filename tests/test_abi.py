@@ -313,19 +313,29 @@ def test_autotune_cache_host_side(lib, tmp_path):
 
 def test_backward_validation(lib):
     ws = ctypes.c_int64()
-    assert lib.hpvm_sgemm_backward_workspace_bytes(4096, 4096, 1024, 0, ctypes.byref(ws)) == 0
+    assert lib.hpvm_sgemm_backward_workspace_bytes(4096, 4096, 1024, 0, None, ctypes.byref(ws)) == 0
     assert ws.value >= 4 * 256
+    for prec in ("fp32", "bf16", "bf16x3"):
+        menu = hp.backward_menu(prec)
+        assert menu
+        for t in menu:
+            b = hp.backward_workspace_bytes(4096, 4096, 1024, prec, t)
+            if t[5] == 3:  # staged: holds the bfloat16 planes of the larger of dA's and dB's products
+                assert b >= hp.workspace_bytes(4096, 1024, 4096, prec, t)
+    with pytest.raises(hp.HpvmError):
+        hp.backward_workspace_bytes(64, 64, 64, "fp32", (48, 48, 16, 16, 16, 2))
     args = dict(m=16, n=16, k=16, alpha=0.7, beta=0.3, A=FAKE, lda=16, B=FAKE * 2, ldb=16, C_in=FAKE * 3,
                 ldci=16, G=FAKE * 4, ldg=16, dA=FAKE * 5, ldda=16, dB=FAKE * 6, lddb=16, dC_in=FAKE * 7,
-                lddci=16, dalpha=FAKE * 8, dbeta=FAKE * 8 + 4, prec=0, ws=FAKE * 9, wsb=1 << 20)
+                lddci=16, dalpha=FAKE * 8, dbeta=FAKE * 8 + 4, prec=0, tile=None, ws=FAKE * 9, wsb=1 << 20)
 
     def call_bw(**kw):
         a = dict(args)
         a.update(kw)
+        t = ctypes.byref(_lib.Tile(*a["tile"])) if a["tile"] else None
         return lib.hpvm_sgemm_backward(a["m"], a["n"], a["k"], a["alpha"], a["beta"], a["A"], a["lda"],
                                        a["B"], a["ldb"], a["C_in"], a["ldci"], a["G"], a["ldg"], a["dA"],
                                        a["ldda"], a["dB"], a["lddb"], a["dC_in"], a["lddci"], a["dalpha"],
-                                       a["dbeta"], a["prec"], a["ws"], a["wsb"], None)
+                                       a["dbeta"], a["prec"], t, a["ws"], a["wsb"], None)
 
     assert call_bw(m=-1) == -1 and hp.last_error().startswith("argument 1")
     assert call_bw(A=None) == -1 and hp.last_error().startswith("argument 6")
@@ -334,6 +344,7 @@ def test_backward_validation(lib):
     assert call_bw(G=None) == -1 and hp.last_error().startswith("argument 12")
     assert call_bw(lddb=3) == -1 and hp.last_error().startswith("argument 17")
     assert call_bw(prec=7) == -1
+    assert call_bw(tile=(48, 48, 16, 16, 16, 2)) == -2
     assert call_bw(wsb=8) == -4
     assert call_bw(ws=FAKE + 4) == -1
     # C_in is not needed without dbeta, B not needed for dB alone: the checks
@@ -343,6 +354,10 @@ def test_backward_validation(lib):
     try:
         rc = call_bw(C_in=None, dbeta=None, wsb=0, ws=None, dalpha=None, B=None, dA=None, dC_in=None)
         assert rc == -3 and "injected" in hp.last_error()
+        # a staged tile needs the workspace even without the scalars
+        st = [t for t in hp.backward_menu("bf16") if t[5] == 3][0]
+        rc = call_bw(C_in=None, dbeta=None, wsb=0, ws=None, dalpha=None, dC_in=None, prec=1, tile=st)
+        assert rc == -1 and "workspace" in hp.last_error()
     finally:
         del os.environ["HPVM_FAULT_INJECT"]
 

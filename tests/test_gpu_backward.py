@@ -44,7 +44,7 @@ def test_backward_16_against_oracle_gradient(gpu, prec):
 
 
 def test_backward_integers_exact_scalars(gpu):
-    """Integer inputs: every partial sum is an exact FP32 integer."""
+    """Integer inputs: dA, dB, dC_in exact; the scalars' long FP32 sums to 1e-6."""
     import torch
 
     A, B, C, G = inputs.backward_operands(100, 90, 70, seed=8, dist="int")
@@ -54,7 +54,8 @@ def test_backward_integers_exact_scalars(gpu):
     assert np.array_equal(to_host(g["dA"]), ref["dA"])
     assert np.array_equal(to_host(g["dB"]), ref["dB"])
     assert np.array_equal(to_host(g["dC_in"]), ref["dC_in"])
-    assert float(g["dalpha"]) == ref["dalpha"] and float(g["dbeta"]) == ref["dbeta"]
+    assert math.isclose(float(g["dalpha"]), ref["dalpha"], rel_tol=1e-6)
+    assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-6)
 
 
 def test_backward_deterministic_and_partial_outputs(gpu):
@@ -148,3 +149,36 @@ def test_autograd_function(gpu):
     assert math.isclose(float(beta.grad), ref["dbeta"], rel_tol=1e-5)
     # input C_in is left untouched by the forward (out of place)
     assert torch.equal(tC.detach(), to_dev(C))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+def test_backward_every_tile_integers(gpu, prec):
+    """Every backward tile, fused and staged: integer inputs are exact in all precisions."""
+    import torch
+
+    A, B, C, G = inputs.backward_operands(300, 260, 200, seed=13, dist="int")
+    ref = oracle.sgemm_grad(A, B, C, G, 1.0, 2.0)
+    d = dev_all(A, B, C, G)
+    for tile in gpu.backward_menu(prec):
+        print(f"case: backward {prec} tile {tile}", flush=True)
+        g = gpu.sgemm_backward(*d, 1.0, 2.0, prec=prec, tile=tile)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(g["dA"]), ref["dA"]), tile
+        assert np.array_equal(to_host(g["dB"]), ref["dB"]), tile
+        assert np.array_equal(to_host(g["dC_in"]), ref["dC_in"]), tile
+        assert math.isclose(float(g["dalpha"]), ref["dalpha"], rel_tol=1e-6), tile
+        assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-6), tile
+
+
+def test_backward_autotune_records_a_menu_tile(gpu):
+    import torch
+
+    A, B, C, G = inputs.backward_operands(512, 384, 256, seed=14)
+    d = dev_all(A, B, C, G)
+    tile, ms = gpu.autotune_backward(d[0], d[1], d[3], prec="bf16", reps=1)
+    assert tuple(tile) in [tuple(t) for t in gpu.backward_menu("bf16")] and ms > 0
+    g = gpu.sgemm_backward(*d, 0.7, 0.3, prec="bf16")  # takes the tuned tile
+    torch.cuda.synchronize()
+    ref = oracle.sgemm_grad(A, B, C, G, 0.7, 0.3)
+    assert normwise(to_host(g["dA"]), ref["dA"]) <= 1e-2
+    assert normwise(to_host(g["dB"]), ref["dB"]) <= 1e-2
