@@ -51,6 +51,7 @@ def log(msg):
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "sgemm_mfma_f32_traffic.txt")
 KERNEL_SOURCES = ("device_common.hpp", "mfma_f32.hpp", "sgemm_mfma.hip")
 COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read, 1 GiB written
+SWEEP_REPS = 2  # launches per (tile, workload entry) in a counter run
 
 
 def kernel_source_sha():
@@ -84,12 +85,13 @@ def load_traffic_table():
     return table if sha == kernel_source_sha() else None
 
 
-def build_traffic_table(fetch_csv, write_csv, tiles_json, steps, warmup, command):
-    """Per-(tile, shape, beta) HBM bytes from two counter runs of this script.
+def build_traffic_table(fetch_csv, write_csv, fetch_log, write_log, command):
+    """Per-(tile, shape, beta) HBM bytes from two --traffic-sweep counter runs.
 
-    The counter runs use --tiles-from, so their FP32 dispatches are exactly
-    warmup + steps + 1 passes over WORKLOAD in order.  Each counter is scaled
-    by what it reads for the calibration copy of COPY_BYTES.
+    Each sweep run prints the order of its FP32 dispatches (every menu tile on
+    every workload entry, SWEEP_REPS times) as its JSON line; the counters of
+    the FP32 dispatches are matched to that order.  Each counter is scaled by
+    what it reads for the calibration copy of COPY_BYTES.
     """
     import csv
 
@@ -97,31 +99,31 @@ def build_traffic_table(fetch_csv, write_csv, tiles_json, steps, warmup, command
         out = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         return sorted(out, key=lambda r: int(r["Dispatch_Id"]))
 
-    with open(tiles_json) as f:
-        per_shape = json.loads(f.read().strip().splitlines()[-1])["config"]["per_shape"]
-    result = {}
-    factors = {}
-    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+    def order(log_path):
+        with open(log_path) as f:
+            line = [l for l in f if l.startswith('{"traffic_sweep"')][-1]
+        return json.loads(line)["traffic_sweep"]
+
+    result, factors = {}, {}
+    for counter, path, log_path in (("FETCH_SIZE", fetch_csv, fetch_log), ("WRITE_SIZE", write_csv, write_log)):
         rs = rows(path, counter)
         copies = [float(r["Counter_Value"]) * 1024 for r in rs if "copyBuffer" in r["Kernel_Name"]][-3:]
         factor = COPY_BYTES / (sum(copies) / len(copies))
         factors[counter] = factor
         gemm = [r for r in rs if "sgemm_mfma_f32<" in r["Kernel_Name"]]
-        expect = (warmup + steps + 1) * len(WORKLOAD)
-        if len(gemm) != expect:
-            raise SystemExit(f"{path}: {len(gemm)} FP32 dispatches, expected {expect}")
-        for i, r in enumerate(gemm):
-            m, n, k, beta = WORKLOAD[i % len(WORKLOAD)]
-            tile = per_shape[f"{m}x{n}x{k}_beta{beta:g}"]["tile"]
+        seq = order(log_path)
+        if len(gemm) != len(seq):
+            raise SystemExit(f"{path}: {len(gemm)} FP32 dispatches, the sweep made {len(seq)}")
+        for r, (tile, m, n, k, beta) in zip(gemm, seq):
             key = _tile_key(tile, m, n, k, beta)
             result.setdefault(key, {}).setdefault(counter, []).append(float(r["Counter_Value"]) * 1024 * factor)
     lines = ["# HBM traffic of sgemm_mfma_f32 per launch (bytes), from rocprofv3 counters",
              "# counter runs (GPU, repository root), once with FETCH_SIZE and once with WRITE_SIZE:",
-             "#   rocprofv3 --pmc <COUNTER> --output-format csv -d <dir> -o pmc -- python3 bench.py --steps 2"
-             " --warmup 1 --no-variants --no-cpu-baseline --calibrate-copy --tiles-from <bench.json>",
-             "#   (<bench.json> = the JSON line of a default bench.py run, whose tuned tiles are reused)",
+             "#   rocprofv3 --pmc <COUNTER> --output-format csv -d <dir> -o pmc -- python3 bench.py --traffic-sweep",
+             "#   (every FP32 menu tile on every workload entry, "
+             f"{SWEEP_REPS} launches each, then three 1 GiB device copies)",
              f"# table: python3 {command}",
-             "# entry: <tile>|<m>x<n>x<k>|beta<b> <fetch bytes> <write bytes> (median over the dispatches)",
+             "# entry: <tile>|<m>x<n>x<k>|beta<b> <fetch bytes> <write bytes> (median over the launches)",
              f"# FETCH_SIZE factor {factors['FETCH_SIZE']:.4f}, WRITE_SIZE factor {factors['WRITE_SIZE']:.4f} "
              f"(bytes of a plain {COPY_BYTES >> 30} GiB device copy / what the counter reads for it)",
              f"source_sha256_16: {kernel_source_sha()}"]
@@ -330,6 +332,32 @@ def variant_backward(hp, inputs, dev, stream, reps):
     return out
 
 
+def calibration_copies(torch, dev):
+    """Three plain 1 GiB device-to-device copies: the HBM counters' yardstick."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def traffic_sweep(hp, devs, outs, dev):
+    import torch
+
+    seq = []
+    for tile in hp.tile_menu("fp32"):
+        if tile[5] != 2:  # the literal kernel is not the FP32 MFMA kernel
+            continue
+        for (m, n, k, beta), (dA, dB, dC), out in zip(WORKLOAD, devs, outs):
+            for _ in range(SWEEP_REPS):
+                hp.sgemm(dA, dB, out, 1.0, beta, tile=tile)
+                seq.append([list(tile), m, n, k, beta])
+            torch.cuda.synchronize()
+    calibration_copies(torch, dev)
+    print(json.dumps({"traffic_sweep": seq}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,12 +369,14 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain 1 GiB device-to-device copies (HBM counter calibration)")
     ap.add_argument("--tiles-from", help="take the FP32 tiles from a previous bench JSON line instead of tuning")
-    ap.add_argument("--traffic-table", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
-                    help="build profiles/sgemm_mfma_f32_traffic.txt from two counter runs and exit")
+    ap.add_argument("--traffic-sweep", action="store_true",
+                    help="launch every FP32 menu tile on every workload entry, then the calibration copies, "
+                         "and print the launch order (the run that HBM counters are taken over)")
+    ap.add_argument("--traffic-table", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_LOG", "WRITE_LOG"),
+                    help="build profiles/sgemm_mfma_f32_traffic.txt from two --traffic-sweep counter runs and exit")
     args = ap.parse_args()
     if args.traffic_table:
-        build_traffic_table(*args.traffic_table, steps=args.steps, warmup=args.warmup,
-                            command=" ".join(sys.argv))
+        build_traffic_table(*args.traffic_table, command=" ".join(sys.argv))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -372,6 +402,10 @@ def main():
         devs.append(tuple(torch.from_numpy(x).to(dev) for x in (A, B, C)))
     outs = [d[2].clone() for d in devs]
     flops_step = sum(2.0 * m * n * k for (m, n, k, _) in WORKLOAD)
+
+    if args.traffic_sweep:
+        traffic_sweep(hp, devs, outs, dev)
+        return
 
     tiles = {}
     if args.tiles_from:
@@ -482,13 +516,7 @@ def main():
 
     if args.calibrate_copy:
         log("calibration: three 1 GiB device copies")
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copies(torch, dev)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
