@@ -280,6 +280,89 @@ def variant_grouped(hp, inputs, dev, reps):
         "autotuned_ms": round(tuned_ms, 4), "max_instance_normwise_rel_error_sampled": worst, "bar": 1e-5}}
 
 
+def variant_stream(hp, inputs, dev, reps):
+    """The 512 uneven sgemms pushed one by one into a streaming graph.
+
+    The argument structs are packed before the timed passes (the producer
+    hands over packed structs, as llvm.hpvm.push takes them); a pass pushes
+    every item, popping the oldest whenever the ring is full, and ends with
+    the last pop.
+    """
+    import torch
+
+    import oracle
+
+    dims, alphas, betas, rng = inputs.grouped_problem(512, seed=3)
+    As_h, Bs_h, Cs_h = inputs.grouped_operands(dims, rng)
+    As = [torch.from_numpy(x).to(dev) for x in As_h]
+    Bs = [torch.from_numpy(x).to(dev) for x in Bs_h]
+    Cs = [torch.from_numpy(x).to(dev) for x in Cs_h]
+    flops = float(sum(2.0 * m * n * k for m, n, k in dims))
+    capacity = 64
+    grid = 2 * torch.cuda.get_device_properties(dev).multi_processor_count
+    packed = [hp.SgemmStream.pack(As[i], Bs[i], Cs[i], float(alphas[i]), float(betas[i])) for i in range(512)]
+
+    def one_pass(st):
+        for p in packed:
+            if st.in_flight == capacity:
+                st.pop()
+            st.push_packed(p)
+        while st.in_flight:
+            st.pop()
+
+    with hp.SgemmStream(capacity=capacity, grid=grid, idle_ms=10000) as st:
+        one_pass(st)  # warm-up
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            one_pass(st)
+            times.append(time.perf_counter() - t0)
+        # host cost of the same pushes and pops with nothing to compute
+        # (m = 0 items complete at push)
+        empty = [hp.SgemmStream.pack(As[i][:0], Bs[i], Cs[i][:0], 1.0, 0.0) for i in range(512)]
+        t0 = time.perf_counter()
+        for p in empty:
+            if st.in_flight == capacity:
+                st.pop()
+            st.push_packed(p)
+        while st.in_flight:
+            st.pop()
+        host_ms = (time.perf_counter() - t0) * 1e3
+        for c, c0 in zip(Cs, Cs_h):
+            c.copy_(torch.from_numpy(c0))
+        torch.cuda.current_stream().synchronize()  # not the device: the resident kernel never idles
+        one_pass(st)
+    ms = float(np.median(times)) * 1e3
+    worst = 0.0
+    rs = np.random.default_rng(6)
+    for i in range(512):
+        m, n, k = (int(v) for v in dims[i])
+        rows, cols = rs.integers(0, m, 8), rs.integers(0, n, 8)
+        ref = oracle.sgemm_entries(As_h[i], Bs_h[i], Cs_h[i], float(alphas[i]), float(betas[i]), rows, cols)
+        g = gather(Cs[i], rows, cols).astype(np.float64)
+        worst = max(worst, float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
+    # the same instances as one launch each on one stream
+    stream = torch.cuda.Stream()
+
+    def launches():
+        with torch.cuda.stream(stream):
+            for i in range(512):
+                hp.sgemm(As[i], Bs[i], Cs[i], float(alphas[i]), float(betas[i]))
+
+    launches()
+    stream.synchronize()
+    ms_launch = event_time(launches, reps, stream)
+    tf = flops / (ms / 1e3) / 1e12
+    return {"stream_512_push_pop": {
+        "tflops": round(tf, 2), "ms": round(ms, 4), "frac_of_peak": round(tf / PEAK["fp32"], 4),
+        "items_per_s": round(512 / (ms / 1e3), 1), "capacity": capacity, "persistent_workgroups": grid,
+        "timing": "host clock from the first push to the last pop (median of passes)",
+        "host_push_pop_ms_empty_items": round(host_ms, 4),
+        "one_launch_per_item_ms": round(ms_launch, 4),
+        "one_launch_per_item_tflops": round(flops / (ms_launch / 1e3) / 1e12, 2),
+        "max_instance_normwise_rel_error_sampled": worst, "bar": 1e-5}}
+
+
 def variant_backward(hp, inputs, dev, stream, reps):
     import torch
 
@@ -510,6 +593,8 @@ def main():
         variants.update(variant_precision(hp, inputs, dev, stream, reps=10))
         log("variant: grouped 512 from a HIP graph")
         variants.update(variant_grouped(hp, inputs, dev, reps=10))
+        log("variant: the 512 sgemms through a streaming graph")
+        variants.update(variant_stream(hp, inputs, dev, reps=5))
         log("variant: forward + backward 4096x4096x1024")
         variants.update(variant_backward(hp, inputs, dev, stream, reps=5))
         result["variants"] = variants

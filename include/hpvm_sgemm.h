@@ -51,7 +51,11 @@ typedef enum hpvm_status {
   HPVM_UNSUPPORTED = -2,      /* tile not in the compiled menu, misalignment */
   HPVM_HIP_ERROR = -3,        /* the HIP runtime reported an error           */
   HPVM_WORKSPACE_TOO_SMALL = -4,
-  HPVM_BAD_HANDLE = -5        /* plan or graph handle unknown or destroyed   */
+  HPVM_BAD_HANDLE = -5,       /* plan, graph or stream handle unknown/closed */
+  HPVM_QUEUE_FULL = -6,       /* stream: every slot holds an unpopped item   */
+  HPVM_TIMEOUT = -7,          /* a bounded wait ran out; the call may be     */
+                              /* repeated                                    */
+  HPVM_STREAM_ENDED = -8      /* the streaming kernel has exited             */
 } hpvm_status;
 
 /* ---- arithmetic of the bulk products ------------------------------------ */
@@ -413,6 +417,82 @@ int hpvm_grouped_plan_destroy(void* plan);
  * C.  Each candidate is launched `reps` times after one warm-up.           */
 int hpvm_grouped_autotune(void* plan, void* workspace, int64_t workspace_bytes, float* scratch,
                           int64_t scratch_bytes, int32_t reps, void* stream, float* best_ms);
+
+/* ======================================================================== */
+/* Streaming graph (llvm.hpvm.launch with Stream = 1, push, pop)              */
+/* ======================================================================== */
+/* Table 1 and Sec. 2.3 define the host intrinsics of a streaming graph:
+ * launch with Stream = 1 returns a handle, push hands the graph one more
+ * packed argument struct, pop returns the next output, in push order.
+ * Sec. 3.5 makes the nodes of such a graph persistent: they stay alive and
+ * process every item until the stream ends.  Here the graph is the sgemm
+ * graph, its argument pack is an hpvm_sgemm_desc (FP32), and the persistent
+ * node is one resident kernel on a stream of the library's own, reading the
+ * pushed packs from pinned host memory.  Items in flight run concurrently
+ * (the tiles of item i are handed out before those of item i + 1, but
+ * nothing waits for item i to finish), so they must be independent.
+ * While a stream is open its kernel is resident: a device-wide wait
+ * (hipDeviceSynchronize, and calls that imply it such as hipFree) waits for
+ * that kernel too, i.e. until the stream is closed or reaches its idle
+ * limit.  Wait on streams or events instead.                                */
+
+typedef struct hpvm_stream_config {
+  int32_t capacity;  /* ring slots = most items pushed and not yet popped,
+                        1..4096                                           */
+  int32_t grid;      /* resident workgroups; 0 = one per compute unit     */
+  int32_t idle_ms;   /* the kernel ends the stream when nothing has been
+                        pushed for this long, 1..60000                    */
+  int32_t reserved;  /* 0                                                 */
+} hpvm_stream_config;
+
+typedef struct hpvm_stream_status {
+  int64_t pushed, popped;
+  int64_t tiles;       /* workgroup tiles of every item pushed so far      */
+  int32_t capacity, grid, idle_ms;
+  int32_t running;     /* 1 while the kernel has not exited                */
+  int32_t idle_ended;  /* 1 if the kernel ended the stream at its idle
+                          limit                                            */
+  int32_t reserved;
+} hpvm_stream_status;
+
+/* Launches the persistent kernel on a new non-blocking stream of the
+ * current device and returns its handle (the paper's graph ID).  The
+ * library owns the handle, a small pinned host ring of `capacity` argument
+ * slots, and 256 + 4 * capacity bytes of device memory, until
+ * hpvm_stream_close.  At process exit every stream still open is closed
+ * (bounded by its idle limit).  Errors: HPVM_INVALID_ARG for a field out of
+ * range or NULL arguments; HPVM_HIP_ERROR if an allocation or the launch
+ * fails (nothing is left running then).                                    */
+int hpvm_stream_open(const hpvm_stream_config* config, void** handle);
+
+/* Pushes one sgemm (llvm.hpvm.push).  The item is checked by the
+ * hpvm_sgemm rules (sizes, leading dimensions, NULLs, C overlapping its own
+ * A or B) and must not overlap an item in flight: its C may not meet
+ * another in-flight item's A, B or C, and its A and B may not meet another
+ * in-flight item's C (HPVM_INVALID_ARG).  The matrices must stay valid
+ * until the item is popped.  HPVM_QUEUE_FULL when `capacity` items are in
+ * flight (pop first); HPVM_STREAM_ENDED once the kernel has exited.
+ * *seq (may be NULL) receives the item's sequence number, 0, 1, 2, ...    */
+int hpvm_stream_push(void* handle, const hpvm_sgemm_desc* item, int64_t* seq);
+
+/* Pops the oldest item in flight once it is complete (llvm.hpvm.pop):
+ * *seq receives its sequence number and *C its output pointer (either may
+ * be NULL).  Its C is then final and visible to later work on any stream.
+ * Waits at most timeout_ms (0 = just test): HPVM_TIMEOUT leaves the item in
+ * flight.  HPVM_INVALID_ARG if nothing is in flight; HPVM_STREAM_ENDED if
+ * the kernel exited (idle limit) before the item completed; HPVM_HIP_ERROR
+ * if it failed.                                                             */
+int hpvm_stream_pop(void* handle, int32_t timeout_ms, int64_t* seq, float** C);
+
+/* Counters and state of a stream.                                          */
+int hpvm_stream_info(const void* handle, hpvm_stream_status* info);
+
+/* Ends the stream: the kernel finishes every item already pushed, then
+ * exits; the call waits for that at most timeout_ms and then frees the
+ * stream's resources and the handle (later use: HPVM_BAD_HANDLE).
+ * HPVM_TIMEOUT if the kernel is still draining (the handle stays valid;
+ * close again).  Unpopped items are dropped after they complete.          */
+int hpvm_stream_close(void* handle, int32_t timeout_ms);
 
 /* ======================================================================== */
 /* Diagnostics                                                               */

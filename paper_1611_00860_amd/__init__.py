@@ -10,6 +10,7 @@ lowering of Sec. 3.4 and 6.2-6.3.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 
 from . import _lib
@@ -440,3 +441,111 @@ class GroupedPlan:
         if self._h is not None:
             _check(load().hpvm_grouped_plan_destroy(self._h))
             self._h = None
+
+
+# ---------------------------------------------------------------------------
+# Streaming graph: launch with Stream = 1, push, pop
+# ---------------------------------------------------------------------------
+_open_streams = set()
+
+
+def _close_open_streams():
+    for st in list(_open_streams):
+        try:
+            st.close()
+        except HpvmError:
+            pass
+
+
+atexit.register(_close_open_streams)
+
+
+class SgemmStream:
+    """A streaming sgemm graph: a resident kernel that runs every pushed sgemm.
+
+    push() hands it C <- alpha A B + beta C (FP32, in place) and returns the
+    item's sequence number; pop() returns (seq, C) of the oldest item once it
+    is complete.  Items in flight run concurrently and must be independent.
+    The tensors of an item are kept alive until it is popped.  While the
+    stream is open, synchronize streams (torch.cuda.current_stream()
+    .synchronize()), not the device: torch.cuda.synchronize() waits for the
+    resident kernel until the stream is closed or reaches its idle limit.
+    """
+
+    def __init__(self, capacity: int = 64, grid: int = 0, idle_ms: int = 2000):
+        cfg = _lib.StreamConfig(int(capacity), int(grid), int(idle_ms), 0)
+        h = ctypes.c_void_p()
+        _check(load().hpvm_stream_open(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._items = {}
+        self._seq = ctypes.c_int64(-1)
+        lib = load()
+        self._push, self._pop = lib.hpvm_stream_push, lib.hpvm_stream_pop
+        _open_streams.add(self)
+
+    @staticmethod
+    def pack(A, B, C, alpha: float = 1.0, beta: float = 0.0, k: int | None = None):
+        """The packed argument struct of one item (validated once; reusable).
+
+        A or B may be None when alpha == 0 or k == 0 (pass k then).  Returns
+        (desc, tensors) for push_packed.
+        """
+        m, n = C.shape
+        if A is not None:
+            k = A.shape[1]
+        elif k is None:
+            raise ValueError("k is needed when A is None")
+        pa, lda = _mat(A, "A") if A is not None else (ctypes.c_void_p(0), max(k, 1))
+        pb, ldb = _mat(B, "B") if B is not None else (ctypes.c_void_p(0), max(n, 1))
+        pc, ldc = _mat(C, "C")
+        if A is not None and tuple(A.shape) != (m, k):
+            raise ValueError("A must be m x k")
+        if B is not None and tuple(B.shape) != (k, n):
+            raise ValueError("B must be k x n")
+        d = _lib.SgemmDesc(m, n, k, float(alpha), float(beta), pa.value, lda, pb.value, ldb, pc.value, ldc)
+        return d, (A, B, C)
+
+    def push_packed(self, packed) -> int:
+        """llvm.hpvm.push of a struct from pack(); returns the sequence number."""
+        desc, tensors = packed
+        rc = self._push(self._h, ctypes.byref(desc), ctypes.byref(self._seq))
+        if rc != 0:
+            raise HpvmError(rc, last_error())
+        self._items[self._seq.value] = tensors
+        return self._seq.value
+
+    def push(self, A, B, C, alpha: float = 1.0, beta: float = 0.0, k: int | None = None) -> int:
+        """Packs and pushes one item: C <- alpha A B + beta C."""
+        return self.push_packed(self.pack(A, B, C, alpha, beta, k))
+
+    @property
+    def in_flight(self) -> int:
+        """Items pushed and not yet popped."""
+        return len(self._items)
+
+    def pop(self, timeout_ms: int = 10000):
+        """llvm.hpvm.pop: (seq, C) of the oldest item, once it is complete."""
+        rc = self._pop(self._h, int(timeout_ms), ctypes.byref(self._seq), None)
+        if rc != 0:
+            raise HpvmError(rc, last_error())
+        _, _, C = self._items.pop(self._seq.value)
+        return self._seq.value, C
+
+    def info(self) -> dict:
+        st = _lib.StreamStatus()
+        _check(load().hpvm_stream_info(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _lib.StreamStatus._fields_ if f != "reserved"}
+
+    def close(self, timeout_ms: int = 30000):
+        if self._h is not None:
+            _check(load().hpvm_stream_close(self._h, int(timeout_ms)))
+            self._h = None
+            self._items.clear()
+            _open_streams.discard(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+

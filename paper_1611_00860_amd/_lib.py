@@ -51,6 +51,15 @@ class SgemmDesc(ctypes.Structure):
                 ("A", vp), ("lda", i64), ("B", vp), ("ldb", i64), ("C", vp), ("ldc", i64)]
 
 
+class StreamConfig(ctypes.Structure):
+    _fields_ = [("capacity", i32), ("grid", i32), ("idle_ms", i32), ("reserved", i32)]
+
+
+class StreamStatus(ctypes.Structure):
+    _fields_ = [("pushed", i64), ("popped", i64), ("tiles", i64), ("capacity", i32), ("grid", i32),
+                ("idle_ms", i32), ("running", i32), ("idle_ended", i32), ("reserved", i32)]
+
+
 class GroupedInfo(ctypes.Structure):
     _fields_ = [("count", i32), ("total_tiles", i32), ("grid", i32), ("shapes_used", i32),
                 ("workspace_bytes", i64), ("scratch_bytes", i64), ("flops", ctypes.c_double)]
@@ -99,6 +108,11 @@ SIGNATURES = {
                                               vp, i64, i32, vp, PTile, ctypes.POINTER(f32)]),
     "hpvm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "hpvm_last_error": (ctypes.c_char_p, []),
+    "hpvm_stream_open": (ctypes.c_int, [ctypes.POINTER(StreamConfig), ctypes.POINTER(vp)]),
+    "hpvm_stream_push": (ctypes.c_int, [vp, ctypes.POINTER(SgemmDesc), ctypes.POINTER(i64)]),
+    "hpvm_stream_pop": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp)]),
+    "hpvm_stream_info": (ctypes.c_int, [vp, ctypes.POINTER(StreamStatus)]),
+    "hpvm_stream_close": (ctypes.c_int, [vp, i32]),
 }
 
 _lib = None

@@ -171,6 +171,9 @@ const char* hpvm_status_string(int status) {
     case HPVM_HIP_ERROR: return "HPVM_HIP_ERROR";
     case HPVM_WORKSPACE_TOO_SMALL: return "HPVM_WORKSPACE_TOO_SMALL";
     case HPVM_BAD_HANDLE: return "HPVM_BAD_HANDLE";
+    case HPVM_QUEUE_FULL: return "HPVM_QUEUE_FULL";
+    case HPVM_TIMEOUT: return "HPVM_TIMEOUT";
+    case HPVM_STREAM_ENDED: return "HPVM_STREAM_ENDED";
     default: return "HPVM_UNKNOWN_STATUS";
   }
 }

@@ -36,10 +36,12 @@ struct GemmArgs {
 
 // True when the TM x TN tile at (m0, n0) and every K-slab of depth TK lie
 // inside the matrices and both operands allow 16-byte loads: the main loop
-// then needs no per-element checks.  Uniform across the workgroup.
+// then needs no per-element checks.  k == 0 (which the persistent kernels
+// pass for alpha == 0) is never interior: the masked loads then read no
+// memory at all, so A and B may be NULL.  Uniform across the workgroup.
 template <int TM, int TN, int TK>
 __device__ __forceinline__ bool interior_tile(const GemmArgs& p, int m0, int n0) {
-  return p.vec_a && p.vec_b && m0 + TM <= p.m && n0 + TN <= p.n && p.k % TK == 0;
+  return p.vec_a && p.vec_b && m0 + TM <= p.m && n0 + TN <= p.n && p.k > 0 && p.k % TK == 0;
 }
 
 // --------------------------------------------------------------------------

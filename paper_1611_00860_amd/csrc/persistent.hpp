@@ -1,0 +1,91 @@
+// Pieces shared by the two persistent lowerings of the sgemm graph: grouped
+// batches (many graphs, one launch) and the streaming graph (argument packs
+// pushed while the kernel runs).
+//
+// Both keep a fixed set of resident workgroups that pull SgemmInternal
+// instances (tiles) from a device-side counter -- the persistent-node form
+// of Sec. 3.5 -- and both let every sgemm carry its own tile shape, chosen
+// from a menu whose shapes share one workgroup size and one LDS size so a
+// single kernel can run any of them.
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+
+#include "device_common.hpp"
+#include "hpvm_sgemm.h"
+#include "mfma_f32.hpp"
+
+namespace hpvm {
+
+struct GroupedShape {
+  hpvm_tile tile;
+  double cost_per_flop;  // relative cost of a useful flop, for the cost model
+};
+
+// The shapes a persistent kernel can run: all use 256 lanes (4 waves).
+static const GroupedShape kGroupedShapes[] = {
+    {{128, 128, 16, 64, 64, 2}, 1.00},
+    {{128, 64, 16, 64, 32, 2}, 1.12},
+    {{64, 128, 16, 32, 64, 2}, 1.12},
+    {{64, 64, 16, 32, 32, 2}, 1.35},
+};
+constexpr int kNumGroupedShapes = 4;
+constexpr int kGroupedThreads = 256;
+constexpr int64_t kGroupedLds = F32Tile<128, 128, 16, 64, 64, false, false>::kLdsBytes;
+static_assert(F32Tile<128, 64, 16, 64, 32, false, false>::kLdsBytes <= kGroupedLds, "LDS");
+static_assert(F32Tile<64, 128, 16, 32, 64, false, false>::kLdsBytes <= kGroupedLds, "LDS");
+static_assert(F32Tile<64, 64, 16, 32, 32, false, false>::kLdsBytes <= kGroupedLds, "LDS");
+
+template <int TM, int TN, int TK, int WM, int WN>
+__device__ __forceinline__ void grouped_tile(const GemmArgs& p, int tm, int tn, float* lds) {
+  static_assert(F32Tile<TM, TN, TK, WM, WN, false, false>::NT == kGroupedThreads, "256 lanes");
+  f32x16 acc[WM / 32][WN / 32];
+  f32_mainloop<TM, TN, TK, WM, WN, false, false>(p, tm * TM, tn * TN, lds, acc);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  store_c<WM / 32, WN / 32>(p, acc, tm * TM + (wave / (TN / WN)) * WM,
+                            tn * TN + (wave % (TN / WN)) * WN, lane);
+}
+
+// Runs tile `local` (row-major over the instance's tile grid) of one sgemm
+// with menu shape `shape`.  Uniform across the workgroup.
+__device__ __forceinline__ void run_shape_tile(int shape, const GemmArgs& p, int tiles_n, int local,
+                                               float* lds) {
+  const int tm = local / tiles_n, tn = local - (local / tiles_n) * tiles_n;
+  switch (shape) {
+    case 0: grouped_tile<128, 128, 16, 64, 64>(p, tm, tn, lds); break;
+    case 1: grouped_tile<128, 64, 16, 64, 32>(p, tm, tn, lds); break;
+    case 2: grouped_tile<64, 128, 16, 32, 64>(p, tm, tn, lds); break;
+    default: grouped_tile<64, 64, 16, 32, 32>(p, tm, tn, lds); break;
+  }
+}
+
+// Host side ---------------------------------------------------------------
+
+inline int64_t shape_tiles(int64_t m, int64_t n, int shape) {
+  if (m == 0 || n == 0) return 0;
+  const hpvm_tile& t = kGroupedShapes[shape].tile;
+  return ((m + t.tile_m - 1) / t.tile_m) * ((n + t.tile_n - 1) / t.tile_n);
+}
+
+// Cost model: padded flops of the tiles an instance needs, weighted by the
+// shape's relative cost per flop raised to `lambda`, plus a fixed per-tile
+// cost (prologue / epilogue) worth 32 steps of k.
+inline int cost_model_shape(int64_t m, int64_t n, int64_t k, double lambda) {
+  int best = 0;
+  double best_cost = 0.0;
+  for (int s = 0; s < kNumGroupedShapes; ++s) {
+    const hpvm_tile& t = kGroupedShapes[s].tile;
+    const double per_tile = (double)t.tile_m * t.tile_n * (double)((k > 0 ? k : 0) + 32);
+    const double cost = (double)shape_tiles(m, n, s) * per_tile * std::pow(kGroupedShapes[s].cost_per_flop, lambda);
+    if (s == 0 || cost < best_cost) {
+      best = s;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+inline bool vec16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
+
+}  // namespace hpvm

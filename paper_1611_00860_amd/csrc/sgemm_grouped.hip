@@ -23,6 +23,7 @@
 #include "hpvm_sgemm.h"
 #include "internal.hpp"
 #include "mfma_f32.hpp"
+#include "persistent.hpp"
 
 namespace hpvm {
 
@@ -39,34 +40,6 @@ struct alignas(16) GroupDesc {
   int32_t tile_start;  // first entry of this instance in the tile list
   int32_t vec_a, vec_b;
 };
-
-// The shapes one persistent kernel can run: all use 256 lanes (4 waves).
-struct GroupedShape {
-  hpvm_tile tile;
-  double cost_per_flop;  // relative cost of a useful flop, for the cost model
-};
-static const GroupedShape kGroupedShapes[] = {
-    {{128, 128, 16, 64, 64, 2}, 1.00},
-    {{128, 64, 16, 64, 32, 2}, 1.12},
-    {{64, 128, 16, 32, 64, 2}, 1.12},
-    {{64, 64, 16, 32, 32, 2}, 1.35},
-};
-constexpr int kNumGroupedShapes = 4;
-constexpr int kGroupedThreads = 256;
-constexpr int64_t kGroupedLds = F32Tile<128, 128, 16, 64, 64, false, false>::kLdsBytes;
-static_assert(F32Tile<128, 64, 16, 64, 32, false, false>::kLdsBytes <= kGroupedLds, "LDS");
-static_assert(F32Tile<64, 128, 16, 32, 64, false, false>::kLdsBytes <= kGroupedLds, "LDS");
-static_assert(F32Tile<64, 64, 16, 32, 32, false, false>::kLdsBytes <= kGroupedLds, "LDS");
-
-template <int TM, int TN, int TK, int WM, int WN>
-__device__ __forceinline__ void grouped_tile(const GemmArgs& p, int tm, int tn, float* lds) {
-  static_assert(F32Tile<TM, TN, TK, WM, WN, false, false>::NT == kGroupedThreads, "256 lanes");
-  f32x16 acc[WM / 32][WN / 32];
-  f32_mainloop<TM, TN, TK, WM, WN, false, false>(p, tm * TM, tn * TN, lds, acc);
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  store_c<WM / 32, WN / 32>(p, acc, tm * TM + (wave / (TN / WN)) * WM,
-                            tn * TN + (wave % (TN / WN)) * WN, lane);
-}
 
 // Persistent kernel.  Every workgroup loops: take the next tile index from
 // the shared counter, find its instance and position, run that tile.  All
@@ -97,14 +70,7 @@ __global__ void __launch_bounds__(kGroupedThreads)
     p.beta = d.beta;
     p.vec_a = d.vec_a;
     p.vec_b = d.vec_b;
-    const int local = t - d.tile_start;
-    const int tm = local / d.tiles_n, tn = local - (local / d.tiles_n) * d.tiles_n;
-    switch (d.shape) {
-      case 0: grouped_tile<128, 128, 16, 64, 64>(p, tm, tn, lds); break;
-      case 1: grouped_tile<128, 64, 16, 64, 32>(p, tm, tn, lds); break;
-      case 2: grouped_tile<64, 128, 16, 32, 64>(p, tm, tn, lds); break;
-      default: grouped_tile<64, 64, 16, 32, 32>(p, tm, tn, lds); break;
-    }
+    run_shape_tile(d.shape, p, d.tiles_n, t - d.tile_start, lds);
   }
 }
 
@@ -161,31 +127,7 @@ Graph* live_graph(const void* h) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int64_t tiles_of(const hpvm_sgemm_desc& d, int shape) {
-  if (d.m == 0 || d.n == 0) return 0;
-  const hpvm_tile& t = kGroupedShapes[shape].tile;
-  return ceil_div(d.m, t.tile_m) * ceil_div(d.n, t.tile_n);
-}
-
-// Cost model: padded flops of the tiles an instance needs, weighted by the
-// shape's relative cost per flop raised to `lambda`, plus a fixed per-tile
-// cost (prologue / epilogue) worth 32 steps of k.
-int cost_model_shape(const hpvm_sgemm_desc& d, double lambda) {
-  int best = 0;
-  double best_cost = 0.0;
-  for (int s = 0; s < kNumGroupedShapes; ++s) {
-    const hpvm_tile& t = kGroupedShapes[s].tile;
-    const double per_tile = (double)t.tile_m * t.tile_n * (double)(std::max<int64_t>(d.k, 0) + 32);
-    const double cost = (double)tiles_of(d, s) * per_tile * std::pow(kGroupedShapes[s].cost_per_flop, lambda);
-    if (s == 0 || cost < best_cost) {
-      best = s;
-      best_cost = cost;
-    }
-  }
-  return best;
-}
-
-bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
+int64_t tiles_of(const hpvm_sgemm_desc& d, int shape) { return shape_tiles(d.m, d.n, shape); }
 
 // Rebuilds the device schedule from plan->user and plan->shape.  With
 // `scratch`, every instance writes to its own slice of scratch (ldc = n,
@@ -229,8 +171,8 @@ void build_schedule(Plan* p, float* scratch) {
     d.shape = p->shape[i];
     d.tiles_n = (int32_t)ceil_div(u.n, kGroupedShapes[d.shape].tile.tile_n);
     d.tile_start = (int32_t)p->tile_inst.size();
-    d.vec_a = aligned16(u.A, u.lda);
-    d.vec_b = aligned16(u.B, u.ldb);
+    d.vec_a = vec16(u.A, u.lda);
+    d.vec_b = vec16(u.B, u.ldb);
     const int32_t idx = (int32_t)p->dev.size();
     p->dev.push_back(d);
     p->tile_inst.insert(p->tile_inst.end(), (size_t)tiles, idx);
@@ -406,7 +348,8 @@ int hpvm_grouped_plan_create(int32_t count, const hpvm_sgemm_desc* descs, int32_
   if (!p) return set_error(HPVM_INVALID_ARG, "out of host memory");
   p->user.assign(descs, descs + count);
   p->shape.resize(count);
-  for (int32_t i = 0; i < count; ++i) p->shape[i] = fixed >= 0 ? fixed : cost_model_shape(descs[i], 1.0);
+  for (int32_t i = 0; i < count; ++i)
+    p->shape[i] = fixed >= 0 ? fixed : cost_model_shape(descs[i].m, descs[i].n, descs[i].k, 1.0);
   build_schedule(p, nullptr);
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -582,7 +525,7 @@ int hpvm_grouped_autotune(void* plan, void* workspace, int64_t workspace_bytes_,
   for (int sh = 0; sh < kNumGroupedShapes; ++sh) cands.emplace_back(p->user.size(), sh);
   for (double lambda : {0.0, 0.5, 1.0, 2.0, 4.0}) {
     std::vector<int> c(p->user.size());
-    for (size_t i = 0; i < p->user.size(); ++i) c[i] = cost_model_shape(p->user[i], lambda);
+    for (size_t i = 0; i < p->user.size(); ++i) c[i] = cost_model_shape(p->user[i].m, p->user[i].n, p->user[i].k, lambda);
     cands.push_back(c);
   }
   const std::vector<int> original = p->shape;

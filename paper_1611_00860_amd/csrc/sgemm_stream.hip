@@ -1,0 +1,557 @@
+// Streaming sgemm graph: llvm.hpvm.launch with Stream = 1, then push / pop
+// (HPVM report, Table 1 and Sec. 2.3 for the intrinsics, Sec. 3.5 for the
+// persistent nodes a streaming graph needs).
+//
+// A streaming graph stays alive after its launch: every argument pack pushed
+// into it is one more sgemm for its nodes to process, and pop returns the
+// outputs in push order.  On the GPU the persistent node is one resident
+// kernel.  Argument packs go into a ring of slots in pinned, coherent host
+// memory; the host publishes each with a release store of the ring's tail.
+// The resident workgroups take tickets from a device counter; the tiles of
+// item i are tickets [first_i, end_i), handed out in push order, so each
+// workgroup walks the ring forward until it finds the item holding its
+// ticket and runs that tile.  The workgroup that finishes an item's last
+// tile raises the item's completion flag in host memory, which pop waits on.
+//
+// Every wait in the kernel is bounded: a workgroup with nothing to do leaves
+// when the host has closed the stream, when another workgroup has ended it,
+// or when it has been idle for the configured limit (it then ends the stream
+// for all).  The host side never waits without a time limit either.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <thread>
+#include <unordered_set>
+#include <vector>
+
+#include "device_common.hpp"
+#include "hpvm_sgemm.h"
+#include "internal.hpp"
+#include "mfma_f32.hpp"
+#include "persistent.hpp"
+
+namespace hpvm {
+
+constexpr uint64_t kSlotWriting = ~0ull;  // slot being rewritten by the host
+
+// One argument pack as the kernel reads it (host memory).
+struct alignas(128) StreamSlot {
+  uint64_t seq;    // sequence number of the item held; kSlotWriting while rewritten
+  uint64_t first;  // first ticket of the item
+  uint64_t end;    // one past its last ticket
+  const float* A;
+  const float* B;
+  float* C;
+  int64_t lda, ldb, ldc;
+  int32_t m, n, k;
+  float alpha, beta;
+  int32_t shape, tiles_n, vec_a, vec_b;
+};
+
+// Control words (host memory).  done[] follows the struct.
+struct alignas(128) StreamCtl {
+  uint64_t tail;    // items pushed (host writes, kernel reads)
+  uint32_t closed;  // host: no more pushes; drain and leave
+  uint32_t status;  // kernel: 0 running, else why it ended the stream
+};
+constexpr uint32_t kStreamIdle = 2;      // nothing pushed for the idle limit
+constexpr uint32_t kStreamIncoherent = 3;  // a slot kept showing an older item
+constexpr int kMaxStaleReads = 1 << 20;
+
+__device__ __forceinline__ uint64_t ld_acquire(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t ld_acquire32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// What thread 0 tells the workgroup after a ticket lookup.
+struct StreamTask {
+  GemmArgs p;
+  int32_t exit;
+  int32_t slot;
+  int32_t local;  // tile index inside the item
+  int32_t shape, tiles_n;
+  uint32_t tiles;
+  uint64_t seq;
+};
+
+// Thread 0: find the item that holds ticket t, starting from item *cur.
+// Returns false when the workgroup must leave.
+// The idle clock restarts whenever the tail moves: a workgroup whose ticket
+// lies far ahead of the pushed items is waiting, but the stream is not idle.
+__device__ bool stream_find(StreamCtl* ctl, const StreamSlot* slots, int cap, uint64_t t, uint64_t* cur,
+                            uint64_t idle_ticks, StreamTask* task) {
+  uint64_t last_tail = ld_acquire(&ctl->tail);
+  uint64_t since = wall_clock64();
+  int backoff = 1, stale = 0;
+  for (;;) {
+    const uint64_t tail = ld_acquire(&ctl->tail);
+    if (tail != last_tail) {
+      last_tail = tail;
+      since = wall_clock64();
+      backoff = 1;
+    }
+    if (wall_clock64() - since > idle_ticks) {
+      __hip_atomic_store(&ctl->status, kStreamIdle, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      return false;
+    }
+    if (*cur < tail) {
+      const int s = (int)(*cur % (uint64_t)cap);
+      const StreamSlot* q = slots + s;
+      const uint64_t s1 = ld_acquire(&q->seq);
+      const volatile StreamSlot* vq = q;
+      const uint64_t first = vq->first, end = vq->end;
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      const uint64_t s2 = ld_acquire(&q->seq);
+      if (s1 != *cur || s2 != *cur) {
+        // The slot already holds a later item (or is being rewritten for
+        // one): item *cur is complete, so it cannot hold ticket t.
+        if (s1 > *cur && s2 > *cur) {
+          ++*cur;
+          continue;
+        }
+        // An older item: the tail's release should make that impossible.
+        if (++stale > kMaxStaleReads) {
+          __hip_atomic_store(&ctl->status, kStreamIncoherent, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+          return false;
+        }
+        continue;
+      }
+      if (t >= end) {
+        ++*cur;
+        continue;
+      }
+      // t is in [first, end): item *cur stays in its slot until this tile is done.
+      GemmArgs& p = task->p;
+      p.A = vq->A;
+      p.B = vq->B;
+      p.C = vq->C;
+      p.lda = vq->lda;
+      p.ldb = vq->ldb;
+      p.ldc = vq->ldc;
+      p.m = vq->m;
+      p.n = vq->n;
+      p.k = vq->k;
+      p.alpha = vq->alpha;
+      p.beta = vq->beta;
+      p.vec_a = vq->vec_a;
+      p.vec_b = vq->vec_b;
+      p.tiles_m = 0;
+      p.tiles_n = 0;
+      task->shape = vq->shape;
+      task->tiles_n = vq->tiles_n;
+      task->exit = 0;
+      task->slot = s;
+      task->local = (int32_t)(t - first);
+      task->tiles = (uint32_t)(end - first);
+      task->seq = *cur;
+      return true;
+    }
+    // Nothing pushed for this ticket yet.
+    if (ld_acquire32(&ctl->closed)) {
+      // Pushes that came before the close are visible now.
+      if (*cur < ld_acquire(&ctl->tail)) continue;
+      return false;
+    }
+    if (ld_acquire32(&ctl->status) != 0) return false;
+    for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(127);
+    backoff = backoff < 8 ? 2 * backoff : 8;
+  }
+}
+
+// Workgroup-uniform copies (scalar registers) of values thread 0 put in LDS.
+__device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uni(T* x) { return (T*)uni((int64_t)x); }
+
+__global__ void __launch_bounds__(kGroupedThreads)
+    sgemm_stream_f32(StreamCtl* ctl, const StreamSlot* slots, uint64_t* done, int32_t cap,
+                     unsigned long long* ticket, uint32_t* pending, uint64_t idle_ticks) {
+  extern __shared__ __align__(16) float lds[];
+  __shared__ StreamTask task;
+  uint64_t cur = 0;  // meaningful in thread 0 only
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint64_t t = atomicAdd(ticket, 1ull);
+      if (!stream_find(ctl, slots, cap, t, &cur, idle_ticks, &task)) task.exit = 1;
+    }
+    __syncthreads();
+    if (task.exit) break;
+    GemmArgs p;
+    p.A = uni(task.p.A);
+    p.B = uni(task.p.B);
+    p.C = uni(task.p.C);
+    p.lda = uni(task.p.lda);
+    p.ldb = uni(task.p.ldb);
+    p.ldc = uni(task.p.ldc);
+    p.m = uni(task.p.m);
+    p.n = uni(task.p.n);
+    p.k = uni(task.p.k);
+    p.alpha = uni(task.p.alpha);
+    p.beta = uni(task.p.beta);
+    p.vec_a = uni(task.p.vec_a);
+    p.vec_b = uni(task.p.vec_b);
+    p.tiles_m = 0;
+    p.tiles_n = 0;
+    run_shape_tile(uni(task.shape), p, uni(task.tiles_n), uni(task.local), lds);
+    __threadfence();  // this lane's C stores, visible device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t old = atomicAdd(pending + task.slot, 1u);
+      if (old + 1 == task.tiles) {
+        __threadfence();
+        atomicExch(pending + task.slot, 0u);  // ready for the slot's next item
+        __hip_atomic_store(done + task.slot, task.seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+namespace {
+
+constexpr uint64_t kStreamMagic = 0x48505653474d4d53ull;  // "HPVSGMMS"
+constexpr int kMaxCapacity = 4096;
+constexpr int kMaxIdleMs = 60000;
+
+struct Stream {
+  uint64_t magic = kStreamMagic;
+  std::mutex mu;
+  int32_t capacity = 0, grid = 0, idle_ms = 0;
+  // host memory shared with the kernel
+  char* host = nullptr;
+  int64_t host_size = 0;
+  StreamCtl* ctl = nullptr;
+  StreamSlot* slots = nullptr;
+  uint64_t* done = nullptr;
+  // device counters
+  void* dev = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t finished = nullptr;
+  // host bookkeeping
+  uint64_t pushed = 0, popped = 0, next_ticket = 0;
+  int64_t tiles = 0;
+  bool ended = false;     // the kernel has exited
+  hipError_t exit_error = hipSuccess;
+};
+
+std::mutex g_mu;
+std::unordered_set<const void*> g_streams;
+bool g_atexit = false;
+// Pinned host blocks of closed streams, kept for reuse: freeing pinned
+// memory can wait for the whole device, including other streams' kernels.
+std::vector<std::pair<int64_t, char*>> g_host_pool;
+
+char* pool_take(int64_t bytes, int64_t* size) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (size_t i = 0; i < g_host_pool.size(); ++i)
+    if (g_host_pool[i].first >= bytes) {
+      char* p = g_host_pool[i].second;
+      *size = g_host_pool[i].first;
+      g_host_pool.erase(g_host_pool.begin() + (long)i);
+      return p;
+    }
+  return nullptr;
+}
+
+void pool_give(int64_t bytes, char* p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_host_pool.push_back({bytes, p});
+}
+
+Stream* live_stream(const void* h) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!h || !g_streams.count(h)) return nullptr;
+  Stream* s = (Stream*)h;
+  return s->magic == kStreamMagic ? s : nullptr;
+}
+
+void host_store(uint64_t* p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELEASE); }
+uint64_t host_load(const uint64_t* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+uint32_t host_load32(const uint32_t* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+
+// Non-blocking check whether the kernel has exited.
+bool kernel_exited(Stream* s) {
+  if (s->ended) return true;
+  hipError_t e = hipEventQuery(s->finished);
+  if (e == hipErrorNotReady) return false;
+  s->ended = true;
+  s->exit_error = e;
+  return true;
+}
+
+// Frees a stream whose kernel has exited (or never started).  Device memory
+// is stream-ordered, so nothing here waits for other streams' kernels.
+void release(Stream* s) {
+  if (s->dev) (void)hipFreeAsync(s->dev, s->stream);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->finished) (void)hipEventDestroy(s->finished);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->host) pool_give(s->host_size, s->host);
+  s->magic = 0;
+  delete s;
+}
+
+int64_t host_bytes(int cap) {
+  return (int64_t)sizeof(StreamCtl) + (int64_t)cap * (int64_t)sizeof(StreamSlot) +
+         ((int64_t)cap * 8 + 127) / 128 * 128;
+}
+
+// Waits (bounded) for the kernel to exit after `closed` is set.
+bool wait_exit(Stream* s, int32_t timeout_ms) {
+  const auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+  while (!kernel_exited(s)) {
+    if (std::chrono::steady_clock::now() >= until) return false;
+    std::this_thread::sleep_for(std::chrono::microseconds(200));
+  }
+  return true;
+}
+
+// At process exit: tell every live stream's kernel to leave and give it a
+// bounded time to do so, so no workgroup still reads host memory that the
+// process is about to release.
+void close_all_at_exit() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (const void* h : g_streams) {
+    Stream* s = (Stream*)h;
+    __atomic_store_n(&s->ctl->closed, 1u, __ATOMIC_RELEASE);
+    (void)wait_exit(s, s->idle_ms + 1000);
+  }
+}
+
+bool overlaps(const void* a, int64_t ra, int64_t ca, int64_t lda, const void* b, int64_t rb, int64_t cb,
+              int64_t ldb) {
+  if (!a || !b || ra == 0 || ca == 0 || rb == 0 || cb == 0) return false;
+  uintptr_t a0, a1, b0, b1;
+  matrix_extent((const float*)a, ra, ca, lda, &a0, &a1);
+  matrix_extent((const float*)b, rb, cb, ldb, &b0, &b1);
+  return a0 < b1 && b0 < a1;
+}
+
+}  // namespace
+}  // namespace hpvm
+
+using namespace hpvm;
+
+extern "C" {
+
+int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
+  if (!cfg) return set_error(HPVM_INVALID_ARG, "argument 1: config is NULL");
+  if (cfg->capacity < 1 || cfg->capacity > kMaxCapacity)
+    return set_error(HPVM_INVALID_ARG, "argument 1: capacity = %d not in [1, %d]", cfg->capacity, kMaxCapacity);
+  if (cfg->grid < 0 || cfg->grid > 65536)
+    return set_error(HPVM_INVALID_ARG, "argument 1: grid = %d not in [0, 65536]", cfg->grid);
+  if (cfg->idle_ms < 1 || cfg->idle_ms > kMaxIdleMs)
+    return set_error(HPVM_INVALID_ARG, "argument 1: idle_ms = %d not in [1, %d]", cfg->idle_ms, kMaxIdleMs);
+  if (!handle) return set_error(HPVM_INVALID_ARG, "argument 2: handle is NULL");
+  *handle = nullptr;
+  if (fault_injected("launch")) return set_error(HPVM_HIP_ERROR, "injected launch failure (HPVM_FAULT_INJECT)");
+
+  Stream* s = new (std::nothrow) Stream();
+  if (!s) return set_error(HPVM_INVALID_ARG, "out of host memory");
+  s->capacity = cfg->capacity;
+  s->idle_ms = cfg->idle_ms;
+  int dev = 0, cus = 0, rate_khz = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+  if (e == hipSuccess && rate_khz <= 0) e = hipErrorInvalidValue;
+  s->grid = cfg->grid > 0 ? cfg->grid : std::max(cus, 1);
+  const int64_t hb = host_bytes(s->capacity);
+  if (e == hipSuccess) {
+    s->host = pool_take(hb, &s->host_size);  // a block of at least hb bytes
+    if (!s->host) {
+      e = hipHostMalloc((void**)&s->host, (size_t)hb, hipHostMallocCoherent | hipHostMallocMapped);
+      if (e == hipSuccess) s->host_size = hb;
+      else s->host = nullptr;
+    }
+  }
+  if (e == hipSuccess) {
+    std::memset(s->host, 0, (size_t)hb);
+    s->ctl = (StreamCtl*)s->host;
+    s->slots = (StreamSlot*)(s->host + sizeof(StreamCtl));
+    s->done = (uint64_t*)(s->host + sizeof(StreamCtl) + (size_t)s->capacity * sizeof(StreamSlot));
+    for (int i = 0; i < s->capacity; ++i) s->slots[i].seq = kSlotWriting;
+  }
+  const size_t db = 256 + (size_t)s->capacity * 4;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->finished, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMallocAsync(&s->dev, db, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->dev, 0, db, s->stream);  // ordered before the kernel
+  StreamCtl* dctl = nullptr;
+  StreamSlot* dslots = nullptr;
+  uint64_t* ddone = nullptr;
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&dctl, s->ctl, 0);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&dslots, s->slots, 0);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&ddone, s->done, 0);
+  if (e == hipSuccess) {
+    unsigned long long* ticket = (unsigned long long*)s->dev;
+    uint32_t* pending = (uint32_t*)((char*)s->dev + 256);
+    int32_t cap = s->capacity;
+    uint64_t idle_ticks = (uint64_t)s->idle_ms * (uint64_t)rate_khz;
+    void* kargs[] = {&dctl, &dslots, &ddone, &cap, &ticket, &pending, &idle_ticks};
+    e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_stream_f32), dim3(s->grid), dim3(kGroupedThreads),
+                        kargs, (size_t)kGroupedLds, s->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(s->finished, s->stream);
+  if (e != hipSuccess) {
+    // A launched kernel must not outlive its host memory: close it first.
+    if (s->ctl) __atomic_store_n(&s->ctl->closed, 1u, __ATOMIC_RELEASE);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    release(s);
+    return hip_error(e, "stream open");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_streams.insert(s);
+    if (!g_atexit) {
+      std::atexit(close_all_at_exit);
+      g_atexit = true;
+    }
+  }
+  *handle = s;
+  return clear_error();
+}
+
+int hpvm_stream_push(void* handle, const hpvm_sgemm_desc* item, int64_t* seq) {
+  Stream* s = live_stream(handle);
+  if (!s) return set_error(HPVM_BAD_HANDLE, "argument 1: unknown or closed stream");
+  if (!item) return set_error(HPVM_INVALID_ARG, "argument 2: item is NULL");
+  const hpvm_sgemm_desc& d = *item;
+  bool reads_ab;
+  int rc = check_gemm_args("item: ", d.m, d.n, d.k, d.alpha, d.A, d.lda, d.B, d.ldb, d.beta, d.C, d.ldc, &reads_ab);
+  if (rc != HPVM_OK) return rc;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (host_load32(&s->ctl->status) != 0 || kernel_exited(s))
+    return set_error(HPVM_STREAM_ENDED, "argument 1: the streaming kernel has ended (idle limit or error)");
+  if (s->pushed - s->popped >= (uint64_t)s->capacity)
+    return set_error(HPVM_QUEUE_FULL, "argument 1: all %d slots hold items not yet popped", s->capacity);
+  // Items in flight run concurrently: the new one may not write what another
+  // one reads or writes, nor read what another one writes.
+  if (d.m > 0 && d.n > 0) {
+    for (uint64_t q = s->popped; q < s->pushed; ++q) {
+      const StreamSlot& o = s->slots[q % (uint64_t)s->capacity];
+      if (o.m == 0 || o.n == 0) continue;
+      const bool o_reads = o.k > 0 && o.alpha != 0.0f;
+      bool clash = overlaps(d.C, d.m, d.n, d.ldc, o.C, o.m, o.n, o.ldc);
+      if (o_reads) clash = clash || overlaps(d.C, d.m, d.n, d.ldc, o.A, o.m, o.k, o.lda) ||
+                           overlaps(d.C, d.m, d.n, d.ldc, o.B, o.k, o.n, o.ldb);
+      if (reads_ab) clash = clash || overlaps(d.A, d.m, d.k, d.lda, o.C, o.m, o.n, o.ldc) ||
+                            overlaps(d.B, d.k, d.n, d.ldb, o.C, o.m, o.n, o.ldc);
+      if (clash)
+        return set_error(HPVM_INVALID_ARG, "argument 2: item overlaps in-flight item %llu; pop it first",
+                         (unsigned long long)q);
+    }
+  }
+  const uint64_t sq = s->pushed;
+  const int slot = (int)(sq % (uint64_t)s->capacity);
+  StreamSlot* q = s->slots + slot;
+  const int shape = cost_model_shape(d.m, d.n, reads_ab ? d.k : 0, 1.0);
+  const uint64_t tiles = (uint64_t)shape_tiles(d.m, d.n, shape);
+  host_store(&q->seq, kSlotWriting);
+  q->first = s->next_ticket;
+  q->end = s->next_ticket + tiles;
+  q->A = d.A;
+  q->B = d.B;
+  q->C = d.C;
+  q->lda = d.lda;
+  q->ldb = d.ldb;
+  q->ldc = d.ldc;
+  q->m = (int32_t)d.m;
+  q->n = (int32_t)d.n;
+  q->k = reads_ab ? (int32_t)d.k : 0;  // alpha == 0 or k == 0: C <- beta C, A and B unread
+  q->alpha = d.alpha;
+  q->beta = d.beta;
+  q->shape = shape;
+  q->tiles_n = (int32_t)((d.n + kGroupedShapes[shape].tile.tile_n - 1) / kGroupedShapes[shape].tile.tile_n);
+  q->vec_a = vec16(d.A, d.lda);
+  q->vec_b = vec16(d.B, d.ldb);
+  host_store(&q->seq, sq);
+  if (tiles == 0) host_store(s->done + slot, sq + 1);  // nothing for the kernel to do
+  s->next_ticket += tiles;
+  s->tiles += (int64_t)tiles;
+  s->pushed = sq + 1;
+  host_store(&s->ctl->tail, s->pushed);
+  if (seq) *seq = (int64_t)sq;
+  return clear_error();
+}
+
+int hpvm_stream_pop(void* handle, int32_t timeout_ms, int64_t* seq, float** C) {
+  Stream* s = live_stream(handle);
+  if (!s) return set_error(HPVM_BAD_HANDLE, "argument 1: unknown or closed stream");
+  if (timeout_ms < 0) return set_error(HPVM_INVALID_ARG, "argument 2: timeout_ms = %d < 0", timeout_ms);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->popped == s->pushed) return set_error(HPVM_INVALID_ARG, "argument 1: no item in flight to pop");
+  const uint64_t sq = s->popped;
+  const int slot = (int)(sq % (uint64_t)s->capacity);
+  const auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+  int spins = 0;
+  while (host_load(s->done + slot) != sq + 1) {
+    if (host_load32(&s->ctl->status) != 0 || kernel_exited(s)) {
+      if (host_load(s->done + slot) == sq + 1) break;
+      if (s->exit_error != hipSuccess) return hip_error(s->exit_error, "streaming kernel");
+      return set_error(HPVM_STREAM_ENDED, "the streaming kernel ended before item %llu completed",
+                       (unsigned long long)sq);
+    }
+    if (std::chrono::steady_clock::now() >= until)
+      return set_error(HPVM_TIMEOUT, "item %llu not complete after %d ms", (unsigned long long)sq, timeout_ms);
+    if (++spins > 64) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  if (seq) *seq = (int64_t)sq;
+  if (C) *C = s->slots[slot].C;
+  s->popped = sq + 1;
+  return clear_error();
+}
+
+int hpvm_stream_info(const void* handle, hpvm_stream_status* info) {
+  Stream* s = live_stream(handle);
+  if (!s) return set_error(HPVM_BAD_HANDLE, "argument 1: unknown or closed stream");
+  if (!info) return set_error(HPVM_INVALID_ARG, "argument 2: info is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  info->pushed = (int64_t)s->pushed;
+  info->popped = (int64_t)s->popped;
+  info->tiles = s->tiles;
+  info->capacity = s->capacity;
+  info->grid = s->grid;
+  info->idle_ms = s->idle_ms;
+  info->running = kernel_exited(s) ? 0 : 1;
+  info->idle_ended = host_load32(&s->ctl->status) == kStreamIdle ? 1 : 0;
+  return clear_error();
+}
+
+int hpvm_stream_close(void* handle, int32_t timeout_ms) {
+  Stream* s = live_stream(handle);
+  if (!s) return set_error(HPVM_BAD_HANDLE, "argument 1: unknown or closed stream");
+  if (timeout_ms < 0) return set_error(HPVM_INVALID_ARG, "argument 2: timeout_ms = %d < 0", timeout_ms);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    __atomic_store_n(&s->ctl->closed, 1u, __ATOMIC_RELEASE);
+    if (!wait_exit(s, timeout_ms))
+      return set_error(HPVM_TIMEOUT, "the streaming kernel is still draining after %d ms; close again",
+                       timeout_ms);
+  }
+  const hipError_t e = hipStreamSynchronize(s->stream);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_streams.erase(s);
+  }
+  const hipError_t ke = s->exit_error;
+  release(s);
+  if (ke != hipSuccess) return hip_error(ke, "streaming kernel");
+  if (e != hipSuccess) return hip_error(e, "stream close");
+  return clear_error();
+}
+
+}  // extern "C"

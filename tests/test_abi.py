@@ -168,7 +168,8 @@ def test_fault_injection_reports_hip_error(lib, monkeypatch):
 
 def test_status_strings(lib):
     for code, name in [(0, "HPVM_OK"), (-1, "HPVM_INVALID_ARG"), (-2, "HPVM_UNSUPPORTED"),
-                       (-3, "HPVM_HIP_ERROR"), (-4, "HPVM_WORKSPACE_TOO_SMALL"), (-5, "HPVM_BAD_HANDLE")]:
+                       (-3, "HPVM_HIP_ERROR"), (-4, "HPVM_WORKSPACE_TOO_SMALL"), (-5, "HPVM_BAD_HANDLE"),
+                       (-6, "HPVM_QUEUE_FULL"), (-7, "HPVM_TIMEOUT"), (-8, "HPVM_STREAM_ENDED")]:
         assert hp.status_string(code) == name
 
 
@@ -393,3 +394,38 @@ def test_staged_workspace_rules(lib):
         finally:
             del os.environ["HPVM_FAULT_INJECT"]
     assert all(t[5] != 3 for t in hp.tile_menu("fp32"))
+
+
+def test_stream_validation(lib, monkeypatch):
+    """Config checks run before any HIP call; unknown handles are refused."""
+    h = ctypes.c_void_p()
+
+    def open_(cap=8, grid=0, idle=100, handle=True):
+        cfg = _lib.StreamConfig(cap, grid, idle, 0)
+        return lib.hpvm_stream_open(ctypes.byref(cfg), ctypes.byref(h) if handle else None)
+
+    assert lib.hpvm_stream_open(None, ctypes.byref(h)) == -1
+    assert open_(cap=0) == -1 and "capacity" in hp.last_error()
+    assert open_(cap=4097) == -1
+    assert open_(grid=-1) == -1 and "grid" in hp.last_error()
+    assert open_(idle=0) == -1 and "idle_ms" in hp.last_error()
+    assert open_(idle=60001) == -1
+    assert open_(handle=False) == -1 and "argument 2" in hp.last_error()
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    assert open_() == -3 and "injected" in hp.last_error()
+    monkeypatch.delenv("HPVM_FAULT_INJECT")
+    bogus = ctypes.c_void_p(FAKE)
+    d = _lib.SgemmDesc(4, 4, 4, 1.0, 0.0, FAKE, 4, FAKE + 4096, 4, FAKE + 8192, 4)
+    assert lib.hpvm_stream_push(bogus, ctypes.byref(d), None) == -5
+    assert lib.hpvm_stream_push(None, ctypes.byref(d), None) == -5
+    seq = ctypes.c_int64()
+    assert lib.hpvm_stream_pop(bogus, 0, ctypes.byref(seq), None) == -5
+    st = _lib.StreamStatus()
+    assert lib.hpvm_stream_info(bogus, ctypes.byref(st)) == -5
+    assert lib.hpvm_stream_close(bogus, 0) == -5
+
+
+def test_stream_status_layout():
+    assert ctypes.sizeof(_lib.StreamConfig) == 16
+    assert ctypes.sizeof(_lib.StreamStatus) == 48
+
