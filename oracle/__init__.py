@@ -12,6 +12,9 @@ Functions (each follows the definition stated in ``sgemm_oracle.c``):
 * ``sgemm_grad``     -- closed-form gradient of <G, C_out>.
 * ``grad_entries``   -- selected elements of dA or dB.
 * ``bf16_round`` / ``bf16_split`` -- the oracle's own RNE bfloat16 rounder.
+* ``consumer``       -- a one-to-one element-wise node after the sgemm node
+  (the dependent pair that node fusion merges): relu, bias, bias+relu, clamp.
+* ``sgemm_consumed`` -- consumer(sgemm(...)): what the fused node computes.
 
 Mode names: ``"fp32"`` (inputs as given), ``"bf16"`` (A, B rounded to
 bfloat16 first), ``"bf16x3"`` (hi*hi + hi*lo + lo*hi of the bfloat16 split).
@@ -59,6 +62,8 @@ def _load():
     lib.oracle_grad_entries.argtypes = [ctypes.c_int, _i64, _i64, _i64, _dbl, _ptr,
                                         _i64, _ptr, _i64, _ptr, _i64, _i64, _ptr,
                                         _ptr, _ptr]
+    lib.oracle_consumer.restype = ctypes.c_int
+    lib.oracle_consumer.argtypes = [_i64, _i64, _ptr, ctypes.c_int, _ptr, _dbl, _dbl, _ptr]
     _lib = lib
     return lib
 
@@ -197,3 +202,34 @@ def bf16_split(x):
     lo = np.empty_like(x)
     lib.oracle_bf16_split_array(_p(x), _p(hi), _p(lo), x.size)
     return hi, lo
+
+
+CONSUMER_OPS = {"none": 0, "relu": 1, "bias": 2, "bias_relu": 3, "clamp": 4}
+
+
+def consumer(X, op, bias=None, lo=-np.inf, hi=np.inf):
+    """The consumer node's function applied to an m x n FP64 array (FP64 out).
+
+    ``bias`` (one float32 per column) is used by "bias" and "bias_relu";
+    ``lo`` and ``hi`` by "clamp".
+    """
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    m, n = X.shape
+    code = CONSUMER_OPS[op] if isinstance(op, str) else int(op)
+    b = np.ascontiguousarray(bias if bias is not None else np.zeros(n), dtype=np.float32)
+    if b.shape != (n,):
+        raise ValueError("bias must hold one value per column")
+    D = np.empty_like(X)
+    if X.size == 0:
+        return D
+    rc = lib.oracle_consumer(m, n, _p(X), code, _p(b), float(lo), float(hi), _p(D))
+    if rc != 0:
+        raise ValueError(f"unknown consumer op {op!r}")
+    return D
+
+
+def sgemm_consumed(A, B, C, alpha, beta, op, bias=None, lo=-np.inf, hi=np.inf):
+    """consumer(alpha A B + beta C): the dependent pair, evaluated one node after the other."""
+    return consumer(sgemm(A, B, C, alpha, beta), op, bias, lo, hi)
+

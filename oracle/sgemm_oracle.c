@@ -430,3 +430,39 @@ int oracle_grad_entries(int which, int64_t m, int64_t n, int64_t k,
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* A one-to-one consumer node after the sgemm node: the pair the           */
+/* MergeDependentNodes primitive of Sec. 4.1 fuses into one node.  Every   */
+/* consumer instance reads the element its producer instance wrote and     */
+/* writes one element (a 1-1 edge).  The paper gives no consumer for sgemm; */
+/* these are the element-wise functions the fused entry point offers, each  */
+/* written from its definition, in FP64:                                    */
+/*   0 identity    d = v                                                    */
+/*   1 relu        d = v when v > 0, else 0 (so NaN gives 0)                */
+/*   2 bias        d = v + bias[j]   (bias: one FP32 value per column)      */
+/*   3 bias, relu  d = relu(v + bias[j])                                    */
+/*   4 clamp       d = lo when v < lo, hi when v > hi, else v (NaN stays)   */
+/* X and D are m x n, row-major, leading dimension n.  Returns -1 for an    */
+/* unknown op.                                                              */
+/* ------------------------------------------------------------------------ */
+static double relu64(double v) { return v > 0.0 ? v : 0.0; }
+
+int oracle_consumer(int64_t m, int64_t n, const double* X, int op, const float* bias,
+                    double lo, double hi, double* D) {
+  if (op < 0 || op > 4) return -1;
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const double v = X[i * n + j];
+      double d;
+      switch (op) {
+        case 1: d = relu64(v); break;
+        case 2: d = v + (double)bias[j]; break;
+        case 3: d = relu64(v + (double)bias[j]); break;
+        case 4: d = v < lo ? lo : (v > hi ? hi : v); break;
+        default: d = v; break;
+      }
+      D[i * n + j] = d;
+    }
+  return 0;
+}

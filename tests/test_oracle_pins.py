@@ -330,3 +330,53 @@ def test_gradient_identities():
     cols = np.array([8, 0, 3])
     np.testing.assert_allclose(oracle.grad_entries("dB", A, B, G, alpha, rows, cols),
                                g["dB"][rows, cols], rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# The one-to-one consumer node (the dependent pair that node fusion merges).
+# ---------------------------------------------------------------------------
+def test_consumer_worked_example():
+    """Worked by hand from each function's definition."""
+    X = np.array([[-2.5, 0.0, 3.25], [0.5, -0.0, 7.0]])
+    bias = np.array([1.0, -1.0, 0.5], dtype=np.float32)
+    expect = {
+        "none": [[-2.5, 0.0, 3.25], [0.5, -0.0, 7.0]],
+        "relu": [[0.0, 0.0, 3.25], [0.5, 0.0, 7.0]],         # v > 0 ? v : 0
+        "bias": [[-1.5, -1.0, 3.75], [1.5, -1.0, 7.5]],      # v + bias[column]
+        "bias_relu": [[0.0, 0.0, 3.75], [1.5, 0.0, 7.5]],
+        "clamp": [[-1.0, 0.0, 2.0], [0.5, -0.0, 2.0]],       # into [-1, 2]
+    }
+    for op, want in expect.items():
+        got = oracle.consumer(X, op, bias=bias, lo=-1.0, hi=2.0)
+        assert got.tolist() == want, op
+
+
+def test_consumer_invariants():
+    rng = np.random.default_rng(11)
+    X = rng.uniform(-4, 4, (37, 29))
+    X[0, :5] = [0.0, -0.0, np.inf, -np.inf, 1e-300]
+    bias = (rng.integers(-64, 64, 29) / 8.0).astype(np.float32)
+    relu = oracle.consumer(X, "relu")
+    # relu(x) - relu(-x) == x exactly, relu >= 0, and it never mixes columns
+    assert np.array_equal(relu - oracle.consumer(-X, "relu"), X + 0.0)
+    assert np.all(relu >= 0)
+    # clamp into [0, inf) is relu; clamp into (-inf, inf) is the identity
+    assert np.array_equal(oracle.consumer(X, "clamp", lo=0.0, hi=np.inf), relu)
+    assert np.array_equal(oracle.consumer(X, "clamp"), X)
+    c = oracle.consumer(X, "clamp", lo=-1.0, hi=0.5)
+    assert c.min() == -1.0 and c.max() == 0.5
+    inside = (X >= -1.0) & (X <= 0.5)
+    assert np.array_equal(c[inside], X[inside])
+    # bias adds column j's value to column j (dyadic: exact), bias+relu composes
+    D = rng.integers(-1000, 1000, (37, 29)) / 64.0
+    assert np.array_equal(oracle.consumer(D, "bias", bias=bias) - D, np.broadcast_to(bias, D.shape))
+    assert np.array_equal(oracle.consumer(X, "bias_relu", bias=bias),
+                          oracle.consumer(oracle.consumer(X, "bias", bias=bias), "relu"))
+    assert np.array_equal(oracle.consumer(X, "bias", bias=np.zeros(29, np.float32)), X)
+    # NaN: relu gives 0, bias and clamp keep it
+    N = np.array([[np.nan, 1.0]])
+    assert oracle.consumer(N, "relu")[0, 0] == 0.0
+    assert np.isnan(oracle.consumer(N, "bias", bias=np.ones(2, np.float32))[0, 0])
+    assert np.isnan(oracle.consumer(N, "clamp", lo=-1.0, hi=1.0)[0, 0])
+    with pytest.raises(ValueError):
+        oracle.consumer(X, 7)
