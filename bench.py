@@ -363,6 +363,79 @@ def variant_stream(hp, inputs, dev, reps):
         "max_instance_normwise_rel_error_sampled": worst, "bar": 1e-5}}
 
 
+def variant_fusion(hp, inputs, dev, stream, reps):
+    """Node fusion: sgemm + consumer in one launch, and two sgemms sharing A."""
+    import torch
+
+    import oracle
+
+    out = {}
+    # -- MergeDependentNodes: D <- relu(A B + bias), 4096^3 --
+    n = 4096
+    A, B, _ = inputs.sgemm_operands(n, n, n, seed=1)
+    bias = np.random.default_rng(2).uniform(-1, 1, n).astype(np.float32)
+    dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    dbias = torch.from_numpy(bias).to(dev)
+    D = torch.empty((n, n), device=dev)
+    hp.autotune(dA, dB, prec="fp32", reps=3)
+    fused_ms = event_time(lambda: hp.sgemm_consumer(dA, dB, None, 1.0, 0.0, op="bias_relu", bias=dbias, D=D),
+                          reps, stream)
+
+    def unfused():
+        hp.sgemm(dA, dB, D, 1.0, 0.0)
+        D.add_(dbias)
+        D.relu_()
+
+    unfused_ms = event_time(unfused, reps, stream)
+    hp.sgemm_consumer(dA, dB, None, 1.0, 0.0, op="bias_relu", bias=dbias, D=D)
+    torch.cuda.synchronize()
+    rs = np.random.default_rng(3)
+    rows, cols = rs.integers(0, n, 256), rs.integers(0, n, 256)
+    v = oracle.sgemm_entries(A, B, None, 1.0, 0.0, rows, cols)
+    ref = oracle.consumer(v.reshape(1, -1), "bias_relu", bias=bias[cols])[0]
+    err = float(np.linalg.norm(gather(D, rows, cols) - ref) / np.linalg.norm(ref))
+    flops = 2.0 * n ** 3
+    out["consumer_bias_relu_4096^3"] = {
+        "fused_tflops": round(flops / (fused_ms / 1e3) / 1e12, 2), "fused_ms": round(fused_ms, 4),
+        "unfused_ms": round(unfused_ms, 4), "unfused": "sgemm, then add_(bias) and relu_() in torch",
+        "speedup": round(unfused_ms / fused_ms, 3), "normwise_rel_error_sampled": err, "bar": 1e-5}
+    del D
+    # -- MergeIndependentNodes with a shared A --
+    for (m, nn, k) in ((4096, 4096, 4096), (1024, 1024, 4096)):
+        A, B1, C1 = inputs.sgemm_operands(m, nn, k, seed=5)
+        _, B2, C2 = inputs.sgemm_operands(m, nn, k, seed=6)
+        dA = torch.from_numpy(A).to(dev)
+        dB1, dB2 = torch.from_numpy(B1).to(dev), torch.from_numpy(B2).to(dev)
+        c1, c2 = torch.from_numpy(C1).to(dev), torch.from_numpy(C2).to(dev)
+        hp.autotune(dA, dB1, prec="fp32", reps=3)
+        best_pair, best_ms = None, None
+        for tile in hp.fusion_menu("pair"):
+            ms = event_time(lambda: hp.sgemm_pair(dA, dB1, c1, dB2, c2, 1.0, 0.0, 1.0, 0.0, tile=tile),
+                            reps, stream)
+            if best_ms is None or ms < best_ms:
+                best_pair, best_ms = tile, ms
+
+        def two():
+            hp.sgemm(dA, dB1, c1, 1.0, 0.0)
+            hp.sgemm(dA, dB2, c2, 1.0, 0.0)
+
+        two_ms = event_time(two, reps, stream)
+        hp.sgemm_pair(dA, dB1, c1, dB2, c2, 1.0, 0.0, 1.0, 0.0, tile=best_pair)
+        torch.cuda.synchronize()
+        rows, cols = rs.integers(0, m, 256), rs.integers(0, nn, 256)
+        err = 0.0
+        for X, Bh in ((c1, B1), (c2, B2)):
+            ref = oracle.sgemm_entries(A, Bh, None, 1.0, 0.0, rows, cols)
+            err = max(err, float(np.linalg.norm(gather(X, rows, cols) - ref) / np.linalg.norm(ref)))
+        flops = 2 * 2.0 * m * nn * k
+        out[f"pair_shared_A_{m}x{nn}x{k}"] = {
+            "pair_tflops": round(flops / (best_ms / 1e3) / 1e12, 2), "pair_ms": round(best_ms, 4),
+            "pair_tile": list(best_pair), "two_launches_ms": round(two_ms, 4),
+            "two_launches_tile": list(hp.autotune_lookup(m, nn, k, "fp32")[0]),
+            "speedup": round(two_ms / best_ms, 3), "max_normwise_rel_error_sampled": err, "bar": 1e-5}
+    return out
+
+
 def variant_backward(hp, inputs, dev, stream, reps):
     import torch
 
@@ -595,6 +668,8 @@ def main():
         variants.update(variant_grouped(hp, inputs, dev, reps=10))
         log("variant: the 512 sgemms through a streaming graph")
         variants.update(variant_stream(hp, inputs, dev, reps=5))
+        log("variant: node fusion")
+        variants.update(variant_fusion(hp, inputs, dev, stream, reps=10))
         log("variant: forward + backward 4096x4096x1024")
         variants.update(variant_backward(hp, inputs, dev, stream, reps=5))
         result["variants"] = variants

@@ -419,6 +419,78 @@ int hpvm_grouped_autotune(void* plan, void* workspace, int64_t workspace_bytes, 
                           int64_t scratch_bytes, int32_t reps, void* stream, float* best_ms);
 
 /* ======================================================================== */
+/* Node fusion (Sec. 4.1 merge primitives, applied as in Sec. 4.2)           */
+/* ======================================================================== */
+/* Sec. 4.1 defines MergeDependentNodes (two leaves joined only by 1-1
+ * edges become one leaf; the edges become assignments) and
+ * MergeIndependentNodes (two leaves with the same parent and dimensions and
+ * no path between them become one leaf); Sec. 4.2 uses them to fuse
+ * kernels, for fewer launches and better reuse of data.  Two merges of the
+ * sgemm leaf are offered here (FP32); independent sgemms that share no
+ * operand merge into one launch with the grouped entry points above.      */
+
+typedef enum hpvm_fusion {
+  HPVM_FUSION_CONSUMER = 0,  /* sgemm leaf + 1-1 consumer leaf             */
+  HPVM_FUSION_PAIR = 1       /* two sgemm leaves sharing input A           */
+} hpvm_fusion;
+
+/* The consumer leaf's function, applied to v = alpha (A B)_ij + beta C_ij:
+ *   NONE       d = v
+ *   RELU       d = v if v > 0, else 0   (NaN gives 0)
+ *   BIAS       d = v + bias[j]
+ *   BIAS_RELU  d = relu(v + bias[j])
+ *   CLAMP      d = lo if v < lo, hi if v > hi, else v   (NaN stays NaN)  */
+typedef enum hpvm_consumer_op {
+  HPVM_CONSUMER_NONE = 0,
+  HPVM_CONSUMER_RELU = 1,
+  HPVM_CONSUMER_BIAS = 2,
+  HPVM_CONSUMER_BIAS_RELU = 3,
+  HPVM_CONSUMER_CLAMP = 4
+} hpvm_consumer_op;
+
+typedef struct hpvm_consumer {
+  int32_t op;         /* hpvm_consumer_op                                   */
+  int32_t reserved;   /* 0                                                  */
+  const float* bias;  /* device, n floats (BIAS ops; else unused)          */
+  float lo, hi;       /* CLAMP bounds, lo <= hi                             */
+} hpvm_consumer;
+
+/* Tiles compiled for a fusion: `which` is an hpvm_fusion.  For the pair,
+ * tile_m x tile_n is the tile of each output.  Same conventions as
+ * hpvm_tile_menu.                                                           */
+int hpvm_fusion_menu(int32_t which, hpvm_tile* out, int32_t capacity, int32_t* count);
+
+/* MergeDependentNodes(sgemm leaf, consumer leaf):
+ *   D <- consumer(alpha * A B + beta * C)   element-wise, FP32,
+ * in one launch; the sgemm result stays in registers.  A, B, C as in
+ * hpvm_sgemm, except that C is only read (beta == 0: never read, may be
+ * NULL).  D (m x n, leading dimension ldd >= max(1, n), device) receives
+ * the consumer's output; it may be C itself (same pointer and leading
+ * dimension) but may not otherwise overlap C, nor A, B or the bias vector.
+ * tile: NULL = the autotuner's FP32 choice for the shape if it is in the
+ * consumer menu, else the menu's first tile.  Errors as hpvm_sgemm, with
+ * argument 12 the consumer (unknown op, NULL bias, lo > hi), 13/14 D.     */
+int hpvm_sgemm_consumer(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
+                        const float* B, int64_t ldb, float beta, const float* C, int64_t ldc,
+                        const hpvm_consumer* consumer, float* D, int64_t ldd, const hpvm_tile* tile,
+                        void* stream);
+
+/* MergeIndependentNodes of two sgemm leaves whose parents share input A:
+ *   C1 <- alpha1 A B1 + beta1 C1   and   C2 <- alpha2 A B2 + beta2 C2
+ * (same m, n, k) in one launch; every workgroup stages one A tile and
+ * computes the same tile of C1 and C2 from it.  Each output follows the
+ * hpvm_sgemm rules (its checks run in that order, the detail text names
+ * the output and the hpvm_sgemm argument position); C1 and C2 may not
+ * overlap each other or the other output's B.  An output with k == 0 or
+ * alpha == 0 shares nothing; the two outputs then take single launches.
+ * tile: NULL = 128 x 128 per output when that gives 256 tiles or more, else
+ * 64 x 64.                                                                  */
+int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, float alpha1,
+                    const float* B1, int64_t ldb1, float beta1, float* C1, int64_t ldc1, float alpha2,
+                    const float* B2, int64_t ldb2, float beta2, float* C2, int64_t ldc2,
+                    const hpvm_tile* tile, void* stream);
+
+/* ======================================================================== */
 /* Streaming graph (llvm.hpvm.launch with Stream = 1, push, pop)              */
 /* ======================================================================== */
 /* Table 1 and Sec. 2.3 define the host intrinsics of a streaming graph:

@@ -444,6 +444,78 @@ class GroupedPlan:
 
 
 # ---------------------------------------------------------------------------
+# Node fusion: sgemm + one-to-one consumer, two sgemms sharing A
+# ---------------------------------------------------------------------------
+CONSUMER_OPS = {"none": 0, "relu": 1, "bias": 2, "bias_relu": 3, "clamp": 4}
+FUSIONS = {"consumer": 0, "pair": 1}
+
+
+def fusion_menu(which="consumer") -> list:
+    """Tiles compiled for a fusion ('consumer' or 'pair'); entry 0 is the default."""
+    lib = load()
+    w = FUSIONS[which] if isinstance(which, str) else int(which)
+    count = ctypes.c_int32(0)
+    _check(lib.hpvm_fusion_menu(w, None, 0, ctypes.byref(count)))
+    arr = (_lib.Tile * count.value)()
+    _check(lib.hpvm_fusion_menu(w, arr, count.value, ctypes.byref(count)))
+    return [t.as_tuple() for t in arr]
+
+
+def sgemm_consumer(A, B, C, alpha: float = 1.0, beta: float = 0.0, op="none", bias=None,
+                   lo: float = float("-inf"), hi: float = float("inf"), D=None, tile=None, stream=None):
+    """D <- op(alpha A B + beta C) in one launch (hpvm_sgemm_consumer); returns D.
+
+    ``C`` may be None when beta == 0; ``D`` defaults to C (in place) when C
+    is given, else to a new tensor.  ``bias``: float32 device vector of n.
+    """
+    import torch
+
+    lib = load()
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}")
+    if D is None:
+        D = C if C is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
+    if tuple(D.shape) != (m, n) or (C is not None and tuple(C.shape) != (m, n)):
+        raise ValueError("C and D must be m x n")
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C") if C is not None else (ctypes.c_void_p(0), max(n, 1))
+    pd, ldd = _mat(D, "D")
+    code = CONSUMER_OPS[op] if isinstance(op, str) else int(op)
+    pbias = 0
+    if bias is not None:
+        if bias.dtype != torch.float32 or not bias.is_cuda or tuple(bias.shape) != (n,) or \
+                (n > 1 and bias.stride(0) != 1):
+            raise TypeError("bias must be a contiguous float32 CUDA vector of length n")
+        pbias = bias.data_ptr()
+    cons = _lib.Consumer(code, 0, pbias, float(lo), float(hi))
+    _check(lib.hpvm_sgemm_consumer(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
+                                   ctypes.byref(cons), pd, ldd, _tile(tile), _stream(stream)))
+    return D
+
+
+def sgemm_pair(A, B1, C1, B2, C2, alpha1: float = 1.0, beta1: float = 0.0, alpha2: float = 1.0,
+               beta2: float = 0.0, tile=None, stream=None):
+    """C1 <- alpha1 A B1 + beta1 C1 and C2 <- alpha2 A B2 + beta2 C2 in one launch."""
+    lib = load()
+    m, k = A.shape
+    n = B1.shape[1]
+    for name, X, shape in (("B1", B1, (k, n)), ("B2", B2, (k, n)), ("C1", C1, (m, n)), ("C2", C2, (m, n))):
+        if tuple(X.shape) != shape:
+            raise ValueError(f"{name} must be {shape[0]} x {shape[1]}")
+    pa, lda = _mat(A, "A")
+    p1, l1 = _mat(B1, "B1")
+    q1, m1 = _mat(C1, "C1")
+    p2, l2 = _mat(B2, "B2")
+    q2, m2 = _mat(C2, "C2")
+    _check(lib.hpvm_sgemm_pair(m, n, k, pa, lda, float(alpha1), p1, l1, float(beta1), q1, m1,
+                               float(alpha2), p2, l2, float(beta2), q2, m2, _tile(tile), _stream(stream)))
+    return C1, C2
+
+
+# ---------------------------------------------------------------------------
 # Streaming graph: launch with Stream = 1, push, pop
 # ---------------------------------------------------------------------------
 _open_streams = set()

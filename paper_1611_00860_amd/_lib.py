@@ -51,6 +51,10 @@ class SgemmDesc(ctypes.Structure):
                 ("A", vp), ("lda", i64), ("B", vp), ("ldb", i64), ("C", vp), ("ldc", i64)]
 
 
+class Consumer(ctypes.Structure):
+    _fields_ = [("op", i32), ("reserved", i32), ("bias", vp), ("lo", f32), ("hi", f32)]
+
+
 class StreamConfig(ctypes.Structure):
     _fields_ = [("capacity", i32), ("grid", i32), ("idle_ms", i32), ("reserved", i32)]
 
@@ -108,6 +112,11 @@ SIGNATURES = {
                                               vp, i64, i32, vp, PTile, ctypes.POINTER(f32)]),
     "hpvm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "hpvm_last_error": (ctypes.c_char_p, []),
+    "hpvm_fusion_menu": (ctypes.c_int, [i32, ctypes.POINTER(Tile), i32, ctypes.POINTER(i32)]),
+    "hpvm_sgemm_consumer": (ctypes.c_int, [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64,
+                                           ctypes.POINTER(Consumer), vp, i64, ctypes.POINTER(Tile), vp]),
+    "hpvm_sgemm_pair": (ctypes.c_int, [i64, i64, i64, vp, i64, f32, vp, i64, f32, vp, i64,
+                                       f32, vp, i64, f32, vp, i64, ctypes.POINTER(Tile), vp]),
     "hpvm_stream_open": (ctypes.c_int, [ctypes.POINTER(StreamConfig), ctypes.POINTER(vp)]),
     "hpvm_stream_push": (ctypes.c_int, [vp, ctypes.POINTER(SgemmDesc), ctypes.POINTER(i64)]),
     "hpvm_stream_pop": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp)]),

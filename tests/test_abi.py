@@ -429,3 +429,69 @@ def test_stream_status_layout():
     assert ctypes.sizeof(_lib.StreamConfig) == 16
     assert ctypes.sizeof(_lib.StreamStatus) == 48
 
+
+def test_fusion_menus(lib):
+    assert hp.fusion_menu("consumer") == [t for t in hp.tile_menu("fp32") if t[5] == 2]
+    pair = hp.fusion_menu("pair")
+    assert len(pair) == 2 and all(t[5] == 2 for t in pair)
+    cnt = ctypes.c_int32()
+    assert lib.hpvm_fusion_menu(2, None, 0, ctypes.byref(cnt)) == -1
+
+
+def _consumer_call(lib, **kw):
+    a = dict(m=64, n=48, k=32, alpha=1.0, A=FAKE, lda=32, B=FAKE + (1 << 24), ldb=48, beta=1.0,
+             C=FAKE + (2 << 24), ldc=48, op=1, bias=0, lo=0.0, hi=1.0, D=FAKE + (3 << 24), ldd=48,
+             tile=None, cons=True)
+    a.update(kw)
+    cons = _lib.Consumer(a["op"], 0, a["bias"], a["lo"], a["hi"])
+    t = None
+    if a["tile"] is not None:
+        t = ctypes.byref(_lib.Tile(*a["tile"]))
+    return lib.hpvm_sgemm_consumer(a["m"], a["n"], a["k"], a["alpha"], a["A"], a["lda"], a["B"], a["ldb"],
+                                   a["beta"], a["C"], a["ldc"], ctypes.byref(cons) if a["cons"] else None,
+                                   a["D"], a["ldd"], t, None)
+
+
+@pytest.mark.parametrize("kw,argno", [
+    (dict(m=-1), 1), (dict(n=-1), 2), (dict(k=-1), 3), (dict(A=None), 5), (dict(lda=31), 6),
+    (dict(B=None), 7), (dict(ldb=47), 8), (dict(C=None), 10), (dict(ldc=47), 11),
+    (dict(cons=False), 12), (dict(op=9), 12), (dict(op=2), 12), (dict(op=4, lo=2.0, hi=1.0), 12),
+    (dict(D=None), 13), (dict(ldd=47), 14), (dict(D=FAKE + 64), 13), (dict(D=FAKE + (2 << 24) + 64), 13),
+])
+def test_consumer_validation(lib, kw, argno):
+    assert _consumer_call(lib, **kw) == -1
+    assert f"argument {argno}:" in hp.last_error(), hp.last_error()
+
+
+def test_consumer_accepts_in_place_and_null_c(lib, monkeypatch):
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    # D == C with the same leading dimension is in place
+    assert _consumer_call(lib, D=FAKE + (2 << 24)) == -3
+    # beta == 0: C may be NULL and may overlap D
+    assert _consumer_call(lib, beta=0.0, C=None) == -3
+    # alpha == 0: A and B may be NULL
+    assert _consumer_call(lib, alpha=0.0, A=None, B=None) == -3
+    assert _consumer_call(lib, tile=(32, 32, 8, 32, 32, 2)) == -2
+    assert _consumer_call(lib, m=0) == 0  # empty: quick return
+
+
+def test_pair_validation(lib, monkeypatch):
+    def call(**kw):
+        a = dict(m=64, n=48, k=32, A=FAKE, lda=32, a1=1.0, B1=FAKE + (1 << 24), ldb1=48, b1=1.0,
+                 C1=FAKE + (2 << 24), ldc1=48, a2=1.0, B2=FAKE + (3 << 24), ldb2=48, b2=0.0,
+                 C2=FAKE + (4 << 24), ldc2=48, tile=None)
+        a.update(kw)
+        t = ctypes.byref(_lib.Tile(*a["tile"])) if a["tile"] is not None else None
+        return lib.hpvm_sgemm_pair(a["m"], a["n"], a["k"], a["A"], a["lda"], a["a1"], a["B1"], a["ldb1"],
+                                   a["b1"], a["C1"], a["ldc1"], a["a2"], a["B2"], a["ldb2"], a["b2"],
+                                   a["C2"], a["ldc2"], t, None)
+
+    assert call(C2=FAKE + (2 << 24) + 128) == -1 and "overlap" in hp.last_error()
+    assert call(C1=FAKE + (3 << 24)) == -1 and "C1 overlaps B2" in hp.last_error()
+    assert call(B2=None) == -1 and "output 2" in hp.last_error()
+    assert call(lda=31) == -1 and "output 1" in hp.last_error()
+    assert call(tile=(128, 128, 32, 64, 64, 2)) == -2
+    assert call(n=0) == 0
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    assert call() == -3
+

@@ -1,0 +1,164 @@
+"""GPU parity of the fused sgemm nodes (node fusion, Sec. 4.1 / 4.2).
+
+Consumer fusion (sgemm + one-to-one consumer) is compared with the oracle's
+dependent pair consumer(sgemm(...)); the pair fusion (two sgemms sharing A)
+with two oracle sgemms.  Integer inputs make every product and sum exact, so
+those comparisons are bit for bit; random inputs are held to the FP32 bar and
+to bitwise agreement with the unfused kernels that use the same wave tiles.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1611_00860_amd import inputs
+from gpu_util import normwise, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+OPS = ["none", "relu", "bias", "bias_relu", "clamp"]
+SHAPES = [(300, 260, 200), (129, 257, 77), (1, 1, 1), (256, 256, 64)]
+
+
+def bias_for(n, seed):
+    return (np.random.default_rng(seed).integers(-40, 40, n)).astype(np.float32)
+
+
+@pytest.mark.parametrize("m,n,k", SHAPES)
+def test_consumer_integers_bit_exact_every_op_and_tile(gpu, m, n, k):
+    import torch
+
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=m + 7 * k, dist="int")
+    bias = bias_for(n, m)
+    dbias = torch.from_numpy(bias).cuda()
+    dA, dB = to_dev(A, pad=4), to_dev(B, pad=4)
+    for op in OPS:
+        ref = oracle.sgemm_consumed(A, B, C, 1.0, -1.0, op, bias=bias, lo=-50.0, hi=60.0)
+        for tile in gpu.fusion_menu("consumer"):
+            print(f"case: consumer {op} {m}x{n}x{k} tile {tile}", flush=True)
+            dC = to_dev(C, pad=4)
+            gpu.sgemm_consumer(dA, dB, dC, 1.0, -1.0, op=op, bias=dbias, lo=-50.0, hi=60.0, tile=tile)
+            torch.cuda.synchronize()
+            assert np.array_equal(to_host(dC), ref), (op, tile)
+
+
+def test_consumer_separate_output_and_beta_zero(gpu):
+    import torch
+
+    m, n, k = 200, 150, 90
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=3, dist="int")
+    dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+    bias = bias_for(n, 9)
+    dbias = torch.from_numpy(bias).cuda()
+    D = torch.full((m, n + 3), float("nan"), device="cuda")[:, :n]  # ldd != n
+    gpu.sgemm_consumer(dA, dB, dC, 2.0, 0.5, op="bias_relu", bias=dbias, D=D)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(D), oracle.sgemm_consumed(A, B, C, 2.0, 0.5, "bias_relu", bias=bias))
+    assert np.array_equal(to_host(dC), C)  # C is only read
+    # beta = 0: C is not read (NULL here), D gets consumer(alpha A B)
+    D2 = gpu.sgemm_consumer(dA, dB, None, 1.0, 0.0, op="relu")
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(D2), oracle.sgemm_consumed(A, B, None, 1.0, 0.0, "relu"))
+    # NaN in C with beta = 0 never reaches D
+    Cn = to_dev(np.full((m, n), np.nan, dtype=np.float32))
+    gpu.sgemm_consumer(dA, dB, Cn, 1.0, 0.0, op="clamp", lo=-100.0, hi=100.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(Cn), oracle.sgemm_consumed(A, B, None, 1.0, 0.0, "clamp", lo=-100.0, hi=100.0))
+    # alpha = 0: D = consumer(beta C) with A and B unread
+    D3 = gpu.sgemm_consumer(dA, dB, dC, 0.0, 2.0, op="relu", D=torch.empty((m, n), device="cuda"))
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(D3), oracle.consumer(2.0 * C.astype(np.float64), "relu"))
+
+
+def test_consumer_random_matches_unfused_bitwise(gpu):
+    """Same tile, same FP32 value v, then the consumer: the fused kernel gives
+    exactly sgemm followed by the same element-wise op in torch."""
+    import torch
+
+    m, n, k = 520, 390, 300
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=4)
+    bias = np.random.default_rng(1).uniform(-1, 1, n).astype(np.float32)
+    dA, dB = to_dev(A), to_dev(B)
+    dbias = torch.from_numpy(bias).cuda()
+    for tile in gpu.fusion_menu("consumer"):
+        fused = to_dev(C)
+        gpu.sgemm_consumer(dA, dB, fused, 1.5, 0.5, op="bias_relu", bias=dbias, tile=tile)
+        plain = to_dev(C)
+        gpu.sgemm(dA, dB, plain, 1.5, 0.5, tile=tile)
+        torch.cuda.synchronize()
+        unfused = torch.relu(plain + dbias)
+        assert torch.equal(fused, unfused), tile
+        ref = oracle.sgemm_consumed(A, B, C, 1.5, 0.5, "bias_relu", bias=bias)
+        assert normwise(to_host(fused), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("m,n,k", SHAPES + [(64, 520, 48)])
+def test_pair_integers_bit_exact_every_tile(gpu, m, n, k):
+    import torch
+
+    A, B1, C1 = inputs.sgemm_operands(m, n, k, seed=m + k, dist="int")
+    _, B2, C2 = inputs.sgemm_operands(m, n, k, seed=m + k + 1, dist="int")
+    ref1 = oracle.sgemm(A, B1, C1, 1.0, 1.0)
+    ref2 = oracle.sgemm(A, B2, C2, -2.0, 0.5)
+    dA, dB1, dB2 = to_dev(A, pad=4), to_dev(B1), to_dev(B2, pad=8)
+    for tile in gpu.fusion_menu("pair"):
+        print(f"case: pair {m}x{n}x{k} tile {tile}", flush=True)
+        dC1, dC2 = to_dev(C1), to_dev(C2, pad=4)
+        gpu.sgemm_pair(dA, dB1, dC1, dB2, dC2, 1.0, 1.0, -2.0, 0.5, tile=tile)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(dC1), ref1), tile
+        assert np.array_equal(to_host(dC2), ref2), tile
+
+
+def test_pair_random_matches_single_launches_bitwise(gpu):
+    """Per wave the pair kernel runs the MFMA sequence of the single-output
+    kernel with the same wave tile, so each output agrees bit for bit."""
+    import torch
+
+    m, n, k = 700, 600, 333
+    A, B1, C1 = inputs.sgemm_operands(m, n, k, seed=21)
+    _, B2, C2 = inputs.sgemm_operands(m, n, k, seed=22)
+    dA, dB1, dB2 = to_dev(A), to_dev(B1), to_dev(B2)
+    singles = {t[3:5]: t for t in gpu.tile_menu("fp32") if t[5] == 2}
+    for tile in gpu.fusion_menu("pair"):
+        single = singles[tile[3:5]]
+        c1, c2 = to_dev(C1), to_dev(C2)
+        gpu.sgemm_pair(dA, dB1, c1, dB2, c2, 0.75, 0.5, 1.25, 0.0, tile=tile)
+        s1, s2 = to_dev(C1), to_dev(C2)
+        gpu.sgemm(dA, dB1, s1, 0.75, 0.5, tile=single)
+        gpu.sgemm(dA, dB2, s2, 1.25, 0.0, tile=single)
+        torch.cuda.synchronize()
+        assert torch.equal(c1, s1) and torch.equal(c2, s2), (tile, single)
+        assert normwise(to_host(c1), oracle.sgemm(A, B1, C1, 0.75, 0.5)) <= 1e-5
+
+
+def test_pair_scale_only_output(gpu):
+    """alpha2 = 0: output 2 is beta2 C2 with B2 unread (NULL-free here), output 1 as usual."""
+    import torch
+
+    m, n, k = 150, 140, 60
+    A, B1, C1 = inputs.sgemm_operands(m, n, k, seed=31, dist="int")
+    _, B2, C2 = inputs.sgemm_operands(m, n, k, seed=32, dist="int")
+    dC1, dC2 = to_dev(C1), to_dev(C2)
+    gpu.sgemm_pair(to_dev(A), to_dev(B1), dC1, to_dev(B2), dC2, 1.0, 0.0, 0.0, 3.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(dC1), oracle.sgemm(A, B1, None, 1.0, 0.0))
+    assert np.array_equal(to_host(dC2), 3.0 * C2.astype(np.float64))
+
+
+def test_consumer_full_size_sampled(gpu):
+    """4096^3, uniform, bias+relu: sampled entries against the oracle."""
+    import torch
+
+    n = 4096
+    A, B, C = inputs.sgemm_operands(n, n, n, seed=1)
+    bias = np.random.default_rng(2).uniform(-1, 1, n).astype(np.float32)
+    dA, dB = to_dev(A), to_dev(B)
+    dD = torch.empty((n, n), device="cuda")
+    gpu.sgemm_consumer(dA, dB, None, 1.0, 0.0, op="bias_relu", bias=torch.from_numpy(bias).cuda(), D=dD)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    rows, cols = rng.integers(0, n, 500), rng.integers(0, n, 500)
+    got = dD[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.float64)
+    v = oracle.sgemm_entries(A, B, None, 1.0, 0.0, rows, cols)
+    ref = oracle.consumer(v.reshape(1, -1), "bias_relu", bias=bias[cols])[0]
+    assert normwise(got, ref) <= 1e-5
