@@ -436,6 +436,51 @@ def variant_fusion(hp, inputs, dev, stream, reps):
     return out
 
 
+def variant_tracked(hp, inputs, dev, reps):
+    """4096^3 on tracked host arrays: copies in and out included, then resident."""
+    import torch
+
+    import oracle
+
+    n = 4096
+    A, B, _ = inputs.sgemm_operands(n, n, n, seed=1)
+    tA, tB = torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory()
+    tC = torch.empty((n, n), dtype=torch.float32).pin_memory()
+    for x in (tA, tB, tC):
+        hp.track(x)
+    try:
+        hp.sgemm(torch.from_numpy(A[:256, :256].copy()).to(dev), torch.from_numpy(B[:256, :256].copy()).to(dev),
+                 torch.empty((256, 256), device=dev), 1.0, 0.0)  # load the kernels before timing
+        torch.cuda.synchronize()
+        c0 = hp.tracker_counters()
+        t0 = time.perf_counter()
+        hp.sgemm_tracked(tA, tB, tC, 1.0, 0.0)  # A, B copied in; C overwritten whole: not copied in
+        hp.request(tC)                          # C copied back
+        cold_s = time.perf_counter() - t0
+        c1 = hp.tracker_counters()
+        stream = torch.cuda.current_stream()
+        resident_ms = event_time(lambda: hp.sgemm_tracked(tA, tB, tC, 1.0, 0.0), reps, stream)
+        c2 = hp.tracker_counters()
+        hp.request(tC)
+        rs = np.random.default_rng(7)
+        rows, cols = rs.integers(0, n, 256), rs.integers(0, n, 256)
+        ref = oracle.sgemm_entries(A, B, None, 1.0, 0.0, rows, cols)
+        err = float(np.linalg.norm(tC.numpy()[rows, cols] - ref) / np.linalg.norm(ref))
+    finally:
+        for x in (tA, tB, tC):
+            hp.untrack(x)
+        torch.cuda.synchronize()
+    flops = 2.0 * n ** 3
+    moved = (c1["h2d_bytes"] - c0["h2d_bytes"]) + (c1["d2h_bytes"] - c0["d2h_bytes"])
+    return {"tracked_host_4096^3": {
+        "pcie_inclusive_tflops": round(flops / cold_s / 1e12, 2), "pcie_inclusive_ms": round(cold_s * 1e3, 3),
+        "bytes_copied": moved, "copies_in": c1["h2d_copies"] - c0["h2d_copies"],
+        "copies_out": c1["d2h_copies"] - c0["d2h_copies"],
+        "resident_tflops": round(flops / (resident_ms / 1e3) / 1e12, 2), "resident_ms": round(resident_ms, 4),
+        "copies_while_resident": c2["h2d_copies"] - c1["h2d_copies"],
+        "host_memory": "pinned", "normwise_rel_error_sampled": err, "bar": 1e-5}}
+
+
 def variant_backward(hp, inputs, dev, stream, reps):
     import torch
 
@@ -670,6 +715,8 @@ def main():
         variants.update(variant_stream(hp, inputs, dev, reps=5))
         log("variant: node fusion")
         variants.update(variant_fusion(hp, inputs, dev, stream, reps=10))
+        log("variant: tracked host arrays")
+        variants.update(variant_tracked(hp, inputs, dev, reps=5))
         log("variant: forward + backward 4096x4096x1024")
         variants.update(variant_backward(hp, inputs, dev, stream, reps=5))
         result["variants"] = variants

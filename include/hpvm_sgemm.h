@@ -567,6 +567,69 @@ int hpvm_stream_info(const void* handle, hpvm_stream_status* info);
 int hpvm_stream_close(void* handle, int32_t timeout_ms);
 
 /* ======================================================================== */
+/* Memory tracker for host-resident arrays                                   */
+/* ======================================================================== */
+/* Sec. 2.3 ("Performance features") has the runtime record where the latest
+ * copy of each data array lives, so that copies between address spaces
+ * happen only when needed; node arguments marked in / out / inout tell it
+ * which copies a launch needs, and host code uses track / request / untrack
+ * explicitly (the runtime calls listed there and used by the host code of
+ * the Sec. 6.1 listing).  Here the tracked regions are host memory (pinned
+ * or pageable) and the library keeps one device copy per region, allocated
+ * on first use, stream-ordered, on the stream of that call.  The table is
+ * process-wide and guarded by a lock; a region must not be untracked while
+ * a launch that uses it is being enqueued on another thread.             */
+
+typedef struct hpvm_tracked {
+  void* start;        /* host start of the region holding the pointer    */
+  int64_t bytes;
+  void* device;       /* its device copy, NULL before first use           */
+  int32_t on_host;    /* 1 when the host copy is current                  */
+  int32_t on_device;  /* 1 when the device copy is current                */
+} hpvm_tracked;
+
+typedef struct hpvm_tracker_stats {
+  int64_t h2d_bytes, h2d_copies;  /* copies made so far, process-wide    */
+  int64_t d2h_bytes, d2h_copies;
+  int64_t launches;               /* hpvm_sgemm_tracked launches          */
+  int64_t regions;                /* regions tracked now                  */
+} hpvm_tracker_stats;
+
+/* llvm_hpvm_track_mem: adds [ptr, ptr + bytes) of host memory to the table,
+ * with the host copy current.  HPVM_INVALID_ARG for NULL, bytes <= 0, or a
+ * region overlapping one already tracked.                                 */
+int hpvm_track_mem(void* ptr, int64_t bytes);
+
+/* llvm_hpvm_request_mem: the host is about to access [ptr, ptr + bytes).
+ * If the latest copy of the region holding it is on the device, the whole
+ * region is copied back on `stream` and the call waits for it; otherwise
+ * nothing happens.  HPVM_INVALID_ARG if the range is not inside one tracked
+ * region.                                                                  */
+int hpvm_request_mem(void* ptr, int64_t bytes, void* stream);
+
+/* llvm_hpvm_untrack_mem: removes the region starting at ptr; its device
+ * copy is freed stream-ordered on `stream`, after the work queued there and
+ * on the stream that allocated it.  The host copy is left as it is (request
+ * it first to keep the device's latest data).                             */
+int hpvm_untrack_mem(void* ptr, void* stream);
+
+/* Where the latest copy of the region holding ptr lives.                  */
+int hpvm_tracked_state(const void* ptr, hpvm_tracked* out);
+int hpvm_tracker_counters(hpvm_tracker_stats* out);
+
+/* The sgemm root launch on host arrays, as the host code of the Sec. 6.1
+ * listing runs it: A, B and C are host pointers inside tracked regions.
+ * A and B are `in` (copied to the device only when their device copy is
+ * stale), C is `in out` (copied in unless the node overwrites its whole
+ * region: beta == 0, ldc == n and the region is exactly C); after the
+ * launch the latest C is on the device, until hpvm_request_mem.  Checks as
+ * hpvm_sgemm, then HPVM_INVALID_ARG for an untracked operand (argument 5,
+ * 7 or 10).  The copies and the launch are enqueued on `stream`.          */
+int hpvm_sgemm_tracked(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
+                       const hpvm_tile* tile, void* stream);
+
+/* ======================================================================== */
 /* Diagnostics                                                               */
 /* ======================================================================== */
 

@@ -64,6 +64,8 @@ def _stream(stream=None):
     import torch
 
     if stream is None:
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(None)  # host-only calls; a HIP call then fails loudly
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
 
@@ -513,6 +515,82 @@ def sgemm_pair(A, B1, C1, B2, C2, alpha1: float = 1.0, beta1: float = 0.0, alpha
     _check(lib.hpvm_sgemm_pair(m, n, k, pa, lda, float(alpha1), p1, l1, float(beta1), q1, m1,
                                float(alpha2), p2, l2, float(beta2), q2, m2, _tile(tile), _stream(stream)))
     return C1, C2
+
+
+# ---------------------------------------------------------------------------
+# Memory tracker for host-resident arrays
+# ---------------------------------------------------------------------------
+def _host(x, name):
+    """(address, bytes, row stride in elements) of a host float32 array or CPU tensor."""
+    import numpy as np
+    import torch
+
+    if isinstance(x, np.ndarray):
+        if x.dtype != np.float32 and name != "region":
+            raise TypeError(f"{name} must be float32")
+        ld = x.strides[0] // x.itemsize if x.ndim == 2 and x.shape[0] > 1 else (x.shape[-1] if x.ndim else 1)
+        if x.ndim == 2 and x.shape[1] > 1 and x.strides[1] != x.itemsize:
+            raise ValueError(f"{name} must have unit column stride (row-major)")
+        return x.ctypes.data, x.nbytes, max(int(ld), 1)
+    if isinstance(x, torch.Tensor):
+        if x.is_cuda:
+            raise TypeError(f"{name} must be host memory (the tracker manages the device copy)")
+        if x.dtype != torch.float32 and name != "region":
+            raise TypeError(f"{name} must be float32")
+        ld = x.stride(0) if x.dim() == 2 and x.shape[0] > 1 else (x.shape[-1] if x.dim() else 1)
+        if x.dim() == 2 and x.shape[1] > 1 and x.stride(1) != 1:
+            raise ValueError(f"{name} must have unit column stride (row-major)")
+        return x.data_ptr(), x.numel() * x.element_size(), max(int(ld), 1)
+    raise TypeError(f"{name} must be a numpy array or a CPU torch tensor")
+
+
+def track(x):
+    """llvm_hpvm_track_mem on a host array (numpy or CPU tensor)."""
+    addr, nbytes, _ = _host(x, "region")
+    _check(load().hpvm_track_mem(ctypes.c_void_p(addr), nbytes))
+    return x
+
+
+def request(x, stream=None):
+    """llvm_hpvm_request_mem: make the host copy of x current (copies back only if needed)."""
+    addr, nbytes, _ = _host(x, "region")
+    _check(load().hpvm_request_mem(ctypes.c_void_p(addr), nbytes, _stream(stream)))
+    return x
+
+
+def untrack(x, stream=None):
+    """llvm_hpvm_untrack_mem: forget x and free its device copy."""
+    addr, _, _ = _host(x, "region")
+    _check(load().hpvm_untrack_mem(ctypes.c_void_p(addr), _stream(stream)))
+
+
+def tracked_state(x) -> dict:
+    addr, _, _ = _host(x, "region")
+    st = _lib.Tracked()
+    _check(load().hpvm_tracked_state(ctypes.c_void_p(addr), ctypes.byref(st)))
+    return {"start": st.start or 0, "bytes": st.bytes, "device": st.device or 0,
+            "on_host": bool(st.on_host), "on_device": bool(st.on_device)}
+
+
+def tracker_counters() -> dict:
+    st = _lib.TrackerStats()
+    _check(load().hpvm_tracker_counters(ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in _lib.TrackerStats._fields_}
+
+
+def sgemm_tracked(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None, stream=None):
+    """C <- alpha A B + beta C on tracked host arrays (the latest C stays on the device until request(C))."""
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch")
+    pa, _, lda = _host(A, "A")
+    pb, _, ldb = _host(B, "B")
+    pc, _, ldc = _host(C, "C")
+    _check(load().hpvm_sgemm_tracked(m, n, k, float(alpha), ctypes.c_void_p(pa), lda, ctypes.c_void_p(pb),
+                                     ldb, float(beta), ctypes.c_void_p(pc), ldc, _prec(prec), _tile(tile),
+                                     _stream(stream)))
+    return C
 
 
 # ---------------------------------------------------------------------------

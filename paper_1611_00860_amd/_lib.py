@@ -55,6 +55,15 @@ class Consumer(ctypes.Structure):
     _fields_ = [("op", i32), ("reserved", i32), ("bias", vp), ("lo", f32), ("hi", f32)]
 
 
+class Tracked(ctypes.Structure):
+    _fields_ = [("start", vp), ("bytes", i64), ("device", vp), ("on_host", i32), ("on_device", i32)]
+
+
+class TrackerStats(ctypes.Structure):
+    _fields_ = [("h2d_bytes", i64), ("h2d_copies", i64), ("d2h_bytes", i64), ("d2h_copies", i64),
+                ("launches", i64), ("regions", i64)]
+
+
 class StreamConfig(ctypes.Structure):
     _fields_ = [("capacity", i32), ("grid", i32), ("idle_ms", i32), ("reserved", i32)]
 
@@ -117,6 +126,13 @@ SIGNATURES = {
                                            ctypes.POINTER(Consumer), vp, i64, ctypes.POINTER(Tile), vp]),
     "hpvm_sgemm_pair": (ctypes.c_int, [i64, i64, i64, vp, i64, f32, vp, i64, f32, vp, i64,
                                        f32, vp, i64, f32, vp, i64, ctypes.POINTER(Tile), vp]),
+    "hpvm_track_mem": (ctypes.c_int, [vp, i64]),
+    "hpvm_request_mem": (ctypes.c_int, [vp, i64, vp]),
+    "hpvm_untrack_mem": (ctypes.c_int, [vp, vp]),
+    "hpvm_tracked_state": (ctypes.c_int, [vp, ctypes.POINTER(Tracked)]),
+    "hpvm_tracker_counters": (ctypes.c_int, [ctypes.POINTER(TrackerStats)]),
+    "hpvm_sgemm_tracked": (ctypes.c_int, [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32,
+                                          ctypes.POINTER(Tile), vp]),
     "hpvm_stream_open": (ctypes.c_int, [ctypes.POINTER(StreamConfig), ctypes.POINTER(vp)]),
     "hpvm_stream_push": (ctypes.c_int, [vp, ctypes.POINTER(SgemmDesc), ctypes.POINTER(i64)]),
     "hpvm_stream_pop": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp)]),

@@ -495,3 +495,44 @@ def test_pair_validation(lib, monkeypatch):
     monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
     assert call() == -3
 
+
+def test_tracker_table_host_side(lib, monkeypatch):
+    """Track / state / request / untrack on host memory; no copy is needed, so no HIP call."""
+    import numpy as np
+
+    base = hp.tracker_counters()
+    A = np.zeros((8, 8), np.float32)
+    B = np.zeros((8, 8), np.float32)
+    hp.track(A)
+    hp.track(B)
+    with pytest.raises(hp.HpvmError) as ei:
+        hp.track(A)  # already tracked: overlap
+    assert ei.value.status == -1
+    assert lib.hpvm_track_mem(ctypes.c_void_p(A.ctypes.data + 16), 16) == -1  # inside A
+    st = hp.tracked_state(A[3:])  # any address inside the region resolves to it
+    assert st["start"] == A.ctypes.data and st["bytes"] == A.nbytes
+    assert st["on_host"] and not st["on_device"] and st["device"] == 0
+    hp.request(A)  # host copy is current: nothing to copy
+    assert lib.hpvm_request_mem(ctypes.c_void_p(A.ctypes.data), A.nbytes + 4, None) == -1  # past the region
+    assert lib.hpvm_untrack_mem(ctypes.c_void_p(A.ctypes.data + 4), None) == -1  # not a region start
+    C = np.zeros((8, 8), np.float32)
+    # the launch refuses untracked operands, in argument order
+    assert lib.hpvm_sgemm_tracked(8, 8, 8, 1.0, ctypes.c_void_p(C.ctypes.data), 8, ctypes.c_void_p(B.ctypes.data),
+                                  8, 0.0, ctypes.c_void_p(A.ctypes.data), 8, 0, None, None) == -1
+    assert "argument 5" in hp.last_error()
+    assert lib.hpvm_sgemm_tracked(8, 8, 8, 1.0, ctypes.c_void_p(A.ctypes.data), 8, ctypes.c_void_p(B.ctypes.data),
+                                  8, 0.0, ctypes.c_void_p(C.ctypes.data), 8, 0, None, None) == -1
+    assert "argument 10" in hp.last_error()
+    hp.track(C)
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    assert lib.hpvm_sgemm_tracked(8, 8, 8, 1.0, ctypes.c_void_p(A.ctypes.data), 8, ctypes.c_void_p(B.ctypes.data),
+                                  8, 0.0, ctypes.c_void_p(C.ctypes.data), 8, 0, None, None) == -3
+    monkeypatch.delenv("HPVM_FAULT_INJECT")
+    assert hp.tracker_counters()["regions"] == base["regions"] + 3
+    for x in (A, B, C):
+        hp.untrack(x)
+    after = hp.tracker_counters()
+    assert after["regions"] == base["regions"] and after["h2d_copies"] == base["h2d_copies"]
+    with pytest.raises(hp.HpvmError):
+        hp.tracked_state(A)
+
