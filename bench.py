@@ -197,6 +197,29 @@ def cpu_baseline(host, target_s=30.0):
             "sample": f"{sample}: {flops / 1e9:.1f} GFLOP in {dt:.1f} s"}
 
 
+def cpu_lowering(hp, host):
+    """The CPU lowering of the same graph on the step's first product (context
+    beside the oracle baseline; FP32, all host threads), with sampled parity."""
+    import oracle
+
+    (A, B, C), (m, n, k, beta) = host[0], WORKLOAD[0]
+    threads = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit() and int(os.environ["OMP_NUM_THREADS"]) > 0:
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    out = C.copy()
+    hp.sgemm_cpu(A[:64], B, out[:64], 1.0, beta, threads=threads)  # warm the threads' pages
+    t0 = time.perf_counter()
+    hp.sgemm_cpu(A, B, out, 1.0, beta, threads=threads)
+    dt = time.perf_counter() - t0
+    rs = np.random.default_rng(8)
+    rows, cols = rs.integers(0, m, 256), rs.integers(0, n, 256)
+    ref = oracle.sgemm_entries(A, B, C, 1.0, beta, rows, cols)
+    err = float(np.linalg.norm(out[rows, cols] - ref) / np.linalg.norm(ref))
+    return {"value": round(2.0 * m * n * k / dt / 1e12, 4), "unit": "TFLOP/s", "isa": hp.cpu_isa(),
+            "threads": threads, "sample": f"one {m}x{n}x{k} product, beta={beta:g}",
+            "normwise_rel_error_sampled": err}
+
+
 # --------------------------------------------------------------------------- #
 # Variants                                                                     #
 # --------------------------------------------------------------------------- #
@@ -728,6 +751,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(host)
+        log("timing the CPU lowering of the graph")
+        result["cpu_lowering"] = cpu_lowering(hp, host)
     print(json.dumps(result), flush=True)
 
 

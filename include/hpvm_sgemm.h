@@ -630,6 +630,32 @@ int hpvm_sgemm_tracked(int64_t m, int64_t n, int64_t k, float alpha, const float
                        const hpvm_tile* tile, void* stream);
 
 /* ======================================================================== */
+/* CPU (vector) lowering of the same graph                                   */
+/* ======================================================================== */
+/* The paper compiles one graph to GPUs, to the vector units of a CPU and to
+ * host threads (Sec. 3.3, evaluated in Sec. 5).  This is the sgemm graph
+ * lowered by hand onto host cores: SgemmInternal instances are tile_m x
+ * tile_n tiles of C pulled by worker threads, the Allocation node is each
+ * worker's packed tile_k panels of A and B, and SgemmLeaf instances are a
+ * leaf_m x leaf_n block of outputs in vector registers.  FP32 arithmetic.
+ * A separate target: no GPU entry point ever calls it.                    */
+
+/* The compiled CPU tiles (stages = 1); entry 0 is the default.            */
+int hpvm_cpu_menu(hpvm_tile* out, int32_t capacity, int32_t* count);
+
+/* The instruction set the micro-kernel runs with on this host ("avx512f",
+ * "avx2" or "x86-64").                                                      */
+const char* hpvm_cpu_isa(void);
+
+/* C <- alpha A B + beta C on host memory, synchronously, with `threads`
+ * workers (0 = the host's cores, capped by OMP_NUM_THREADS when set).
+ * Arguments and errors as hpvm_sgemm (host pointers); tile NULL = the
+ * default, else one of hpvm_cpu_menu (HPVM_UNSUPPORTED otherwise).        */
+int hpvm_sgemm_cpu(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
+                   const float* B, int64_t ldb, float beta, float* C, int64_t ldc, const hpvm_tile* tile,
+                   int32_t threads);
+
+/* ======================================================================== */
 /* Diagnostics                                                               */
 /* ======================================================================== */
 

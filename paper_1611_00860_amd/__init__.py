@@ -528,6 +528,8 @@ def _host(x, name):
     if isinstance(x, np.ndarray):
         if x.dtype != np.float32 and name != "region":
             raise TypeError(f"{name} must be float32")
+        if x.size == 0:  # numpy gives empty arrays zero strides
+            return x.ctypes.data, 0, max(x.shape[-1] if x.ndim else 1, 1)
         ld = x.strides[0] // x.itemsize if x.ndim == 2 and x.shape[0] > 1 else (x.shape[-1] if x.ndim else 1)
         if x.ndim == 2 and x.shape[1] > 1 and x.strides[1] != x.itemsize:
             raise ValueError(f"{name} must have unit column stride (row-major)")
@@ -590,6 +592,44 @@ def sgemm_tracked(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", t
     _check(load().hpvm_sgemm_tracked(m, n, k, float(alpha), ctypes.c_void_p(pa), lda, ctypes.c_void_p(pb),
                                      ldb, float(beta), ctypes.c_void_p(pc), ldc, _prec(prec), _tile(tile),
                                      _stream(stream)))
+    return C
+
+
+# ---------------------------------------------------------------------------
+# CPU (vector) lowering of the same graph: a separate target on host memory
+# ---------------------------------------------------------------------------
+def cpu_menu() -> list:
+    lib = load()
+    count = ctypes.c_int32(0)
+    _check(lib.hpvm_cpu_menu(None, 0, ctypes.byref(count)))
+    arr = (_lib.Tile * count.value)()
+    _check(lib.hpvm_cpu_menu(arr, count.value, ctypes.byref(count)))
+    return [t.as_tuple() for t in arr]
+
+
+def cpu_isa() -> str:
+    return load().hpvm_cpu_isa().decode()
+
+
+def sgemm_cpu(A, B, C, alpha: float = 1.0, beta: float = 0.0, tile=None, threads: int = 0, k: int | None = None):
+    """C <- alpha A B + beta C on host arrays with the CPU lowering (synchronous); returns C.
+
+    A or B may be None when alpha == 0 or k == 0 (pass k then).
+    """
+    m, n = C.shape
+    if A is not None:
+        k = A.shape[1]
+    elif k is None:
+        raise ValueError("k is needed when A is None")
+    pa, _, lda = _host(A, "A") if A is not None else (0, 0, max(k, 1))
+    pb, _, ldb = _host(B, "B") if B is not None else (0, 0, max(n, 1))
+    pc, _, ldc = _host(C, "C")
+    if A is not None and tuple(A.shape) != (m, k):
+        raise ValueError("A must be m x k")
+    if B is not None and tuple(B.shape) != (k, n):
+        raise ValueError("B must be k x n")
+    _check(load().hpvm_sgemm_cpu(m, n, k, float(alpha), ctypes.c_void_p(pa), lda, ctypes.c_void_p(pb), ldb,
+                                 float(beta), ctypes.c_void_p(pc), ldc, _tile(tile), int(threads)))
     return C
 
 

@@ -133,6 +133,10 @@ SIGNATURES = {
     "hpvm_tracker_counters": (ctypes.c_int, [ctypes.POINTER(TrackerStats)]),
     "hpvm_sgemm_tracked": (ctypes.c_int, [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32,
                                           ctypes.POINTER(Tile), vp]),
+    "hpvm_cpu_menu": (ctypes.c_int, [ctypes.POINTER(Tile), i32, ctypes.POINTER(i32)]),
+    "hpvm_cpu_isa": (ctypes.c_char_p, []),
+    "hpvm_sgemm_cpu": (ctypes.c_int, [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64,
+                                      ctypes.POINTER(Tile), i32]),
     "hpvm_stream_open": (ctypes.c_int, [ctypes.POINTER(StreamConfig), ctypes.POINTER(vp)]),
     "hpvm_stream_push": (ctypes.c_int, [vp, ctypes.POINTER(SgemmDesc), ctypes.POINTER(i64)]),
     "hpvm_stream_pop": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp)]),

@@ -1,9 +1,10 @@
 """Build libhpvm_sgemm.so: the gfx950 kernels and the C-ABI host layer.
 
-Every ``csrc/*.hip`` file is compiled with hipcc for gfx950 only and linked
-into one shared library under ``lib/``.  Packed FP32 instructions are turned
-off (``-packed-fp32-ops``); hipcc's host pass warns that it does not know that
-feature, which is harmless.
+Every ``csrc/*.hip`` file is compiled with hipcc for gfx950 only, every
+``csrc/*.cpp`` file (host-only C++: the CPU lowering) with the host compiler,
+and all are linked into one shared library under ``lib/``.  Packed FP32
+instructions are turned off (``-packed-fp32-ops``); hipcc's host pass warns
+that it does not know that feature, which is harmless.
 """
 from __future__ import annotations
 
@@ -45,14 +46,30 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+CXX = os.environ.get("CXX", "g++")
+CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
+
+
+def _compile_host(src: str, verbose: bool) -> str:
+    """Host-only C++ (the CPU lowering): compiled by the host compiler."""
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = [CXX, *CXXFLAGS, "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"{CXX} failed on {src}:\n{res.stderr}")
+    return obj
+
+
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     """Compile every kernel source for gfx950 and link the library; returns its path."""
     os.makedirs(OBJDIR, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
-    sources = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    sources = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(len(sources), max(1, (os.cpu_count() or 2) // 2))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), sources))
+        objs = list(ex.map(lambda s: (_compile_host if s.endswith(".cpp") else _compile)(s, verbose), sources))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "host_common.hpp"
 #include "hpvm_sgemm.h"
 
 namespace hpvm {
@@ -62,26 +63,11 @@ int64_t literal_alloc_bytes(int block_x, int block_y);
 // C <- beta * C (beta == 0 writes zeros without reading C).
 hipError_t launch_scale(float* C, int64_t ldc, int64_t m, int64_t n, float beta, hipStream_t s);
 
-// Error state shared by every entry point (thread-local detail text).
-int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int clear_error();
-const char* last_error_text();
 int hip_error(hipError_t e, const char* what);
-bool fault_injected(const char* site);
-
-// Checks one sgemm's arguments in argument order (hpvm_sgemm's rules); `what`
-// prefixes the message (e.g. "instance 7: ").  *reads_ab tells whether A and
-// B are read at all (m, n, k > 0 and alpha != 0).
-int check_gemm_args(const char* what, int64_t m, int64_t n, int64_t k, float alpha, const float* A,
-                    int64_t lda, const float* B, int64_t ldb, float beta, const float* C,
-                    int64_t ldc, bool* reads_ab);
 
 // Autotuned tile for a problem: 2 exact entry, 1 shape-class entry, 0 none.
 // With allow_workspace the overall winner is returned, otherwise the best
 // tile that needs no workspace.
 int tuned_tile(int32_t prec, int64_t m, int64_t n, int64_t k, bool allow_workspace, hpvm_tile* out);
-
-// Byte range [lo, hi) of a row-major rows x cols float matrix.
-void matrix_extent(const void* p, int64_t rows, int64_t cols, int64_t ld, uintptr_t* lo, uintptr_t* hi);
 
 }  // namespace hpvm
