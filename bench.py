@@ -303,7 +303,7 @@ def variant_grouped(hp, inputs, dev, reps):
         "autotuned_ms": round(tuned_ms, 4), "max_instance_normwise_rel_error_sampled": worst, "bar": 1e-5}}
 
 
-def variant_stream(hp, inputs, dev, reps):
+def variant_stream(hp, inputs, dev, reps, capacity=256, grid=None):
     """The 512 uneven sgemms pushed one by one into a streaming graph.
 
     The argument structs are packed before the timed passes (the producer
@@ -321,8 +321,7 @@ def variant_stream(hp, inputs, dev, reps):
     Bs = [torch.from_numpy(x).to(dev) for x in Bs_h]
     Cs = [torch.from_numpy(x).to(dev) for x in Cs_h]
     flops = float(sum(2.0 * m * n * k for m, n, k in dims))
-    capacity = 64
-    grid = 2 * torch.cuda.get_device_properties(dev).multi_processor_count
+    grid = grid or 2 * torch.cuda.get_device_properties(dev).multi_processor_count
     packed = [hp.SgemmStream.pack(As[i], Bs[i], Cs[i], float(alphas[i]), float(betas[i])) for i in range(512)]
 
     def one_pass(st):

@@ -86,10 +86,17 @@ __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 
 __device__ __forceinline__ int acc_col(int lane) { return lane & 31; }
 
 // Epilogue: C <- alpha * acc + beta * C, element-wise, masked at the edges.
-// beta == 0 never reads C.
+// beta == 0 never reads C.  The 16 accumulators of a lane in a 32 x 32
+// block cover 4 groups of 4 consecutive rows; each group's 4 loads of C are
+// issued before its 4 stores.  (A load placed after a store to C could not
+// be moved above it -- the addresses may alias as far as the compiler
+// knows -- so element by element every load would wait for its own memory
+// round trip; four at a time keeps the address registers few enough not
+// to cost occupancy.)
 template <int BM, int BN>
 __device__ __forceinline__ void store_c(const GemmArgs& p, const f32x16 (&acc)[BM][BN], int row0,
                                         int col0, int lane) {
+  const bool read_c = p.beta != 0.0f;
 #pragma unroll
   for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
@@ -97,13 +104,21 @@ __device__ __forceinline__ void store_c(const GemmArgs& p, const f32x16 (&acc)[B
       const int j = col0 + 32 * bj + acc_col(lane);
       if (j >= p.n) continue;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = row0 + 32 * bi + acc_row(r, lane);
-        if (i < p.m) {
-          float* c = p.C + (int64_t)i * p.ldc + j;
-          float v = p.alpha * acc[bi][bj][r];
-          if (p.beta != 0.0f) v = fmaf(p.beta, *c, v);
-          *c = v;
+      for (int g = 0; g < 4; ++g) {
+        float c[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+          c[t] = (read_c && i < p.m) ? p.C[(int64_t)i * p.ldc + j] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+          if (i < p.m) {
+            float v = p.alpha * acc[bi][bj][4 * g + t];
+            if (read_c) v = fmaf(p.beta, c[t], v);
+            p.C[(int64_t)i * p.ldc + j] = v;
+          }
         }
       }
     }

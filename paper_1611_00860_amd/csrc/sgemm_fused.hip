@@ -54,11 +54,13 @@ __device__ __forceinline__ float consume(float v, float b, float lo, float hi) {
 }
 
 // D <- consumer(alpha * acc + beta * C), element-wise, masked at the edges.
-// C is read-only here (beta == 0 never reads it); D may be C itself.
+// C is read-only here (beta == 0 never reads it); D may be C itself.  As in
+// store_c, each group of 4 rows loads its C values before its stores.
 template <int OP, int BM, int BN>
 __device__ __forceinline__ void store_consumed(const GemmArgs& p, const ConsumerArgs& c,
                                                const f32x16 (&acc)[BM][BN], int row0, int col0, int lane) {
   constexpr bool kBias = OP == HPVM_CONSUMER_BIAS || OP == HPVM_CONSUMER_BIAS_RELU;
+  const bool read_c = p.beta != 0.0f;
 #pragma unroll
   for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
@@ -67,12 +69,21 @@ __device__ __forceinline__ void store_consumed(const GemmArgs& p, const Consumer
       if (j >= p.n) continue;
       const float b = kBias ? c.bias[j] : 0.0f;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = row0 + 32 * bi + acc_row(r, lane);
-        if (i < p.m) {
-          float v = p.alpha * acc[bi][bj][r];
-          if (p.beta != 0.0f) v = fmaf(p.beta, p.C[(int64_t)i * p.ldc + j], v);
-          c.D[(int64_t)i * c.ldd + j] = consume<OP>(v, b, c.lo, c.hi);
+      for (int g = 0; g < 4; ++g) {
+        float cin[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+          cin[t] = (read_c && i < p.m) ? p.C[(int64_t)i * p.ldc + j] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+          if (i < p.m) {
+            float v = p.alpha * acc[bi][bj][4 * g + t];
+            if (read_c) v = fmaf(p.beta, cin[t], v);
+            c.D[(int64_t)i * c.ldd + j] = consume<OP>(v, b, c.lo, c.hi);
+          }
         }
       }
     }

@@ -8,10 +8,12 @@
 // kernel.  Argument packs go into a ring of slots in pinned, coherent host
 // memory; the host publishes each with a release store of the ring's tail.
 // The resident workgroups take tickets from a device counter; the tiles of
-// item i are tickets [first_i, end_i), handed out in push order, so each
-// workgroup walks the ring forward until it finds the item holding its
-// ticket and runs that tile.  The workgroup that finishes an item's last
-// tile raises the item's completion flag in host memory, which pop waits on.
+// item i are tickets [first_i, end_i), handed out in push order.  At push
+// the host also writes, for every ticket of the item, the item's sequence
+// number into a ticket map (a window of kTicketWindow entries, tagged with
+// the ticket), so a workgroup finds the item that holds its ticket with one
+// read.  The workgroup that finishes an item's last tile raises the item's
+// completion flag in host memory, which pop waits on.
 //
 // Every wait in the kernel is bounded: a workgroup with nothing to do leaves
 // when the host has closed the stream, when another workgroup has ended it,
@@ -38,6 +40,10 @@
 namespace hpvm {
 
 constexpr uint64_t kSlotWriting = ~0ull;  // slot being rewritten by the host
+// Ticket map entries: tickets in flight (from the oldest unpopped item's
+// first ticket to the next ticket) never exceed this, so an entry is not
+// rewritten while a workgroup may still look it up.
+constexpr uint64_t kTicketWindow = 1ull << 18;
 
 // One argument pack as the kernel reads it (host memory).
 struct alignas(128) StreamSlot {
@@ -59,9 +65,8 @@ struct alignas(128) StreamCtl {
   uint32_t closed;  // host: no more pushes; drain and leave
   uint32_t status;  // kernel: 0 running, else why it ended the stream
 };
-constexpr uint32_t kStreamIdle = 2;      // nothing pushed for the idle limit
-constexpr uint32_t kStreamIncoherent = 3;  // a slot kept showing an older item
-constexpr int kMaxStaleReads = 1 << 20;
+constexpr uint32_t kStreamIdle = 2;  // nothing pushed for the idle limit
+
 
 __device__ __forceinline__ uint64_t ld_acquire(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -81,85 +86,85 @@ struct StreamTask {
   uint64_t seq;
 };
 
-// Thread 0: find the item that holds ticket t, starting from item *cur.
-// Returns false when the workgroup must leave.
-// The idle clock restarts whenever the tail moves: a workgroup whose ticket
-// lies far ahead of the pushed items is waiting, but the stream is not idle.
-__device__ bool stream_find(StreamCtl* ctl, const StreamSlot* slots, int cap, uint64_t t, uint64_t* cur,
-                            uint64_t idle_ticks, StreamTask* task) {
+// Ticket map entry: the ticket + 1 (0 = never written) and the item.
+struct TicketEntry {
+  uint64_t tag;  // ticket + 1, written last (release)
+  uint64_t seq;  // sequence number of the item holding the ticket
+};
+
+// Thread 0: find the item that holds ticket t.  Returns false when the
+// workgroup must leave.  The idle clock restarts whenever the tail moves:
+// a workgroup whose ticket lies ahead of the pushed items is waiting, but
+// the stream is not idle.
+__device__ bool stream_find(StreamCtl* ctl, const StreamSlot* slots, const TicketEntry* tmap, int cap,
+                            uint64_t t, uint64_t idle_ticks, StreamTask* task) {
+  const TicketEntry* e = tmap + (t & (kTicketWindow - 1));
   uint64_t last_tail = ld_acquire(&ctl->tail);
   uint64_t since = wall_clock64();
-  int backoff = 1, stale = 0;
+  int backoff = 1;
+  uint32_t polls = 0;
   for (;;) {
+    if (ld_acquire(&e->tag) == t + 1) {
+      // The item holding t stays in its slot until this tile is done, and
+      // the acquire above orders these plain loads after the host's writes
+      // of the slot, which is read as eight 16-byte loads issued together.
+      const uint64_t seq = e->seq;
+      const int s = (int)(seq % (uint64_t)cap);
+      StreamSlot slot;
+      {
+        const u32x4* src = reinterpret_cast<const u32x4*>(slots + s);
+        u32x4 v[sizeof(StreamSlot) / 16];
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(StreamSlot) / 16); ++i) v[i] = src[i];
+        __builtin_memcpy(&slot, v, sizeof slot);
+      }
+      const StreamSlot* q = &slot;
+      GemmArgs& p = task->p;
+      p.A = q->A;
+      p.B = q->B;
+      p.C = q->C;
+      p.lda = q->lda;
+      p.ldb = q->ldb;
+      p.ldc = q->ldc;
+      p.m = q->m;
+      p.n = q->n;
+      p.k = q->k;
+      p.alpha = q->alpha;
+      p.beta = q->beta;
+      p.vec_a = q->vec_a;
+      p.vec_b = q->vec_b;
+      p.tiles_m = 0;
+      p.tiles_n = 0;
+      task->shape = q->shape;
+      task->tiles_n = q->tiles_n;
+      task->exit = 0;
+      task->slot = s;
+      task->local = (int32_t)(t - q->first);
+      task->tiles = (uint32_t)(q->end - q->first);
+      task->seq = seq;
+      return true;
+    }
+    // Nothing pushed for this ticket yet: the entry is polled every time,
+    // the control words every 8th time.
+    if ((++polls & 7) != 0) {
+      for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(127);
+      continue;
+    }
+    if (ld_acquire32(&ctl->closed)) {
+      // A push before the close is visible now: look once more.
+      if (ld_acquire(&e->tag) == t + 1) continue;
+      return false;
+    }
+    if (ld_acquire32(&ctl->status) != 0) return false;
     const uint64_t tail = ld_acquire(&ctl->tail);
     if (tail != last_tail) {
       last_tail = tail;
       since = wall_clock64();
       backoff = 1;
-    }
-    if (wall_clock64() - since > idle_ticks) {
+    } else if (wall_clock64() - since > idle_ticks) {
       __hip_atomic_store(&ctl->status, kStreamIdle, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       return false;
     }
-    if (*cur < tail) {
-      const int s = (int)(*cur % (uint64_t)cap);
-      const StreamSlot* q = slots + s;
-      const uint64_t s1 = ld_acquire(&q->seq);
-      const volatile StreamSlot* vq = q;
-      const uint64_t first = vq->first, end = vq->end;
-      __atomic_thread_fence(__ATOMIC_ACQUIRE);
-      const uint64_t s2 = ld_acquire(&q->seq);
-      if (s1 != *cur || s2 != *cur) {
-        // The slot already holds a later item (or is being rewritten for
-        // one): item *cur is complete, so it cannot hold ticket t.
-        if (s1 > *cur && s2 > *cur) {
-          ++*cur;
-          continue;
-        }
-        // An older item: the tail's release should make that impossible.
-        if (++stale > kMaxStaleReads) {
-          __hip_atomic_store(&ctl->status, kStreamIncoherent, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-          return false;
-        }
-        continue;
-      }
-      if (t >= end) {
-        ++*cur;
-        continue;
-      }
-      // t is in [first, end): item *cur stays in its slot until this tile is done.
-      GemmArgs& p = task->p;
-      p.A = vq->A;
-      p.B = vq->B;
-      p.C = vq->C;
-      p.lda = vq->lda;
-      p.ldb = vq->ldb;
-      p.ldc = vq->ldc;
-      p.m = vq->m;
-      p.n = vq->n;
-      p.k = vq->k;
-      p.alpha = vq->alpha;
-      p.beta = vq->beta;
-      p.vec_a = vq->vec_a;
-      p.vec_b = vq->vec_b;
-      p.tiles_m = 0;
-      p.tiles_n = 0;
-      task->shape = vq->shape;
-      task->tiles_n = vq->tiles_n;
-      task->exit = 0;
-      task->slot = s;
-      task->local = (int32_t)(t - first);
-      task->tiles = (uint32_t)(end - first);
-      task->seq = *cur;
-      return true;
-    }
-    // Nothing pushed for this ticket yet.
-    if (ld_acquire32(&ctl->closed)) {
-      // Pushes that came before the close are visible now.
-      if (*cur < ld_acquire(&ctl->tail)) continue;
-      return false;
-    }
-    if (ld_acquire32(&ctl->status) != 0) return false;
     for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(127);
     backoff = backoff < 8 ? 2 * backoff : 8;
   }
@@ -177,15 +182,14 @@ template <class T>
 __device__ __forceinline__ T* uni(T* x) { return (T*)uni((int64_t)x); }
 
 __global__ void __launch_bounds__(kGroupedThreads)
-    sgemm_stream_f32(StreamCtl* ctl, const StreamSlot* slots, uint64_t* done, int32_t cap,
-                     unsigned long long* ticket, uint32_t* pending, uint64_t idle_ticks) {
+    sgemm_stream_f32(StreamCtl* ctl, const StreamSlot* slots, const TicketEntry* tmap, uint64_t* done,
+                     int32_t cap, unsigned long long* ticket, uint32_t* pending, uint64_t idle_ticks) {
   extern __shared__ __align__(16) float lds[];
   __shared__ StreamTask task;
-  uint64_t cur = 0;  // meaningful in thread 0 only
   for (;;) {
     if (threadIdx.x == 0) {
       const uint64_t t = atomicAdd(ticket, 1ull);
-      if (!stream_find(ctl, slots, cap, t, &cur, idle_ticks, &task)) task.exit = 1;
+      if (!stream_find(ctl, slots, tmap, cap, t, idle_ticks, &task)) task.exit = 1;
     }
     __syncthreads();
     if (task.exit) break;
@@ -206,12 +210,17 @@ __global__ void __launch_bounds__(kGroupedThreads)
     p.tiles_m = 0;
     p.tiles_n = 0;
     run_shape_tile(uni(task.shape), p, uni(task.tiles_n), uni(task.local), lds);
-    __threadfence();  // this lane's C stores, visible device-wide
+    // The tile's C stores: complete within the workgroup, then one
+    // device-scope release (a write-back of this XCD's L2) by thread 0
+    // before it counts the tile; the barrier carries the other lanes'
+    // stores into that release.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const uint32_t old = atomicAdd(pending + task.slot, 1u);
       if (old + 1 == task.tiles) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         atomicExch(pending + task.slot, 0u);  // ready for the slot's next item
         __hip_atomic_store(done + task.slot, task.seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
@@ -236,12 +245,14 @@ struct Stream {
   StreamCtl* ctl = nullptr;
   StreamSlot* slots = nullptr;
   uint64_t* done = nullptr;
+  TicketEntry* tmap = nullptr;
   // device counters
   void* dev = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t finished = nullptr;
   // host bookkeeping
   uint64_t pushed = 0, popped = 0, next_ticket = 0;
+  std::vector<uint64_t> first_ticket;  // per slot: first ticket of its item
   int64_t tiles = 0;
   bool ended = false;     // the kernel has exited
   hipError_t exit_error = hipSuccess;
@@ -304,9 +315,11 @@ void release(Stream* s) {
   delete s;
 }
 
+int64_t done_bytes(int cap) { return ((int64_t)cap * 8 + 127) / 128 * 128; }
+
 int64_t host_bytes(int cap) {
-  return (int64_t)sizeof(StreamCtl) + (int64_t)cap * (int64_t)sizeof(StreamSlot) +
-         ((int64_t)cap * 8 + 127) / 128 * 128;
+  return (int64_t)sizeof(StreamCtl) + (int64_t)cap * (int64_t)sizeof(StreamSlot) + done_bytes(cap) +
+         (int64_t)kTicketWindow * (int64_t)sizeof(TicketEntry);
 }
 
 // Waits (bounded) for the kernel to exit after `closed` is set.
@@ -383,6 +396,8 @@ int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
     s->ctl = (StreamCtl*)s->host;
     s->slots = (StreamSlot*)(s->host + sizeof(StreamCtl));
     s->done = (uint64_t*)(s->host + sizeof(StreamCtl) + (size_t)s->capacity * sizeof(StreamSlot));
+    s->tmap = (TicketEntry*)((char*)s->done + done_bytes(s->capacity));
+    s->first_ticket.assign((size_t)s->capacity, 0);
     for (int i = 0; i < s->capacity; ++i) s->slots[i].seq = kSlotWriting;
   }
   const size_t db = 256 + (size_t)s->capacity * 4;
@@ -393,6 +408,8 @@ int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
   StreamCtl* dctl = nullptr;
   StreamSlot* dslots = nullptr;
   uint64_t* ddone = nullptr;
+  TicketEntry* dtmap = nullptr;
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&dtmap, s->tmap, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&dctl, s->ctl, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&dslots, s->slots, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&ddone, s->done, 0);
@@ -401,7 +418,7 @@ int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
     uint32_t* pending = (uint32_t*)((char*)s->dev + 256);
     int32_t cap = s->capacity;
     uint64_t idle_ticks = (uint64_t)s->idle_ms * (uint64_t)rate_khz;
-    void* kargs[] = {&dctl, &dslots, &ddone, &cap, &ticket, &pending, &idle_ticks};
+    void* kargs[] = {&dctl, &dslots, &dtmap, &ddone, &cap, &ticket, &pending, &idle_ticks};
     e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_stream_f32), dim3(s->grid), dim3(kGroupedThreads),
                         kargs, (size_t)kGroupedLds, s->stream);
   }
@@ -460,6 +477,14 @@ int hpvm_stream_push(void* handle, const hpvm_sgemm_desc* item, int64_t* seq) {
   StreamSlot* q = s->slots + slot;
   const int shape = cost_model_shape(d.m, d.n, reads_ab ? d.k : 0, 1.0);
   const uint64_t tiles = (uint64_t)shape_tiles(d.m, d.n, shape);
+  if (tiles > kTicketWindow)
+    return set_error(HPVM_UNSUPPORTED, "argument 2: the item needs %llu tiles, more than the %llu a stream "
+                     "can hold in flight", (unsigned long long)tiles, (unsigned long long)kTicketWindow);
+  // Tickets in flight stay within the ticket map's window.
+  const uint64_t oldest = s->popped < s->pushed ? s->first_ticket[s->popped % (uint64_t)s->capacity]
+                                                 : s->next_ticket;
+  if (s->next_ticket + tiles - oldest > kTicketWindow)
+    return set_error(HPVM_QUEUE_FULL, "argument 1: the items in flight hold too many tiles; pop first");
   host_store(&q->seq, kSlotWriting);
   q->first = s->next_ticket;
   q->end = s->next_ticket + tiles;
@@ -479,6 +504,12 @@ int hpvm_stream_push(void* handle, const hpvm_sgemm_desc* item, int64_t* seq) {
   q->vec_a = vec16(d.A, d.lda);
   q->vec_b = vec16(d.B, d.ldb);
   host_store(&q->seq, sq);
+  s->first_ticket[slot] = s->next_ticket;
+  for (uint64_t t = s->next_ticket; t < s->next_ticket + tiles; ++t) {
+    TicketEntry* te = s->tmap + (t & (kTicketWindow - 1));
+    te->seq = sq;
+    host_store(&te->tag, t + 1);
+  }
   if (tiles == 0) host_store(s->done + slot, sq + 1);  // nothing for the kernel to do
   s->next_ticket += tiles;
   s->tiles += (int64_t)tiles;
@@ -496,18 +527,26 @@ int hpvm_stream_pop(void* handle, int32_t timeout_ms, int64_t* seq, float** C) {
   if (s->popped == s->pushed) return set_error(HPVM_INVALID_ARG, "argument 1: no item in flight to pop");
   const uint64_t sq = s->popped;
   const int slot = (int)(sq % (uint64_t)s->capacity);
-  const auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
-  int spins = 0;
-  while (host_load(s->done + slot) != sq + 1) {
-    if (host_load32(&s->ctl->status) != 0 || kernel_exited(s)) {
+  // The completion flag is in coherent host memory, so polling it is a
+  // cached load.  Spin (yielding) for the first 2 ms -- a sleep costs tens
+  // of microseconds of timer slack per item -- then poll every 50 us.
+  const auto start = std::chrono::steady_clock::now();
+  const auto until = start + std::chrono::milliseconds(timeout_ms);
+  const auto spin_until = start + std::chrono::milliseconds(2);
+  for (uint64_t spins = 0; host_load(s->done + slot) != sq + 1; ++spins) {
+    if (spins % 256 == 255 && (host_load32(&s->ctl->status) != 0 || kernel_exited(s))) {
       if (host_load(s->done + slot) == sq + 1) break;
       if (s->exit_error != hipSuccess) return hip_error(s->exit_error, "streaming kernel");
       return set_error(HPVM_STREAM_ENDED, "the streaming kernel ended before item %llu completed",
                        (unsigned long long)sq);
     }
-    if (std::chrono::steady_clock::now() >= until)
+    const auto now = std::chrono::steady_clock::now();
+    if (now >= until)
       return set_error(HPVM_TIMEOUT, "item %llu not complete after %d ms", (unsigned long long)sq, timeout_ms);
-    if (++spins > 64) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    if (now < spin_until)
+      std::this_thread::yield();
+    else
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
   if (seq) *seq = (int64_t)sq;
   if (C) *C = s->slots[slot].C;
