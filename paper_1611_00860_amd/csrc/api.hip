@@ -282,6 +282,8 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   if (rc != HPVM_OK) return rc;
   const int64_t need = hpvm::entry_workspace_bytes(entry, m, n, k);
   if (need > 0 && reads_ab) {
+    if (!hpvm::staged_k_ok(k))
+      return fail(HPVM_UNSUPPORTED, "argument 13: k = %lld is too deep for a tile with stages = 3", (long long)k);
     if (!ws_ok)
       return fail(HPVM_UNSUPPORTED, "argument 13: tile with stages = 3 needs a workspace (use hpvm_sgemm_ws)");
     if (!workspace) return fail(HPVM_INVALID_ARG, "argument 14: workspace is NULL");

@@ -120,6 +120,7 @@ int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A,
     for (int i = 0; i < count && e == hipSuccess; ++i) {
       const MfmaEntry* me = menu_entry_at(prec, i);
       if (entry_workspace_bytes(me, m, n, k) > workspace_bytes) continue;
+      if (me->launch_staged && !staged_k_ok(k)) continue;
       rc = run(me);
       if (rc != HPVM_OK) break;
       e = hipEventRecord(e0, s);

@@ -43,6 +43,10 @@ int staged_menu(int32_t prec, const MfmaEntry** entries);
 // Workspace bytes the staged lowering needs for one m x n x k product.
 int64_t staged_workspace_bytes(int32_t prec, int64_t m, int64_t n, int64_t k);
 
+// Deepest contraction a staged tile takes: its loads address a tile's
+// rows of a bfloat16 plane with 32-bit byte offsets.
+bool staged_k_ok(int64_t k);
+
 // Every compiled entry of a precision: fused first (entry 0 is the default),
 // then staged.  Returns nullptr past the end.
 const MfmaEntry* menu_entry_at(int32_t prec, int index);

@@ -169,8 +169,10 @@ const BwdEntry* pick(int32_t prec, int64_t m, int64_t n, int64_t k) {
     if (e) return e;
   }
   const BwdEntry* most = nullptr;
+  const bool staged_ok = staged_k_ok(n) && staged_k_ok(m);  // the dA and dB contractions
   for (int i = 0; i < kNumBwd; ++i) {
     if (kBwd[i].prec != prec) continue;
+    if (!kBwd[i].grad_a && !staged_ok) continue;
     if (tiles_for(kBwd[i].tile, m, k) >= kTargetTiles) return &kBwd[i];
     if (!most || tiles_for(kBwd[i].tile, m, k) > tiles_for(most->tile, m, k)) most = &kBwd[i];
   }
@@ -216,6 +218,8 @@ int resolve_bwd(int32_t prec, const hpvm_tile* tile, int64_t m, int64_t n, int64
   if (!*out)
     return set_error(HPVM_UNSUPPORTED, "argument %d: tile not in the backward menu for precision %d", argno,
                      prec);
+  if (!(*out)->grad_a && !(staged_k_ok(n) && staged_k_ok(m)))
+    return set_error(HPVM_UNSUPPORTED, "argument %d: m or n too deep a contraction for a staged tile", argno);
   return HPVM_OK;
 }
 
@@ -430,6 +434,7 @@ int hpvm_autotune_backward(int64_t m, int64_t n, int64_t k, int32_t prec, const 
     for (int i = 0; i < kNumBwd && e == hipSuccess; ++i) {
       const BwdEntry* c = &kBwd[i];
       if (c->prec != prec) continue;
+      if (!c->grad_a && !(staged_k_ok(n) && staged_k_ok(m))) continue;
       const BwdLayout L = bwd_layout(c, m, n, k);
       if (L.total + 256 > workspace_bytes) continue;
       // the last 256 bytes of the workspace hold dalpha

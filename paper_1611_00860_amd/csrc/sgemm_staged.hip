@@ -35,6 +35,11 @@ struct StagedLayout {
   int64_t total;
 };
 
+bool staged_k_ok(int64_t k) {
+  const int64_t k_pad = (k + kPadK - 1) / kPadK * kPadK;
+  return (int64_t)kPadMN * k_pad * 2 < ((int64_t)1 << 32);
+}
+
 static StagedLayout staged_layout(int32_t prec, int64_t m, int64_t n, int64_t k) {
   StagedLayout L;
   L.m_pad = (m + kPadMN - 1) / kPadMN * kPadMN;
@@ -183,20 +188,23 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
   auto b_st = [&](int st, int pl) { return smem + st * T::kStageBytes + P * T::kABytes + pl * T::kBBytes; };
 
   u32x4 ra[DEPTH][P * UA], rb[DEPTH][P * UB];
+  // A unit's address is a workgroup-uniform base (the plane's tile corner
+  // plus the slab) and a 32-bit per-lane byte offset (planes are under
+  // 4 GiB): one register per load instead of a 64-bit address.
+  auto unit_off = [&](int j) {
+    const int u = tid + j * NT, r = u / kUnitsPerRow, c = (u % kUnitsPerRow) * 8;
+    return (uint32_t)(((int64_t)r * p.kp + c) * 2);
+  };
   auto load = [&](u32x4(&a)[P * UA], u32x4(&b)[P * UB], int slab) {
     const int64_t k0 = (int64_t)slab * TK;
 #pragma unroll
     for (int pl = 0; pl < P; ++pl) {
+      const char* abase = reinterpret_cast<const char*>(aplane[pl] + k0);
+      const char* bbase = reinterpret_cast<const char*>(bplane[pl] + k0);
 #pragma unroll
-      for (int j = 0; j < UA; ++j) {
-        const int u = tid + j * NT, r = u / kUnitsPerRow, c = (u % kUnitsPerRow) * 8;
-        a[pl * UA + j] = *reinterpret_cast<const u32x4*>(aplane[pl] + r * p.kp + k0 + c);
-      }
+      for (int j = 0; j < UA; ++j) a[pl * UA + j] = *reinterpret_cast<const u32x4*>(abase + unit_off(j));
 #pragma unroll
-      for (int j = 0; j < UB; ++j) {
-        const int u = tid + j * NT, r = u / kUnitsPerRow, c = (u % kUnitsPerRow) * 8;
-        b[pl * UB + j] = *reinterpret_cast<const u32x4*>(bplane[pl] + r * p.kp + k0 + c);
-      }
+      for (int j = 0; j < UB; ++j) b[pl * UB + j] = *reinterpret_cast<const u32x4*>(bbase + unit_off(j));
     }
   };
   auto store = [&](const u32x4(&a)[P * UA], const u32x4(&b)[P * UB], int st) {
@@ -235,23 +243,30 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
     }
   } else {
     load(ra[0], rb[0], 0);
-    if (S > 1) load(ra[1], rb[1], 1);
+    load(ra[1], rb[1], S > 1 ? 1 : 0);
     store(ra[0], rb[0], 0);
     __syncthreads();
-    if (S > 2) load(ra[0], rb[0], 2);
+    load(ra[0], rb[0], S > 2 ? 2 : S - 1);
     // One slab: multiply stage B, move slab s + 1 (register buffer B ^ 1)
-    // into stage B ^ 1, refill that buffer with slab s + 3.
+    // into stage B ^ 1, refill that buffer with slab s + 3.  No branch in
+    // a step: past the end the store fills a stage nobody reads and the
+    // load re-reads the last slab.  The compiler's wait counting then
+    // sees the same loads in flight on every path through the loop and
+    // waits only for the older buffer's loads before the store, leaving
+    // the newer buffer's in flight (with branches it waited for all).
     auto step = [&](auto parity, int s) {
       constexpr int B = decltype(parity)::value;
       mfma_stage(B);
-      if (s + 1 < S) store(ra[B ^ 1], rb[B ^ 1], B ^ 1);
-      if (s + 3 < S) load(ra[B ^ 1], rb[B ^ 1], s + 3);
+      store(ra[B ^ 1], rb[B ^ 1], B ^ 1);
+      load(ra[B ^ 1], rb[B ^ 1], s + 3 < S ? s + 3 : S - 1);
       __syncthreads();
     };
-    for (int s = 0; s < S; s += 2) {
+    int s = 0;
+    for (; s + 1 < S; s += 2) {
       step(std::integral_constant<int, 0>{}, s);
-      if (s + 1 < S) step(std::integral_constant<int, 1>{}, s + 1);
+      step(std::integral_constant<int, 1>{}, s + 1);
     }
+    if (s < S) step(std::integral_constant<int, 0>{}, s);
   }
 
   if constexpr (EPI == 0) {

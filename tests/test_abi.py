@@ -536,3 +536,25 @@ def test_tracker_table_host_side(lib, monkeypatch):
     with pytest.raises(hp.HpvmError):
         hp.tracked_state(A)
 
+
+
+def test_staged_tiles_refuse_too_deep_a_contraction(lib):
+    """Staged loads use 32-bit offsets within a tile's rows of a plane: k must
+    stay below 2^32 / (256 rows * 2 bytes) once padded; deeper k is refused."""
+    BIG = 1 << 40  # fake, never dereferenced: the check comes first
+    staged = [t for t in hp.tile_menu("bf16") if t[5] == 3][0]
+    t = ctypes.byref(_lib.Tile(*staged))
+    k = 1 << 23
+    rc = lib.hpvm_sgemm_ws(4, 4, k, 1.0, BIG, k, BIG * 2, 4, 0.0, BIG * 3, 4, hp.PREC["bf16"], t,
+                           BIG * 4, 1 << 40, None)
+    assert rc == -2 and "too deep" in hp.last_error()
+    # one padded block less is accepted (stopped by the fault injection instead)
+    import os
+    os.environ["HPVM_FAULT_INJECT"] = "launch"
+    try:
+        k = (1 << 23) - 64
+        rc = lib.hpvm_sgemm_ws(4, 4, k, 1.0, BIG, k, BIG * 2, 4, 0.0, BIG * 3, 4, hp.PREC["bf16"], t,
+                               BIG * 4, 1 << 40, None)
+        assert rc == -3
+    finally:
+        del os.environ["HPVM_FAULT_INJECT"]
