@@ -123,11 +123,6 @@ bool literal_ok(const hpvm_tile& t) {
          lanes % hpvm::kWave == 0 && t.tile_k == t.tile_m && t.stages == 1;
 }
 
-bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
-  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k &&
-         a.leaf_m == b.leaf_m && a.leaf_n == b.leaf_n && a.stages == b.stages;
-}
-
 const hpvm::MfmaEntry* find_entry(int32_t prec, const hpvm_tile* tile) {
   if (!tile) return hpvm::menu_entry_at(prec, 0);
   return hpvm::find_menu_entry(prec, *tile);
@@ -156,8 +151,6 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
   }
   return HPVM_OK;
 }
-
-bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
 
 }  // namespace
 
@@ -314,8 +307,8 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   a.k = (int32_t)k;
   a.alpha = alpha;
   a.beta = beta;
-  a.vec_a = aligned16(A, lda);
-  a.vec_b = aligned16(B, ldb);
+  a.vec_a = hpvm::vec16(A, lda);
+  a.vec_b = hpvm::vec16(B, ldb);
   if (entry && entry->launch_staged)
     e = entry->launch_staged(a, workspace, s);
   else if (entry)

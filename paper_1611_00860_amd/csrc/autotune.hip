@@ -40,11 +40,6 @@ Key class_key(int32_t prec, int64_t m, int64_t n, int64_t k) {
   return Key{prec, clog2(m), clog2(n), clog2(k), 1};
 }
 
-bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
-  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k && a.leaf_m == b.leaf_m &&
-         a.leaf_n == b.leaf_n && a.stages == b.stages;
-}
-
 bool in_menu(int32_t prec, const hpvm_tile& t) { return find_menu_entry(prec, t) != nullptr; }
 
 bool needs_workspace(int32_t prec, const hpvm_tile& t) {

@@ -5,7 +5,18 @@
 
 #include <stdint.h>
 
+#include "hpvm_sgemm.h"
+
 namespace hpvm {
+
+// An operand allows 16-byte vector loads: 16-byte aligned base and a
+// leading dimension that keeps every row 16-byte aligned.
+inline bool vec16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
+
+inline bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
+  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k && a.leaf_m == b.leaf_m &&
+         a.leaf_n == b.leaf_n && a.stages == b.stages;
+}
 
 // Error state shared by every entry point (thread-local detail text).
 int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));

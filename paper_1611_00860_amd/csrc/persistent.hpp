@@ -13,6 +13,7 @@
 #include <cstdint>
 
 #include "device_common.hpp"
+#include "host_common.hpp"
 #include "hpvm_sgemm.h"
 #include "mfma_f32.hpp"
 
@@ -85,7 +86,5 @@ inline int cost_model_shape(int64_t m, int64_t n, int64_t k, double lambda) {
   }
   return best;
 }
-
-inline bool vec16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
 
 }  // namespace hpvm

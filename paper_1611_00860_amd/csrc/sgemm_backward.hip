@@ -144,11 +144,6 @@ const BwdEntry kBwd[] = {
 };
 constexpr int kNumBwd = sizeof(kBwd) / sizeof(kBwd[0]);
 
-bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
-  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k && a.leaf_m == b.leaf_m &&
-         a.leaf_n == b.leaf_n && a.stages == b.stages;
-}
-
 int64_t tiles_for(const hpvm_tile& t, int64_t rows, int64_t cols) {
   return ((rows + t.tile_m - 1) / t.tile_m) * ((cols + t.tile_n - 1) / t.tile_n);
 }
@@ -204,8 +199,6 @@ BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
   L.total = L.stage_off + stage;
   return L;
 }
-
-bool aligned16(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int32_t, int64_t, int64_t, int64_t>, hpvm_tile> g_tuned;
@@ -336,8 +329,8 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     a.k = (int32_t)n;
     a.alpha = alpha;
     a.beta = 0.0f;
-    a.vec_a = aligned16(G, ldg);
-    a.vec_b = aligned16(B, ldb);
+    a.vec_a = vec16(G, ldg);
+    a.vec_b = vec16(B, ldb);
     a.tiles_m = (a.m + cfg->tile.tile_m - 1) / cfg->tile.tile_m;
     a.tiles_n = (a.n + cfg->tile.tile_n - 1) / cfg->tile.tile_n;
     if (staged) {
@@ -379,8 +372,8 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     b.k = (int32_t)m;
     b.alpha = alpha;
     b.beta = 0.0f;
-    b.vec_a = aligned16(A, lda);
-    b.vec_b = aligned16(G, ldg);
+    b.vec_a = vec16(A, lda);
+    b.vec_b = vec16(G, ldg);
     if (!me) e = hipErrorInvalidValue;
     else if (staged) e = me->launch_staged_form(b, true, false, stage, nullptr, 0, nullptr, s);
     else e = me->launch(b, true, false, s);

@@ -225,11 +225,6 @@ void worker(const Problem& P, std::atomic<int64_t>* next, int64_t tiles_n, int64
   std::free(Cb);
 }
 
-bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
-  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k && a.leaf_m == b.leaf_m &&
-         a.leaf_n == b.leaf_n && a.stages == b.stages;
-}
-
 }  // namespace
 }  // namespace hpvm
 

@@ -298,18 +298,11 @@ static const FusedEntry kPairMenu[] = {
 constexpr int kNumConsumer = (int)(sizeof(kConsumerMenu) / sizeof(kConsumerMenu[0]));
 constexpr int kNumPair = (int)(sizeof(kPairMenu) / sizeof(kPairMenu[0]));
 
-bool same_tile(const hpvm_tile& a, const hpvm_tile& b) {
-  return a.tile_m == b.tile_m && a.tile_n == b.tile_n && a.tile_k == b.tile_k && a.leaf_m == b.leaf_m &&
-         a.leaf_n == b.leaf_n && a.stages == b.stages;
-}
-
 const FusedEntry* find_fused(const FusedEntry* menu, int count, const hpvm_tile& t) {
   for (int i = 0; i < count; ++i)
     if (same_tile(menu[i].tile, t)) return &menu[i];
   return nullptr;
 }
-
-bool vec_ok(const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); }
 
 bool ranges_meet(const float* a, int64_t ra, int64_t ca, int64_t lda, const float* b, int64_t rb, int64_t cb,
                  int64_t ldb) {
@@ -398,8 +391,8 @@ int hpvm_sgemm_consumer(int64_t m, int64_t n, int64_t k, float alpha, const floa
   g.k = reads_ab ? (int32_t)k : 0;  // k == 0 or alpha == 0: A and B are not read
   g.alpha = alpha;
   g.beta = beta;
-  g.vec_a = vec_ok(A, lda);
-  g.vec_b = vec_ok(B, ldb);
+  g.vec_a = vec16(A, lda);
+  g.vec_b = vec16(B, ldb);
   ConsumerArgs c{};
   c.D = D;
   c.ldd = ldd;
@@ -451,21 +444,21 @@ int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda
   g1.m = g2.m = (int32_t)m;
   g1.n = g2.n = (int32_t)n;
   g1.k = g2.k = (int32_t)k;
-  g1.vec_a = g2.vec_a = vec_ok(A, lda);
+  g1.vec_a = g2.vec_a = vec16(A, lda);
   g1.B = B1;
   g1.ldb = ldb1;
   g1.C = C1;
   g1.ldc = ldc1;
   g1.alpha = alpha1;
   g1.beta = beta1;
-  g1.vec_b = vec_ok(B1, ldb1);
+  g1.vec_b = vec16(B1, ldb1);
   g2.B = B2;
   g2.ldb = ldb2;
   g2.C = C2;
   g2.ldc = ldc2;
   g2.alpha = alpha2;
   g2.beta = beta2;
-  g2.vec_b = vec_ok(B2, ldb2);
+  g2.vec_b = vec16(B2, ldb2);
   const hipError_t he = e->pair(g1, g2, reinterpret_cast<hipStream_t>(stream));
   return he == hipSuccess ? clear_error() : hip_error(he, "pair launch");
 }

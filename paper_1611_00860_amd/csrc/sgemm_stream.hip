@@ -39,7 +39,6 @@
 
 namespace hpvm {
 
-constexpr uint64_t kSlotWriting = ~0ull;  // slot being rewritten by the host
 // Ticket map entries: tickets in flight (from the oldest unpopped item's
 // first ticket to the next ticket) never exceed this, so an entry is not
 // rewritten while a workgroup may still look it up.
@@ -47,7 +46,7 @@ constexpr uint64_t kTicketWindow = 1ull << 18;
 
 // One argument pack as the kernel reads it (host memory).
 struct alignas(128) StreamSlot {
-  uint64_t seq;    // sequence number of the item held; kSlotWriting while rewritten
+  uint64_t seq;    // sequence number of the item held (for inspection)
   uint64_t first;  // first ticket of the item
   uint64_t end;    // one past its last ticket
   const float* A;
@@ -398,7 +397,6 @@ int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
     s->done = (uint64_t*)(s->host + sizeof(StreamCtl) + (size_t)s->capacity * sizeof(StreamSlot));
     s->tmap = (TicketEntry*)((char*)s->done + done_bytes(s->capacity));
     s->first_ticket.assign((size_t)s->capacity, 0);
-    for (int i = 0; i < s->capacity; ++i) s->slots[i].seq = kSlotWriting;
   }
   const size_t db = 256 + (size_t)s->capacity * 4;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
@@ -485,7 +483,6 @@ int hpvm_stream_push(void* handle, const hpvm_sgemm_desc* item, int64_t* seq) {
                                                  : s->next_ticket;
   if (s->next_ticket + tiles - oldest > kTicketWindow)
     return set_error(HPVM_QUEUE_FULL, "argument 1: the items in flight hold too many tiles; pop first");
-  host_store(&q->seq, kSlotWriting);
   q->first = s->next_ticket;
   q->end = s->next_ticket + tiles;
   q->A = d.A;
@@ -503,7 +500,7 @@ int hpvm_stream_push(void* handle, const hpvm_sgemm_desc* item, int64_t* seq) {
   q->tiles_n = (int32_t)((d.n + kGroupedShapes[shape].tile.tile_n - 1) / kGroupedShapes[shape].tile.tile_n);
   q->vec_a = vec16(d.A, d.lda);
   q->vec_b = vec16(d.B, d.ldb);
-  host_store(&q->seq, sq);
+  q->seq = sq;
   s->first_ticket[slot] = s->next_ticket;
   for (uint64_t t = s->next_ticket; t < s->next_ticket + tiles; ++t) {
     TicketEntry* te = s->tmap + (t & (kTicketWindow - 1));

@@ -168,3 +168,17 @@ def test_stream_many_random_items(gpu):
     for (A, B, C), (_, _, dC) in zip(data, dev):
         worst = max(worst, normwise(to_host(dC), oracle.sgemm(A, B, C, 1.25, 0.5)))
     assert worst <= 1e-5, worst
+
+
+def test_stream_refuses_an_item_larger_than_the_ticket_window(gpu):
+    """An item needing more tiles than the stream can hold in flight is refused
+    at push (its pointers are never used: the check comes first)."""
+    from paper_1611_00860_amd import _lib
+
+    with gpu.SgemmStream(capacity=4, idle_ms=10000) as st:
+        fake = 1 << 44
+        n = 70000  # ceil(70000 / 128)^2 > 2^18 tiles of 128 x 128
+        d = _lib.SgemmDesc(n, n, 1, 1.0, 0.0, fake, 1, fake + (1 << 40), n, fake + (2 << 40), n)
+        rc = gpu.load().hpvm_stream_push(st._h, ctypes.byref(d), None)
+        assert rc == -2 and "tiles" in gpu.last_error()
+        assert st.info()["pushed"] == 0
