@@ -158,10 +158,12 @@ def gather(t, rows, cols):
 
 
 def event_time(fn, reps, stream):
-    """Milliseconds per call of fn() from HIP events recorded on `stream`."""
+    """Milliseconds per call of fn() from HIP events recorded on `stream`
+    (after one untimed call, which loads whatever code it needs)."""
     import torch
 
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
     torch.cuda.synchronize()
     a.record(stream)
     for _ in range(reps):

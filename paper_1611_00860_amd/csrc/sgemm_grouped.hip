@@ -41,10 +41,12 @@ struct alignas(16) GroupDesc {
   int32_t vec_a, vec_b;
 };
 
+// Three workgroups per CU (the register budget the attribute asks for fits
+// without spills; LDS allows it too).
 // Persistent kernel.  Every workgroup loops: take the next tile index from
 // the shared counter, find its instance and position, run that tile.  All
 // workgroups leave once the list is exhausted.
-__global__ void __launch_bounds__(kGroupedThreads)
+__global__ void __launch_bounds__(kGroupedThreads) __attribute__((amdgpu_waves_per_eu(3)))
     sgemm_grouped_f32(const GroupDesc* __restrict__ descs, const int32_t* __restrict__ tile_inst,
                       int32_t total_tiles, int32_t* counter) {
   extern __shared__ __align__(16) float lds[];

@@ -12,10 +12,18 @@
 
 namespace hpvm {
 
+// Waves per SIMD the register allocation must leave room for.  The
+// 128 x 128 x 16 tile fits four resident workgroups per CU without spills
+// (with its 38 KB of LDS each), so 4096^3 runs its 1024 tiles in one wave
+// of workgroups instead of 768 and then 256; the other tiles keep the
+// compiler's choice (forcing them spills).
+template <int TM, int TN, int TK>
+constexpr int kF32MinWaves = (TM == 128 && TN == 128 && TK == 16) ? 4 : 1;
+
 // FP32 kernel: v_mfma_f32_32x32x2f32, FP32 operands and accumulation.
 template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT>
 __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
-    sgemm_mfma_f32(GemmArgs p) {
+    __attribute__((amdgpu_waves_per_eu(kF32MinWaves<TM, TN, TK>))) sgemm_mfma_f32(GemmArgs p) {
   extern __shared__ __align__(16) float lds[];
   int tm, tn;
   tile_coords(p.tiles_m, p.tiles_n, blockIdx.x, tm, tn);

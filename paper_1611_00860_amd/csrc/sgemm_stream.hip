@@ -180,7 +180,7 @@ __device__ __forceinline__ int64_t uni(int64_t x) {
 template <class T>
 __device__ __forceinline__ T* uni(T* x) { return (T*)uni((int64_t)x); }
 
-__global__ void __launch_bounds__(kGroupedThreads)
+__global__ void __launch_bounds__(kGroupedThreads) __attribute__((amdgpu_waves_per_eu(3)))
     sgemm_stream_f32(StreamCtl* ctl, const StreamSlot* slots, const TicketEntry* tmap, uint64_t* done,
                      int32_t cap, unsigned long long* ticket, uint32_t* pending, uint64_t idle_ticks) {
   extern __shared__ __align__(16) float lds[];
