@@ -39,6 +39,9 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int row0 = tm * TM + (wave / (TN / WN)) * WM;
   const int col0 = tn * TN + (wave % (TN / WN)) * WN;
+  // Each group of 4 rows loads its elements of A before storing its dA
+  // values (a load after a possibly aliasing store would wait for a full
+  // memory round trip, element by element).
   float part = 0.0f;
 #pragma unroll
   for (int bi = 0; bi < BM; ++bi)
@@ -47,12 +50,21 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
       const int j = col0 + 32 * bj + acc_col(lane);
       if (j >= p.n) continue;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = row0 + 32 * bi + acc_row(r, lane);
-        if (i < p.m) {
-          const float v = acc[bi][bj][r];
-          if (p.C) p.C[(int64_t)i * p.ldc + j] = p.alpha * v;
-          part = fmaf(Aorig[(int64_t)i * lda + j], v, part);
+      for (int g = 0; g < 4; ++g) {
+        float a[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+          a[t] = i < p.m ? Aorig[(int64_t)i * lda + j] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+          if (i < p.m) {
+            const float v = acc[bi][bj][4 * g + t];
+            if (p.C) p.C[(int64_t)i * p.ldc + j] = p.alpha * v;
+            part = fmaf(a[t], v, part);
+          }
         }
       }
     }
@@ -64,18 +76,37 @@ constexpr int kElemThreads = 256;
 constexpr int kElemBlocks = 1024;
 
 // dC_in = beta G (zeros when beta == 0) and per-block partials of <G, C_in>.
+// Rows are dealt to blocks in turn; a block's threads walk a row in 16-byte
+// units when every matrix it touches allows them (vec), one element at a
+// time otherwise.  The element-to-thread assignment depends only on m, n
+// and the grid, so the partials repeat bit for bit.
 __global__ void __launch_bounds__(kElemThreads)
     sgemm_grad_c(const float* __restrict__ G, int64_t ldg, const float* __restrict__ Cin, int64_t ldci,
                  float* __restrict__ dCin, int64_t lddci, int64_t m, int64_t n, float beta,
-                 float* __restrict__ partial) {
+                 float* __restrict__ partial, int32_t vec) {
   __shared__ float red[kElemThreads / kWave];
-  const int64_t total = m * n;
   float part = 0.0f;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / n, j = e - i * n;
-    const float g = G[i * ldg + j];
-    if (dCin) dCin[i * lddci + j] = (beta == 0.0f) ? 0.0f : beta * g;
-    if (partial) part = fmaf(g, Cin[i * ldci + j], part);
+  const int64_t n4 = vec ? n / 4 : 0;
+  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const float* g = G + i * ldg;
+    const float* c = partial ? Cin + i * ldci : nullptr;
+    float* d = dCin ? dCin + i * lddci : nullptr;
+    for (int64_t q = threadIdx.x; q < n4; q += blockDim.x) {
+      const f32x4 gv = reinterpret_cast<const f32x4*>(g)[q];
+      if (d) reinterpret_cast<f32x4*>(d)[q] = (beta == 0.0f) ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : beta * gv;
+      if (c) {
+        const f32x4 cv = reinterpret_cast<const f32x4*>(c)[q];
+        part = fmaf(gv[0], cv[0], part);
+        part = fmaf(gv[1], cv[1], part);
+        part = fmaf(gv[2], cv[2], part);
+        part = fmaf(gv[3], cv[3], part);
+      }
+    }
+    for (int64_t j = 4 * n4 + threadIdx.x; j < n; j += blockDim.x) {
+      const float gv = g[j];
+      if (d) d[j] = (beta == 0.0f) ? 0.0f : beta * gv;
+      if (c) part = fmaf(gv, c[j], part);
+    }
   }
   if (!partial) return;
   const float s = block_sum(part, red);
@@ -388,7 +419,8 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     float* dCp = dC_in;
     int64_t ldg_ = ldg, ldci_ = ldci, lddci_ = lddci, m_ = m, n_ = n;
     float beta_ = beta;
-    void* kargs[] = {&Gp, &ldg_, &Cp, &ldci_, &dCp, &lddci_, &m_, &n_, &beta_, &part};
+    int32_t vec = vec16(G, ldg) && (!dC_in || vec16(dC_in, lddci)) && (!part || vec16(C_in, ldci));
+    void* kargs[] = {&Gp, &ldg_, &Cp, &ldci_, &dCp, &lddci_, &m_, &n_, &beta_, &part, &vec};
     e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_grad_c), dim3((unsigned)L.nb), dim3(kElemThreads),
                         kargs, 0, s);
   }

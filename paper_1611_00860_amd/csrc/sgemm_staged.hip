@@ -279,6 +279,7 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
     e.beta = p.beta;
     store_c<BM, BN>(e, acc, (int)m0 + wm0, (int)n0 + wn0, lane);
   } else {
+    // Each group of 4 rows loads its elements of A before its dA stores.
     float part = 0.0f;
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
@@ -287,12 +288,21 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
         const int j = (int)n0 + wn0 + 32 * bj + acc_col(lane);
         if (j >= p.n) continue;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int i = (int)m0 + wm0 + 32 * bi + acc_row(r, lane);
-          if (i < p.m) {
-            const float v = acc[bi][bj][r];
-            if (p.C) p.C[(int64_t)i * p.ldc + j] = p.alpha * v;
-            part = fmaf(p.aorig[(int64_t)i * p.lda_orig + j], v, part);
+        for (int g = 0; g < 4; ++g) {
+          float a[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i = (int)m0 + wm0 + 32 * bi + acc_row(4 * g + t, lane);
+            a[t] = i < p.m ? p.aorig[(int64_t)i * p.lda_orig + j] : 0.0f;
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i = (int)m0 + wm0 + 32 * bi + acc_row(4 * g + t, lane);
+            if (i < p.m) {
+              const float v = acc[bi][bj][4 * g + t];
+              if (p.C) p.C[(int64_t)i * p.ldc + j] = p.alpha * v;
+              part = fmaf(a[t], v, part);
+            }
           }
         }
       }
