@@ -83,12 +83,19 @@ typedef enum hpvm_precision {
  *                   (= tile_m) x tile_n slab of B, as in Sec. 6.1-6.3.
  *                   Larger values select an MFMA lowering in which every
  *                   wavefront owns a leaf_m x leaf_n sub-tile of C.
- * stages          : 1 = one LDS buffer (literal lowering); 2 = two LDS
- *                   stages, conversion to bfloat16 (if any) fused into the
- *                   HBM -> LDS copy; 3 = staged BF16 / bf16x3 lowering:
- *                   operands converted into a workspace by a separate pass,
- *                   two K-slabs in flight in registers ahead of two LDS
- *                   stages (hpvm_sgemm_ws only).
+ * stages          : the Allocation node's LDS stages.  1 = one buffer
+ *                   (literal lowering); 2 = two stages filled through
+ *                   registers, conversion to bfloat16 (if any) fused into
+ *                   that copy; 3 = staged BF16 / bf16x3 lowering: operands
+ *                   converted into a workspace by a separate pass, then
+ *                   moved straight from HBM into a ring of LDS stages (BF16)
+ *                   or through registers into two (bf16x3); hpvm_sgemm_ws
+ *                   only.  FP32 tiles with leaf_n = 128 are DMA-fed: a ring
+ *                   of `stages` LDS stages filled straight from HBM, for
+ *                   whole-tile problems (m, n, k multiples of the tile, A, B
+ *                   and C 16-byte aligned with leading dimensions that are
+ *                   multiples of 4); any other problem given such a tile
+ *                   runs the 128 x 128 x 16 tile.
  * hpvm_tile_menu lists the combinations compiled into this library.       */
 typedef struct hpvm_tile {
   int32_t tile_m;

@@ -8,11 +8,12 @@
 //   A (m x k)  -> Ah[, Al]  [m_pad][k_pad], k contiguous;
 //   B (k x n)  -> Bh[, Bl]  [n_pad][k_pad], k contiguous (B transposed);
 // zero-padded to whole 256 x 64 blocks, with hi = bf16(x) and, for bf16x3,
-// lo = bf16(x - hi).  The GEMM then moves 16-byte units with no edge checks
-// and keeps two K-slabs in flight in registers ahead of the LDS stage being
-// multiplied.  The hierarchy is the same as in the other lowerings: one
-// workgroup per SgemmInternal instance, the Allocation node as LDS stages,
-// SgemmLeaf outputs as MFMA accumulators.
+// lo = bf16(x - hi).  The GEMM then moves 16-byte units with no edge checks:
+// for BF16 straight from HBM into a ring of LDS stages (sgemm_bf16_dma), for
+// bf16x3 through registers two K-slabs ahead of the LDS stage being
+// multiplied (sgemm_bf16_staged).  The hierarchy is the same as in the other
+// lowerings: one workgroup per SgemmInternal instance, the Allocation node as
+// LDS stages, SgemmLeaf outputs as MFMA accumulators.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +21,7 @@
 #include "device_common.hpp"
 #include "hpvm_sgemm.h"
 #include "internal.hpp"
+#include "lds_dma.hpp"
 #include "mfma_bf16.hpp"
 #include "mfma_f32.hpp"
 
@@ -157,14 +159,49 @@ struct StagedArgs {
   float* partial;
 };
 
-// The GEMM over staged planes.  DEPTH = 1: each K-slab is loaded into
-// registers while the previous one, already in LDS, feeds the matrix cores,
-// and is written to the other LDS stage after those MFMAs.  DEPTH = 2: slab j
-// is loaded into register buffer j % 2 two slabs before it is written to LDS,
-// so two slabs of MFMA work cover each load.  One barrier per slab either
-// way.  PIPE reads the fragments of the next 16-k step ahead of the current
-// MFMAs.
-template <int TM, int TN, int TK, int WM, int WN, bool X3, int DEPTH, bool PIPE, int EPI>
+// Backward epilogue (EPI = 1): C (may be null) <- alpha acc, and this
+// workgroup's partial of dalpha, the sum over its tile of aorig .* acc, into
+// partial[blockIdx.x].  Each group of 4 rows loads its elements of aorig
+// before its stores.  Reuses `smem`: every LDS transfer must be complete.
+template <int BM, int BN>
+__device__ __forceinline__ void dalpha_epilogue(const StagedArgs& p, const f32x16 (&acc)[BM][BN], int row0,
+                                                int col0, int lane, char* smem) {
+  float part = 0.0f;
+#pragma unroll
+  for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BN; ++bj) {
+      const int j = col0 + 32 * bj + acc_col(lane);
+      if (j >= p.n) continue;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        float a[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+          a[t] = i < p.m ? p.aorig[(int64_t)i * p.lda_orig + j] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+          if (i < p.m) {
+            const float v = acc[bi][bj][4 * g + t];
+            if (p.C) p.C[(int64_t)i * p.ldc + j] = p.alpha * v;
+            part = fmaf(a[t], v, part);
+          }
+        }
+      }
+    }
+  const float sum = block_sum(part, reinterpret_cast<float*>(smem));
+  if (threadIdx.x == 0) p.partial[blockIdx.x] = sum;
+}
+
+// The bf16x3 GEMM over staged planes: each K-slab (hi and lo planes) is
+// loaded into registers while the previous one, already in LDS, feeds the
+// matrix cores, and is written to the other LDS stage after those MFMAs;
+// one barrier per slab.  PIPE reads the fragments of the next 16-k step
+// ahead of the current MFMAs.
+template <int TM, int TN, int TK, int WM, int WN, bool X3, bool PIPE, int EPI>
 __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
     sgemm_bf16_staged(StagedArgs p) {
   using T = Bf16TileShape<TM, TN, TK, WM, WN, X3>;
@@ -172,7 +209,6 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
   constexpr int kUnitsPerRow = TK / 8;
   constexpr int UA = TM * kUnitsPerRow / NT, UB = TN * kUnitsPerRow / NT;
   static_assert(UA * NT == TM * kUnitsPerRow && UB * NT == TN * kUnitsPerRow, "even split");
-  static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
   extern __shared__ __align__(16) char smem[];
 
   const int tid = threadIdx.x;
@@ -187,7 +223,7 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
   auto a_st = [&](int st, int pl) { return smem + st * T::kStageBytes + pl * T::kABytes; };
   auto b_st = [&](int st, int pl) { return smem + st * T::kStageBytes + P * T::kABytes + pl * T::kBBytes; };
 
-  u32x4 ra[DEPTH][P * UA], rb[DEPTH][P * UB];
+  u32x4 ra[P * UA], rb[P * UB];
   // A unit's address is a workgroup-uniform base (the plane's tile corner
   // plus the slab) and a 32-bit per-lane byte offset (planes are under
   // 4 GiB): one register per load instead of a 64-bit address.
@@ -229,44 +265,16 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
                                           wm0, wn0, lane, acc);
   };
   const int S = p.slabs;
-  if constexpr (DEPTH == 1) {
-    load(ra[0], rb[0], 0);
-    store(ra[0], rb[0], 0);
+  load(ra, rb, 0);
+  store(ra, rb, 0);
+  __syncthreads();
+  for (int s = 0; s < S; ++s) {
+    const int st = s & 1;
+    const bool more = s + 1 < S;
+    if (more) load(ra, rb, s + 1);
+    mfma_stage(st);
+    if (more) store(ra, rb, st ^ 1);
     __syncthreads();
-    for (int s = 0; s < S; ++s) {
-      const int st = s & 1;
-      const bool more = s + 1 < S;
-      if (more) load(ra[0], rb[0], s + 1);
-      mfma_stage(st);
-      if (more) store(ra[0], rb[0], st ^ 1);
-      __syncthreads();
-    }
-  } else {
-    load(ra[0], rb[0], 0);
-    load(ra[1], rb[1], S > 1 ? 1 : 0);
-    store(ra[0], rb[0], 0);
-    __syncthreads();
-    load(ra[0], rb[0], S > 2 ? 2 : S - 1);
-    // One slab: multiply stage B, move slab s + 1 (register buffer B ^ 1)
-    // into stage B ^ 1, refill that buffer with slab s + 3.  No branch in
-    // a step: past the end the store fills a stage nobody reads and the
-    // load re-reads the last slab.  The compiler's wait counting then
-    // sees the same loads in flight on every path through the loop and
-    // waits only for the older buffer's loads before the store, leaving
-    // the newer buffer's in flight (with branches it waited for all).
-    auto step = [&](auto parity, int s) {
-      constexpr int B = decltype(parity)::value;
-      mfma_stage(B);
-      store(ra[B ^ 1], rb[B ^ 1], B ^ 1);
-      load(ra[B ^ 1], rb[B ^ 1], s + 3 < S ? s + 3 : S - 1);
-      __syncthreads();
-    };
-    int s = 0;
-    for (; s + 1 < S; s += 2) {
-      step(std::integral_constant<int, 0>{}, s);
-      step(std::integral_constant<int, 1>{}, s + 1);
-    }
-    if (s < S) step(std::integral_constant<int, 0>{}, s);
   }
 
   if constexpr (EPI == 0) {
@@ -279,35 +287,147 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
     e.beta = p.beta;
     store_c<BM, BN>(e, acc, (int)m0 + wm0, (int)n0 + wn0, lane);
   } else {
-    // Each group of 4 rows loads its elements of A before its dA stores.
-    float part = 0.0f;
+    dalpha_epilogue<BM, BN>(p, acc, (int)m0 + wm0, (int)n0 + wn0, lane, smem);
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// DMA-fed BF16 GEMM over the staged planes.  Each K-slab of A and B goes
+// from HBM straight into one of NST LDS stages (slab s + NST - 1 is
+// requested while slab s is multiplied), so no register holds a slab in
+// transit; the registers this frees keep two sets of MFMA fragments, and
+// the fragments of a step are read while the previous step's MFMAs run.
+// Both tiles are rows (m or n) of TK bf16 k values, laid out by
+// SwizzledRows; the planes are padded, so no access needs a check.
+// ---------------------------------------------------------------------------
+template <int TM, int TN, int TK, int WM, int WN, int NST>
+struct Bf16DmaShape {
+  static constexpr int NW = (TM / WM) * (TN / WN), BM = WM / 32, BN = WN / 32;
+  static constexpr int RB = 2 * TK;  // bytes of a row
+  static constexpr int kABytes = TM * RB, kStage = (TM + TN) * RB;
+  static constexpr int64_t kLdsBytes = (int64_t)NST * kStage;
+  static constexpr int kRowsPerDma = SwizzledRows<RB>::kRowsPerDma;
+  static constexpr int QA = TM / kRowsPerDma / NW, QB = TN / kRowsPerDma / NW, Q = QA + QB;
+  static constexpr int kMaxWaves = (163840 / (NST * kStage)) * NW / 4;
+  static_assert(QA * NW * kRowsPerDma == TM && QB * NW * kRowsPerDma == TN && QA % 2 == 0 && QB % 2 == 0,
+                "even DMA split");
+  static_assert((TK / 16) % 2 == 0, "a slab's last step uses fragment buffer 1");
+  static_assert((NST - 2) * Q < 64, "vmcnt range");
+};
+
+// Scheduling hint: NM MFMAs with NR LDS reads spread evenly among them.
+template <int NR, int NM>
+__device__ __forceinline__ void interleave_mfma_reads() {
+  constexpr int per = NM / NR;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, per, 0);  // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);    // LDS read
+  }
+  if constexpr (NM - per * NR > 0) __builtin_amdgcn_sched_group_barrier(0x008, NM - per * NR, 0);
+}
+
+template <int TM, int TN, int TK, int WM, int WN, int NST, int EPI>
+__global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST>::NW * kWave))
+    __attribute__((amdgpu_waves_per_eu(1, (Bf16DmaShape<TM, TN, TK, WM, WN, NST>::kMaxWaves))))
+    sgemm_bf16_dma(StagedArgs p) {
+  using S = Bf16DmaShape<TM, TN, TK, WM, WN, NST>;
+  using Lay = SwizzledRows<S::RB>;
+  constexpr int BM = S::BM, BN = S::BN, QA = S::QA, QB = S::QB, KS = TK / 16, R = S::kRowsPerDma;
+  extern __shared__ __align__(16) char smem[];
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int wm0 = (wave / (TN / WN)) * WM, wn0 = (wave % (TN / WN)) * WN;
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, blockIdx.x, tm, tn);
+  const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
+  const int64_t rowb = p.kp * 2;
+  const uint32_t lds0 = lds_addr(smem);
+
+  // This wave fills row slots [wave*QA*R, (wave+1)*QA*R) of the A stage and
+  // the same share of the B stage; instruction j's group parity is j's.
+  const char* asrc = reinterpret_cast<const char*>(p.ah) + (m0 + (int64_t)wave * QA * R) * rowb;
+  const char* bsrc = reinterpret_cast<const char*>(p.bh) + (n0 + (int64_t)wave * QB * R) * rowb;
+  const uint32_t voff[2] = {Lay::src(lane, 0, rowb), Lay::src(lane, 1, rowb)};
+  auto dma_slab = [&](int slab, int st) {
+    const uint32_t la = lds0 + st * S::kStage + wave * QA * 1024;
+    const uint32_t lb = lds0 + st * S::kStage + S::kABytes + wave * QB * 1024;
+    const char* a = asrc + slab * S::RB;
+    const char* b = bsrc + slab * S::RB;
+#pragma unroll
+    for (int j = 0; j < QA; ++j) dma16(la + j * 1024, a + j * R * rowb, voff[j & 1]);
+#pragma unroll
+    for (int j = 0; j < QB; ++j) dma16(lb + j * 1024, b + j * R * rowb, voff[j & 1]);
+  };
+
+  int foff[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) foff[ks] = Lay::frag(lane, ks);
+  f32x16 acc[BM][BN];
+  zero_acc(acc);
+  bf16x8 fa[2][BM], fb[2][BN];
+  // B first: a step's first MFMAs use A block 0 with every B block.
+  auto read = [&](int buf, const char* st, int ks) {
+#pragma unroll
+    for (int bj = 0; bj < BN; ++bj)
+      fb[buf][bj] = *reinterpret_cast<const bf16x8*>(st + S::kABytes + (wn0 + 32 * bj) * S::RB + foff[ks]);
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi)
+      fa[buf][bi] = *reinterpret_cast<const bf16x8*>(st + (wm0 + 32 * bi) * S::RB + foff[ks]);
+  };
+  auto mfma = [&](int buf) {
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < BN; ++bj) {
-        const int j = (int)n0 + wn0 + 32 * bj + acc_col(lane);
-        if (j >= p.n) continue;
+      for (int bj = 0; bj < BN; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][bi], fb[buf][bj], acc[bi][bj], 0, 0, 0);
+  };
+
+  const int slabs = p.slabs;
+  if (slabs > 0) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          float a[4];
+    for (int i = 0; i < NST - 1; ++i) dma_slab(i < slabs ? i : slabs - 1, i);
+    dma_wait_barrier<(NST - 2) * S::Q>();
+    read(0, smem, 0);
+    dma_slab(NST - 1 < slabs ? NST - 1 : slabs - 1, NST - 1);
+  }
+  int st = 0;
+  for (int s = 0; s < slabs; ++s) {
+    const char* cur = smem + st * S::kStage;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int i = (int)m0 + wm0 + 32 * bi + acc_row(4 * g + t, lane);
-            a[t] = i < p.m ? p.aorig[(int64_t)i * p.lda_orig + j] : 0.0f;
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int i = (int)m0 + wm0 + 32 * bi + acc_row(4 * g + t, lane);
-            if (i < p.m) {
-              const float v = acc[bi][bj][4 * g + t];
-              if (p.C) p.C[(int64_t)i * p.ldc + j] = p.alpha * v;
-              part = fmaf(a[t], v, part);
-            }
-          }
-        }
-      }
-    const float sum = block_sum(part, reinterpret_cast<float*>(smem));
-    if (threadIdx.x == 0) p.partial[blockIdx.x] = sum;
+    for (int ks = 0; ks + 1 < KS; ++ks) {
+      read((ks + 1) & 1, cur, ks + 1);
+      interleave_mfma_reads<BM + BN, BM * BN>();
+      mfma(ks & 1);
+    }
+    // Slab s + 1 has landed everywhere and slab s is no longer read:
+    // request slab s + NST into its stage (the last slab again past the
+    // end, keeping the wait counts exact) and read slab s + 1's first step
+    // under the last step's MFMAs.
+    const int nst = st + 1 == NST ? 0 : st + 1;
+    dma_wait_barrier<(NST - 2) * S::Q>();
+    read(0, smem + nst * S::kStage, 0);
+    dma_slab(s + NST < slabs ? s + NST : slabs - 1, st);
+    interleave_mfma_reads<BM + BN, BM * BN>();
+    mfma(1);
+    st = nst;
+  }
+  // No transfer may still be writing LDS when it is reused or released.
+  dma_wait_barrier<0>();
+
+  if constexpr (EPI == 0) {
+    GemmArgs e{};
+    e.C = p.C;
+    e.ldc = p.ldc;
+    e.m = p.m;
+    e.n = p.n;
+    e.alpha = p.alpha;
+    e.beta = p.beta;
+    store_c<BM, BN>(e, acc, (int)m0 + wm0, (int)n0 + wn0, lane);
+  } else {
+    dalpha_epilogue<BM, BN>(p, acc, (int)m0 + wm0, (int)n0 + wn0, lane, smem);
   }
 }
 
@@ -358,7 +478,32 @@ hipError_t stage_operands(const GemmArgs& a, bool at, bool bt, const StagedLayou
   return stage_rows_launch<X3>(a.B, a.ldb, a.n, a.k, L.n_pad, L.k_pad, bh, bl, a.vec_b, s);
 }
 
-template <int TM, int TN, int TK, int WM, int WN, bool X3, int DEPTH, bool PIPE>
+// Kernel arguments for the planes of layout L in workspace ws.
+template <bool X3>
+StagedArgs staged_args(const GemmArgs& a, const StagedLayout& L, char* ws, int tm, int tn, int tk,
+                       const float* aorig, int64_t lda_orig, float* partial) {
+  StagedArgs p{};
+  p.ah = reinterpret_cast<const uint16_t*>(ws);
+  p.al = X3 ? reinterpret_cast<const uint16_t*>(ws + L.a_plane) : nullptr;
+  p.bh = reinterpret_cast<const uint16_t*>(ws + L.planes * L.a_plane);
+  p.bl = X3 ? reinterpret_cast<const uint16_t*>(ws + L.planes * L.a_plane + L.b_plane) : nullptr;
+  p.kp = L.k_pad;
+  p.C = a.C;
+  p.ldc = a.ldc;
+  p.m = a.m;
+  p.n = a.n;
+  p.slabs = (int32_t)(L.k_pad / tk);
+  p.tiles_m = (a.m + tm - 1) / tm;
+  p.tiles_n = (a.n + tn - 1) / tn;
+  p.alpha = a.alpha;
+  p.beta = a.beta;
+  p.aorig = aorig;
+  p.lda_orig = lda_orig;
+  p.partial = partial;
+  return p;
+}
+
+template <int TM, int TN, int TK, int WM, int WN, bool X3, bool PIPE>
 struct StagedConfig {
   using T = Bf16TileShape<TM, TN, TK, WM, WN, X3>;
   static constexpr int kThreads = T::NT;
@@ -372,25 +517,8 @@ struct StagedConfig {
     char* ws = reinterpret_cast<char*>(workspace);
     hipError_t e = stage_operands<X3>(a, at, bt, L, ws, s);
     if (e != hipSuccess) return e;
-    StagedArgs p{};
-    p.ah = reinterpret_cast<const uint16_t*>(ws);
-    p.al = X3 ? reinterpret_cast<const uint16_t*>(ws + L.a_plane) : nullptr;
-    p.bh = reinterpret_cast<const uint16_t*>(ws + L.planes * L.a_plane);
-    p.bl = X3 ? reinterpret_cast<const uint16_t*>(ws + L.planes * L.a_plane + L.b_plane) : nullptr;
-    p.kp = L.k_pad;
-    p.C = a.C;
-    p.ldc = a.ldc;
-    p.m = a.m;
-    p.n = a.n;
-    p.slabs = (int32_t)(L.k_pad / TK);
-    p.tiles_m = (a.m + TM - 1) / TM;
-    p.tiles_n = (a.n + TN - 1) / TN;
-    p.alpha = a.alpha;
-    p.beta = a.beta;
-    p.aorig = aorig;
-    p.lda_orig = lda_orig;
-    p.partial = partial;
-    auto* fn = &sgemm_bf16_staged<TM, TN, TK, WM, WN, X3, DEPTH, PIPE, EPI>;
+    StagedArgs p = staged_args<X3>(a, L, ws, TM, TN, TK, aorig, lda_orig, partial);
+    auto* fn = &sgemm_bf16_staged<TM, TN, TK, WM, WN, X3, PIPE, EPI>;
     e = allow_lds_staged(fn, (size_t)T::kLdsBytes);
     if (e != hipSuccess) return e;
     void* kargs[] = {&p};
@@ -407,22 +535,59 @@ struct StagedConfig {
   }
 };
 
-#define HPVM_STAGED_ENTRY(PREC, X3, DEPTH, PIPE, TM, TN, TK, WM, WN)                                     \
-  {{TM, TN, TK, WM, WN, 3}, PREC, StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::kThreads,           \
+#define HPVM_STAGED_ENTRY(PREC, X3, PIPE, TM, TN, TK, WM, WN)                                           \
+  {{TM, TN, TK, WM, WN, 3}, PREC, StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::kThreads,                  \
    Bf16TileShape<TM, TN, TK, WM, WN, X3>::kLdsBytes, nullptr,                                             \
-   &StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::launch,                                           \
-   &StagedConfig<TM, TN, TK, WM, WN, X3, DEPTH, PIPE>::launch_form}
+   &StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::launch,                                                  \
+   &StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::launch_form}
+
+// BF16 on the DMA-fed kernel (NST LDS stages); same planes and workspace.
+template <int TM, int TN, int TK, int WM, int WN, int NST>
+struct DmaConfig {
+  using S = Bf16DmaShape<TM, TN, TK, WM, WN, NST>;
+  static constexpr int kThreads = S::NW * kWave;
+  static_assert(kPadMN % TM == 0 && kPadMN % TN == 0 && kPadK % TK == 0, "padding covers the tile");
+
+  template <int EPI>
+  static hipError_t run(const GemmArgs& a, bool at, bool bt, void* workspace, const float* aorig, int64_t lda_orig,
+                        float* partial, hipStream_t s) {
+    const StagedLayout L = staged_layout(HPVM_PREC_BF16, a.m, a.n, a.k);
+    char* ws = reinterpret_cast<char*>(workspace);
+    hipError_t e = stage_operands<false>(a, at, bt, L, ws, s);
+    if (e != hipSuccess) return e;
+    StagedArgs p = staged_args<false>(a, L, ws, TM, TN, TK, aorig, lda_orig, partial);
+    auto* fn = &sgemm_bf16_dma<TM, TN, TK, WM, WN, NST, EPI>;
+    e = allow_lds_staged(fn, (size_t)S::kLdsBytes);
+    if (e != hipSuccess) return e;
+    void* kargs[] = {&p};
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(p.tiles_m * p.tiles_n)),
+                           dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
+  }
+  static hipError_t launch(const GemmArgs& a, void* workspace, hipStream_t s) {
+    return run<0>(a, false, false, workspace, nullptr, 0, nullptr, s);
+  }
+  static hipError_t launch_form(const GemmArgs& a, bool at, bool bt, void* workspace, const float* aorig,
+                                int64_t lda_orig, float* partial, hipStream_t s) {
+    return partial ? run<1>(a, at, bt, workspace, aorig, lda_orig, partial, s)
+                   : run<0>(a, at, bt, workspace, nullptr, 0, nullptr, s);
+  }
+};
+
+#define HPVM_DMA_ENTRY(NST, TM, TN, TK, WM, WN)                                                          \
+  {{TM, TN, TK, WM, WN, 3}, HPVM_PREC_BF16, DmaConfig<TM, TN, TK, WM, WN, NST>::kThreads,               \
+   DmaConfig<TM, TN, TK, WM, WN, NST>::S::kLdsBytes, nullptr, &DmaConfig<TM, TN, TK, WM, WN, NST>::launch, \
+   &DmaConfig<TM, TN, TK, WM, WN, NST>::launch_form}
 
 const MfmaEntry kStagedMenuBf16[] = {
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 2, false, 256, 256, 64, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 1, true, 256, 256, 32, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 1, true, 256, 128, 64, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16, false, 1, true, 128, 128, 64, 64, 64),
+    HPVM_DMA_ENTRY(2, 256, 256, 64, 128, 64),
+    HPVM_DMA_ENTRY(3, 256, 256, 32, 128, 64),
+    HPVM_DMA_ENTRY(3, 256, 128, 64, 128, 64),
+    HPVM_DMA_ENTRY(2, 128, 128, 64, 64, 64),
 };
 const MfmaEntry kStagedMenuBf16x3[] = {
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, 1, false, 256, 256, 32, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, 1, true, 256, 128, 32, 128, 64),
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, 1, true, 128, 128, 64, 64, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, false, 256, 256, 32, 128, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, true, 256, 128, 32, 128, 64),
+    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, true, 128, 128, 64, 64, 64),
 };
 
 }  // namespace

@@ -431,7 +431,8 @@ def test_stream_status_layout():
 
 
 def test_fusion_menus(lib):
-    assert hp.fusion_menu("consumer") == [t for t in hp.tile_menu("fp32") if t[5] == 2]
+    # the consumer kernel covers the FP32 tiles staged through registers (leaf_n <= 64)
+    assert hp.fusion_menu("consumer") == [t for t in hp.tile_menu("fp32") if t[5] == 2 and t[4] <= 64]
     pair = hp.fusion_menu("pair")
     assert len(pair) == 2 and all(t[5] == 2 for t in pair)
     cnt = ctypes.c_int32()

@@ -79,9 +79,12 @@ def _menu(prec):
 
 
 SHAPES = [(300, 260, 200), (128, 128, 16), (1, 1, 1), (257, 129, 77), (64, 520, 36)]
+# Whole tiles of every DMA-fed tile (m, n multiples of 256, k of 32): one
+# K-slab, a few, and more slabs than LDS stages.
+WHOLE_TILE_SHAPES = [(256, 256, 32), (512, 768, 96), (256, 512, 320)]
 
 
-@pytest.mark.parametrize("m,n,k", SHAPES)
+@pytest.mark.parametrize("m,n,k", SHAPES + WHOLE_TILE_SHAPES)
 def test_f32_mfma_integers_bit_exact_all_tiles(gpu, m, n, k):
     A, B, C = inputs.sgemm_operands(m, n, k, seed=m + n + k, dist="int")
     ref = oracle.sgemm(A, B, C, 1.0, 1.0)
@@ -91,7 +94,7 @@ def test_f32_mfma_integers_bit_exact_all_tiles(gpu, m, n, k):
         assert np.array_equal(got, ref), tile
 
 
-@pytest.mark.parametrize("m,n,k", SHAPES[:2])
+@pytest.mark.parametrize("m,n,k", SHAPES[:2] + WHOLE_TILE_SHAPES[1:2])
 def test_f32_mfma_uniform_within_bound_all_tiles(gpu, m, n, k):
     A, B, C = inputs.sgemm_operands(m, n, k, seed=5)
     alpha, beta = 1.0, 0.5
