@@ -48,14 +48,14 @@ def log(msg):
 # --------------------------------------------------------------------------- #
 # HBM traffic of the FP32 kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs  #
 # --------------------------------------------------------------------------- #
-TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "sgemm_mfma_f32_traffic.txt")
-KERNEL_SOURCES = ("device_common.hpp", "mfma_f32.hpp", "sgemm_mfma.hip")
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "fp32_sgemm_tiles_traffic.txt")
+KERNEL_SOURCES = ("device_common.hpp", "mfma_f32.hpp", "lds_dma.hpp", "sgemm_mfma.hip")
 COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read, 1 GiB written
 SWEEP_REPS = 2  # launches per (tile, workload entry) in a counter run
 
 
 def kernel_source_sha():
-    """Hash of the FP32 kernel's sources: traffic figures are void once it changes."""
+    """Hash of the FP32 kernels' sources: traffic figures are void once they change."""
     import hashlib
 
     h = hashlib.sha256()
@@ -63,6 +63,20 @@ def kernel_source_sha():
         with open(os.path.join(ROOT, "paper_1611_00860_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def is_fp32_gemm(kernel_name):
+    return "sgemm_f32_dma<" in kernel_name or "sgemm_mfma_f32<" in kernel_name
+
+
+def fp32_kernel_name(tile, m, n, k):
+    """The kernel an FP32 menu tile launches for a row-major problem with aligned operands."""
+    tm, tn, tk, lm, ln, st = tile
+    if ln == 128 and m % tm == 0 and n % tn == 0 and k % tk == 0:
+        return f"sgemm_f32_dma<{tm}, {tn}, {tk}, {lm}, {st}>"
+    if ln == 128:
+        tm, tn, tk, lm, ln = 128, 128, 16, 64, 64
+    return f"sgemm_mfma_f32<{tm}, {tn}, {tk}, {lm}, {ln}, false, false>"
 
 
 def _tile_key(tile, m, n, k, beta):
@@ -110,14 +124,15 @@ def build_traffic_table(fetch_csv, write_csv, fetch_log, write_log, command):
         copies = [float(r["Counter_Value"]) * 1024 for r in rs if "copyBuffer" in r["Kernel_Name"]][-3:]
         factor = COPY_BYTES / (sum(copies) / len(copies))
         factors[counter] = factor
-        gemm = [r for r in rs if "sgemm_mfma_f32<" in r["Kernel_Name"]]
+        gemm = [r for r in rs if is_fp32_gemm(r["Kernel_Name"])]
         seq = order(log_path)
         if len(gemm) != len(seq):
             raise SystemExit(f"{path}: {len(gemm)} FP32 dispatches, the sweep made {len(seq)}")
         for r, (tile, m, n, k, beta) in zip(gemm, seq):
             key = _tile_key(tile, m, n, k, beta)
             result.setdefault(key, {}).setdefault(counter, []).append(float(r["Counter_Value"]) * 1024 * factor)
-    lines = ["# HBM traffic of sgemm_mfma_f32 per launch (bytes), from rocprofv3 counters",
+    lines = ["# HBM traffic per launch (bytes) of the FP32 sgemm kernels (sgemm_f32_dma, sgemm_mfma_f32),",
+             "# every FP32 menu tile on the FP32 workload, from rocprofv3 counters",
              "# counter runs (GPU, repository root), once with FETCH_SIZE and once with WRITE_SIZE:",
              "#   rocprofv3 --pmc <COUNTER> --output-format csv -d <dir> -o pmc -- python3 bench.py --traffic-sweep",
              "#   (every FP32 menu tile on every workload entry, "
@@ -572,7 +587,7 @@ def traffic_sweep(hp, devs, outs, dev):
 
     seq = []
     for tile in hp.tile_menu("fp32"):
-        if tile[5] != 2:  # the literal kernel is not the FP32 MFMA kernel
+        if tile[3] == 1:  # the literal kernel is not an FP32 MFMA kernel
             continue
         for (m, n, k, beta), (dA, dB, dC), out in zip(WORKLOAD, devs, outs):
             for _ in range(SWEEP_REPS):
@@ -598,7 +613,7 @@ def main():
                     help="launch every FP32 menu tile on every workload entry, then the calibration copies, "
                          "and print the launch order (the run that HBM counters are taken over)")
     ap.add_argument("--traffic-table", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_LOG", "WRITE_LOG"),
-                    help="build profiles/sgemm_mfma_f32_traffic.txt from two --traffic-sweep counter runs and exit")
+                    help="build profiles/fp32_sgemm_tiles_traffic.txt from two --traffic-sweep counter runs and exit")
     args = ap.parse_args()
     if args.traffic_table:
         build_traffic_table(*args.traffic_table, command=" ".join(sys.argv))
@@ -725,7 +740,9 @@ def main():
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "algorithmic_bytes_per_launch": float(np.mean(
                          [4.0 * (m * k + k * n + m * n * (2 if beta else 1)) for (m, n, k, beta) in WORKLOAD])),
-                     "kernel": "sgemm_mfma_f32", "avg_launch_ms": round(kernel_ms / len(launch_ms), 5),
+                     "kernel": sorted(set(fp32_kernel_name(per_shape[f"{m}x{n}x{k}_beta{beta:g}"]["tile"], m, n, k)
+                                          for (m, n, k, beta) in WORKLOAD)),
+                     "avg_launch_ms": round(kernel_ms / len(launch_ms), 5),
                      "flops_per_launch_avg": flops_step / len(WORKLOAD)},
     }
 

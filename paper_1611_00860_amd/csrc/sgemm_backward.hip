@@ -7,6 +7,13 @@
 // element-wise pass writes dC_in = beta G and the partial sums of
 // dbeta = <G, C_in>; a single workgroup then reduces the partials.  Every
 // reduction is FP32 with a fixed order, so results repeat bit for bit.
+//
+// FP32 whole-tile problems can instead run both GEMMs on the DMA-fed loop
+// (mfma_f32_dma.hpp) with the contraction split into slices: dA and dB have
+// few outputs next to their long contractions (m x k and k x n against n and
+// m), so big tiles alone would leave most CUs idle.  Each slice writes its
+// raw partial tile to the workspace; one pass then sums the slices in order,
+// scales by alpha and forms dalpha's partials.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +26,7 @@
 #include "internal.hpp"
 #include "mfma_bf16.hpp"
 #include "mfma_f32.hpp"
+#include "mfma_f32_dma.hpp"
 
 namespace hpvm {
 
@@ -129,6 +137,37 @@ __global__ void __launch_bounds__(kElemThreads)
   }
 }
 
+// Sum of one gradient's slice partials part[z] (rows x cols, contiguous), in
+// slice order: v = part[0] + part[1] + ...; out <- alpha v when out is
+// given; with aorig, this block's partial of <aorig, v> into dpart.  Float4
+// units are dealt to threads grid-stride, so everything repeats bit for bit.
+// cols, ldo and ldao are multiples of 4 and the arrays 16-byte aligned.
+__global__ void __launch_bounds__(kElemThreads)
+    sgemm_split_sum(const float* __restrict__ part, int32_t splits, int64_t rows, int64_t cols, float alpha,
+                    float* __restrict__ out, int64_t ldo, const float* __restrict__ aorig, int64_t ldao,
+                    float* __restrict__ dpart) {
+  __shared__ float red[kElemThreads / kWave];
+  const int64_t c4 = cols / 4, units = rows * c4, plane = rows * cols;
+  float sum = 0.0f;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = u / c4, j = (u - i * c4) * 4;
+    f32x4 v = *reinterpret_cast<const f32x4*>(part + i * cols + j);
+    for (int z = 1; z < splits; ++z) v += *reinterpret_cast<const f32x4*>(part + z * plane + i * cols + j);
+    if (out) *reinterpret_cast<f32x4*>(out + i * ldo + j) = alpha * v;
+    if (dpart) {
+      const f32x4 a = *reinterpret_cast<const f32x4*>(aorig + i * ldao + j);
+      sum = fmaf(a[0], v[0], sum);
+      sum = fmaf(a[1], v[1], sum);
+      sum = fmaf(a[2], v[2], sum);
+      sum = fmaf(a[3], v[3], sum);
+    }
+  }
+  if (!dpart) return;
+  const float t = block_sum(sum, red);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = t;
+}
+
 namespace {
 
 // One candidate tile of the backward.  Fused entries run dA through
@@ -141,6 +180,7 @@ struct BwdEntry {
   int32_t threads;
   int64_t lds;
   void (*grad_a)(GemmArgs, const float*, int64_t, float*);  // null for staged entries
+  bool dma = false;  // split-contraction DMA-fed FP32 entry (falls back to kBwd[1])
 };
 
 template <int TM, int TN, int TK, int WM, int WN, int PREC>
@@ -155,8 +195,25 @@ constexpr BwdEntry staged_entry(int tm, int tn, int tk, int wm, int wn, int prec
   return BwdEntry{{tm, tn, tk, wm, wn, 3}, prec, 0, 0, nullptr};
 }
 
-// Per precision, in the order the built-in choice tries them.
+// The DMA-fed FP32 backward: 256 x 256 x 32 tiles of 8 waves (64 x 128 each),
+// two LDS stages.  dA reads G (k contiguous) and B transposed (k
+// contiguous); dB reads A transposed (m contiguous, two adjacent rows per
+// fragment) and G (n contiguous, four adjacent columns).
+constexpr int kDmaTile = 256, kDmaK = 32, kDmaWM = 64, kDmaWN = 128, kDmaStages = 2;
+using DmaA = F32DmaShape<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, false, true, kDmaStages>;
+using DmaB = F32DmaShape<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, true, false, kDmaStages>;
+constexpr BwdEntry dma_entry() {
+  BwdEntry e{{kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, kDmaStages}, HPVM_PREC_FP32, DmaA::NW * kWave,
+             DmaA::kLdsBytes > DmaB::kLdsBytes ? DmaA::kLdsBytes : DmaB::kLdsBytes,
+             &sgemm_grad_a<128, 128, 32, 64, 64, HPVM_PREC_FP32>};
+  e.dma = true;
+  return e;
+}
+
+// Per precision, in the order the built-in choice tries them.  kBwd[1] is
+// the DMA entry's fallback for problems that are not whole tiles.
 const BwdEntry kBwd[] = {
+    dma_entry(),
     fused_entry<128, 128, 32, 64, 64, HPVM_PREC_FP32>(),
     fused_entry<128, 128, 16, 64, 64, HPVM_PREC_FP32>(),
     fused_entry<128, 64, 16, 64, 32, HPVM_PREC_FP32>(),
@@ -185,9 +242,41 @@ const BwdEntry* find_bwd(int32_t prec, const hpvm_tile& t) {
   return nullptr;
 }
 
-// Built-in choice: the first entry giving dA at least one tile per CU of a
-// 256-CU part, else the one giving the most tiles.
 constexpr int64_t kTargetTiles = 256;
+
+// Contraction slices for a DMA-fed gradient with `tiles` output tiles:
+// doubled while the workgroups would not cover 256 CUs, each slice staying a
+// whole number of slabs and at least 256 deep.  0 when the gradient is not
+// whole tiles (by size; alignment is checked at launch).
+int dma_splits(int64_t rows, int64_t cols, int64_t contraction) {
+  if (rows <= 0 || cols <= 0 || contraction <= 0 || rows % kDmaTile || cols % kDmaTile ||
+      contraction % kDmaK)
+    return 0;
+  const int64_t tiles = (rows / kDmaTile) * (cols / kDmaTile);
+  int s = 1;
+  while (s < 16 && tiles * s < kTargetTiles && contraction % (2 * s * kDmaK) == 0 && contraction / (2 * s) >= 256)
+    s *= 2;
+  return s;
+}
+
+struct DmaPlan {
+  int sa = 0, sb = 0;  // slices of dA (m x k over n) and dB (k x n over m); 0 = not DMA-fed
+};
+DmaPlan dma_plan(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
+  DmaPlan d;
+  if (e->dma) {
+    d.sa = dma_splits(m, k, n);
+    d.sb = dma_splits(k, n, m);
+  }
+  return d;
+}
+int64_t split_sum_blocks(int64_t rows, int64_t cols) {
+  return std::max<int64_t>(1, std::min<int64_t>(kElemBlocks, (rows * cols / 4 + kElemThreads - 1) / kElemThreads));
+}
+
+// Built-in choice: the DMA entry when dA is whole tiles, else the first
+// entry giving dA at least one tile per CU of a 256-CU part, else the one
+// giving the most tiles.
 const BwdEntry* pick(int32_t prec, int64_t m, int64_t n, int64_t k) {
   hpvm_tile tuned;
   if (tuned_backward_tile(prec, m, n, k, &tuned)) {
@@ -198,6 +287,10 @@ const BwdEntry* pick(int32_t prec, int64_t m, int64_t n, int64_t k) {
   const bool staged_ok = staged_k_ok(n) && staged_k_ok(m);  // the dA and dB contractions
   for (int i = 0; i < kNumBwd; ++i) {
     if (kBwd[i].prec != prec) continue;
+    if (kBwd[i].dma) {
+      if (dma_splits(m, k, n)) return &kBwd[i];
+      continue;
+    }
     if (!kBwd[i].grad_a && !staged_ok) continue;
     if (tiles_for(kBwd[i].tile, m, k) >= kTargetTiles) return &kBwd[i];
     if (!most || tiles_for(kBwd[i].tile, m, k) > tiles_for(most->tile, m, k)) most = &kBwd[i];
@@ -217,18 +310,53 @@ struct BwdLayout {
   int64_t pb_off, stage_off, total;
 };
 
+// A DMA entry sizes for both of its paths: the slice partials (dA's and
+// dB's passes share the region) and the larger of its dalpha partial counts.
 BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
   BwdLayout L;
-  L.na = (m > 0 && k > 0) ? tiles_for(e->tile, m, k) : 0;
+  L.na = (m > 0 && k > 0) ? tiles_for(e->dma ? kBwd[1].tile : e->tile, m, k) : 0;
+  const DmaPlan d = dma_plan(e, m, n, k);
+  if (d.sa) L.na = std::max(L.na, split_sum_blocks(m, k));
   L.nb = elem_blocks(m, n);
   L.pb_off = up(L.na * 4);
   L.stage_off = L.pb_off + up(L.nb * 4);
   int64_t stage = 0;
   if (!e->grad_a)
     stage = std::max(staged_workspace_bytes(e->prec, m, k, n), staged_workspace_bytes(e->prec, k, n, m));
+  if (e->dma) stage = 4 * std::max<int64_t>(d.sa * m * k, d.sb * k * n);
   L.total = L.stage_off + stage;
   return L;
+}
+
+// One gradient on the DMA-fed loop: `splits` contraction slices write their
+// partial tiles to part ([splits][a.m][a.n]), then sgemm_split_sum adds
+// them, writes out = alpha * sum (when out is given) and dalpha's partials
+// (when aorig is given).
+template <bool AT, bool BT>
+hipError_t launch_split(const GemmArgs& args, int splits, float* part, float* out, int64_t ldo, const float* aorig,
+                        int64_t ldao, float* dpart, hipStream_t s) {
+  using S = F32DmaShape<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, AT, BT, kDmaStages>;
+  auto* fn = &sgemm_f32_dma<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, AT, BT, kDmaStages, true>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLdsBytes);
+  if (e != hipSuccess) return e;
+  GemmArgs a = args;
+  a.C = part;
+  a.ldc = a.n;
+  a.tiles_m = a.m / kDmaTile;
+  a.tiles_n = a.n / kDmaTile;
+  int32_t sp = splits;
+  void* kargs[] = {&a, &sp};
+  e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n * splits)),
+                      dim3(S::NW * kWave), kargs, (size_t)S::kLdsBytes, s);
+  if (e != hipSuccess || (!out && !dpart)) return e;
+  const float* pp = part;
+  int64_t rows = a.m, cols = a.n;
+  float alpha = args.alpha;
+  void* sargs[] = {&pp, &sp, &rows, &cols, &alpha, &out, &ldo, &aorig, &ldao, &dpart};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_sum), dim3((unsigned)split_sum_blocks(rows, cols)),
+                         dim3(kElemThreads), sargs, 0, s);
 }
 
 std::mutex g_tune_mu;
@@ -325,7 +453,8 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   if (rc != HPVM_OK) return rc;
   const BwdLayout L = bwd_layout(cfg, m, n, k);
   const bool staged = cfg->grad_a == nullptr;
-  const bool need_ws = dalpha || dbeta || (staged && (run_a || run_b));
+  const DmaPlan plan = dma_plan(cfg, m, n, k);
+  const bool need_ws = dalpha || dbeta || (staged && (run_a || run_b)) || (cfg->dma && (run_a || run_b));
   if (need_ws && !workspace) return set_error(HPVM_INVALID_ARG, "argument 24: workspace is NULL");
   if (need_ws && workspace_bytes < L.total)
     return set_error(HPVM_WORKSPACE_TOO_SMALL, "argument 25: workspace has %lld bytes, needs %lld",
@@ -339,7 +468,13 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   float* pa = ws ? reinterpret_cast<float*>(ws) : nullptr;
   float* pb = ws ? reinterpret_cast<float*>(ws + L.pb_off) : nullptr;
   void* stage = ws ? ws + L.stage_off : nullptr;
-  const MfmaEntry* me = find_menu_entry(prec, cfg->tile);
+  // A DMA entry runs a pass it does not cover in whole, aligned tiles on
+  // its fallback entry.
+  const BwdEntry* fb = cfg->dma ? &kBwd[1] : cfg;
+  const MfmaEntry* me = find_menu_entry(prec, fb->tile);
+  const bool dma_a = plan.sa && vec16(G, ldg) && vec16(B, ldb) && (!dA || vec16(dA, ldda)) &&
+                     (!dalpha || vec16(A, lda));
+  const bool dma_b = plan.sb && vec16(A, lda) && vec16(G, ldg) && vec16(dB, lddb);
   hipError_t e = hipSuccess;
   int64_t na = L.na;
 
@@ -362,23 +497,28 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     a.beta = 0.0f;
     a.vec_a = vec16(G, ldg);
     a.vec_b = vec16(B, ldb);
-    a.tiles_m = (a.m + cfg->tile.tile_m - 1) / cfg->tile.tile_m;
-    a.tiles_n = (a.n + cfg->tile.tile_n - 1) / cfg->tile.tile_n;
-    if (staged) {
+    a.tiles_m = (a.m + fb->tile.tile_m - 1) / fb->tile.tile_m;
+    a.tiles_n = (a.n + fb->tile.tile_n - 1) / fb->tile.tile_n;
+    if (dma_a) {
+      e = launch_split<false, true>(a, plan.sa, reinterpret_cast<float*>(stage), dA, ldda, dalpha ? A : nullptr,
+                                    lda, dalpha ? pa : nullptr, s);
+      na = dalpha ? split_sum_blocks(m, k) : 0;
+    } else if (staged) {
       e = me ? me->launch_staged_form(a, false, true, stage, A, lda, dalpha ? pa : nullptr, s) : hipErrorInvalidValue;
     } else if (dalpha) {
       // Fused pass: dA (when requested) and the per-tile partials of dalpha.
-      if (cfg->lds > 65536)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(cfg->grad_a),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg->lds);
+      if (fb->lds > 65536)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(fb->grad_a),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fb->lds);
       if (e == hipSuccess) {
         const float* Ao = A;
         int64_t ldao = lda;
         float* part = pa;
         void* kargs[] = {&a, &Ao, &ldao, &part};
-        e = hipLaunchKernel(reinterpret_cast<const void*>(cfg->grad_a), dim3((unsigned)(a.tiles_m * a.tiles_n)),
-                            dim3(cfg->threads), kargs, (size_t)cfg->lds, s);
+        e = hipLaunchKernel(reinterpret_cast<const void*>(fb->grad_a), dim3((unsigned)(a.tiles_m * a.tiles_n)),
+                            dim3(fb->threads), kargs, (size_t)fb->lds, s);
       }
+      na = a.tiles_m * a.tiles_n;
     } else {
       e = me ? me->launch(a, false, true, s) : hipErrorInvalidValue;
     }
@@ -405,7 +545,9 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     b.beta = 0.0f;
     b.vec_a = vec16(A, lda);
     b.vec_b = vec16(G, ldg);
-    if (!me) e = hipErrorInvalidValue;
+    if (dma_b) e = launch_split<true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb, nullptr, 0,
+                                             nullptr, s);
+    else if (!me) e = hipErrorInvalidValue;
     else if (staged) e = me->launch_staged_form(b, true, false, stage, nullptr, 0, nullptr, s);
     else e = me->launch(b, true, false, s);
   }

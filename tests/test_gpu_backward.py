@@ -101,6 +101,48 @@ def test_backward_edge_cases(gpu):
     del A0, B0
 
 
+@pytest.mark.parametrize("m,n,k", [(512, 512, 256), (256, 1024, 512)])
+def test_backward_dma_split_integers(gpu, m, n, k):
+    """FP32 whole tiles take the DMA-fed loop with the contraction split into
+    slices (dA over n, dB over m) and one ordered pass summing the slices:
+    integer inputs stay exact, and the DMA tile named explicitly or chosen
+    by default gives the same bits."""
+    import torch
+
+    print(f"case: backward dma split {m}x{n}x{k}", flush=True)
+    A, B, C, G = inputs.backward_operands(m, n, k, seed=m + n + k, dist="int")
+    ref = oracle.sgemm_grad(A, B, C, G, 1.0, 2.0)
+    d = dev_all(A, B, C, G)
+    dma_tile = gpu.backward_menu("fp32")[0]
+    assert dma_tile[4] == 128
+    g = gpu.sgemm_backward(*d, 1.0, 2.0, prec="fp32", tile=dma_tile)
+    g0 = gpu.sgemm_backward(*d, 1.0, 2.0, prec="fp32")
+    torch.cuda.synchronize()
+    for key in ("dA", "dB", "dC_in"):
+        assert np.array_equal(to_host(g[key]), ref[key]), key
+        assert torch.equal(g[key], g0[key]), key
+    # dalpha: a long FP32 sum of exact products, within its rounding bound
+    terms = np.abs(A.astype(np.float64) * (G.astype(np.float64) @ B.astype(np.float64).T))
+    assert abs(float(g["dalpha"]) - ref["dalpha"]) <= 4 * U32 * np.log2(terms.size) * terms.sum()
+    assert float(g["dalpha"]) == float(g0["dalpha"])
+    assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-6)
+
+
+def test_backward_dma_misaligned_falls_back(gpu):
+    """An operand off 16-byte alignment sends that gradient to the fallback tile."""
+    import torch
+
+    m, n, k = 256, 512, 256
+    A, B, C, G = inputs.backward_operands(m, n, k, seed=77, dist="int")
+    ref = oracle.sgemm_grad(A, B, C, G, 1.0, 0.5)
+    dA_, dB_, dC_ = dev_all(A, B, C)
+    dG_ = to_dev(G, 0, True)
+    g = gpu.sgemm_backward(dA_, dB_, dC_, dG_, 1.0, 0.5, prec="fp32", tile=gpu.backward_menu("fp32")[0])
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(g["dA"]), ref["dA"])
+    assert np.array_equal(to_host(g["dB"]), ref["dB"])
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_backward_full_size_sampled(gpu, prec):
     """M = N = 4096, K = 1024, alpha = 0.7, beta = 0.3, G uniform, seed 4."""
