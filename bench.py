@@ -49,7 +49,7 @@ def log(msg):
 # HBM traffic of the FP32 kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs  #
 # --------------------------------------------------------------------------- #
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "fp32_sgemm_tiles_traffic.txt")
-KERNEL_SOURCES = ("device_common.hpp", "mfma_f32.hpp", "lds_dma.hpp", "sgemm_mfma.hip")
+KERNEL_SOURCES = ("device_common.hpp", "mfma_f32.hpp", "lds_dma.hpp", "mfma_f32_dma.hpp", "sgemm_mfma.hip")
 COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read, 1 GiB written
 SWEEP_REPS = 2  # launches per (tile, workload entry) in a counter run
 
@@ -73,7 +73,7 @@ def fp32_kernel_name(tile, m, n, k):
     """The kernel an FP32 menu tile launches for a row-major problem with aligned operands."""
     tm, tn, tk, lm, ln, st = tile
     if ln == 128 and m % tm == 0 and n % tn == 0 and k % tk == 0:
-        return f"sgemm_f32_dma<{tm}, {tn}, {tk}, {lm}, {st}>"
+        return f"sgemm_f32_dma<{tm}, {tn}, {tk}, {lm}, 128, false, false, {st}, 0, 0, false>"
     if ln == 128:
         tm, tn, tk, lm, ln = 128, 128, 16, 64, 64
     return f"sgemm_mfma_f32<{tm}, {tn}, {tk}, {lm}, {ln}, false, false>"

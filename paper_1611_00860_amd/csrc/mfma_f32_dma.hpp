@@ -26,6 +26,7 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "hpvm_sgemm.h"
 #include "lds_dma.hpp"
 #include "mfma_f32.hpp"
 
@@ -92,38 +93,76 @@ struct F32DmaOperand {
   __device__ static int index(int b, int x, int w0) { return KC ? w0 + 32 * b + x : w0 + V * x + b; }
 };
 
-template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, int NST>
+// PAIR: two B operands (B1, B2) share A, MergeIndependentNodes with a
+// merged Allocation: the B stage holds B1's tile and then B2's, and the
+// waves covering the second TN columns produce the second output.
+template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, int NST, bool PAIR = false>
 struct F32DmaShape {
   using OA = F32DmaOperand<!AT, TM, WM, TK>;
   using OB = F32DmaOperand<BT, TN, WN, TK>;
-  static constexpr int NWN = TN / WN, NW = (TM / WM) * NWN;
-  static constexpr int kStage = OA::kBytes + OB::kBytes;
+  static constexpr int kOuts = PAIR ? 2 : 1;
+  static constexpr int NWN = kOuts * TN / WN, NW = (TM / WM) * NWN;
+  static constexpr int kBBytes = kOuts * OB::kBytes;
+  static constexpr int kStage = OA::kBytes + kBBytes;
   static constexpr int64_t kLdsBytes = (int64_t)NST * kStage;
-  static constexpr int QA = OA::kDma / NW, QB = OB::kDma / NW, Q = QA + QB;
+  static constexpr int QA = OA::kDma / NW, QB = kOuts * OB::kDma / NW, Q = QA + QB;
   static constexpr int kMaxWaves = (163840 / (NST * kStage)) * NW / 4;
   static_assert(TM % WM == 0 && TN % WN == 0, "wave tiles");
-  static_assert(QA * NW == OA::kDma && QB * NW == OB::kDma, "DMA instructions split evenly over the waves");
+  static_assert(QA * NW == OA::kDma && QB * NW == kOuts * OB::kDma, "DMA instructions split evenly over the waves");
+  static_assert(!PAIR || (!AT && !BT), "the pair reads A and both B as stored");
   static_assert((AT || QA % 2 == 0) && (!BT || QB % 2 == 0), "swizzled row groups: a wave starts at an even one");
   static_assert(TK % 16 == 0, "a slab holds an even number of 8-k groups");
   static_assert((NST - 2) * Q < 64, "vmcnt range");
 };
 
-// Output of the DMA-fed loop.  SPLIT = false: C <- alpha acc + beta C (beta
-// == 0 never reads C).  SPLIT = true: the raw accumulators of contraction
-// slice z go to C + z m ldc (a [splits][m][ldc] partial array).
-template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, int NST, bool SPLIT>
-__global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>::NW * kWave))
-    __attribute__((amdgpu_waves_per_eu(1, (F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>::kMaxWaves))))
-    sgemm_f32_dma(GemmArgs p, int32_t splits) {
-  using S = F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>;
+// The consumer of MergeDependentNodes, applied to each output element.
+template <int OP>
+__device__ __forceinline__ float consume(float v, float b, float lo, float hi) {
+  if constexpr (OP == HPVM_CONSUMER_RELU) return v > 0.0f ? v : 0.0f;
+  if constexpr (OP == HPVM_CONSUMER_BIAS) return v + b;
+  if constexpr (OP == HPVM_CONSUMER_BIAS_RELU) {
+    const float w = v + b;
+    return w > 0.0f ? w : 0.0f;
+  }
+  if constexpr (OP == HPVM_CONSUMER_CLAMP) return v < lo ? lo : (v > hi ? hi : v);
+  return v;
+}
+
+// Where the DMA-fed loop's results go.
+enum F32DmaMode {
+  kDmaUpdate = 0,   // C <- alpha acc + beta C (beta == 0 never reads C)
+  kDmaSplit = 1,    // raw accumulators of contraction slice z to C + z m ldc
+  kDmaConsume = 2,  // D <- consumer(alpha acc + beta C); C only read
+};
+struct F32DmaOut {
+  int32_t splits;     // contraction slices (kDmaSplit), else 1
+  int32_t reserved;
+  float* D;           // kDmaConsume: output and its leading dimension
+  int64_t ldd;
+  const float* bias;  // one value per column (BIAS ops)
+  float lo, hi;       // CLAMP
+};
+
+// p: the sgemm (for PAIR, output 1); p2: PAIR's output 2 (B2, C2, alpha2,
+// beta2; the rest as p), ignored otherwise.
+template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, int NST, int MODE, int OP = 0,
+          bool PAIR = false>
+__global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>::NW * kWave))
+    __attribute__((amdgpu_waves_per_eu(1, (F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>::kMaxWaves))))
+    sgemm_f32_dma(GemmArgs p, GemmArgs p2, F32DmaOut o) {
+  using S = F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>;
   using OA = typename S::OA;
   using OB = typename S::OB;
   constexpr int NA = OA::kBlocks, NB = OB::kBlocks, KG = TK / 8;
+  static_assert(MODE != kDmaConsume || !BT, "the consumer epilogue stores rows of adjacent outputs");
   extern __shared__ __align__(16) char smem[];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-  const int wm0 = (wave / S::NWN) * WM, wn0 = (wave % S::NWN) * WN;
+  const int wm0 = (wave / S::NWN) * WM, wcol = (wave % S::NWN) * WN;
+  const int half = PAIR ? wcol / TN : 0;  // which output this wave's columns belong to
+  const int wn0 = wcol - half * TN;
+  const int splits = MODE == kDmaSplit ? o.splits : 1;
   const int tiles = p.tiles_m * p.tiles_n;
   const int z = blockIdx.x / tiles;  // contraction slice: co-resident workgroups share it
   int tm, tn;
@@ -134,11 +173,11 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>:
   const int sbeg = z * per, slabs = (slabs_all - sbeg < per ? slabs_all - sbeg : per);
   const uint32_t lds0 = lds_addr(smem);
 
-  const int64_t lda4 = p.lda * 4, ldb4 = p.ldb * 4;
+  const int64_t lda4 = p.lda * 4, ldb4 = p.ldb * 4, ldb24 = p2.ldb * 4;
   const char* abase = reinterpret_cast<const char*>(p.A);
-  const char* bbase = reinterpret_cast<const char*>(p.B);
   const uint32_t aoff[2] = {OA::lane_off(lane, 0, lda4), OA::lane_off(lane, 1, lda4)};
-  const uint32_t boff[2] = {OB::lane_off(lane, 0, ldb4), OB::lane_off(lane, 1, ldb4)};
+  const uint32_t boff[2][2] = {{OB::lane_off(lane, 0, ldb4), OB::lane_off(lane, 1, ldb4)},
+                               {OB::lane_off(lane, 0, ldb24), OB::lane_off(lane, 1, ldb24)}};
   auto dma_slab = [&](int slab, int st) {
     const int64_t k0 = (int64_t)(sbeg + slab) * TK;
     const uint32_t la = lds0 + st * S::kStage + wave * S::QA * 1024;
@@ -147,13 +186,17 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>:
     for (int j = 0; j < S::QA; ++j)
       dma16(la + j * 1024, abase + OA::base(wave * S::QA + j, m0, k0, p.lda) * 4, aoff[j & 1]);
 #pragma unroll
-    for (int j = 0; j < S::QB; ++j)
-      dma16(lb + j * 1024, bbase + OB::base(wave * S::QB + j, n0, k0, p.ldb) * 4, boff[j & 1]);
+    for (int j = 0; j < S::QB; ++j) {
+      const int q = wave * S::QB + j, h = PAIR ? q / OB::kDma : 0, qq = q - h * OB::kDma;
+      const GemmArgs& pb = h ? p2 : p;
+      dma16(lb + j * 1024, reinterpret_cast<const char*>(pb.B) + OB::base(qq, n0, k0, pb.ldb) * 4, boff[h][qq & 1]);
+    }
   };
 
   int foff[KG];
 #pragma unroll
   for (int g = 0; g < KG; ++g) foff[g] = OA::Rows::frag(lane, g);
+  const int bstage = OA::kBytes + half * OB::kBytes;
 
   f32x16 acc[NA][NB];
   zero_acc(acc);
@@ -161,7 +204,7 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>:
   typename OB::Frag fb[2][OB::kFrags];
   auto read = [&](int buf, const char* st, int g) {
 #pragma unroll
-    for (int j = 0; j < OB::kFrags; ++j) fb[buf][j] = OB::frag(st + OA::kBytes, j, g, wn0, lane, foff[g]);
+    for (int j = 0; j < OB::kFrags; ++j) fb[buf][j] = OB::frag(st + bstage, j, g, wn0, lane, foff[g]);
 #pragma unroll
     for (int j = 0; j < OA::kFrags; ++j) fa[buf][j] = OA::frag(st, j, g, wm0, lane, foff[g]);
   };
@@ -207,24 +250,33 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>:
   // No transfer may still be writing LDS when the workgroup ends.
   dma_wait_barrier<0>();
 
-  float* out = p.C + (SPLIT ? (int64_t)z * p.m * p.ldc : 0);
-  const float alpha = SPLIT ? 1.0f : p.alpha;
-  const bool read_c = !SPLIT && p.beta != 0.0f;
+  const GemmArgs& q = half ? p2 : p;
+  const float* cin = q.C + (MODE == kDmaSplit ? (int64_t)z * q.m * q.ldc : 0);
+  float* out = MODE == kDmaConsume ? o.D : q.C + (MODE == kDmaSplit ? (int64_t)z * q.m * q.ldc : 0);
+  const int64_t ldo = MODE == kDmaConsume ? o.ldd : q.ldc;
+  const float alpha = MODE == kDmaSplit ? 1.0f : q.alpha;
+  const bool read_c = MODE != kDmaSplit && q.beta != 0.0f;
+  constexpr bool kBias = OP == HPVM_CONSUMER_BIAS || OP == HPVM_CONSUMER_BIAS_RELU;
   const int I = lane & 31;
+  if constexpr (!BT) {
+    // The NB blocks give a lane NB adjacent outputs of a row: one vector
+    // access per row.  A group of 4 rows loads its C values first.
+    using VB = typename OB::Frag;
+    const int64_t col = n0 + OB::index(0, I, wn0);
+    VB bias{};
+    if constexpr (MODE == kDmaConsume && kBias) {
 #pragma unroll
-  for (int a = 0; a < NA; ++a)
+      for (int b = 0; b < NB; ++b) bias[b] = o.bias[col + b];
+    }
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      if constexpr (!BT) {
-        // The NB blocks give a lane NB adjacent outputs of a row: one
-        // vector access per row.  Loads of a group of 4 rows go first.
-        using VB = typename OB::Frag;
-        const int64_t col = n0 + OB::index(0, I, wn0);
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
         VB c[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-          if (read_c) c[u] = *reinterpret_cast<const VB*>(out + i * p.ldc + col);
+          if (read_c) c[u] = *reinterpret_cast<const VB*>(cin + i * q.ldc + col);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -233,11 +285,17 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>:
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
             v[b] = alpha * acc[a][b][4 * g + u];
-            if (read_c) v[b] = fmaf(p.beta, c[u][b], v[b]);
+            if (read_c) v[b] = fmaf(q.beta, c[u][b], v[b]);
+            if constexpr (MODE == kDmaConsume) v[b] = consume<OP>(v[b], bias[b], o.lo, o.hi);
           }
-          *reinterpret_cast<VB*>(out + i * p.ldc + col) = v;
+          *reinterpret_cast<VB*>(out + i * ldo + col) = v;
         }
-      } else {
+      }
+  } else {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const int64_t col = n0 + OB::index(b, I, wn0);
@@ -245,18 +303,17 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST>:
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-            c[u] = read_c ? out[i * p.ldc + col] : 0.0f;
+            c[u] = read_c ? cin[i * q.ldc + col] : 0.0f;
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
             float v = alpha * acc[a][b][4 * g + u];
-            if (read_c) v = fmaf(p.beta, c[u], v);
-            out[i * p.ldc + col] = v;
+            if (read_c) v = fmaf(q.beta, c[u], v);
+            out[i * ldo + col] = v;
           }
         }
-      }
-    }
+  }
 }
 
 // True when the DMA-fed loop covers the problem in whole tiles: m, n and k

@@ -337,7 +337,7 @@ template <bool AT, bool BT>
 hipError_t launch_split(const GemmArgs& args, int splits, float* part, float* out, int64_t ldo, const float* aorig,
                         int64_t ldao, float* dpart, hipStream_t s) {
   using S = F32DmaShape<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, AT, BT, kDmaStages>;
-  auto* fn = &sgemm_f32_dma<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, AT, BT, kDmaStages, true>;
+  auto* fn = &sgemm_f32_dma<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, AT, BT, kDmaStages, kDmaSplit>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLdsBytes);
   if (e != hipSuccess) return e;
@@ -346,8 +346,11 @@ hipError_t launch_split(const GemmArgs& args, int splits, float* part, float* ou
   a.ldc = a.n;
   a.tiles_m = a.m / kDmaTile;
   a.tiles_n = a.n / kDmaTile;
+  GemmArgs unused = a;
+  F32DmaOut o{};
+  o.splits = splits;
   int32_t sp = splits;
-  void* kargs[] = {&a, &sp};
+  void* kargs[] = {&a, &unused, &o};
   e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n * splits)),
                       dim3(S::NW * kWave), kargs, (size_t)S::kLdsBytes, s);
   if (e != hipSuccess || (!out && !dpart)) return e;

@@ -27,6 +27,7 @@
 #include "hpvm_sgemm.h"
 #include "internal.hpp"
 #include "mfma_f32.hpp"
+#include "mfma_f32_dma.hpp"
 
 namespace hpvm {
 
@@ -40,18 +41,6 @@ struct ConsumerArgs {
   float lo, hi;       // CLAMP
   int32_t op;
 };
-
-template <int OP>
-__device__ __forceinline__ float consume(float v, float b, float lo, float hi) {
-  if constexpr (OP == HPVM_CONSUMER_RELU) return v > 0.0f ? v : 0.0f;
-  if constexpr (OP == HPVM_CONSUMER_BIAS) return v + b;
-  if constexpr (OP == HPVM_CONSUMER_BIAS_RELU) {
-    const float w = v + b;
-    return w > 0.0f ? w : 0.0f;
-  }
-  if constexpr (OP == HPVM_CONSUMER_CLAMP) return v < lo ? lo : (v > hi ? hi : v);
-  return v;
-}
 
 // D <- consumer(alpha * acc + beta * C), element-wise, masked at the edges.
 // C is read-only here (beta == 0 never reads it); D may be C itself.  As in
@@ -276,6 +265,78 @@ struct PairConfig {
   }
 };
 
+// Whole, aligned tiles of the consumer on the DMA-fed loop (the consumer
+// applied in its epilogue); any other problem on the 128 x 128 x 16 tile.
+template <int TM, int TN, int TK, int WM, int NST>
+struct ConsumerDmaConfig {
+  using S = F32DmaShape<TM, TN, TK, WM, 128, false, false, NST>;
+  static constexpr int kThreads = S::NW * kWave;
+  template <int OP>
+  static hipError_t run(const GemmArgs& a, const F32DmaOut& o, hipStream_t s) {
+    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaConsume, OP>;
+    hipError_t e = allow_lds_fused(fn, (size_t)S::kLdsBytes);
+    if (e != hipSuccess) return e;
+    GemmArgs a1 = a, a2 = a;
+    F32DmaOut oo = o;
+    void* kargs[] = {&a1, &a2, &oo};
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n)),
+                           dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
+  }
+  static hipError_t launch(const GemmArgs& args, const ConsumerArgs& c, hipStream_t s) {
+    const bool c_ok = args.beta == 0.0f || (args.ldc % 4 == 0 && (reinterpret_cast<uintptr_t>(args.C) & 15) == 0);
+    if (!c_ok || !f32_dma_fits<TM, TN, TK>(args, c.D, c.ldd, 1))
+      return ConsumerConfig<128, 128, 16, 64, 64>::launch(args, c, s);
+    GemmArgs a = args;
+    a.tiles_m = a.m / TM;
+    a.tiles_n = a.n / TN;
+    F32DmaOut o{};
+    o.splits = 1;
+    o.D = c.D;
+    o.ldd = c.ldd;
+    o.bias = c.bias;
+    o.lo = c.lo;
+    o.hi = c.hi;
+    switch (c.op) {
+      case HPVM_CONSUMER_RELU: return run<HPVM_CONSUMER_RELU>(a, o, s);
+      case HPVM_CONSUMER_BIAS: return run<HPVM_CONSUMER_BIAS>(a, o, s);
+      case HPVM_CONSUMER_BIAS_RELU: return run<HPVM_CONSUMER_BIAS_RELU>(a, o, s);
+      case HPVM_CONSUMER_CLAMP: return run<HPVM_CONSUMER_CLAMP>(a, o, s);
+      default: return run<HPVM_CONSUMER_NONE>(a, o, s);
+    }
+  }
+};
+
+// Whole, aligned tiles of the pair on the DMA-fed loop: per stage one A slab
+// and both B slabs (B1's tile, then B2's); any other problem on the
+// 128 x 128 x 16 pair tile.
+template <int TM, int TN, int TK, int WM, int NST>
+struct PairDmaConfig {
+  using S = F32DmaShape<TM, TN, TK, WM, 128, false, false, NST, true>;
+  static constexpr int kThreads = S::NW * kWave;
+  static hipError_t launch(const GemmArgs& a1, const GemmArgs& a2, hipStream_t s) {
+    const bool ok = f32_dma_fits<TM, TN, TK>(a1, a1.C, a1.ldc, 1) && a2.vec_b && a2.ldc % 4 == 0 &&
+                    (reinterpret_cast<uintptr_t>(a2.C) & 15) == 0;
+    if (!ok) return PairConfig<128, 128, 16, 64, 64>::launch(a1, a2, s);
+    GemmArgs p1 = a1, p2 = a2;
+    p1.tiles_m = p2.tiles_m = p1.m / TM;
+    p1.tiles_n = p2.tiles_n = p1.n / TN;
+    F32DmaOut o{};
+    o.splits = 1;
+    void* kargs[] = {&p1, &p2, &o};
+    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaUpdate, 0, true>;
+    hipError_t e = allow_lds_fused(fn, (size_t)S::kLdsBytes);
+    if (e != hipSuccess) return e;
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(p1.tiles_m * p1.tiles_n)),
+                           dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
+  }
+};
+
+#define HPVM_CONSUMER_DMA_ENTRY(TM, TN, TK, WM, NST)                                                 \
+  {{TM, TN, TK, WM, 128, NST}, ConsumerDmaConfig<TM, TN, TK, WM, NST>::kThreads,                       \
+   ConsumerDmaConfig<TM, TN, TK, WM, NST>::S::kLdsBytes, &ConsumerDmaConfig<TM, TN, TK, WM, NST>::launch, nullptr}
+#define HPVM_PAIR_DMA_ENTRY(TM, TN, TK, WM, NST)                                                     \
+  {{TM, TN, TK, WM, 128, NST}, PairDmaConfig<TM, TN, TK, WM, NST>::kThreads,                           \
+   PairDmaConfig<TM, TN, TK, WM, NST>::S::kLdsBytes, nullptr, &PairDmaConfig<TM, TN, TK, WM, NST>::launch}
 #define HPVM_CONSUMER_ENTRY(TM, TN, TK, WM, WN)                                                   \
   {{TM, TN, TK, WM, WN, 2}, ConsumerConfig<TM, TN, TK, WM, WN>::kThreads,                           \
    ConsumerConfig<TM, TN, TK, WM, WN>::kLds, &ConsumerConfig<TM, TN, TK, WM, WN>::launch, nullptr}
@@ -283,15 +344,20 @@ struct PairConfig {
   {{TM, TN, TK, WM, WN, 2}, PairConfig<TM, TN, TK, WM, WN>::kThreads, PairConfig<TM, TN, TK, WM, WN>::kLds, \
    nullptr, &PairConfig<TM, TN, TK, WM, WN>::launch}
 
-// The consumer kernel takes the tiles of the FP32 single-launch menu, so the
-// autotuner's choice for a shape carries over.
+// The consumer kernel takes the tiles of the FP32 single-launch menu, in its
+// order, so the autotuner's choice for a shape carries over.
 static const FusedEntry kConsumerMenu[] = {
+    HPVM_CONSUMER_DMA_ENTRY(256, 256, 32, 64, 2),
     HPVM_CONSUMER_ENTRY(128, 128, 16, 64, 64), HPVM_CONSUMER_ENTRY(256, 128, 16, 128, 64),
     HPVM_CONSUMER_ENTRY(128, 128, 32, 64, 64), HPVM_CONSUMER_ENTRY(64, 64, 16, 32, 32),
     HPVM_CONSUMER_ENTRY(128, 64, 16, 64, 32), HPVM_CONSUMER_ENTRY(64, 128, 16, 32, 64),
+    HPVM_CONSUMER_DMA_ENTRY(256, 256, 16, 64, 4),
+    HPVM_CONSUMER_DMA_ENTRY(128, 256, 32, 32, 2),
 };
-// Pair tiles: tile_m x tile_n of each output; 8 and 4 waves.
+// Pair tiles: tile_m x tile_n of each output; 8, 8 and 4 waves.  The DMA-fed
+// entry's two stages of one A slab and two B slabs take all 160 KB of LDS.
 static const FusedEntry kPairMenu[] = {
+    HPVM_PAIR_DMA_ENTRY(128, 256, 32, 64, 2),
     HPVM_PAIR_ENTRY(128, 128, 16, 64, 64),
     HPVM_PAIR_ENTRY(64, 64, 16, 32, 64),
 };

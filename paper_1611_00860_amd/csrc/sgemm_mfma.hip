@@ -125,9 +125,11 @@ struct F32DmaConfig {
     GemmArgs a = args;
     a.tiles_m = a.m / TM;
     a.tiles_n = a.n / TN;
-    int32_t splits = 1;
-    void* kargs[] = {&a, &splits};
-    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, false>;
+    GemmArgs unused = a;
+    F32DmaOut o{};
+    o.splits = 1;
+    void* kargs[] = {&a, &unused, &o};
+    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaUpdate>;
     hipError_t e = allow_lds(fn, (size_t)S::kLdsBytes);
     if (e != hipSuccess) return e;
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n)),

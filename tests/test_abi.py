@@ -431,10 +431,10 @@ def test_stream_status_layout():
 
 
 def test_fusion_menus(lib):
-    # the consumer kernel covers the FP32 tiles staged through registers (leaf_n <= 64)
-    assert hp.fusion_menu("consumer") == [t for t in hp.tile_menu("fp32") if t[5] == 2 and t[4] <= 64]
+    # the consumer kernel takes the FP32 single-launch tiles, in order
+    assert hp.fusion_menu("consumer") == hp.tile_menu("fp32")
     pair = hp.fusion_menu("pair")
-    assert len(pair) == 2 and all(t[5] == 2 for t in pair)
+    assert len(pair) == 3 and all(t[5] == 2 for t in pair) and pair[0][4] == 128
     cnt = ctypes.c_int32()
     assert lib.hpvm_fusion_menu(2, None, 0, ctypes.byref(cnt)) == -1
 

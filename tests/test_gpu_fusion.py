@@ -69,12 +69,13 @@ def test_consumer_separate_output_and_beta_zero(gpu):
     assert np.array_equal(to_host(D3), oracle.consumer(2.0 * C.astype(np.float64), "relu"))
 
 
-def test_consumer_random_matches_unfused_bitwise(gpu):
+@pytest.mark.parametrize("m,n,k", [(520, 390, 300), (512, 512, 96)])
+def test_consumer_random_matches_unfused_bitwise(gpu, m, n, k):
     """Same tile, same FP32 value v, then the consumer: the fused kernel gives
-    exactly sgemm followed by the same element-wise op in torch."""
+    exactly sgemm followed by the same element-wise op in torch (whole tiles:
+    both on the DMA-fed loop)."""
     import torch
 
-    m, n, k = 520, 390, 300
     A, B, C = inputs.sgemm_operands(m, n, k, seed=4)
     bias = np.random.default_rng(1).uniform(-1, 1, n).astype(np.float32)
     dA, dB = to_dev(A), to_dev(B)
@@ -109,12 +110,12 @@ def test_pair_integers_bit_exact_every_tile(gpu, m, n, k):
         assert np.array_equal(to_host(dC2), ref2), tile
 
 
-def test_pair_random_matches_single_launches_bitwise(gpu):
+@pytest.mark.parametrize("m,n,k", [(700, 600, 333), (512, 512, 96)])
+def test_pair_random_matches_single_launches_bitwise(gpu, m, n, k):
     """Per wave the pair kernel runs the MFMA sequence of the single-output
     kernel with the same wave tile, so each output agrees bit for bit."""
     import torch
 
-    m, n, k = 700, 600, 333
     A, B1, C1 = inputs.sgemm_operands(m, n, k, seed=21)
     _, B2, C2 = inputs.sgemm_operands(m, n, k, seed=22)
     dA, dB1, dB2 = to_dev(A), to_dev(B1), to_dev(B2)
