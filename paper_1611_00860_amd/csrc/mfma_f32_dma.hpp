@@ -143,19 +143,20 @@ struct F32DmaOut {
   float lo, hi;       // CLAMP
 };
 
+// One tile (tm, tn) of contraction slice z on the DMA-fed loop, by the
+// whole workgroup (S::NW waves), with the Allocation at smem (S::kLdsBytes).
 // p: the sgemm (for PAIR, output 1); p2: PAIR's output 2 (B2, C2, alpha2,
-// beta2; the rest as p), ignored otherwise.
+// beta2; the rest as p), ignored otherwise.  Ends with every transfer
+// drained and the workgroup past a barrier, so smem may be reused at once.
 template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, int NST, int MODE, int OP = 0,
           bool PAIR = false>
-__global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>::NW * kWave))
-    __attribute__((amdgpu_waves_per_eu(1, (F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>::kMaxWaves))))
-    sgemm_f32_dma(GemmArgs p, GemmArgs p2, F32DmaOut o) {
+__device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& p2, const F32DmaOut& o, int tm,
+                                             int tn, int z, char* smem) {
   using S = F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>;
   using OA = typename S::OA;
   using OB = typename S::OB;
   constexpr int NA = OA::kBlocks, NB = OB::kBlocks, KG = TK / 8;
   static_assert(MODE != kDmaConsume || !BT, "the consumer epilogue stores rows of adjacent outputs");
-  extern __shared__ __align__(16) char smem[];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -163,10 +164,6 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, 
   const int half = PAIR ? wcol / TN : 0;  // which output this wave's columns belong to
   const int wn0 = wcol - half * TN;
   const int splits = MODE == kDmaSplit ? o.splits : 1;
-  const int tiles = p.tiles_m * p.tiles_n;
-  const int z = blockIdx.x / tiles;  // contraction slice: co-resident workgroups share it
-  int tm, tn;
-  tile_coords(p.tiles_m, p.tiles_n, blockIdx.x - z * tiles, tm, tn);
   const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
   const int slabs_all = p.k / TK;
   const int per = (slabs_all + splits - 1) / splits;
@@ -314,6 +311,21 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, 
           }
         }
   }
+}
+
+// One launch: a workgroup per tile and contraction slice (slice-major, so
+// co-resident workgroups share a slice), XCD-aware tile order.
+template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, int NST, int MODE, int OP = 0,
+          bool PAIR = false>
+__global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>::NW * kWave))
+    __attribute__((amdgpu_waves_per_eu(1, (F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>::kMaxWaves))))
+    sgemm_f32_dma(GemmArgs p, GemmArgs p2, F32DmaOut o) {
+  extern __shared__ __align__(16) char smem[];
+  const int tiles = p.tiles_m * p.tiles_n;
+  const int z = blockIdx.x / tiles;
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, blockIdx.x - z * tiles, tm, tn);
+  f32_dma_tile<TM, TN, TK, WM, WN, AT, BT, NST, MODE, OP, PAIR>(p, p2, o, tm, tn, z, smem);
 }
 
 // True when the DMA-fed loop covers the problem in whole tiles: m, n and k

@@ -16,6 +16,7 @@
 #include "host_common.hpp"
 #include "hpvm_sgemm.h"
 #include "mfma_f32.hpp"
+#include "mfma_f32_dma.hpp"
 
 namespace hpvm {
 
@@ -48,13 +49,33 @@ __device__ __forceinline__ void grouped_tile(const GemmArgs& p, int tm, int tn, 
                             tn * TN + (wave % (TN / WN)) * WN, lane);
 }
 
+// Interior 128 x 128 tiles of instances whose k is a multiple of 16 and
+// whose rows are 16-byte aligned take the DMA-fed loop: four waves of
+// 32 x 128, 16-deep slabs in two 16 KB stages.
+using GroupedDma = F32DmaShape<128, 128, 16, 32, 128, false, false, 2>;
+static_assert(GroupedDma::NW * kWave == kGroupedThreads && GroupedDma::kLdsBytes <= kGroupedLds, "DMA tile fits");
+
+__device__ __forceinline__ bool grouped_dma_ok(const GemmArgs& p, int tm, int tn) {
+  return p.vec_a && p.vec_b && p.k > 0 && p.k % 16 == 0 && (tm + 1) * 128 <= p.m && (tn + 1) * 128 <= p.n &&
+         p.ldc % 4 == 0 && (reinterpret_cast<uintptr_t>(p.C) & 15) == 0;
+}
+
 // Runs tile `local` (row-major over the instance's tile grid) of one sgemm
 // with menu shape `shape`.  Uniform across the workgroup.
 __device__ __forceinline__ void run_shape_tile(int shape, const GemmArgs& p, int tiles_n, int local,
                                                float* lds) {
   const int tm = local / tiles_n, tn = local - (local / tiles_n) * tiles_n;
   switch (shape) {
-    case 0: grouped_tile<128, 128, 16, 64, 64>(p, tm, tn, lds); break;
+    case 0:
+      if (grouped_dma_ok(p, tm, tn)) {
+        F32DmaOut o{};
+        o.splits = 1;
+        f32_dma_tile<128, 128, 16, 32, 128, false, false, 2, kDmaUpdate>(p, p, o, tm, tn, 0,
+                                                                       reinterpret_cast<char*>(lds));
+      } else {
+        grouped_tile<128, 128, 16, 64, 64>(p, tm, tn, lds);
+      }
+      break;
     case 1: grouped_tile<128, 64, 16, 64, 32>(p, tm, tn, lds); break;
     case 2: grouped_tile<64, 128, 16, 32, 64>(p, tm, tn, lds); break;
     default: grouped_tile<64, 64, 16, 32, 32>(p, tm, tn, lds); break;

@@ -90,6 +90,35 @@ def test_grouped_matches_single_launch_bitwise(gpu, shape_idx):
     plan.destroy()
 
 
+def test_grouped_dma_interior_tiles_bit_exact(gpu):
+    """Aligned instances whose k is a multiple of 16 run their interior
+    128 x 128 tiles on the DMA-fed loop and their edge tiles on the masked
+    one (k = 40: every tile masked): integer inputs stay exact, and the bits
+    equal single launches of the same tile shape, whose loop accumulates
+    every output in the same k order."""
+    import torch
+
+    shapes = [(256, 256, 64), (300, 260, 48), (384, 128, 160), (130, 520, 32), (128, 128, 16), (512, 256, 40)]
+    alphas = [1.0, -2.0, 0.5, 1.0, 2.0, 1.0]
+    betas = [0.0, 1.0, -0.5, 1.0, 0.0, 0.5]
+    ops = [inputs.sgemm_operands(m, n, k, seed=500 + i, dist="int") for i, (m, n, k) in enumerate(shapes)]
+    As = [to_dev(A) for A, _, _ in ops]
+    Bs = [to_dev(B) for _, B, _ in ops]
+    Cs = [to_dev(C) for _, _, C in ops]
+    Cs_single = [to_dev(C) for _, _, C in ops]
+    tile = gpu.grouped_menu()[0]
+    print(f"case: grouped dma interior tiles, tile {tile}", flush=True)
+    plan = gpu.GroupedPlan(As, Bs, Cs, alphas, betas, tile=tile)
+    plan.run()
+    for A, B, C, a, b in zip(As, Bs, Cs_single, alphas, betas):
+        gpu.sgemm(A, B, C, a, b, tile=tile)
+    torch.cuda.synchronize()
+    for i, ((A, B, C), a, b) in enumerate(zip(ops, alphas, betas)):
+        assert np.array_equal(to_host(Cs[i]), oracle.sgemm(A, B, C, a, b)), shapes[i]
+        assert torch.equal(Cs[i], Cs_single[i]), shapes[i]
+    plan.destroy()
+
+
 def test_grouped_permutation_invariant(gpu):
     import torch
 
