@@ -109,18 +109,37 @@ __global__ void __launch_bounds__(256)
 // src[r * ld + c]) -> [cols_pad][rows_pad] bfloat16: transposed so that k is
 // contiguous.  One workgroup moves a 64 x 64 block through LDS.
 constexpr int kTB = 64;
+// A block reads its rows in 16-byte units when the whole 64 x 64 block is
+// inside the matrix and the rows allow them (vec), element by element
+// otherwise; LDS rows are 65 floats, so both the row-wise writes and the
+// column-wise reads of a wavefront fall on distinct banks.
 template <bool X3>
 __global__ void __launch_bounds__(256)
     stage_cols(const float* __restrict__ src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
-               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int32_t vec) {
   __shared__ float t[kTB][kTB + 1];
   const int64_t r0 = (int64_t)blockIdx.y * kTB, c0 = (int64_t)blockIdx.x * kTB;
   const int tid = threadIdx.x;
+  if (vec && r0 + kTB <= rows && c0 + kTB <= cols) {
+    f32x4 v[kTB * kTB / 4 / 256];
 #pragma unroll
-  for (int i = 0; i < kTB * kTB / 256; ++i) {
-    const int r = i * (256 / kTB) + tid / kTB, c = tid % kTB;
-    const int64_t gr = r0 + r, gc = c0 + c;
-    t[r][c] = (gr < rows && gc < cols) ? src[gr * ld + gc] : 0.0f;
+    for (int i = 0; i < kTB * kTB / 4 / 256; ++i) {
+      const int r = i * (256 / (kTB / 4)) + tid / (kTB / 4), c = (tid % (kTB / 4)) * 4;
+      v[i] = *reinterpret_cast<const f32x4*>(src + (r0 + r) * ld + c0 + c);
+    }
+#pragma unroll
+    for (int i = 0; i < kTB * kTB / 4 / 256; ++i) {
+      const int r = i * (256 / (kTB / 4)) + tid / (kTB / 4), c = (tid % (kTB / 4)) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) t[r][c + e] = v[i][e];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTB * kTB / 256; ++i) {
+      const int r = i * (256 / kTB) + tid / kTB, c = tid % kTB;
+      const int64_t gr = r0 + r, gc = c0 + c;
+      t[r][c] = (gr < rows && gc < cols) ? src[gr * ld + gc] : 0.0f;
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -451,8 +470,8 @@ hipError_t stage_rows_launch(const float* src, int64_t ld, int64_t rows, int64_t
 
 template <bool X3>
 hipError_t stage_cols_launch(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
-                             int64_t cols_pad, uint16_t* hi, uint16_t* lo, hipStream_t s) {
-  void* args[] = {&src, &ld, &rows, &cols, &rows_pad, &hi, &lo};
+                             int64_t cols_pad, uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s) {
+  void* args[] = {&src, &ld, &rows, &cols, &rows_pad, &hi, &lo, &vec};
   const dim3 grid((unsigned)(cols_pad / kTB), (unsigned)(rows_pad / kTB));
   return hipLaunchKernel(reinterpret_cast<const void*>(&stage_cols<X3>), grid, dim3(256), args, 0, s);
 }
@@ -470,10 +489,10 @@ hipError_t stage_operands(const GemmArgs& a, bool at, bool bt, const StagedLayou
   if (!at)  // A: m x k, k contiguous
     e = stage_rows_launch<X3>(a.A, a.lda, a.m, a.k, L.m_pad, L.k_pad, ah, al, a.vec_a, s);
   else      // A stored k x m
-    e = stage_cols_launch<X3>(a.A, a.lda, a.k, a.m, L.k_pad, L.m_pad, ah, al, s);
+    e = stage_cols_launch<X3>(a.A, a.lda, a.k, a.m, L.k_pad, L.m_pad, ah, al, a.vec_a, s);
   if (e != hipSuccess) return e;
   if (!bt)  // B: k x n, n contiguous
-    return stage_cols_launch<X3>(a.B, a.ldb, a.k, a.n, L.k_pad, L.n_pad, bh, bl, s);
+    return stage_cols_launch<X3>(a.B, a.ldb, a.k, a.n, L.k_pad, L.n_pad, bh, bl, a.vec_b, s);
   // B stored n x k
   return stage_rows_launch<X3>(a.B, a.ldb, a.n, a.k, L.n_pad, L.k_pad, bh, bl, a.vec_b, s);
 }
