@@ -18,8 +18,11 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
 }
 
 // base (uniform, 64-bit) + voff (per lane) -> LDS lds (uniform) + 16 * lane.
-// The compiler does not see this transfer: callers order it with
-// dma_wait_barrier, never with the compiler's own waits.
+// The LDS address travels in M0, which the compiler sets right before the
+// asm; the s_nop is the one wait state the hardware needs between a scalar
+// write of M0 and an LDS-DMA load that reads it.  The compiler does not see
+// this transfer (it counts no wait for it and keeps no LDS value across it,
+// the asm clobbering memory): callers order it with dma_wait_barrier.
 __device__ __forceinline__ void dma16(uint32_t lds, const void* base, uint32_t voff) {
   asm volatile(
       "s_nop 0\n\t"
