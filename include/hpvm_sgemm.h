@@ -254,7 +254,9 @@ int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity,
  * dA and dB run on an MFMA lowering of `prec` (FP32, BF16 or bf16x3
  * products, FP32 accumulation): the fused one reads B (for dA) and A (for
  * dB) in transposed form; the staged one (tiles with stages == 3) folds
- * that transposition into its conversion pass.  The two scalars are reduced
+ * that transposition into its conversion passes, and converts G for both
+ * products in one pass that also writes dC_in and the partials of dbeta.
+ * The two scalars are reduced
  * in FP32 with fixed-order tree sums, so repeated calls give identical bits.
  * Any of dA, dB, dC_in, dalpha, dbeta may be NULL to skip that output.
  * dalpha and dbeta are single device floats.  A, B, C_in and G are device

@@ -232,7 +232,7 @@ def sgemm_backward(A, B, C_in, G, alpha: float, beta: float, prec="fp32", need=(
         out["dB"] = torch.empty((k, n), dtype=torch.float32, device=dev)
     if "dC_in" in need:
         out["dC_in"] = torch.empty((m, n), dtype=torch.float32, device=dev)
-    scal = torch.zeros(2, dtype=torch.float32, device=dev)
+    scal = torch.empty(2, dtype=torch.float32, device=dev)  # the call writes each requested scalar
     nbytes = backward_workspace_bytes(m, n, k, prec, tile)
     ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=dev)
 

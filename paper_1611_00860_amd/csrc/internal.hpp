@@ -15,6 +15,17 @@ struct GemmArgs;
 // Lowering ids (hpvm_dfg.lowering).
 enum Lowering { kLiteral = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kMfmaBf16x3 = 3, kStagedBf16 = 4, kStagedBf16x3 = 5 };
 
+// bfloat16 planes of one staged product, the contraction index contiguous:
+// the A side [round256(m)][kp], the B side [round256(n)][kp], kp =
+// round64(k), zero outside the matrices.  The lo planes (x - hi) exist for
+// bf16x3 only.
+struct StagedPlanes {
+  const uint16_t* ah;
+  const uint16_t* al;
+  const uint16_t* bh;
+  const uint16_t* bl;
+};
+
 // One compiled MFMA configuration.
 struct MfmaEntry {
   hpvm_tile tile;
@@ -27,11 +38,12 @@ struct MfmaEntry {
   // Staged lowering (tile.stages == 3): operands converted into `workspace`
   // first, then the GEMM.  Null for fused entries.
   hipError_t (*launch_staged)(const GemmArgs& args, void* workspace, hipStream_t s) = nullptr;
-  // Staged, any operand form; with `partial` the epilogue is the backward's
-  // dA one (C <- alpha acc when C is set; partial[tile] = sum aorig .* acc).
-  hipError_t (*launch_staged_form)(const GemmArgs& args, bool a_trans, bool b_trans, void* workspace,
-                                   const float* aorig, int64_t lda_orig, float* partial,
-                                   hipStream_t s) = nullptr;
+  // Staged GEMM on planes already written (stage_operand, stage_gradient);
+  // args gives the sizes, C, alpha and beta.  With `partial` the epilogue is
+  // the backward's dA one (C <- alpha acc when C is set; partial[tile] = sum
+  // of aorig .* acc over the tile).
+  hipError_t (*launch_staged_planes)(const GemmArgs& args, const StagedPlanes& planes, const float* aorig,
+                                     int64_t lda_orig, float* partial, hipStream_t s) = nullptr;
 };
 
 // The compiled fused menu for `prec` (FP32, BF16, BF16X3); returns the count.
@@ -46,6 +58,33 @@ int64_t staged_workspace_bytes(int32_t prec, int64_t m, int64_t n, int64_t k);
 // Deepest contraction a staged tile takes: its loads address a tile's
 // rows of a bfloat16 plane with 32-bit byte offsets.
 bool staged_k_ok(int64_t k);
+
+// Padded plane extents: rows (m or n) to 256, the contraction to 64.
+int64_t staged_rows_pad(int64_t rows);
+int64_t staged_k_pad(int64_t k);
+
+// One FP32 operand (rows x cols, element (r, c) at src[r * ld + c]) into its
+// plane(s) hi (and lo for bf16x3).  k_along_rows = false: c is the
+// contraction index, plane [round256(rows)][round64(cols)]; true: r is,
+// plane [round256(cols)][round64(rows)] (transposed through LDS).  vec: src
+// and ld allow 16-byte loads.
+hipError_t stage_operand(int32_t prec, const float* src, int64_t ld, int64_t rows, int64_t cols, bool k_along_rows,
+                         uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s);
+
+// The backward's one pass over the upstream gradient G (m x n): each 64 x 64
+// block is read once and gives
+//   gh/gl  <- G as [round256(m)][round64(n)] planes (the dA product's A side),
+//   th/tl  <- G transposed as [round256(n)][round64(m)] (the dB product's
+//             B side),
+//   dCin   <- beta G (zeros when beta == 0),
+//   partial[block] <- sum over the block of G .* Cin,
+// each skipped when its pointer is null (Cin is read only for partial).
+// vec: G, dCin and Cin rows allow 16-byte units.  partial holds
+// stage_gradient_blocks(m, n) floats, in a fixed order.
+int64_t stage_gradient_blocks(int64_t m, int64_t n);
+hipError_t stage_gradient(int32_t prec, const float* G, int64_t ldg, const float* Cin, int64_t ldci, float* dCin,
+                          int64_t lddci, int64_t m, int64_t n, float beta, float* partial, uint16_t* gh,
+                          uint16_t* gl, uint16_t* th, uint16_t* tl, int32_t vec, hipStream_t s);
 
 // Every compiled entry of a precision: fused first (entry 0 is the default),
 // then staged.  Returns nullptr past the end.

@@ -99,7 +99,30 @@ __global__ void __launch_bounds__(kElemThreads)
     const float* g = G + i * ldg;
     const float* c = partial ? Cin + i * ldci : nullptr;
     float* d = dCin ? dCin + i * lddci : nullptr;
-    for (int64_t q = threadIdx.x; q < n4; q += blockDim.x) {
+    int64_t q = threadIdx.x;
+    // Four units per step, all loads ahead of the stores so that they overlap;
+    // the sum still takes this thread's units in ascending order.
+    for (; q + 3 * (int64_t)blockDim.x < n4; q += 4 * (int64_t)blockDim.x) {
+      f32x4 gv[4], cv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        gv[u] = reinterpret_cast<const f32x4*>(g)[q + u * blockDim.x];
+        if (c) cv[u] = reinterpret_cast<const f32x4*>(c)[q + u * blockDim.x];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (d)
+          reinterpret_cast<f32x4*>(d)[q + u * blockDim.x] =
+              (beta == 0.0f) ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : beta * gv[u];
+        if (c) {
+          part = fmaf(gv[u][0], cv[u][0], part);
+          part = fmaf(gv[u][1], cv[u][1], part);
+          part = fmaf(gv[u][2], cv[u][2], part);
+          part = fmaf(gv[u][3], cv[u][3], part);
+        }
+      }
+    }
+    for (; q < n4; q += blockDim.x) {
       const f32x4 gv = reinterpret_cast<const f32x4*>(g)[q];
       if (d) reinterpret_cast<f32x4*>(d)[q] = (beta == 0.0f) ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : beta * gv;
       if (c) {
@@ -126,9 +149,21 @@ __global__ void __launch_bounds__(kElemThreads)
     sgemm_grad_finish(const float* __restrict__ pa, int32_t na, const float* __restrict__ pb, int32_t nb,
                       float* dalpha, float* dbeta) {
   __shared__ float red[kElemThreads / kWave];
-  float a = 0.0f, b = 0.0f;
-  for (int t = threadIdx.x; t < na; t += blockDim.x) a += pa[t];
-  for (int t = threadIdx.x; t < nb; t += blockDim.x) b += pb[t];
+  // Each thread adds its partials in ascending order, loading four ahead.
+  auto strided = [](const float* p, int count) {
+    float s = 0.0f;
+    int t = threadIdx.x;
+    for (; t + 3 * (int)blockDim.x < count; t += 4 * (int)blockDim.x) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = p[t + u * blockDim.x];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s += v[u];
+    }
+    for (; t < count; t += blockDim.x) s += p[t];
+    return s;
+  };
+  const float a = strided(pa, na), b = strided(pb, nb);
   const float sa = block_sum(a, red);
   const float sb = block_sum(b, red);
   if (threadIdx.x == 0) {
@@ -219,6 +254,7 @@ const BwdEntry kBwd[] = {
     fused_entry<128, 64, 16, 64, 32, HPVM_PREC_FP32>(),
     fused_entry<64, 128, 16, 32, 64, HPVM_PREC_FP32>(),
     fused_entry<64, 64, 16, 32, 32, HPVM_PREC_FP32>(),
+    staged_entry(128, 128, 64, 64, 32, HPVM_PREC_BF16),
     staged_entry(128, 128, 64, 64, 64, HPVM_PREC_BF16),
     staged_entry(256, 256, 64, 128, 64, HPVM_PREC_BF16),
     staged_entry(256, 128, 64, 128, 64, HPVM_PREC_BF16),
@@ -302,13 +338,48 @@ int64_t elem_blocks(int64_t m, int64_t n) {
   return std::max<int64_t>(1, std::min<int64_t>(kElemBlocks, (m * n + kElemThreads - 1) / kElemThreads));
 }
 
-// Workspace: [dA partials][element-wise partials][staging planes], each
-// 256-byte aligned.  The dA and dB passes run one after the other on the
-// stream, so they share the staging region.
+// Workspace: [dA partials][element-wise partials][staging region], each
+// 256-byte aligned.  A DMA entry's dA and dB passes run one after the other
+// on the stream and share the region; a staged entry keeps the planes of
+// both products there at once, since one pass over G writes G's planes for
+// both (each plane pair hi, lo adjacent):
+//   [G: round256(m) x round64(n)][G^T: round256(n) x round64(m)]
+//   [B: round256(k) x round64(n)][A^T: round256(k) x round64(m)]
 struct BwdLayout {
-  int64_t na, nb;
+  int64_t na, nb, ng;  // dalpha partials, grad_c partials, partials of the pass over G
   int64_t pb_off, stage_off, total;
 };
+
+// bfloat16 planes of a staged backward (see BwdLayout) from the staging
+// region: ga = the dA product's (G, B), gb = the dB product's (A^T, G^T).
+struct BwdPlanes {
+  uint16_t *gh, *gl, *th, *tl, *bh, *bl, *ah, *al;
+};
+int64_t bwd_plane_elems(int64_t m, int64_t n, int64_t k, int64_t* g, int64_t* gt, int64_t* b, int64_t* a) {
+  *g = staged_rows_pad(m) * staged_k_pad(n);
+  *gt = staged_rows_pad(n) * staged_k_pad(m);
+  *b = staged_rows_pad(k) * staged_k_pad(n);
+  *a = staged_rows_pad(k) * staged_k_pad(m);
+  return *g + *gt + *b + *a;
+}
+BwdPlanes bwd_planes(int32_t prec, void* stage, int64_t m, int64_t n, int64_t k) {
+  const bool x3 = prec == HPVM_PREC_BF16X3;
+  int64_t g, gt, b, a;
+  bwd_plane_elems(m, n, k, &g, &gt, &b, &a);
+  uint16_t* p = reinterpret_cast<uint16_t*>(stage);
+  BwdPlanes P;
+  auto take = [&](int64_t elems, uint16_t** hi, uint16_t** lo) {
+    *hi = p;
+    p += elems;
+    *lo = x3 ? p : nullptr;
+    if (x3) p += elems;
+  };
+  take(g, &P.gh, &P.gl);
+  take(gt, &P.th, &P.tl);
+  take(b, &P.bh, &P.bl);
+  take(a, &P.ah, &P.al);
+  return P;
+}
 
 // A DMA entry sizes for both of its paths: the slice partials (dA's and
 // dB's passes share the region) and the larger of its dalpha partial counts.
@@ -319,11 +390,14 @@ BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
   const DmaPlan d = dma_plan(e, m, n, k);
   if (d.sa) L.na = std::max(L.na, split_sum_blocks(m, k));
   L.nb = elem_blocks(m, n);
+  L.ng = (!e->grad_a && !e->dma && m > 0 && n > 0) ? stage_gradient_blocks(m, n) : 0;
   L.pb_off = up(L.na * 4);
-  L.stage_off = L.pb_off + up(L.nb * 4);
+  L.stage_off = L.pb_off + up(std::max(L.nb, L.ng) * 4);
   int64_t stage = 0;
-  if (!e->grad_a)
-    stage = std::max(staged_workspace_bytes(e->prec, m, k, n), staged_workspace_bytes(e->prec, k, n, m));
+  if (!e->grad_a && !e->dma) {
+    int64_t g, gt, b, a;
+    stage = (e->prec == HPVM_PREC_BF16X3 ? 2 : 1) * 2 * bwd_plane_elems(m, n, k, &g, &gt, &b, &a);
+  }
   if (e->dma) stage = 4 * std::max<int64_t>(d.sa * m * k, d.sb * k * n);
   L.total = L.stage_off + stage;
   return L;
@@ -481,6 +555,21 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   hipError_t e = hipSuccess;
   int64_t na = L.na;
 
+  // Staged entries: one pass over G writes its planes for both products,
+  // dC_in and dbeta's partials; each product then converts its other operand.
+  BwdPlanes P{};
+  bool g_pass = false;
+  if (staged && (run_a || run_b)) {
+    if (!me || !me->launch_staged_planes) return hip_error(hipErrorInvalidValue, "backward staged entry");
+    P = bwd_planes(prec, stage, m, n, k);
+    const int32_t gvec = vec16(G, ldg) && (!dC_in || vec16(dC_in, lddci)) && (!dbeta || vec16(C_in, ldci));
+    e = stage_gradient(prec, G, ldg, dbeta ? C_in : nullptr, ldci, dC_in, lddci, m, n, beta, dbeta ? pb : nullptr,
+                       run_a ? P.gh : nullptr, run_a ? P.gl : nullptr, run_b ? P.th : nullptr,
+                       run_b ? P.tl : nullptr, gvec, s);
+    if (e != hipSuccess) return hip_error(e, "backward gradient staging launch");
+    g_pass = true;
+  }
+
   // dA (and dalpha's partials): contraction over n.
   if (want_a && mk && n == 0) {
     if (dA) e = launch_scale(dA, ldda, m, k, 0.0f, s);
@@ -507,7 +596,9 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
                                     lda, dalpha ? pa : nullptr, s);
       na = dalpha ? split_sum_blocks(m, k) : 0;
     } else if (staged) {
-      e = me ? me->launch_staged_form(a, false, true, stage, A, lda, dalpha ? pa : nullptr, s) : hipErrorInvalidValue;
+      e = stage_operand(prec, B, ldb, k, n, false, P.bh, P.bl, vec16(B, ldb), s);
+      if (e == hipSuccess)
+        e = me->launch_staged_planes(a, StagedPlanes{P.gh, P.gl, P.bh, P.bl}, A, lda, dalpha ? pa : nullptr, s);
     } else if (dalpha) {
       // Fused pass: dA (when requested) and the per-tile partials of dalpha.
       if (fb->lds > 65536)
@@ -551,13 +642,16 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     if (dma_b) e = launch_split<true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb, nullptr, 0,
                                              nullptr, s);
     else if (!me) e = hipErrorInvalidValue;
-    else if (staged) e = me->launch_staged_form(b, true, false, stage, nullptr, 0, nullptr, s);
+    else if (staged) {
+      e = stage_operand(prec, A, lda, m, k, true, P.ah, P.al, vec16(A, lda), s);
+      if (e == hipSuccess) e = me->launch_staged_planes(b, StagedPlanes{P.ah, P.al, P.th, P.tl}, nullptr, 0, nullptr, s);
+    }
     else e = me->launch(b, true, false, s);
   }
   if (e != hipSuccess) return hip_error(e, "backward dB launch");
 
-  // dC_in and dbeta's partials.
-  if (mn && (dC_in || dbeta)) {
+  // dC_in and dbeta's partials (already written by a pass over G).
+  if (mn && (dC_in || dbeta) && !g_pass) {
     float* part = dbeta ? pb : nullptr;
     const float* Gp = G;
     const float* Cp = C_in;
@@ -575,7 +669,7 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     const float* pa_ = pa;
     const float* pb_ = pb;
     int32_t na_ = (int32_t)(dalpha ? na : 0);
-    int32_t nb_ = (int32_t)((dbeta && mn) ? L.nb : 0);
+    int32_t nb_ = (int32_t)((dbeta && mn) ? (g_pass ? L.ng : L.nb) : 0);
     void* kargs[] = {&pa_, &na_, &pb_, &nb_, &dalpha, &dbeta};
     e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_grad_finish), dim3(1), dim3(kElemThreads), kargs, 0, s);
   }

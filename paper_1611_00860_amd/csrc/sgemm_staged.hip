@@ -42,11 +42,14 @@ bool staged_k_ok(int64_t k) {
   return (int64_t)kPadMN * k_pad * 2 < ((int64_t)1 << 32);
 }
 
+int64_t staged_rows_pad(int64_t rows) { return (rows + kPadMN - 1) / kPadMN * kPadMN; }
+int64_t staged_k_pad(int64_t k) { return (k + kPadK - 1) / kPadK * kPadK; }
+
 static StagedLayout staged_layout(int32_t prec, int64_t m, int64_t n, int64_t k) {
   StagedLayout L;
-  L.m_pad = (m + kPadMN - 1) / kPadMN * kPadMN;
-  L.n_pad = (n + kPadMN - 1) / kPadMN * kPadMN;
-  L.k_pad = (k + kPadK - 1) / kPadK * kPadK;
+  L.m_pad = staged_rows_pad(m);
+  L.n_pad = staged_rows_pad(n);
+  L.k_pad = staged_k_pad(k);
   L.planes = prec == HPVM_PREC_BF16X3 ? 2 : 1;
   L.a_plane = L.m_pad * L.k_pad * 2;
   L.b_plane = L.n_pad * L.k_pad * 2;
@@ -107,7 +110,8 @@ __global__ void __launch_bounds__(256)
 
 // rows x cols FP32 with the k index along rows (element (r, c) at
 // src[r * ld + c]) -> [cols_pad][rows_pad] bfloat16: transposed so that k is
-// contiguous.  One workgroup moves a 64 x 64 block through LDS.
+// contiguous.  One workgroup moves a 64 x 64 block through LDS; blocks are
+// numbered row-major, col_blocks = cols_pad / 64 per block row.
 constexpr int kTB = 64;
 // A block reads its rows in 16-byte units when the whole 64 x 64 block is
 // inside the matrix and the rows allow them (vec), element by element
@@ -116,9 +120,9 @@ constexpr int kTB = 64;
 template <bool X3>
 __global__ void __launch_bounds__(256)
     stage_cols(const float* __restrict__ src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
-               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int32_t vec) {
+               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int32_t vec, int64_t col_blocks) {
   __shared__ float t[kTB][kTB + 1];
-  const int64_t r0 = (int64_t)blockIdx.y * kTB, c0 = (int64_t)blockIdx.x * kTB;
+  const int64_t r0 = (int64_t)(blockIdx.x / col_blocks) * kTB, c0 = (int64_t)(blockIdx.x % col_blocks) * kTB;
   const int tid = threadIdx.x;
   if (vec && r0 + kTB <= rows && c0 + kTB <= cols) {
     f32x4 v[kTB * kTB / 4 / 256];
@@ -161,6 +165,106 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The backward's pass over G (see stage_gradient in internal.hpp): one
+// workgroup per 64 x 64 block of the round256(m) x round256(n) padded
+// matrix, row-major over blocks (col_blocks per block row).
+// The block goes through LDS as in stage_cols; the row plane is written
+// when the block's columns lie within round64(n), the transposed plane when
+// its rows lie within round64(m).  Each thread's share of <G, Cin> follows a
+// fixed element order, so the partials repeat bit for bit.
+template <bool X3>
+__global__ void __launch_bounds__(256)
+    stage_gradient_k(const float* __restrict__ G, int64_t ldg, const float* __restrict__ Cin, int64_t ldci,
+                     float* __restrict__ dCin, int64_t lddci, int64_t m, int64_t n, float beta,
+                     float* __restrict__ partial, uint16_t* __restrict__ gh, uint16_t* __restrict__ gl,
+                     int64_t n_kp, uint16_t* __restrict__ th, uint16_t* __restrict__ tl, int64_t m_kp,
+                     int32_t vec, int64_t col_blocks) {
+  __shared__ float t[kTB][kTB + 1];
+  __shared__ float red[256 / kWave];
+  const int64_t r0 = (int64_t)(blockIdx.x / col_blocks) * kTB, c0 = (int64_t)(blockIdx.x % col_blocks) * kTB;
+  const int tid = threadIdx.x;
+  float part = 0.0f;
+  if (vec && r0 + kTB <= m && c0 + kTB <= n) {
+    // Every load is issued before the first store, so the loads overlap.
+    constexpr int kU = kTB * kTB / 4 / 256;
+    f32x4 g[kU], cv[kU];
+#pragma unroll
+    for (int i = 0; i < kU; ++i) {
+      const int r = i * (256 / (kTB / 4)) + tid / (kTB / 4), c = (tid % (kTB / 4)) * 4;
+      g[i] = *reinterpret_cast<const f32x4*>(G + (r0 + r) * ldg + c0 + c);
+      if (partial) cv[i] = *reinterpret_cast<const f32x4*>(Cin + (r0 + r) * ldci + c0 + c);
+    }
+#pragma unroll
+    for (int i = 0; i < kU; ++i) {
+      const int r = i * (256 / (kTB / 4)) + tid / (kTB / 4), c = (tid % (kTB / 4)) * 4;
+      if (dCin)
+        *reinterpret_cast<f32x4*>(dCin + (r0 + r) * lddci + c0 + c) =
+            beta == 0.0f ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : beta * g[i];
+      if (partial) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) part = fmaf(g[i][e], cv[i][e], part);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) t[r][c + e] = g[i][e];
+    }
+  } else {
+#pragma unroll 4
+    for (int i = 0; i < kTB * kTB / 256; ++i) {
+      const int r = i * (256 / kTB) + tid / kTB, c = tid % kTB;
+      const int64_t gr = r0 + r, gc = c0 + c;
+      float g = 0.0f;
+      if (gr < m && gc < n) {
+        g = G[gr * ldg + gc];
+        if (dCin) dCin[gr * lddci + gc] = beta == 0.0f ? 0.0f : beta * g;
+        if (partial) part = fmaf(g, Cin[gr * ldci + gc], part);
+      }
+      t[r][c] = g;
+    }
+  }
+  __syncthreads();
+  if (gh && c0 < n_kp) {
+#pragma unroll
+    for (int j = 0; j < kTB * kTB / 8 / 256; ++j) {
+      const int u = tid + j * 256;
+      const int r = u / (kTB / 8), c = (u % (kTB / 8)) * 8;
+      uint16_t h[8], l[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) to_bf16<X3>(t[r][c + e], h[e], l[e]);
+      u32x4 hv, lv;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hv[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
+        if constexpr (X3) lv[q] = (uint32_t)l[2 * q] | ((uint32_t)l[2 * q + 1] << 16);
+      }
+      const int64_t off = (r0 + r) * n_kp + c0 + c;
+      *reinterpret_cast<u32x4*>(gh + off) = hv;
+      if constexpr (X3) *reinterpret_cast<u32x4*>(gl + off) = lv;
+    }
+  }
+  if (th && r0 < m_kp) {
+#pragma unroll
+    for (int j = 0; j < kTB * kTB / 8 / 256; ++j) {
+      const int u = tid + j * 256;
+      const int cc = u / (kTB / 8), kc = (u % (kTB / 8)) * 8;
+      uint16_t h[8], l[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) to_bf16<X3>(t[kc + e][cc], h[e], l[e]);
+      u32x4 hv, lv;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hv[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
+        if constexpr (X3) lv[q] = (uint32_t)l[2 * q] | ((uint32_t)l[2 * q + 1] << 16);
+      }
+      const int64_t off = (c0 + cc) * m_kp + r0 + kc;
+      *reinterpret_cast<u32x4*>(th + off) = hv;
+      if constexpr (X3) *reinterpret_cast<u32x4*>(tl + off) = lv;
+    }
+  }
+  if (!partial) return;
+  const float sum = block_sum(part, red);
+  if (tid == 0) partial[blockIdx.x] = sum;
+}
+
 struct StagedArgs {
   const uint16_t* ah;
   const uint16_t* al;
@@ -180,37 +284,46 @@ struct StagedArgs {
 
 // Backward epilogue (EPI = 1): C (may be null) <- alpha acc, and this
 // workgroup's partial of dalpha, the sum over its tile of aorig .* acc, into
-// partial[blockIdx.x].  Each group of 4 rows loads its elements of aorig
-// before its stores.  Reuses `smem`: every LDS transfer must be complete.
+// partial[blockIdx.x].  The aorig elements of up to 64 accumulator values
+// per lane are loaded together before any store (a store to C may alias
+// aorig as far as the compiler knows, so loads issued after it would wait
+// for it).  Reuses `smem`: every LDS transfer must be complete.
 template <int BM, int BN>
 __device__ __forceinline__ void dalpha_epilogue(const StagedArgs& p, const f32x16 (&acc)[BM][BN], int row0,
                                                 int col0, int lane, char* smem) {
+  constexpr int kBatch = (BM * BN * 16 <= 64) ? BM : 1;  // row blocks loaded together
   float part = 0.0f;
 #pragma unroll
-  for (int bi = 0; bi < BM; ++bi)
+  for (int b0 = 0; b0 < BM; b0 += kBatch) {
+    float a[kBatch][BN][16];
 #pragma unroll
-    for (int bj = 0; bj < BN; ++bj) {
-      const int j = col0 + 32 * bj + acc_col(lane);
-      if (j >= p.n) continue;
+    for (int bi = 0; bi < kBatch; ++bi)
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        float a[4];
+      for (int bj = 0; bj < BN; ++bj) {
+        const int j = col0 + 32 * bj + acc_col(lane);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
-          a[t] = i < p.m ? p.aorig[(int64_t)i * p.lda_orig + j] : 0.0f;
+        for (int r = 0; r < 16; ++r) {
+          const int i = row0 + 32 * (b0 + bi) + acc_row(r, lane);
+          a[bi][bj][r] = (i < p.m && j < p.n) ? p.aorig[(int64_t)i * p.lda_orig + j] : 0.0f;
         }
+      }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int i = row0 + 32 * bi + acc_row(4 * g + t, lane);
+    for (int bi = 0; bi < kBatch; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj) {
+        const int j = col0 + 32 * bj + acc_col(lane);
+        if (j >= p.n) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = row0 + 32 * (b0 + bi) + acc_row(r, lane);
           if (i < p.m) {
-            const float v = acc[bi][bj][4 * g + t];
+            const float v = acc[b0 + bi][bj][r];
             if (p.C) p.C[(int64_t)i * p.ldc + j] = p.alpha * v;
-            part = fmaf(a[t], v, part);
+            part = fmaf(a[bi][bj][r], v, part);
           }
         }
       }
-    }
+  }
   const float sum = block_sum(part, reinterpret_cast<float*>(smem));
   if (threadIdx.x == 0) p.partial[blockIdx.x] = sum;
 }
@@ -471,47 +584,83 @@ hipError_t stage_rows_launch(const float* src, int64_t ld, int64_t rows, int64_t
 template <bool X3>
 hipError_t stage_cols_launch(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
                              int64_t cols_pad, uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s) {
-  void* args[] = {&src, &ld, &rows, &cols, &rows_pad, &hi, &lo, &vec};
-  const dim3 grid((unsigned)(cols_pad / kTB), (unsigned)(rows_pad / kTB));
+  int64_t col_blocks = cols_pad / kTB;
+  void* args[] = {&src, &ld, &rows, &cols, &rows_pad, &hi, &lo, &vec, &col_blocks};
+  const dim3 grid((unsigned)(col_blocks * (rows_pad / kTB)));
   return hipLaunchKernel(reinterpret_cast<const void*>(&stage_cols<X3>), grid, dim3(256), args, 0, s);
 }
 
-// Writes op(A) as [m_pad][k_pad] and op(B) as [n_pad][k_pad] planes, k
-// contiguous: an operand already k-contiguous in HBM is copied row by row,
-// the other is transposed through LDS.
+// The forward product's planes: A (m x k, k contiguous) copied row by row
+// into [m_pad][k_pad], B (k x n) transposed through LDS into [n_pad][k_pad].
 template <bool X3>
-hipError_t stage_operands(const GemmArgs& a, bool at, bool bt, const StagedLayout& L, char* ws, hipStream_t s) {
+hipError_t stage_operands(const GemmArgs& a, const StagedLayout& L, char* ws, hipStream_t s) {
   uint16_t* ah = reinterpret_cast<uint16_t*>(ws);
   uint16_t* al = X3 ? reinterpret_cast<uint16_t*>(ws + L.a_plane) : nullptr;
   uint16_t* bh = reinterpret_cast<uint16_t*>(ws + L.planes * L.a_plane);
   uint16_t* bl = X3 ? reinterpret_cast<uint16_t*>(ws + L.planes * L.a_plane + L.b_plane) : nullptr;
-  hipError_t e;
-  if (!at)  // A: m x k, k contiguous
-    e = stage_rows_launch<X3>(a.A, a.lda, a.m, a.k, L.m_pad, L.k_pad, ah, al, a.vec_a, s);
-  else      // A stored k x m
-    e = stage_cols_launch<X3>(a.A, a.lda, a.k, a.m, L.k_pad, L.m_pad, ah, al, a.vec_a, s);
+  hipError_t e = stage_rows_launch<X3>(a.A, a.lda, a.m, a.k, L.m_pad, L.k_pad, ah, al, a.vec_a, s);
   if (e != hipSuccess) return e;
-  if (!bt)  // B: k x n, n contiguous
-    return stage_cols_launch<X3>(a.B, a.ldb, a.k, a.n, L.k_pad, L.n_pad, bh, bl, a.vec_b, s);
-  // B stored n x k
-  return stage_rows_launch<X3>(a.B, a.ldb, a.n, a.k, L.n_pad, L.k_pad, bh, bl, a.vec_b, s);
+  return stage_cols_launch<X3>(a.B, a.ldb, a.k, a.n, L.k_pad, L.n_pad, bh, bl, a.vec_b, s);
 }
 
-// Kernel arguments for the planes of layout L in workspace ws.
+}  // namespace
+
+hipError_t stage_operand(int32_t prec, const float* src, int64_t ld, int64_t rows, int64_t cols, bool k_along_rows,
+                         uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s) {
+  const bool x3 = prec == HPVM_PREC_BF16X3;
+  if (!k_along_rows) {
+    const int64_t rp = staged_rows_pad(rows), cp = staged_k_pad(cols);
+    return x3 ? stage_rows_launch<true>(src, ld, rows, cols, rp, cp, hi, lo, vec, s)
+              : stage_rows_launch<false>(src, ld, rows, cols, rp, cp, hi, lo, vec, s);
+  }
+  const int64_t rp = staged_k_pad(rows), cp = staged_rows_pad(cols);
+  return x3 ? stage_cols_launch<true>(src, ld, rows, cols, rp, cp, hi, lo, vec, s)
+            : stage_cols_launch<false>(src, ld, rows, cols, rp, cp, hi, lo, vec, s);
+}
+
+int64_t stage_gradient_blocks(int64_t m, int64_t n) {
+  return (staged_rows_pad(m) / kTB) * (staged_rows_pad(n) / kTB);
+}
+
+hipError_t stage_gradient(int32_t prec, const float* G, int64_t ldg, const float* Cin, int64_t ldci, float* dCin,
+                          int64_t lddci, int64_t m, int64_t n, float beta, float* partial, uint16_t* gh,
+                          uint16_t* gl, uint16_t* th, uint16_t* tl, int32_t vec, hipStream_t s) {
+  int64_t n_kp = staged_k_pad(n), m_kp = staged_k_pad(m), col_blocks = staged_rows_pad(n) / kTB;
+  void* args[] = {&G, &ldg, &Cin, &ldci, &dCin, &lddci, &m, &n, &beta, &partial, &gh, &gl, &n_kp, &th, &tl, &m_kp,
+                  &vec, &col_blocks};
+  const dim3 grid((unsigned)stage_gradient_blocks(m, n));
+  const void* fn = prec == HPVM_PREC_BF16X3 ? reinterpret_cast<const void*>(&stage_gradient_k<true>)
+                                            : reinterpret_cast<const void*>(&stage_gradient_k<false>);
+  return hipLaunchKernel(fn, grid, dim3(256), args, 0, s);
+}
+
+namespace {
+
+// The planes of layout L in workspace ws.
 template <bool X3>
-StagedArgs staged_args(const GemmArgs& a, const StagedLayout& L, char* ws, int tm, int tn, int tk,
-                       const float* aorig, int64_t lda_orig, float* partial) {
+StagedPlanes planes_in(const StagedLayout& L, char* ws) {
+  StagedPlanes P;
+  P.ah = reinterpret_cast<const uint16_t*>(ws);
+  P.al = X3 ? reinterpret_cast<const uint16_t*>(ws + L.a_plane) : nullptr;
+  P.bh = reinterpret_cast<const uint16_t*>(ws + L.planes * L.a_plane);
+  P.bl = X3 ? reinterpret_cast<const uint16_t*>(ws + L.planes * L.a_plane + L.b_plane) : nullptr;
+  return P;
+}
+
+// Kernel arguments for a product on planes P (rows of round64(a.k)).
+StagedArgs staged_args(const GemmArgs& a, const StagedPlanes& P, int tm, int tn, int tk, const float* aorig,
+                       int64_t lda_orig, float* partial) {
   StagedArgs p{};
-  p.ah = reinterpret_cast<const uint16_t*>(ws);
-  p.al = X3 ? reinterpret_cast<const uint16_t*>(ws + L.a_plane) : nullptr;
-  p.bh = reinterpret_cast<const uint16_t*>(ws + L.planes * L.a_plane);
-  p.bl = X3 ? reinterpret_cast<const uint16_t*>(ws + L.planes * L.a_plane + L.b_plane) : nullptr;
-  p.kp = L.k_pad;
+  p.ah = P.ah;
+  p.al = P.al;
+  p.bh = P.bh;
+  p.bl = P.bl;
+  p.kp = staged_k_pad(a.k);
   p.C = a.C;
   p.ldc = a.ldc;
   p.m = a.m;
   p.n = a.n;
-  p.slabs = (int32_t)(L.k_pad / tk);
+  p.slabs = (int32_t)(p.kp / tk);
   p.tiles_m = (a.m + tm - 1) / tm;
   p.tiles_n = (a.n + tn - 1) / tn;
   p.alpha = a.alpha;
@@ -529,28 +678,26 @@ struct StagedConfig {
   static_assert(kPadMN % TM == 0 && kPadMN % TN == 0 && kPadK % TK == 0, "padding covers the tile");
 
   template <int EPI>
-  static hipError_t run(const GemmArgs& a, bool at, bool bt, void* workspace, const float* aorig, int64_t lda_orig,
-                        float* partial, hipStream_t s) {
-    const int32_t prec = X3 ? HPVM_PREC_BF16X3 : HPVM_PREC_BF16;
-    const StagedLayout L = staged_layout(prec, a.m, a.n, a.k);
-    char* ws = reinterpret_cast<char*>(workspace);
-    hipError_t e = stage_operands<X3>(a, at, bt, L, ws, s);
-    if (e != hipSuccess) return e;
-    StagedArgs p = staged_args<X3>(a, L, ws, TM, TN, TK, aorig, lda_orig, partial);
+  static hipError_t gemm(const GemmArgs& a, const StagedPlanes& P, const float* aorig, int64_t lda_orig,
+                         float* partial, hipStream_t s) {
+    StagedArgs p = staged_args(a, P, TM, TN, TK, aorig, lda_orig, partial);
     auto* fn = &sgemm_bf16_staged<TM, TN, TK, WM, WN, X3, PIPE, EPI>;
-    e = allow_lds_staged(fn, (size_t)T::kLdsBytes);
+    hipError_t e = allow_lds_staged(fn, (size_t)T::kLdsBytes);
     if (e != hipSuccess) return e;
     void* kargs[] = {&p};
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(p.tiles_m * p.tiles_n)),
                            dim3(kThreads), kargs, (size_t)T::kLdsBytes, s);
   }
   static hipError_t launch(const GemmArgs& a, void* workspace, hipStream_t s) {
-    return run<0>(a, false, false, workspace, nullptr, 0, nullptr, s);
+    const StagedLayout L = staged_layout(X3 ? HPVM_PREC_BF16X3 : HPVM_PREC_BF16, a.m, a.n, a.k);
+    char* ws = reinterpret_cast<char*>(workspace);
+    hipError_t e = stage_operands<X3>(a, L, ws, s);
+    if (e != hipSuccess) return e;
+    return gemm<0>(a, planes_in<X3>(L, ws), nullptr, 0, nullptr, s);
   }
-  static hipError_t launch_form(const GemmArgs& a, bool at, bool bt, void* workspace, const float* aorig,
-                                int64_t lda_orig, float* partial, hipStream_t s) {
-    return partial ? run<1>(a, at, bt, workspace, aorig, lda_orig, partial, s)
-                   : run<0>(a, at, bt, workspace, nullptr, 0, nullptr, s);
+  static hipError_t launch_planes(const GemmArgs& a, const StagedPlanes& P, const float* aorig, int64_t lda_orig,
+                                  float* partial, hipStream_t s) {
+    return partial ? gemm<1>(a, P, aorig, lda_orig, partial, s) : gemm<0>(a, P, nullptr, 0, nullptr, s);
   }
 };
 
@@ -558,7 +705,7 @@ struct StagedConfig {
   {{TM, TN, TK, WM, WN, 3}, PREC, StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::kThreads,                  \
    Bf16TileShape<TM, TN, TK, WM, WN, X3>::kLdsBytes, nullptr,                                             \
    &StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::launch,                                                  \
-   &StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::launch_form}
+   &StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::launch_planes}
 
 // BF16 on the DMA-fed kernel (NST LDS stages); same planes and workspace.
 template <int TM, int TN, int TK, int WM, int WN, int NST>
@@ -568,40 +715,40 @@ struct DmaConfig {
   static_assert(kPadMN % TM == 0 && kPadMN % TN == 0 && kPadK % TK == 0, "padding covers the tile");
 
   template <int EPI>
-  static hipError_t run(const GemmArgs& a, bool at, bool bt, void* workspace, const float* aorig, int64_t lda_orig,
-                        float* partial, hipStream_t s) {
-    const StagedLayout L = staged_layout(HPVM_PREC_BF16, a.m, a.n, a.k);
-    char* ws = reinterpret_cast<char*>(workspace);
-    hipError_t e = stage_operands<false>(a, at, bt, L, ws, s);
-    if (e != hipSuccess) return e;
-    StagedArgs p = staged_args<false>(a, L, ws, TM, TN, TK, aorig, lda_orig, partial);
+  static hipError_t gemm(const GemmArgs& a, const StagedPlanes& P, const float* aorig, int64_t lda_orig,
+                         float* partial, hipStream_t s) {
+    StagedArgs p = staged_args(a, P, TM, TN, TK, aorig, lda_orig, partial);
     auto* fn = &sgemm_bf16_dma<TM, TN, TK, WM, WN, NST, EPI>;
-    e = allow_lds_staged(fn, (size_t)S::kLdsBytes);
+    hipError_t e = allow_lds_staged(fn, (size_t)S::kLdsBytes);
     if (e != hipSuccess) return e;
     void* kargs[] = {&p};
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(p.tiles_m * p.tiles_n)),
                            dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
   }
   static hipError_t launch(const GemmArgs& a, void* workspace, hipStream_t s) {
-    return run<0>(a, false, false, workspace, nullptr, 0, nullptr, s);
+    const StagedLayout L = staged_layout(HPVM_PREC_BF16, a.m, a.n, a.k);
+    char* ws = reinterpret_cast<char*>(workspace);
+    hipError_t e = stage_operands<false>(a, L, ws, s);
+    if (e != hipSuccess) return e;
+    return gemm<0>(a, planes_in<false>(L, ws), nullptr, 0, nullptr, s);
   }
-  static hipError_t launch_form(const GemmArgs& a, bool at, bool bt, void* workspace, const float* aorig,
-                                int64_t lda_orig, float* partial, hipStream_t s) {
-    return partial ? run<1>(a, at, bt, workspace, aorig, lda_orig, partial, s)
-                   : run<0>(a, at, bt, workspace, nullptr, 0, nullptr, s);
+  static hipError_t launch_planes(const GemmArgs& a, const StagedPlanes& P, const float* aorig, int64_t lda_orig,
+                                  float* partial, hipStream_t s) {
+    return partial ? gemm<1>(a, P, aorig, lda_orig, partial, s) : gemm<0>(a, P, nullptr, 0, nullptr, s);
   }
 };
 
 #define HPVM_DMA_ENTRY(NST, TM, TN, TK, WM, WN)                                                          \
   {{TM, TN, TK, WM, WN, 3}, HPVM_PREC_BF16, DmaConfig<TM, TN, TK, WM, WN, NST>::kThreads,               \
    DmaConfig<TM, TN, TK, WM, WN, NST>::S::kLdsBytes, nullptr, &DmaConfig<TM, TN, TK, WM, WN, NST>::launch, \
-   &DmaConfig<TM, TN, TK, WM, WN, NST>::launch_form}
+   &DmaConfig<TM, TN, TK, WM, WN, NST>::launch_planes}
 
 const MfmaEntry kStagedMenuBf16[] = {
     HPVM_DMA_ENTRY(2, 256, 256, 64, 128, 64),
     HPVM_DMA_ENTRY(3, 256, 256, 32, 128, 64),
     HPVM_DMA_ENTRY(3, 256, 128, 64, 128, 64),
     HPVM_DMA_ENTRY(2, 128, 128, 64, 64, 64),
+    HPVM_DMA_ENTRY(2, 128, 128, 64, 64, 32),
 };
 const MfmaEntry kStagedMenuBf16x3[] = {
     HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, false, 256, 256, 32, 128, 64),

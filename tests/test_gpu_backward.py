@@ -212,6 +212,38 @@ def test_backward_every_tile_integers(gpu, prec):
         assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-6), tile
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_backward_staged_outputs_and_layouts(gpu, prec):
+    """Staged tiles convert G once for both products and take dC_in and the
+    dbeta partials from that pass.  Integer inputs keep every output exact,
+    for each subset of outputs (including the ones that skip the products)
+    and for leading dimensions that rule out 16-byte units (ragged 301 x 259
+    x 203, one padded and one misaligned operand)."""
+    import torch
+
+    m, n, k = 301, 259, 203
+    A, B, C, G = inputs.backward_operands(m, n, k, seed=17, dist="int")
+    ref = oracle.sgemm_grad(A, B, C, G, 1.0, 2.0)
+    staged = [t for t in gpu.backward_menu(prec) if t[5] == 3]
+    layouts = {
+        "dense": dev_all(A, B, C, G),
+        "padded": [to_dev(A, pad=3), to_dev(B, misalign=True), to_dev(C, pad=1), to_dev(G, pad=5)],
+    }
+    subsets = [("dA",), ("dB",), ("dC_in",), ("dbeta",), ("dalpha",), ("dA", "dbeta"), ("dB", "dC_in", "dalpha")]
+    for tile in staged[:2]:
+        for name, d in layouts.items():
+            for need in subsets:
+                print(f"case: backward staged {prec} tile {tile} {name} {need}", flush=True)
+                g = gpu.sgemm_backward(*d, 1.0, 2.0, prec=prec, tile=tile, need=need)
+                torch.cuda.synchronize()
+                for key in need:
+                    got = to_host(g[key]) if g[key].dim() else float(g[key])
+                    if key in ("dalpha", "dbeta"):
+                        assert math.isclose(got, ref[key], rel_tol=1e-6), (tile, name, need, key)
+                    else:
+                        assert np.array_equal(got, ref[key]), (tile, name, need, key)
+
+
 def test_backward_autotune_records_a_menu_tile(gpu):
     import torch
 
