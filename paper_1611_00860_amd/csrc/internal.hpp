@@ -44,6 +44,11 @@ struct MfmaEntry {
   // of aorig .* acc over the tile).
   hipError_t (*launch_staged_planes)(const GemmArgs& args, const StagedPlanes& planes, const float* aorig,
                                      int64_t lda_orig, float* partial, hipStream_t s) = nullptr;
+  // Two staged products in one launch (the first with the optional dA
+  // epilogue as above); null where the entry has no such kernel.
+  hipError_t (*launch_staged_pair)(const GemmArgs& args1, const StagedPlanes& planes1, const float* aorig,
+                                   int64_t lda_orig, float* partial, const GemmArgs& args2,
+                                   const StagedPlanes& planes2, hipStream_t s) = nullptr;
 };
 
 // The compiled fused menu for `prec` (FP32, BF16, BF16X3); returns the count.

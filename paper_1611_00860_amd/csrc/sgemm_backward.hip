@@ -559,6 +559,10 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   // dC_in and dbeta's partials; each product then converts its other operand.
   BwdPlanes P{};
   bool g_pass = false;
+  // Both staged products in one launch when the entry has the kernel: each
+  // gives too few tiles to fill the CUs twice over on its own.
+  const bool pair = staged && run_a && run_b && me && me->launch_staged_pair;
+  GemmArgs a_pair{};
   if (staged && (run_a || run_b)) {
     if (!me || !me->launch_staged_planes) return hip_error(hipErrorInvalidValue, "backward staged entry");
     P = bwd_planes(prec, stage, m, n, k);
@@ -597,7 +601,8 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
       na = dalpha ? split_sum_blocks(m, k) : 0;
     } else if (staged) {
       e = stage_operand(prec, B, ldb, k, n, false, P.bh, P.bl, vec16(B, ldb), s);
-      if (e == hipSuccess)
+      if (e == hipSuccess && pair) a_pair = a;  // launched with dB below
+      else if (e == hipSuccess)
         e = me->launch_staged_planes(a, StagedPlanes{P.gh, P.gl, P.bh, P.bl}, A, lda, dalpha ? pa : nullptr, s);
     } else if (dalpha) {
       // Fused pass: dA (when requested) and the per-tile partials of dalpha.
@@ -644,7 +649,11 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     else if (!me) e = hipErrorInvalidValue;
     else if (staged) {
       e = stage_operand(prec, A, lda, m, k, true, P.ah, P.al, vec16(A, lda), s);
-      if (e == hipSuccess) e = me->launch_staged_planes(b, StagedPlanes{P.ah, P.al, P.th, P.tl}, nullptr, 0, nullptr, s);
+      if (e == hipSuccess && pair)
+        e = me->launch_staged_pair(a_pair, StagedPlanes{P.gh, P.gl, P.bh, P.bl}, A, lda, dalpha ? pa : nullptr, b,
+                                   StagedPlanes{P.ah, P.al, P.th, P.tl}, s);
+      else if (e == hipSuccess)
+        e = me->launch_staged_planes(b, StagedPlanes{P.ah, P.al, P.th, P.tl}, nullptr, 0, nullptr, s);
     }
     else e = me->launch(b, true, false, s);
   }

@@ -284,13 +284,13 @@ struct StagedArgs {
 
 // Backward epilogue (EPI = 1): C (may be null) <- alpha acc, and this
 // workgroup's partial of dalpha, the sum over its tile of aorig .* acc, into
-// partial[blockIdx.x].  The aorig elements of up to 64 accumulator values
+// partial[tile].  The aorig elements of up to 64 accumulator values
 // per lane are loaded together before any store (a store to C may alias
 // aorig as far as the compiler knows, so loads issued after it would wait
 // for it).  Reuses `smem`: every LDS transfer must be complete.
 template <int BM, int BN>
 __device__ __forceinline__ void dalpha_epilogue(const StagedArgs& p, const f32x16 (&acc)[BM][BN], int row0,
-                                                int col0, int lane, char* smem) {
+                                                int col0, int lane, int tile, char* smem) {
   constexpr int kBatch = (BM * BN * 16 <= 64) ? BM : 1;  // row blocks loaded together
   float part = 0.0f;
 #pragma unroll
@@ -325,7 +325,7 @@ __device__ __forceinline__ void dalpha_epilogue(const StagedArgs& p, const f32x1
       }
   }
   const float sum = block_sum(part, reinterpret_cast<float*>(smem));
-  if (threadIdx.x == 0) p.partial[blockIdx.x] = sum;
+  if (threadIdx.x == 0) p.partial[tile] = sum;
 }
 
 // The bf16x3 GEMM over staged planes: each K-slab (hi and lo planes) is
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
     e.beta = p.beta;
     store_c<BM, BN>(e, acc, (int)m0 + wm0, (int)n0 + wn0, lane);
   } else {
-    dalpha_epilogue<BM, BN>(p, acc, (int)m0 + wm0, (int)n0 + wn0, lane, smem);
+    dalpha_epilogue<BM, BN>(p, acc, (int)m0 + wm0, (int)n0 + wn0, lane, (int)blockIdx.x, smem);
   }
 }
 
@@ -460,20 +460,18 @@ __device__ __forceinline__ void interleave_mfma_reads() {
   if constexpr (NM - per * NR > 0) __builtin_amdgcn_sched_group_barrier(0x008, NM - per * NR, 0);
 }
 
+// One output tile (number `tile` of the product p) on this workgroup.
 template <int TM, int TN, int TK, int WM, int WN, int NST, int EPI>
-__global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST>::NW * kWave))
-    __attribute__((amdgpu_waves_per_eu(1, (Bf16DmaShape<TM, TN, TK, WM, WN, NST>::kMaxWaves))))
-    sgemm_bf16_dma(StagedArgs p) {
+__device__ __forceinline__ void bf16_dma_tile(const StagedArgs& p, int tile, char* smem) {
   using S = Bf16DmaShape<TM, TN, TK, WM, WN, NST>;
   using Lay = SwizzledRows<S::RB>;
   constexpr int BM = S::BM, BN = S::BN, QA = S::QA, QB = S::QB, KS = TK / 16, R = S::kRowsPerDma;
-  extern __shared__ __align__(16) char smem[];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int wm0 = (wave / (TN / WN)) * WM, wn0 = (wave % (TN / WN)) * WN;
   int tm, tn;
-  tile_coords(p.tiles_m, p.tiles_n, blockIdx.x, tm, tn);
+  tile_coords(p.tiles_m, p.tiles_n, tile, tm, tn);
   const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
   const int64_t rowb = p.kp * 2;
   const uint32_t lds0 = lds_addr(smem);
@@ -559,7 +557,33 @@ __global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST>::NW * k
     e.beta = p.beta;
     store_c<BM, BN>(e, acc, (int)m0 + wm0, (int)n0 + wn0, lane);
   } else {
-    dalpha_epilogue<BM, BN>(p, acc, (int)m0 + wm0, (int)n0 + wn0, lane, smem);
+    dalpha_epilogue<BM, BN>(p, acc, (int)m0 + wm0, (int)n0 + wn0, lane, tile, smem);
+  }
+}
+
+template <int TM, int TN, int TK, int WM, int WN, int NST, int EPI>
+__global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST>::NW * kWave))
+    __attribute__((amdgpu_waves_per_eu(1, (Bf16DmaShape<TM, TN, TK, WM, WN, NST>::kMaxWaves))))
+    sgemm_bf16_dma(StagedArgs p) {
+  extern __shared__ __align__(16) char smem[];
+  bf16_dma_tile<TM, TN, TK, WM, WN, NST, EPI>(p, blockIdx.x, smem);
+}
+
+// Two independent products in one launch: the tiles of p1 (with the dalpha
+// epilogue when p1.partial is set), then those of p2.  Small products that
+// give one tile per CU each get two co-resident workgroups per CU this way.
+template <int TM, int TN, int TK, int WM, int WN, int NST>
+__global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST>::NW * kWave))
+    __attribute__((amdgpu_waves_per_eu(1, (Bf16DmaShape<TM, TN, TK, WM, WN, NST>::kMaxWaves))))
+    sgemm_bf16_dma_pair(StagedArgs p1, StagedArgs p2) {
+  extern __shared__ __align__(16) char smem[];
+  const int n1 = p1.tiles_m * p1.tiles_n;
+  const int t = blockIdx.x;
+  if (t < n1) {
+    if (p1.partial) bf16_dma_tile<TM, TN, TK, WM, WN, NST, 1>(p1, t, smem);
+    else bf16_dma_tile<TM, TN, TK, WM, WN, NST, 0>(p1, t, smem);
+  } else {
+    bf16_dma_tile<TM, TN, TK, WM, WN, NST, 0>(p2, t - n1, smem);
   }
 }
 
@@ -736,12 +760,24 @@ struct DmaConfig {
                                   float* partial, hipStream_t s) {
     return partial ? gemm<1>(a, P, aorig, lda_orig, partial, s) : gemm<0>(a, P, nullptr, 0, nullptr, s);
   }
+  static hipError_t launch_pair(const GemmArgs& a1, const StagedPlanes& P1, const float* aorig, int64_t lda_orig,
+                                float* partial, const GemmArgs& a2, const StagedPlanes& P2, hipStream_t s) {
+    StagedArgs p1 = staged_args(a1, P1, TM, TN, TK, aorig, lda_orig, partial);
+    StagedArgs p2 = staged_args(a2, P2, TM, TN, TK, nullptr, 0, nullptr);
+    auto* fn = &sgemm_bf16_dma_pair<TM, TN, TK, WM, WN, NST>;
+    hipError_t e = allow_lds_staged(fn, (size_t)S::kLdsBytes);
+    if (e != hipSuccess) return e;
+    void* kargs[] = {&p1, &p2};
+    const int64_t tiles = (int64_t)p1.tiles_m * p1.tiles_n + (int64_t)p2.tiles_m * p2.tiles_n;
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)tiles), dim3(kThreads), kargs,
+                           (size_t)S::kLdsBytes, s);
+  }
 };
 
 #define HPVM_DMA_ENTRY(NST, TM, TN, TK, WM, WN)                                                          \
   {{TM, TN, TK, WM, WN, 3}, HPVM_PREC_BF16, DmaConfig<TM, TN, TK, WM, WN, NST>::kThreads,               \
    DmaConfig<TM, TN, TK, WM, WN, NST>::S::kLdsBytes, nullptr, &DmaConfig<TM, TN, TK, WM, WN, NST>::launch, \
-   &DmaConfig<TM, TN, TK, WM, WN, NST>::launch_planes}
+   &DmaConfig<TM, TN, TK, WM, WN, NST>::launch_planes, &DmaConfig<TM, TN, TK, WM, WN, NST>::launch_pair}
 
 const MfmaEntry kStagedMenuBf16[] = {
     HPVM_DMA_ENTRY(2, 256, 256, 64, 128, 64),
