@@ -128,6 +128,42 @@ def test_backward_dma_split_integers(gpu, m, n, k):
     assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-6)
 
 
+def test_backward_threads_bitwise(gpu):
+    """Two host threads on two streams, each calling the DMA-fed FP32
+    backward repeatedly with its own workspace, get the single-threaded bits
+    every time; each caller's stream alone orders its results."""
+    import threading
+
+    import torch
+
+    m, n, k = 512, 512, 256
+    A, B, C, G = inputs.backward_operands(m, n, k, seed=19)
+    d = dev_all(A, B, C, G)
+    ref = gpu.sgemm_backward(*d, 0.7, 0.3, prec="fp32")
+    torch.cuda.synchronize()
+    errors = []
+
+    def worker(seed):
+        try:
+            st = torch.cuda.Stream()
+            for i in range(4):
+                with torch.cuda.stream(st):
+                    g = gpu.sgemm_backward(*d, 0.7, 0.3, prec="fp32", stream=st)
+                st.synchronize()
+                for key in ("dA", "dB", "dC_in", "dalpha", "dbeta"):
+                    if not torch.equal(g[key], ref[key]):
+                        errors.append((seed, i, key))
+        except Exception as exc:  # reported below
+            errors.append((seed, repr(exc)))
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+
+
 def test_backward_dma_misaligned_falls_back(gpu):
     """An operand off 16-byte alignment sends that gradient to the fallback tile."""
     import torch
