@@ -69,20 +69,43 @@ __device__ __forceinline__ void to_bf16(float x, uint16_t& hi, uint16_t& lo) {
   if constexpr (X3) lo = __builtin_bit_cast(uint16_t, (__bf16)(x - (float)h));
 }
 
-// rows x cols FP32 (element (r, c) at src[r * ld + c], c is the k index)
-// -> [rows_pad][cols_pad] bfloat16, zero outside rows x cols.
+// Packs 8 elements' bfloat16 bits (and their lo parts) into 16-byte units.
 template <bool X3>
-__global__ void __launch_bounds__(256)
-    stage_rows(const float* __restrict__ src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
-               int64_t cols_pad, uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int32_t vec) {
-  const int64_t per_row = cols_pad / 8;
-  const int64_t units = rows_pad * per_row;
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units;
-       u += (int64_t)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void pack8(const float (&v)[8], u32x4& hv, u32x4& lv) {
+  uint16_t h[8], l[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) to_bf16<X3>(v[e], h[e], l[e]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    hv[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
+    if constexpr (X3) lv[q] = (uint32_t)l[2 * q] | ((uint32_t)l[2 * q + 1] << 16);
+  }
+}
+
+// A conversion whose contraction index runs along the rows of src (the
+// copy form) or down its columns (the transposing form).  src is rows x
+// cols FP32, element (r, c) at src[r * ld + c].
+struct StageJob {
+  const float* src;
+  int64_t ld, rows, cols, rows_pad, cols_pad;
+  uint16_t* hi;
+  uint16_t* lo;
+  int32_t vec;
+  int64_t blocks;  // workgroups given to this job
+};
+
+// Copy form: -> [rows_pad][cols_pad] bfloat16, zero outside rows x cols.
+// 8-element units are dealt to the job's workgroups in turn; each thread
+// loads two units before storing either.
+template <bool X3>
+__device__ __forceinline__ void stage_rows_part(const StageJob& j, int64_t block) {
+  const int64_t per_row = j.cols_pad / 8;
+  const int64_t units = j.rows_pad * per_row;
+  const int64_t stride = j.blocks * blockDim.x;
+  auto load = [&](int64_t u, float (&v)[8]) {
     const int64_t r = u / per_row, c = (u - r * per_row) * 8;
-    float v[8];
-    const float* p = src + r * ld + c;
-    if (vec && r < rows && c + 8 <= cols) {
+    const float* p = j.src + r * j.ld + c;
+    if (j.vec && r < j.rows && c + 8 <= j.cols) {
       const f32x4 a = *reinterpret_cast<const f32x4*>(p);
       const f32x4 b = *reinterpret_cast<const f32x4*>(p + 4);
 #pragma unroll
@@ -92,44 +115,51 @@ __global__ void __launch_bounds__(256)
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (r < rows && c + e < cols) ? p[e] : 0.0f;
+      for (int e = 0; e < 8; ++e) v[e] = (r < j.rows && c + e < j.cols) ? p[e] : 0.0f;
     }
-    uint16_t h[8], l[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) to_bf16<X3>(v[e], h[e], l[e]);
+  };
+  auto store = [&](int64_t u, const float (&v)[8]) {
+    const int64_t r = u / per_row, c = (u - r * per_row) * 8;
     u32x4 hv, lv;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      hv[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
-      if constexpr (X3) lv[q] = (uint32_t)l[2 * q] | ((uint32_t)l[2 * q + 1] << 16);
-    }
-    *reinterpret_cast<u32x4*>(hi + r * cols_pad + c) = hv;
-    if constexpr (X3) *reinterpret_cast<u32x4*>(lo + r * cols_pad + c) = lv;
+    pack8<X3>(v, hv, lv);
+    *reinterpret_cast<u32x4*>(j.hi + r * j.cols_pad + c) = hv;
+    if constexpr (X3) *reinterpret_cast<u32x4*>(j.lo + r * j.cols_pad + c) = lv;
+  };
+  int64_t u = block * blockDim.x + threadIdx.x;
+  for (; u + stride < units; u += 2 * stride) {
+    float v0[8], v1[8];
+    load(u, v0);
+    load(u + stride, v1);
+    store(u, v0);
+    store(u + stride, v1);
+  }
+  if (u < units) {
+    float v0[8];
+    load(u, v0);
+    store(u, v0);
   }
 }
 
-// rows x cols FP32 with the k index along rows (element (r, c) at
-// src[r * ld + c]) -> [cols_pad][rows_pad] bfloat16: transposed so that k is
-// contiguous.  One workgroup moves a 64 x 64 block through LDS; blocks are
-// numbered row-major, col_blocks = cols_pad / 64 per block row.
+// Transposing form: -> [cols_pad][rows_pad] bfloat16, so that the
+// contraction index is contiguous.  One workgroup moves a 64 x 64 block
+// through LDS; blocks are numbered row-major, cols_pad / 64 per block row.
 constexpr int kTB = 64;
 // A block reads its rows in 16-byte units when the whole 64 x 64 block is
 // inside the matrix and the rows allow them (vec), element by element
 // otherwise; LDS rows are 65 floats, so both the row-wise writes and the
 // column-wise reads of a wavefront fall on distinct banks.
 template <bool X3>
-__global__ void __launch_bounds__(256)
-    stage_cols(const float* __restrict__ src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
-               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int32_t vec, int64_t col_blocks) {
+__device__ __forceinline__ void stage_cols_block(const StageJob& j, int64_t block) {
   __shared__ float t[kTB][kTB + 1];
-  const int64_t r0 = (int64_t)(blockIdx.x / col_blocks) * kTB, c0 = (int64_t)(blockIdx.x % col_blocks) * kTB;
+  const int64_t col_blocks = j.cols_pad / kTB;
+  const int64_t r0 = (block / col_blocks) * kTB, c0 = (block % col_blocks) * kTB;
   const int tid = threadIdx.x;
-  if (vec && r0 + kTB <= rows && c0 + kTB <= cols) {
+  if (j.vec && r0 + kTB <= j.rows && c0 + kTB <= j.cols) {
     f32x4 v[kTB * kTB / 4 / 256];
 #pragma unroll
     for (int i = 0; i < kTB * kTB / 4 / 256; ++i) {
       const int r = i * (256 / (kTB / 4)) + tid / (kTB / 4), c = (tid % (kTB / 4)) * 4;
-      v[i] = *reinterpret_cast<const f32x4*>(src + (r0 + r) * ld + c0 + c);
+      v[i] = *reinterpret_cast<const f32x4*>(j.src + (r0 + r) * j.ld + c0 + c);
     }
 #pragma unroll
     for (int i = 0; i < kTB * kTB / 4 / 256; ++i) {
@@ -142,33 +172,44 @@ __global__ void __launch_bounds__(256)
     for (int i = 0; i < kTB * kTB / 256; ++i) {
       const int r = i * (256 / kTB) + tid / kTB, c = tid % kTB;
       const int64_t gr = r0 + r, gc = c0 + c;
-      t[r][c] = (gr < rows && gc < cols) ? src[gr * ld + gc] : 0.0f;
+      t[r][c] = (gr < j.rows && gc < j.cols) ? j.src[gr * j.ld + gc] : 0.0f;
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTB * kTB / 8 / 256; ++j) {
-    const int u = tid + j * 256;
+  for (int q = 0; q < kTB * kTB / 8 / 256; ++q) {
+    const int u = tid + q * 256;
     const int cc = u / (kTB / 8), kc = (u % (kTB / 8)) * 8;
-    uint16_t h[8], l[8];
+    float v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) to_bf16<X3>(t[kc + e][cc], h[e], l[e]);
+    for (int e = 0; e < 8; ++e) v[e] = t[kc + e][cc];
     u32x4 hv, lv;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      hv[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
-      if constexpr (X3) lv[q] = (uint32_t)l[2 * q] | ((uint32_t)l[2 * q + 1] << 16);
-    }
-    const int64_t off = (c0 + cc) * rows_pad + r0 + kc;
-    *reinterpret_cast<u32x4*>(hi + off) = hv;
-    if constexpr (X3) *reinterpret_cast<u32x4*>(lo + off) = lv;
+    pack8<X3>(v, hv, lv);
+    const int64_t off = (c0 + cc) * j.rows_pad + r0 + kc;
+    *reinterpret_cast<u32x4*>(j.hi + off) = hv;
+    if constexpr (X3) *reinterpret_cast<u32x4*>(j.lo + off) = lv;
   }
+}
+
+// One conversion, either form.
+template <bool X3, bool COLS>
+__global__ void __launch_bounds__(256) stage_one(StageJob j) {
+  if constexpr (COLS) stage_cols_block<X3>(j, blockIdx.x);
+  else stage_rows_part<X3>(j, blockIdx.x);
+}
+
+// Both operands of a product in one launch: the first a.blocks workgroups
+// copy A (copy form), the rest transpose B, so the two passes overlap.
+template <bool X3>
+__global__ void __launch_bounds__(256) stage_pair(StageJob a, StageJob b) {
+  if ((int64_t)blockIdx.x < a.blocks) stage_rows_part<X3>(a, blockIdx.x);
+  else stage_cols_block<X3>(b, blockIdx.x - a.blocks);
 }
 
 // The backward's pass over G (see stage_gradient in internal.hpp): one
 // workgroup per 64 x 64 block of the round256(m) x round256(n) padded
 // matrix, row-major over blocks (col_blocks per block row).
-// The block goes through LDS as in stage_cols; the row plane is written
+// The block goes through LDS as in stage_cols_block; the row plane is written
 // when the block's columns lie within round64(n), the transposed plane when
 // its rows lie within round64(m).  Each thread's share of <G, Cin> follows a
 // fixed element order, so the partials repeat bit for bit.
@@ -227,15 +268,11 @@ __global__ void __launch_bounds__(256)
     for (int j = 0; j < kTB * kTB / 8 / 256; ++j) {
       const int u = tid + j * 256;
       const int r = u / (kTB / 8), c = (u % (kTB / 8)) * 8;
-      uint16_t h[8], l[8];
+      float v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) to_bf16<X3>(t[r][c + e], h[e], l[e]);
+      for (int e = 0; e < 8; ++e) v[e] = t[r][c + e];
       u32x4 hv, lv;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        hv[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
-        if constexpr (X3) lv[q] = (uint32_t)l[2 * q] | ((uint32_t)l[2 * q + 1] << 16);
-      }
+      pack8<X3>(v, hv, lv);
       const int64_t off = (r0 + r) * n_kp + c0 + c;
       *reinterpret_cast<u32x4*>(gh + off) = hv;
       if constexpr (X3) *reinterpret_cast<u32x4*>(gl + off) = lv;
@@ -246,15 +283,11 @@ __global__ void __launch_bounds__(256)
     for (int j = 0; j < kTB * kTB / 8 / 256; ++j) {
       const int u = tid + j * 256;
       const int cc = u / (kTB / 8), kc = (u % (kTB / 8)) * 8;
-      uint16_t h[8], l[8];
+      float v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) to_bf16<X3>(t[kc + e][cc], h[e], l[e]);
+      for (int e = 0; e < 8; ++e) v[e] = t[kc + e][cc];
       u32x4 hv, lv;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        hv[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
-        if constexpr (X3) lv[q] = (uint32_t)l[2 * q] | ((uint32_t)l[2 * q + 1] << 16);
-      }
+      pack8<X3>(v, hv, lv);
       const int64_t off = (c0 + cc) * m_kp + r0 + kc;
       *reinterpret_cast<u32x4*>(th + off) = hv;
       if constexpr (X3) *reinterpret_cast<u32x4*>(tl + off) = lv;
@@ -596,22 +629,22 @@ hipError_t allow_lds_staged(Kernel* fn, size_t bytes) {
                              (int)bytes);
 }
 
-template <bool X3>
-hipError_t stage_rows_launch(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
-                             int64_t cols_pad, uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s) {
+StageJob rows_job(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
+                  uint16_t* hi, uint16_t* lo, int32_t vec) {
   const int64_t units = rows_pad * cols_pad / 8;
-  const unsigned blocks = (unsigned)std::min<int64_t>((units + 255) / 256, 8192);
-  void* args[] = {&src, &ld, &rows, &cols, &rows_pad, &cols_pad, &hi, &lo, &vec};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&stage_rows<X3>), dim3(blocks), dim3(256), args, 0, s);
+  return StageJob{src, ld, rows, cols, rows_pad, cols_pad, hi, lo, vec,
+                  std::max<int64_t>(1, std::min<int64_t>((units + 511) / 512, 8192))};
+}
+StageJob cols_job(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
+                  uint16_t* hi, uint16_t* lo, int32_t vec) {
+  return StageJob{src, ld, rows, cols, rows_pad, cols_pad, hi, lo, vec, (cols_pad / kTB) * (rows_pad / kTB)};
 }
 
-template <bool X3>
-hipError_t stage_cols_launch(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad,
-                             int64_t cols_pad, uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s) {
-  int64_t col_blocks = cols_pad / kTB;
-  void* args[] = {&src, &ld, &rows, &cols, &rows_pad, &hi, &lo, &vec, &col_blocks};
-  const dim3 grid((unsigned)(col_blocks * (rows_pad / kTB)));
-  return hipLaunchKernel(reinterpret_cast<const void*>(&stage_cols<X3>), grid, dim3(256), args, 0, s);
+template <bool X3, bool COLS>
+hipError_t stage_one_launch(StageJob j, hipStream_t s) {
+  void* args[] = {&j};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&stage_one<X3, COLS>), dim3((unsigned)j.blocks), dim3(256),
+                         args, 0, s);
 }
 
 // The forward product's planes: A (m x k, k contiguous) copied row by row
@@ -622,9 +655,11 @@ hipError_t stage_operands(const GemmArgs& a, const StagedLayout& L, char* ws, hi
   uint16_t* al = X3 ? reinterpret_cast<uint16_t*>(ws + L.a_plane) : nullptr;
   uint16_t* bh = reinterpret_cast<uint16_t*>(ws + L.planes * L.a_plane);
   uint16_t* bl = X3 ? reinterpret_cast<uint16_t*>(ws + L.planes * L.a_plane + L.b_plane) : nullptr;
-  hipError_t e = stage_rows_launch<X3>(a.A, a.lda, a.m, a.k, L.m_pad, L.k_pad, ah, al, a.vec_a, s);
-  if (e != hipSuccess) return e;
-  return stage_cols_launch<X3>(a.B, a.ldb, a.k, a.n, L.k_pad, L.n_pad, bh, bl, a.vec_b, s);
+  StageJob ja = rows_job(a.A, a.lda, a.m, a.k, L.m_pad, L.k_pad, ah, al, a.vec_a);
+  StageJob jb = cols_job(a.B, a.ldb, a.k, a.n, L.k_pad, L.n_pad, bh, bl, a.vec_b);
+  void* args[] = {&ja, &jb};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&stage_pair<X3>), dim3((unsigned)(ja.blocks + jb.blocks)),
+                         dim3(256), args, 0, s);
 }
 
 }  // namespace
@@ -633,13 +668,11 @@ hipError_t stage_operand(int32_t prec, const float* src, int64_t ld, int64_t row
                          uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s) {
   const bool x3 = prec == HPVM_PREC_BF16X3;
   if (!k_along_rows) {
-    const int64_t rp = staged_rows_pad(rows), cp = staged_k_pad(cols);
-    return x3 ? stage_rows_launch<true>(src, ld, rows, cols, rp, cp, hi, lo, vec, s)
-              : stage_rows_launch<false>(src, ld, rows, cols, rp, cp, hi, lo, vec, s);
+    const StageJob j = rows_job(src, ld, rows, cols, staged_rows_pad(rows), staged_k_pad(cols), hi, lo, vec);
+    return x3 ? stage_one_launch<true, false>(j, s) : stage_one_launch<false, false>(j, s);
   }
-  const int64_t rp = staged_k_pad(rows), cp = staged_rows_pad(cols);
-  return x3 ? stage_cols_launch<true>(src, ld, rows, cols, rp, cp, hi, lo, vec, s)
-            : stage_cols_launch<false>(src, ld, rows, cols, rp, cp, hi, lo, vec, s);
+  const StageJob j = cols_job(src, ld, rows, cols, staged_k_pad(rows), staged_rows_pad(cols), hi, lo, vec);
+  return x3 ? stage_one_launch<true, true>(j, s) : stage_one_launch<false, true>(j, s);
 }
 
 int64_t stage_gradient_blocks(int64_t m, int64_t n) {
