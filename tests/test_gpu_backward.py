@@ -179,7 +179,7 @@ def test_backward_dma_misaligned_falls_back(gpu):
     assert np.array_equal(to_host(g["dB"]), ref["dB"])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
 def test_backward_full_size_sampled(gpu, prec):
     """M = N = 4096, K = 1024, alpha = 0.7, beta = 0.3, G uniform, seed 4."""
     import torch
