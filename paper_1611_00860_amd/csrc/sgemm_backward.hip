@@ -295,14 +295,29 @@ int dma_splits(int64_t rows, int64_t cols, int64_t contraction) {
   return s;
 }
 
+// Slices per gradient when both gradients run in one launch (both whole
+// tiles): doubled while the two together would not cover 256 CUs, under the
+// same conditions as dma_splits on both contractions.  0 otherwise.
+int pair_splits(int64_t m, int64_t n, int64_t k) {
+  if (!dma_splits(m, k, n) || !dma_splits(k, n, m)) return 0;
+  const int64_t tiles = (m / kDmaTile) * (k / kDmaTile) + (k / kDmaTile) * (n / kDmaTile);
+  int s = 1;
+  while (s < 16 && tiles * s < kTargetTiles && n % (2 * s * kDmaK) == 0 && n / (2 * s) >= 256 &&
+         m % (2 * s * kDmaK) == 0 && m / (2 * s) >= 256)
+    s *= 2;
+  return s;
+}
+
 struct DmaPlan {
   int sa = 0, sb = 0;  // slices of dA (m x k over n) and dB (k x n over m); 0 = not DMA-fed
+  int sp = 0;          // slices of each when both run in one launch
 };
 DmaPlan dma_plan(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
   DmaPlan d;
   if (e->dma) {
     d.sa = dma_splits(m, k, n);
     d.sb = dma_splits(k, n, m);
+    d.sp = pair_splits(m, n, k);
   }
   return d;
 }
@@ -381,8 +396,9 @@ BwdPlanes bwd_planes(int32_t prec, void* stage, int64_t m, int64_t n, int64_t k)
   return P;
 }
 
-// A DMA entry sizes for both of its paths: the slice partials (dA's and
-// dB's passes share the region) and the larger of its dalpha partial counts.
+// A DMA entry sizes for all of its paths: the slice partials (dA's and dB's
+// passes share the region when they run one after the other and split it
+// when they run in one launch) and the larger of its dalpha partial counts.
 BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
   BwdLayout L;
@@ -398,7 +414,7 @@ BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
     int64_t g, gt, b, a;
     stage = (e->prec == HPVM_PREC_BF16X3 ? 2 : 1) * 2 * bwd_plane_elems(m, n, k, &g, &gt, &b, &a);
   }
-  if (e->dma) stage = 4 * std::max<int64_t>(d.sa * m * k, d.sb * k * n);
+  if (e->dma) stage = 4 * std::max<int64_t>(std::max<int64_t>(d.sa * m * k, d.sb * k * n), d.sp * (m * k + k * n));
   L.total = L.stage_off + stage;
   return L;
 }
@@ -432,6 +448,77 @@ hipError_t launch_split(const GemmArgs& args, int splits, float* part, float* ou
   int64_t rows = a.m, cols = a.n;
   float alpha = args.alpha;
   void* sargs[] = {&pp, &sp, &rows, &cols, &alpha, &out, &ldo, &aorig, &ldao, &dpart};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_sum), dim3((unsigned)split_sum_blocks(rows, cols)),
+                         dim3(kElemThreads), sargs, 0, s);
+}
+
+// Both gradients' contraction slices in one launch: the first
+// tiles(pa) * oa.splits workgroups run dA's (G, B transposed), the rest dB's
+// (A transposed, G), each writing raw slice partials like launch_split.
+constexpr int64_t kDmaPairLds = DmaA::kLdsBytes > DmaB::kLdsBytes ? DmaA::kLdsBytes : DmaB::kLdsBytes;
+constexpr int kDmaPairWaves = DmaA::kMaxWaves < DmaB::kMaxWaves ? DmaA::kMaxWaves : DmaB::kMaxWaves;
+static_assert(DmaA::NW == DmaB::NW, "one workgroup size");
+
+__global__ void __launch_bounds__(DmaA::NW * kWave) __attribute__((amdgpu_waves_per_eu(1, kDmaPairWaves)))
+    sgemm_grad_pair_dma(GemmArgs pa, F32DmaOut oa, GemmArgs pb, F32DmaOut ob) {
+  extern __shared__ __align__(16) char smem[];
+  const int ta = pa.tiles_m * pa.tiles_n, na = ta * oa.splits;
+  int t = blockIdx.x, tm, tn;
+  if (t < na) {
+    const int z = t / ta;
+    tile_coords(pa.tiles_m, pa.tiles_n, t - z * ta, tm, tn);
+    f32_dma_tile<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, false, true, kDmaStages, kDmaSplit>(pa, pa, oa, tm, tn,
+                                                                                               z, smem);
+  } else {
+    t -= na;
+    const int tb = pb.tiles_m * pb.tiles_n, z = t / tb;
+    tile_coords(pb.tiles_m, pb.tiles_n, t - z * tb, tm, tn);
+    f32_dma_tile<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, true, false, kDmaStages, kDmaSplit>(pb, pb, ob, tm, tn,
+                                                                                               z, smem);
+  }
+}
+
+// dA and dB with `splits` slices each in one launch (partials [splits][m][k]
+// at part_a, [splits][k][n] at part_b), then each gradient's slice sum.
+hipError_t launch_split_pair(const GemmArgs& ga, const GemmArgs& gb, int splits, float* part_a, float* part_b,
+                             float* dA, int64_t ldda, float* dB, int64_t lddb, const float* aorig, int64_t ldao,
+                             float* dpart, hipStream_t s) {
+  auto* fn = &sgemm_grad_pair_dma;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDmaPairLds);
+  if (e != hipSuccess) return e;
+  GemmArgs a = ga, b = gb;
+  a.C = part_a;
+  a.ldc = a.n;
+  a.tiles_m = a.m / kDmaTile;
+  a.tiles_n = a.n / kDmaTile;
+  b.C = part_b;
+  b.ldc = b.n;
+  b.tiles_m = b.m / kDmaTile;
+  b.tiles_n = b.n / kDmaTile;
+  F32DmaOut oa{}, ob{};
+  oa.splits = ob.splits = splits;
+  void* kargs[] = {&a, &oa, &b, &ob};
+  const int64_t wgs = ((int64_t)a.tiles_m * a.tiles_n + (int64_t)b.tiles_m * b.tiles_n) * splits;
+  e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)wgs), dim3(DmaA::NW * kWave), kargs,
+                      (size_t)kDmaPairLds, s);
+  if (e != hipSuccess) return e;
+  int32_t sp = splits;
+  float alpha = ga.alpha;
+  if (dA || dpart) {
+    const float* pp = part_a;
+    int64_t rows = a.m, cols = a.n;
+    void* sargs[] = {&pp, &sp, &rows, &cols, &alpha, &dA, &ldda, &aorig, &ldao, &dpart};
+    e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_sum),
+                        dim3((unsigned)split_sum_blocks(rows, cols)), dim3(kElemThreads), sargs, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  const float* pp = part_b;
+  int64_t rows = b.m, cols = b.n;
+  const float* no_a = nullptr;
+  int64_t no_ld = 0;
+  float* no_part = nullptr;
+  void* sargs[] = {&pp, &sp, &rows, &cols, &alpha, &dB, &lddb, &no_a, &no_ld, &no_part};
   return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_sum), dim3((unsigned)split_sum_blocks(rows, cols)),
                          dim3(kElemThreads), sargs, 0, s);
 }
@@ -562,6 +649,9 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   // Both staged products in one launch when the entry has the kernel: each
   // gives too few tiles to fill the CUs twice over on its own.
   const bool pair = staged && run_a && run_b && me && me->launch_staged_pair;
+  // Likewise the DMA entry's slices of both gradients, when both are whole
+  // tiles and aligned.
+  const bool dma_pair = cfg->dma && run_a && run_b && dma_a && dma_b && plan.sp > 0;
   GemmArgs a_pair{};
   if (staged && (run_a || run_b)) {
     if (!me || !me->launch_staged_planes) return hip_error(hipErrorInvalidValue, "backward staged entry");
@@ -596,8 +686,11 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     a.tiles_m = (a.m + fb->tile.tile_m - 1) / fb->tile.tile_m;
     a.tiles_n = (a.n + fb->tile.tile_n - 1) / fb->tile.tile_n;
     if (dma_a) {
-      e = launch_split<false, true>(a, plan.sa, reinterpret_cast<float*>(stage), dA, ldda, dalpha ? A : nullptr,
-                                    lda, dalpha ? pa : nullptr, s);
+      if (dma_pair)
+        a_pair = a;  // launched with dB below
+      else
+        e = launch_split<false, true>(a, plan.sa, reinterpret_cast<float*>(stage), dA, ldda, dalpha ? A : nullptr,
+                                      lda, dalpha ? pa : nullptr, s);
       na = dalpha ? split_sum_blocks(m, k) : 0;
     } else if (staged) {
       e = stage_operand(prec, B, ldb, k, n, false, P.bh, P.bl, vec16(B, ldb), s);
@@ -644,8 +737,12 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     b.beta = 0.0f;
     b.vec_a = vec16(A, lda);
     b.vec_b = vec16(G, ldg);
-    if (dma_b) e = launch_split<true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb, nullptr, 0,
-                                             nullptr, s);
+    if (dma_pair)
+      e = launch_split_pair(a_pair, b, plan.sp, reinterpret_cast<float*>(stage),
+                            reinterpret_cast<float*>(stage) + plan.sp * m * k, dA, ldda, dB, lddb,
+                            dalpha ? A : nullptr, lda, dalpha ? pa : nullptr, s);
+    else if (dma_b)
+      e = launch_split<true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb, nullptr, 0, nullptr, s);
     else if (!me) e = hipErrorInvalidValue;
     else if (staged) {
       e = stage_operand(prec, A, lda, m, k, true, P.ah, P.al, vec16(A, lda), s);
