@@ -128,6 +128,30 @@ def test_backward_dma_split_integers(gpu, m, n, k):
     assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-6)
 
 
+def test_backward_dma_output_subsets(gpu):
+    """The DMA-fed FP32 backward runs both gradients in one launch when both
+    are wanted (dalpha counts as wanting dA's pass) and each alone otherwise:
+    every subset of outputs is exact on integer inputs, including dalpha
+    without dA and dB without dC_in."""
+    import torch
+
+    m, n, k = 512, 512, 256
+    A, B, C, G = inputs.backward_operands(m, n, k, seed=23, dist="int")
+    ref = oracle.sgemm_grad(A, B, C, G, 1.0, 2.0)
+    d = dev_all(A, B, C, G)
+    tile = gpu.backward_menu("fp32")[0]
+    for need in [("dA",), ("dB",), ("dalpha",), ("dB", "dalpha"), ("dA", "dB"), ("dA", "dbeta"),
+                 ("dB", "dC_in", "dalpha", "dbeta")]:
+        print(f"case: backward dma subset {need}", flush=True)
+        g = gpu.sgemm_backward(*d, 1.0, 2.0, prec="fp32", tile=tile, need=need)
+        torch.cuda.synchronize()
+        for key in need:
+            if key in ("dalpha", "dbeta"):
+                assert math.isclose(float(g[key]), ref[key], rel_tol=1e-6), (need, key)
+            else:
+                assert np.array_equal(to_host(g[key]), ref[key]), (need, key)
+
+
 def test_backward_threads_bitwise(gpu):
     """Two host threads on two streams, each calling the DMA-fed FP32
     backward repeatedly with its own workspace, get the single-threaded bits
