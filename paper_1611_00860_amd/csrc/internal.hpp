@@ -38,7 +38,7 @@ struct MfmaEntry {
   // Staged lowering (tile.stages == 3): operands converted into `workspace`
   // first, then the GEMM.  Null for fused entries.
   hipError_t (*launch_staged)(const GemmArgs& args, void* workspace, hipStream_t s) = nullptr;
-  // Staged GEMM on planes already written (stage_operand, stage_gradient);
+  // Staged GEMM on planes already written (stage_backward);
   // args gives the sizes, C, alpha and beta.  With `partial` the epilogue is
   // the backward's dA one (C <- alpha acc when C is set; partial[tile] = sum
   // of aorig .* acc over the tile).
@@ -68,28 +68,43 @@ bool staged_k_ok(int64_t k);
 int64_t staged_rows_pad(int64_t rows);
 int64_t staged_k_pad(int64_t k);
 
-// One FP32 operand (rows x cols, element (r, c) at src[r * ld + c]) into its
-// plane(s) hi (and lo for bf16x3).  k_along_rows = false: c is the
-// contraction index, plane [round256(rows)][round64(cols)]; true: r is,
-// plane [round256(cols)][round64(rows)] (transposed through LDS).  vec: src
-// and ld allow 16-byte loads.
-hipError_t stage_operand(int32_t prec, const float* src, int64_t ld, int64_t rows, int64_t cols, bool k_along_rows,
-                         uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s);
-
-// The backward's one pass over the upstream gradient G (m x n): each 64 x 64
-// block is read once and gives
-//   gh/gl  <- G as [round256(m)][round64(n)] planes (the dA product's A side),
-//   th/tl  <- G transposed as [round256(n)][round64(m)] (the dB product's
-//             B side),
-//   dCin   <- beta G (zeros when beta == 0),
-//   partial[block] <- sum over the block of G .* Cin,
-// each skipped when its pointer is null (Cin is read only for partial).
-// vec: G, dCin and Cin rows allow 16-byte units.  partial holds
-// stage_gradient_blocks(m, n) floats, in a fixed order.
+// The staged backward's conversion passes, in one launch (m x n G, A m x k,
+// B k x n; each plane zero outside its matrix):
+//   the pass over G, each 64 x 64 block read once, giving
+//     gh/gl  <- G as [round256(m)][round64(n)] planes (the dA product's A side),
+//     th/tl  <- G transposed as [round256(n)][round64(m)] (the dB product's
+//               B side),
+//     dCin   <- beta G (zeros when beta == 0),
+//     partial[block] <- sum over the block of G .* Cin,
+//   each skipped when its pointer is null (Cin is read only for partial);
+//   partial holds stage_gradient_blocks(m, n) floats, in a fixed order;
+//   when bh is set, B into bh/bl [round256(k)][round64(n)] (the dA
+//   product's B side, n contiguous as stored);
+//   when ah is set, A transposed into ah/al [round256(k)][round64(m)] (the
+//   dB product's A side).
+// vec_*: that matrix (and for G also dCin and Cin) allows 16-byte units.
+struct BackwardStaging {
+  const float* G;
+  int64_t ldg;
+  const float* Cin;
+  int64_t ldci;
+  float* dCin;
+  int64_t lddci, m, n, k;
+  float beta;
+  float* partial;
+  uint16_t *gh, *gl, *th, *tl;
+  int32_t vec_g;
+  const float* B;
+  int64_t ldb;
+  uint16_t *bh, *bl;
+  int32_t vec_b;
+  const float* A;
+  int64_t lda;
+  uint16_t *ah, *al;
+  int32_t vec_a;
+};
 int64_t stage_gradient_blocks(int64_t m, int64_t n);
-hipError_t stage_gradient(int32_t prec, const float* G, int64_t ldg, const float* Cin, int64_t ldci, float* dCin,
-                          int64_t lddci, int64_t m, int64_t n, float beta, float* partial, uint16_t* gh,
-                          uint16_t* gl, uint16_t* th, uint16_t* tl, int32_t vec, hipStream_t s);
+hipError_t stage_backward(int32_t prec, const BackwardStaging& st, hipStream_t s);
 
 // Every compiled entry of a precision: fused first (entry 0 is the default),
 // then staged.  Returns nullptr past the end.

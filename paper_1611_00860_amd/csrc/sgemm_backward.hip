@@ -642,8 +642,9 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   hipError_t e = hipSuccess;
   int64_t na = L.na;
 
-  // Staged entries: one pass over G writes its planes for both products,
-  // dC_in and dbeta's partials; each product then converts its other operand.
+  // Staged entries: one launch converts everything the products read — one
+  // pass over G (its planes for both products, dC_in and dbeta's partials),
+  // B for dA and A transposed for dB.
   BwdPlanes P{};
   bool g_pass = false;
   // Both staged products in one launch when the entry has the kernel: each
@@ -656,11 +657,39 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   if (staged && (run_a || run_b)) {
     if (!me || !me->launch_staged_planes) return hip_error(hipErrorInvalidValue, "backward staged entry");
     P = bwd_planes(prec, stage, m, n, k);
-    const int32_t gvec = vec16(G, ldg) && (!dC_in || vec16(dC_in, lddci)) && (!dbeta || vec16(C_in, ldci));
-    e = stage_gradient(prec, G, ldg, dbeta ? C_in : nullptr, ldci, dC_in, lddci, m, n, beta, dbeta ? pb : nullptr,
-                       run_a ? P.gh : nullptr, run_a ? P.gl : nullptr, run_b ? P.th : nullptr,
-                       run_b ? P.tl : nullptr, gvec, s);
-    if (e != hipSuccess) return hip_error(e, "backward gradient staging launch");
+    BackwardStaging st{};
+    st.G = G;
+    st.ldg = ldg;
+    st.Cin = dbeta ? C_in : nullptr;
+    st.ldci = ldci;
+    st.dCin = dC_in;
+    st.lddci = lddci;
+    st.m = m;
+    st.n = n;
+    st.k = k;
+    st.beta = beta;
+    st.partial = dbeta ? pb : nullptr;
+    st.vec_g = vec16(G, ldg) && (!dC_in || vec16(dC_in, lddci)) && (!dbeta || vec16(C_in, ldci));
+    if (run_a) {
+      st.gh = P.gh;
+      st.gl = P.gl;
+      st.B = B;
+      st.ldb = ldb;
+      st.bh = P.bh;
+      st.bl = P.bl;
+      st.vec_b = vec16(B, ldb);
+    }
+    if (run_b) {
+      st.th = P.th;
+      st.tl = P.tl;
+      st.A = A;
+      st.lda = lda;
+      st.ah = P.ah;
+      st.al = P.al;
+      st.vec_a = vec16(A, lda);
+    }
+    e = stage_backward(prec, st, s);
+    if (e != hipSuccess) return hip_error(e, "backward staging launch");
     g_pass = true;
   }
 
@@ -693,9 +722,9 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
                                       lda, dalpha ? pa : nullptr, s);
       na = dalpha ? split_sum_blocks(m, k) : 0;
     } else if (staged) {
-      e = stage_operand(prec, B, ldb, k, n, false, P.bh, P.bl, vec16(B, ldb), s);
-      if (e == hipSuccess && pair) a_pair = a;  // launched with dB below
-      else if (e == hipSuccess)
+      if (pair)
+        a_pair = a;  // launched with dB below
+      else
         e = me->launch_staged_planes(a, StagedPlanes{P.gh, P.gl, P.bh, P.bl}, A, lda, dalpha ? pa : nullptr, s);
     } else if (dalpha) {
       // Fused pass: dA (when requested) and the per-tile partials of dalpha.
@@ -744,14 +773,11 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     else if (dma_b)
       e = launch_split<true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb, nullptr, 0, nullptr, s);
     else if (!me) e = hipErrorInvalidValue;
-    else if (staged) {
-      e = stage_operand(prec, A, lda, m, k, true, P.ah, P.al, vec16(A, lda), s);
-      if (e == hipSuccess && pair)
-        e = me->launch_staged_pair(a_pair, StagedPlanes{P.gh, P.gl, P.bh, P.bl}, A, lda, dalpha ? pa : nullptr, b,
-                                   StagedPlanes{P.ah, P.al, P.th, P.tl}, s);
-      else if (e == hipSuccess)
-        e = me->launch_staged_planes(b, StagedPlanes{P.ah, P.al, P.th, P.tl}, nullptr, 0, nullptr, s);
-    }
+    else if (staged && pair)
+      e = me->launch_staged_pair(a_pair, StagedPlanes{P.gh, P.gl, P.bh, P.bl}, A, lda, dalpha ? pa : nullptr, b,
+                                 StagedPlanes{P.ah, P.al, P.th, P.tl}, s);
+    else if (staged)
+      e = me->launch_staged_planes(b, StagedPlanes{P.ah, P.al, P.th, P.tl}, nullptr, 0, nullptr, s);
     else e = me->launch(b, true, false, s);
   }
   if (e != hipSuccess) return hip_error(e, "backward dB launch");

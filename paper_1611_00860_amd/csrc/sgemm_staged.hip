@@ -149,8 +149,7 @@ constexpr int kTB = 64;
 // otherwise; LDS rows are 65 floats, so both the row-wise writes and the
 // column-wise reads of a wavefront fall on distinct banks.
 template <bool X3>
-__device__ __forceinline__ void stage_cols_block(const StageJob& j, int64_t block) {
-  __shared__ float t[kTB][kTB + 1];
+__device__ __forceinline__ void stage_cols_block(const StageJob& j, int64_t block, float (*t)[kTB + 1]) {
   const int64_t col_blocks = j.cols_pad / kTB;
   const int64_t r0 = (block / col_blocks) * kTB, c0 = (block % col_blocks) * kTB;
   const int tid = threadIdx.x;
@@ -192,37 +191,50 @@ __device__ __forceinline__ void stage_cols_block(const StageJob& j, int64_t bloc
 }
 
 // One conversion, either form.
-template <bool X3, bool COLS>
-__global__ void __launch_bounds__(256) stage_one(StageJob j) {
-  if constexpr (COLS) stage_cols_block<X3>(j, blockIdx.x);
-  else stage_rows_part<X3>(j, blockIdx.x);
-}
-
 // Both operands of a product in one launch: the first a.blocks workgroups
 // copy A (copy form), the rest transpose B, so the two passes overlap.
 template <bool X3>
 __global__ void __launch_bounds__(256) stage_pair(StageJob a, StageJob b) {
+  __shared__ float t[kTB][kTB + 1];
   if ((int64_t)blockIdx.x < a.blocks) stage_rows_part<X3>(a, blockIdx.x);
-  else stage_cols_block<X3>(b, blockIdx.x - a.blocks);
+  else stage_cols_block<X3>(b, blockIdx.x - a.blocks, t);
 }
 
-// The backward's pass over G (see stage_gradient in internal.hpp): one
+// The backward's pass over G (see stage_backward in internal.hpp): one
 // workgroup per 64 x 64 block of the round256(m) x round256(n) padded
 // matrix, row-major over blocks (col_blocks per block row).
 // The block goes through LDS as in stage_cols_block; the row plane is written
 // when the block's columns lie within round64(n), the transposed plane when
 // its rows lie within round64(m).  Each thread's share of <G, Cin> follows a
 // fixed element order, so the partials repeat bit for bit.
+struct GradJob {
+  const float* G;
+  int64_t ldg;
+  const float* Cin;
+  int64_t ldci;
+  float* dCin;
+  int64_t lddci, m, n;
+  float beta;
+  float* partial;
+  uint16_t *gh, *gl;
+  int64_t n_kp;
+  uint16_t *th, *tl;
+  int64_t m_kp;
+  int32_t vec;
+  int64_t col_blocks, blocks;
+};
+
 template <bool X3>
-__global__ void __launch_bounds__(256)
-    stage_gradient_k(const float* __restrict__ G, int64_t ldg, const float* __restrict__ Cin, int64_t ldci,
-                     float* __restrict__ dCin, int64_t lddci, int64_t m, int64_t n, float beta,
-                     float* __restrict__ partial, uint16_t* __restrict__ gh, uint16_t* __restrict__ gl,
-                     int64_t n_kp, uint16_t* __restrict__ th, uint16_t* __restrict__ tl, int64_t m_kp,
-                     int32_t vec, int64_t col_blocks) {
-  __shared__ float t[kTB][kTB + 1];
-  __shared__ float red[256 / kWave];
-  const int64_t r0 = (int64_t)(blockIdx.x / col_blocks) * kTB, c0 = (int64_t)(blockIdx.x % col_blocks) * kTB;
+__device__ __forceinline__ void stage_gradient_block(const GradJob& j, int64_t block, float (*t)[kTB + 1],
+                                                     float* red) {
+  const float* __restrict__ G = j.G;
+  const float* __restrict__ Cin = j.Cin;
+  float* __restrict__ dCin = j.dCin;
+  float* __restrict__ partial = j.partial;
+  const int64_t ldg = j.ldg, ldci = j.ldci, lddci = j.lddci, m = j.m, n = j.n;
+  const float beta = j.beta;
+  const int32_t vec = j.vec;
+  const int64_t r0 = (block / j.col_blocks) * kTB, c0 = (block % j.col_blocks) * kTB;
   const int tid = threadIdx.x;
   float part = 0.0f;
   if (vec && r0 + kTB <= m && c0 + kTB <= n) {
@@ -263,6 +275,11 @@ __global__ void __launch_bounds__(256)
     }
   }
   __syncthreads();
+  uint16_t* __restrict__ gh = j.gh;
+  uint16_t* __restrict__ gl = j.gl;
+  uint16_t* __restrict__ th = j.th;
+  uint16_t* __restrict__ tl = j.tl;
+  const int64_t n_kp = j.n_kp, m_kp = j.m_kp;
   if (gh && c0 < n_kp) {
 #pragma unroll
     for (int j = 0; j < kTB * kTB / 8 / 256; ++j) {
@@ -295,7 +312,25 @@ __global__ void __launch_bounds__(256)
   }
   if (!partial) return;
   const float sum = block_sum(part, red);
-  if (tid == 0) partial[blockIdx.x] = sum;
+  if (tid == 0) partial[block] = sum;
+}
+
+// The staged backward's conversions in one launch: g.blocks workgroups for
+// the pass over G, then b.blocks copying B, then a's blocks transposing A
+// (a job with no blocks is absent).  All are bound by HBM; one launch lets
+// them overlap instead of each draining before the next starts.
+template <bool X3>
+__global__ void __launch_bounds__(256) stage_backward_k(GradJob g, StageJob b, StageJob a) {
+  __shared__ float t[kTB][kTB + 1];
+  __shared__ float red[256 / kWave];
+  int64_t blk = blockIdx.x;
+  if (blk < g.blocks) {
+    stage_gradient_block<X3>(g, blk, t, red);
+    return;
+  }
+  blk -= g.blocks;
+  if (blk < b.blocks) stage_rows_part<X3>(b, blk);
+  else stage_cols_block<X3>(a, blk - b.blocks, t);
 }
 
 struct StagedArgs {
@@ -640,12 +675,6 @@ StageJob cols_job(const float* src, int64_t ld, int64_t rows, int64_t cols, int6
   return StageJob{src, ld, rows, cols, rows_pad, cols_pad, hi, lo, vec, (cols_pad / kTB) * (rows_pad / kTB)};
 }
 
-template <bool X3, bool COLS>
-hipError_t stage_one_launch(StageJob j, hipStream_t s) {
-  void* args[] = {&j};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&stage_one<X3, COLS>), dim3((unsigned)j.blocks), dim3(256),
-                         args, 0, s);
-}
 
 // The forward product's planes: A (m x k, k contiguous) copied row by row
 // into [m_pad][k_pad], B (k x n) transposed through LDS into [n_pad][k_pad].
@@ -664,31 +693,21 @@ hipError_t stage_operands(const GemmArgs& a, const StagedLayout& L, char* ws, hi
 
 }  // namespace
 
-hipError_t stage_operand(int32_t prec, const float* src, int64_t ld, int64_t rows, int64_t cols, bool k_along_rows,
-                         uint16_t* hi, uint16_t* lo, int32_t vec, hipStream_t s) {
-  const bool x3 = prec == HPVM_PREC_BF16X3;
-  if (!k_along_rows) {
-    const StageJob j = rows_job(src, ld, rows, cols, staged_rows_pad(rows), staged_k_pad(cols), hi, lo, vec);
-    return x3 ? stage_one_launch<true, false>(j, s) : stage_one_launch<false, false>(j, s);
-  }
-  const StageJob j = cols_job(src, ld, rows, cols, staged_k_pad(rows), staged_rows_pad(cols), hi, lo, vec);
-  return x3 ? stage_one_launch<true, true>(j, s) : stage_one_launch<false, true>(j, s);
-}
-
 int64_t stage_gradient_blocks(int64_t m, int64_t n) {
   return (staged_rows_pad(m) / kTB) * (staged_rows_pad(n) / kTB);
 }
 
-hipError_t stage_gradient(int32_t prec, const float* G, int64_t ldg, const float* Cin, int64_t ldci, float* dCin,
-                          int64_t lddci, int64_t m, int64_t n, float beta, float* partial, uint16_t* gh,
-                          uint16_t* gl, uint16_t* th, uint16_t* tl, int32_t vec, hipStream_t s) {
-  int64_t n_kp = staged_k_pad(n), m_kp = staged_k_pad(m), col_blocks = staged_rows_pad(n) / kTB;
-  void* args[] = {&G, &ldg, &Cin, &ldci, &dCin, &lddci, &m, &n, &beta, &partial, &gh, &gl, &n_kp, &th, &tl, &m_kp,
-                  &vec, &col_blocks};
-  const dim3 grid((unsigned)stage_gradient_blocks(m, n));
-  const void* fn = prec == HPVM_PREC_BF16X3 ? reinterpret_cast<const void*>(&stage_gradient_k<true>)
-                                            : reinterpret_cast<const void*>(&stage_gradient_k<false>);
-  return hipLaunchKernel(fn, grid, dim3(256), args, 0, s);
+hipError_t stage_backward(int32_t prec, const BackwardStaging& st, hipStream_t s) {
+  GradJob g{st.G,   st.ldg, st.Cin, st.ldci, st.dCin, st.lddci, st.m, st.n, st.beta, st.partial, st.gh, st.gl,
+            staged_k_pad(st.n), st.th, st.tl, staged_k_pad(st.m), st.vec_g, staged_rows_pad(st.n) / kTB,
+            stage_gradient_blocks(st.m, st.n)};
+  StageJob b{}, a{};
+  if (st.bh) b = rows_job(st.B, st.ldb, st.k, st.n, staged_rows_pad(st.k), staged_k_pad(st.n), st.bh, st.bl, st.vec_b);
+  if (st.ah) a = cols_job(st.A, st.lda, st.m, st.k, staged_k_pad(st.m), staged_rows_pad(st.k), st.ah, st.al, st.vec_a);
+  void* args[] = {&g, &b, &a};
+  const void* fn = prec == HPVM_PREC_BF16X3 ? reinterpret_cast<const void*>(&stage_backward_k<true>)
+                                            : reinterpret_cast<const void*>(&stage_backward_k<false>);
+  return hipLaunchKernel(fn, dim3((unsigned)(g.blocks + b.blocks + a.blocks)), dim3(256), args, 0, s);
 }
 
 namespace {
