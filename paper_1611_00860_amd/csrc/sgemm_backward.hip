@@ -83,19 +83,35 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
 constexpr int kElemThreads = 256;
 constexpr int kElemBlocks = 1024;
 
-// dC_in = beta G (zeros when beta == 0) and per-block partials of <G, C_in>.
-// Rows are dealt to blocks in turn; a block's threads walk a row in 16-byte
-// units when every matrix it touches allows them (vec), one element at a
-// time otherwise.  The element-to-thread assignment depends only on m, n
-// and the grid, so the partials repeat bit for bit.
-__global__ void __launch_bounds__(kElemThreads)
-    sgemm_grad_c(const float* __restrict__ G, int64_t ldg, const float* __restrict__ Cin, int64_t ldci,
-                 float* __restrict__ dCin, int64_t lddci, int64_t m, int64_t n, float beta,
-                 float* __restrict__ partial, int32_t vec) {
-  __shared__ float red[kElemThreads / kWave];
+// dC_in = beta G (zeros when beta == 0) and per-block partials of <G, C_in>
+// (Cin is read only for partial).  Rows are dealt to the job's blocks in
+// turn; a block's threads walk a row in 16-byte units when every matrix it
+// touches allows them (vec), one element at a time otherwise.  The
+// element-to-thread assignment depends only on m, n and the block count, so
+// the partials repeat bit for bit.
+struct GradCJob {
+  const float* G;
+  int64_t ldg;
+  const float* Cin;
+  int64_t ldci;
+  float* dCin;
+  int64_t lddci, m, n;
+  float beta;
+  float* partial;
+  int32_t vec;
+  int64_t blocks;
+};
+
+__device__ __forceinline__ void grad_c_block(const GradCJob& jb, int64_t block, float* red) {
+  const float* __restrict__ G = jb.G;
+  const float* __restrict__ Cin = jb.Cin;
+  float* __restrict__ dCin = jb.dCin;
+  float* __restrict__ partial = jb.partial;
+  const int64_t ldg = jb.ldg, ldci = jb.ldci, lddci = jb.lddci, m = jb.m, n = jb.n;
+  const float beta = jb.beta;
   float part = 0.0f;
-  const int64_t n4 = vec ? n / 4 : 0;
-  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+  const int64_t n4 = jb.vec ? n / 4 : 0;
+  for (int64_t i = block; i < m; i += jb.blocks) {
     const float* g = G + i * ldg;
     const float* c = partial ? Cin + i * ldci : nullptr;
     float* d = dCin ? dCin + i * lddci : nullptr;
@@ -141,7 +157,12 @@ __global__ void __launch_bounds__(kElemThreads)
   }
   if (!partial) return;
   const float s = block_sum(part, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) partial[block] = s;
+}
+
+__global__ void __launch_bounds__(kElemThreads) sgemm_grad_c(GradCJob j) {
+  __shared__ float red[kElemThreads / kWave];
+  grad_c_block(j, blockIdx.x, red);
 }
 
 // Final fixed-order reduction of both partial arrays.
@@ -175,32 +196,65 @@ __global__ void __launch_bounds__(kElemThreads)
 // Sum of one gradient's slice partials part[z] (rows x cols, contiguous), in
 // slice order: v = part[0] + part[1] + ...; out <- alpha v when out is
 // given; with aorig, this block's partial of <aorig, v> into dpart.  Float4
-// units are dealt to threads grid-stride, so everything repeats bit for bit.
-// cols, ldo and ldao are multiples of 4 and the arrays 16-byte aligned.
-__global__ void __launch_bounds__(kElemThreads)
-    sgemm_split_sum(const float* __restrict__ part, int32_t splits, int64_t rows, int64_t cols, float alpha,
-                    float* __restrict__ out, int64_t ldo, const float* __restrict__ aorig, int64_t ldao,
-                    float* __restrict__ dpart) {
-  __shared__ float red[kElemThreads / kWave];
-  const int64_t c4 = cols / 4, units = rows * c4, plane = rows * cols;
+// units are dealt to the job's threads in turn, so everything repeats bit
+// for bit.  cols, ldo and ldao are multiples of 4 and the arrays 16-byte
+// aligned.
+struct SumJob {
+  const float* part;
+  int32_t splits;
+  int64_t rows, cols;
+  float alpha;
+  float* out;
+  int64_t ldo;
+  const float* aorig;
+  int64_t ldao;
+  float* dpart;
+  int64_t blocks;
+};
+
+__device__ __forceinline__ void split_sum_block(const SumJob& jb, int64_t block, float* red) {
+  const float* __restrict__ part = jb.part;
+  float* __restrict__ out = jb.out;
+  const float* __restrict__ aorig = jb.aorig;
+  const int64_t cols = jb.cols, c4 = cols / 4, units = jb.rows * c4, plane = jb.rows * cols;
+  const int64_t stride = jb.blocks * blockDim.x;
   float sum = 0.0f;
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units;
-       u += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t u = block * blockDim.x + threadIdx.x; u < units; u += stride) {
     const int64_t i = u / c4, j = (u - i * c4) * 4;
     f32x4 v = *reinterpret_cast<const f32x4*>(part + i * cols + j);
-    for (int z = 1; z < splits; ++z) v += *reinterpret_cast<const f32x4*>(part + z * plane + i * cols + j);
-    if (out) *reinterpret_cast<f32x4*>(out + i * ldo + j) = alpha * v;
-    if (dpart) {
-      const f32x4 a = *reinterpret_cast<const f32x4*>(aorig + i * ldao + j);
+    for (int z = 1; z < jb.splits; ++z) v += *reinterpret_cast<const f32x4*>(part + z * plane + i * cols + j);
+    if (out) *reinterpret_cast<f32x4*>(out + i * jb.ldo + j) = jb.alpha * v;
+    if (jb.dpart) {
+      const f32x4 a = *reinterpret_cast<const f32x4*>(aorig + i * jb.ldao + j);
       sum = fmaf(a[0], v[0], sum);
       sum = fmaf(a[1], v[1], sum);
       sum = fmaf(a[2], v[2], sum);
       sum = fmaf(a[3], v[3], sum);
     }
   }
-  if (!dpart) return;
+  if (!jb.dpart) return;
   const float t = block_sum(sum, red);
-  if (threadIdx.x == 0) dpart[blockIdx.x] = t;
+  if (threadIdx.x == 0) jb.dpart[block] = t;
+}
+
+__global__ void __launch_bounds__(kElemThreads) sgemm_split_sum(SumJob j) {
+  __shared__ float red[kElemThreads / kWave];
+  split_sum_block(j, blockIdx.x, red);
+}
+
+// The element-wise passes after both gradients' slices: dA's slice sum,
+// dB's, and grad_c, in one launch of three block ranges (a range with no
+// blocks is absent) so that the passes overlap.
+__global__ void __launch_bounds__(kElemThreads) sgemm_grad_tail(SumJob a, SumJob b, GradCJob c) {
+  __shared__ float red[kElemThreads / kWave];
+  int64_t blk = blockIdx.x;
+  if (blk < a.blocks) {
+    split_sum_block(a, blk, red);
+    return;
+  }
+  blk -= a.blocks;
+  if (blk < b.blocks) split_sum_block(b, blk, red);
+  else grad_c_block(c, blk - b.blocks, red);
 }
 
 namespace {
@@ -444,11 +498,9 @@ hipError_t launch_split(const GemmArgs& args, int splits, float* part, float* ou
   e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n * splits)),
                       dim3(S::NW * kWave), kargs, (size_t)S::kLdsBytes, s);
   if (e != hipSuccess || (!out && !dpart)) return e;
-  const float* pp = part;
-  int64_t rows = a.m, cols = a.n;
-  float alpha = args.alpha;
-  void* sargs[] = {&pp, &sp, &rows, &cols, &alpha, &out, &ldo, &aorig, &ldao, &dpart};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_sum), dim3((unsigned)split_sum_blocks(rows, cols)),
+  SumJob j{part, sp, a.m, a.n, args.alpha, out, ldo, aorig, ldao, dpart, split_sum_blocks(a.m, a.n)};
+  void* sargs[] = {&j};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_sum), dim3((unsigned)j.blocks),
                          dim3(kElemThreads), sargs, 0, s);
 }
 
@@ -479,10 +531,11 @@ __global__ void __launch_bounds__(DmaA::NW * kWave) __attribute__((amdgpu_waves_
 }
 
 // dA and dB with `splits` slices each in one launch (partials [splits][m][k]
-// at part_a, [splits][k][n] at part_b), then each gradient's slice sum.
+// at part_a, [splits][k][n] at part_b), then one launch of both slice sums
+// and the grad_c job gc (absent when gc.blocks == 0).
 hipError_t launch_split_pair(const GemmArgs& ga, const GemmArgs& gb, int splits, float* part_a, float* part_b,
                              float* dA, int64_t ldda, float* dB, int64_t lddb, const float* aorig, int64_t ldao,
-                             float* dpart, hipStream_t s) {
+                             float* dpart, GradCJob gc, hipStream_t s) {
   auto* fn = &sgemm_grad_pair_dma;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDmaPairLds);
@@ -503,24 +556,12 @@ hipError_t launch_split_pair(const GemmArgs& ga, const GemmArgs& gb, int splits,
   e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)wgs), dim3(DmaA::NW * kWave), kargs,
                       (size_t)kDmaPairLds, s);
   if (e != hipSuccess) return e;
-  int32_t sp = splits;
-  float alpha = ga.alpha;
-  if (dA || dpart) {
-    const float* pp = part_a;
-    int64_t rows = a.m, cols = a.n;
-    void* sargs[] = {&pp, &sp, &rows, &cols, &alpha, &dA, &ldda, &aorig, &ldao, &dpart};
-    e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_sum),
-                        dim3((unsigned)split_sum_blocks(rows, cols)), dim3(kElemThreads), sargs, 0, s);
-    if (e != hipSuccess) return e;
-  }
-  const float* pp = part_b;
-  int64_t rows = b.m, cols = b.n;
-  const float* no_a = nullptr;
-  int64_t no_ld = 0;
-  float* no_part = nullptr;
-  void* sargs[] = {&pp, &sp, &rows, &cols, &alpha, &dB, &lddb, &no_a, &no_ld, &no_part};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_sum), dim3((unsigned)split_sum_blocks(rows, cols)),
-                         dim3(kElemThreads), sargs, 0, s);
+  SumJob ja{part_a, splits, a.m, a.n, ga.alpha, dA, ldda, aorig, ldao, dpart,
+            (dA || dpart) ? split_sum_blocks(a.m, a.n) : 0};
+  SumJob jb{part_b, splits, b.m, b.n, gb.alpha, dB, lddb, nullptr, 0, nullptr, split_sum_blocks(b.m, b.n)};
+  void* targs[] = {&ja, &jb, &gc};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_grad_tail),
+                         dim3((unsigned)(ja.blocks + jb.blocks + gc.blocks)), dim3(kElemThreads), targs, 0, s);
 }
 
 std::mutex g_tune_mu;
@@ -642,6 +683,14 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   hipError_t e = hipSuccess;
   int64_t na = L.na;
 
+  // dC_in and dbeta's partials: an element-wise pass over G (and C_in),
+  // launched on its own below unless a launch already carries it.
+  const bool grad_c = mn && (dC_in || dbeta);
+  GradCJob gc{G, ldg, C_in, ldci, dC_in, lddci, m, n, beta, dbeta ? pb : nullptr,
+              vec16(G, ldg) && (!dC_in || vec16(dC_in, lddci)) && (!dbeta || vec16(C_in, ldci)), 0};
+  if (grad_c) gc.blocks = L.nb;
+  bool gc_done = false;
+
   // Staged entries: one launch converts everything the products read — one
   // pass over G (its planes for both products, dC_in and dbeta's partials),
   // B for dA and A transposed for dB.
@@ -690,7 +739,7 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     }
     e = stage_backward(prec, st, s);
     if (e != hipSuccess) return hip_error(e, "backward staging launch");
-    g_pass = true;
+    g_pass = gc_done = true;
   }
 
   // dA (and dalpha's partials): contraction over n.
@@ -766,10 +815,12 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     b.beta = 0.0f;
     b.vec_a = vec16(A, lda);
     b.vec_b = vec16(G, ldg);
-    if (dma_pair)
+    if (dma_pair) {
       e = launch_split_pair(a_pair, b, plan.sp, reinterpret_cast<float*>(stage),
                             reinterpret_cast<float*>(stage) + plan.sp * m * k, dA, ldda, dB, lddb,
-                            dalpha ? A : nullptr, lda, dalpha ? pa : nullptr, s);
+                            dalpha ? A : nullptr, lda, dalpha ? pa : nullptr, gc, s);
+      gc_done = true;
+    }
     else if (dma_b)
       e = launch_split<true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb, nullptr, 0, nullptr, s);
     else if (!me) e = hipErrorInvalidValue;
@@ -782,17 +833,9 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   }
   if (e != hipSuccess) return hip_error(e, "backward dB launch");
 
-  // dC_in and dbeta's partials (already written by a pass over G).
-  if (mn && (dC_in || dbeta) && !g_pass) {
-    float* part = dbeta ? pb : nullptr;
-    const float* Gp = G;
-    const float* Cp = C_in;
-    float* dCp = dC_in;
-    int64_t ldg_ = ldg, ldci_ = ldci, lddci_ = lddci, m_ = m, n_ = n;
-    float beta_ = beta;
-    int32_t vec = vec16(G, ldg) && (!dC_in || vec16(dC_in, lddci)) && (!part || vec16(C_in, ldci));
-    void* kargs[] = {&Gp, &ldg_, &Cp, &ldci_, &dCp, &lddci_, &m_, &n_, &beta_, &part, &vec};
-    e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_grad_c), dim3((unsigned)L.nb), dim3(kElemThreads),
+  if (grad_c && !gc_done) {
+    void* kargs[] = {&gc};
+    e = hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_grad_c), dim3((unsigned)gc.blocks), dim3(kElemThreads),
                         kargs, 0, s);
   }
   if (e != hipSuccess) return hip_error(e, "backward dC_in launch");
