@@ -304,6 +304,27 @@ def test_backward_staged_outputs_and_layouts(gpu, prec):
                         assert np.array_equal(got, ref[key]), (tile, name, need, key)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (7, 300, 65), (300, 7, 1), (63, 65, 257), (257, 64, 3)])
+def test_backward_staged_small_and_ragged(gpu, prec, m, n, k):
+    """Staged tiles pad every plane to 256-row, 64-deep blocks: sizes below
+    one block, one past a block, and contractions of 1 keep every output exact
+    on integer inputs (the padding must hold zeros)."""
+    import torch
+
+    A, B, C, G = inputs.backward_operands(m, n, k, seed=29, dist="int")
+    ref = oracle.sgemm_grad(A, B, C, G, 1.0, 2.0)
+    d = dev_all(A, B, C, G)
+    tile = [t for t in gpu.backward_menu(prec) if t[5] == 3][0]
+    print(f"case: backward staged {prec} {m}x{n}x{k} tile {tile}", flush=True)
+    g = gpu.sgemm_backward(*d, 1.0, 2.0, prec=prec, tile=tile)
+    torch.cuda.synchronize()
+    for key in ("dA", "dB", "dC_in"):
+        assert np.array_equal(to_host(g[key]), ref[key]), key
+    assert math.isclose(float(g["dalpha"]), ref["dalpha"], rel_tol=1e-6, abs_tol=1e-6)
+    assert math.isclose(float(g["dbeta"]), ref["dbeta"], rel_tol=1e-6, abs_tol=1e-6)
+
+
 def test_backward_autotune_records_a_menu_tile(gpu):
     import torch
 
