@@ -759,7 +759,7 @@ def main():
         log("variant: tracked host arrays")
         variants.update(variant_tracked(hp, inputs, dev, reps=5))
         log("variant: forward + backward 4096x4096x1024")
-        variants.update(variant_backward(hp, inputs, dev, stream, reps=5))
+        variants.update(variant_backward(hp, inputs, dev, stream, reps=20))
         result["variants"] = variants
 
     if args.calibrate_copy:
