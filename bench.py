@@ -605,6 +605,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variants", default="precision,grouped,stream,fusion,tracked,backward",
+                    help="comma-separated variants to run after the workload (a subset, e.g. for a counter run)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain 1 GiB device-to-device copies (HBM counter calibration)")
@@ -615,6 +617,11 @@ def main():
     ap.add_argument("--traffic-table", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_LOG", "WRITE_LOG"),
                     help="build profiles/fp32_sgemm_tiles_traffic.txt from two --traffic-sweep counter runs and exit")
     args = ap.parse_args()
+    known = {"precision", "grouped", "stream", "fusion", "tracked", "backward"}
+    unknown = set(v.strip() for v in args.variants.split(",") if v.strip()) - known
+    if unknown:
+        print(f"bench.py: unknown variants {sorted(unknown)} (known: {sorted(known)})", file=sys.stderr)
+        sys.exit(2)
     if args.traffic_table:
         build_traffic_table(*args.traffic_table, command=" ".join(sys.argv))
         return
@@ -748,18 +755,20 @@ def main():
 
     if not args.no_variants:
         variants = {}
-        log("variant: BF16 / bf16x3 at 8192^3")
-        variants.update(variant_precision(hp, inputs, dev, stream, reps=10))
-        log("variant: grouped 512 from a HIP graph")
-        variants.update(variant_grouped(hp, inputs, dev, reps=10))
-        log("variant: the 512 sgemms through a streaming graph")
-        variants.update(variant_stream(hp, inputs, dev, reps=5))
-        log("variant: node fusion")
-        variants.update(variant_fusion(hp, inputs, dev, stream, reps=10))
-        log("variant: tracked host arrays")
-        variants.update(variant_tracked(hp, inputs, dev, reps=5))
-        log("variant: forward + backward 4096x4096x1024")
-        variants.update(variant_backward(hp, inputs, dev, stream, reps=20))
+        chosen = set(v.strip() for v in args.variants.split(",") if v.strip())
+        runs = [
+            ("precision", "BF16 / bf16x3 at 8192^3", lambda: variant_precision(hp, inputs, dev, stream, reps=10)),
+            ("grouped", "grouped 512 from a HIP graph", lambda: variant_grouped(hp, inputs, dev, reps=10)),
+            ("stream", "the 512 sgemms through a streaming graph", lambda: variant_stream(hp, inputs, dev, reps=5)),
+            ("fusion", "node fusion", lambda: variant_fusion(hp, inputs, dev, stream, reps=10)),
+            ("tracked", "tracked host arrays", lambda: variant_tracked(hp, inputs, dev, reps=5)),
+            ("backward", "forward + backward 4096x4096x1024",
+             lambda: variant_backward(hp, inputs, dev, stream, reps=20)),
+        ]
+        for name, what, run in runs:
+            if name in chosen:
+                log(f"variant: {what}")
+                variants.update(run())
         result["variants"] = variants
 
     if args.calibrate_copy:

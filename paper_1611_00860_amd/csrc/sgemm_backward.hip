@@ -314,8 +314,9 @@ const BwdEntry kBwd[] = {
     staged_entry(256, 128, 64, 128, 64, HPVM_PREC_BF16),
     fused_entry<128, 128, 32, 64, 64, HPVM_PREC_BF16>(),
     fused_entry<64, 64, 32, 32, 32, HPVM_PREC_BF16>(),
-    staged_entry(128, 128, 64, 64, 64, HPVM_PREC_BF16X3),
     staged_entry(256, 256, 32, 128, 64, HPVM_PREC_BF16X3),
+    staged_entry(128, 128, 64, 64, 32, HPVM_PREC_BF16X3),
+    staged_entry(128, 128, 64, 64, 64, HPVM_PREC_BF16X3),
     staged_entry(256, 128, 32, 128, 64, HPVM_PREC_BF16X3),
     fused_entry<128, 128, 32, 64, 64, HPVM_PREC_BF16X3>(),
     fused_entry<64, 64, 32, 32, 32, HPVM_PREC_BF16X3>(),
@@ -380,8 +381,18 @@ int64_t split_sum_blocks(int64_t rows, int64_t cols) {
 }
 
 // Built-in choice: the DMA entry when dA is whole tiles, else the first
-// entry giving dA at least one tile per CU of a 256-CU part, else the one
-// giving the most tiles.
+// entry giving at least one tile per CU of a 256-CU part, else the one
+// giving the most tiles -- counting dA's tiles, plus dB's for a staged entry
+// that runs both products in one launch.
+int64_t launch_tiles(const BwdEntry& e, int64_t m, int64_t n, int64_t k) {
+  int64_t tiles = tiles_for(e.tile, m, k);
+  if (!e.grad_a) {
+    const MfmaEntry* me = find_menu_entry(e.prec, e.tile);
+    if (me && me->launch_staged_pair) tiles += tiles_for(e.tile, k, n);
+  }
+  return tiles;
+}
+
 const BwdEntry* pick(int32_t prec, int64_t m, int64_t n, int64_t k) {
   hpvm_tile tuned;
   if (tuned_backward_tile(prec, m, n, k, &tuned)) {
@@ -397,8 +408,9 @@ const BwdEntry* pick(int32_t prec, int64_t m, int64_t n, int64_t k) {
       continue;
     }
     if (!kBwd[i].grad_a && !staged_ok) continue;
-    if (tiles_for(kBwd[i].tile, m, k) >= kTargetTiles) return &kBwd[i];
-    if (!most || tiles_for(kBwd[i].tile, m, k) > tiles_for(most->tile, m, k)) most = &kBwd[i];
+    const int64_t tiles = launch_tiles(kBwd[i], m, n, k);
+    if (tiles >= kTargetTiles) return &kBwd[i];
+    if (!most || tiles > launch_tiles(*most, m, n, k)) most = &kBwd[i];
   }
   return most;
 }

@@ -499,16 +499,22 @@ __global__ void __launch_bounds__((TM / WM) * (TN / WN) * kWave)
 // transit; the registers this frees keep two sets of MFMA fragments, and
 // the fragments of a step are read while the previous step's MFMAs run.
 // Both tiles are rows (m or n) of TK bf16 k values, laid out by
-// SwizzledRows; the planes are padded, so no access needs a check.
+// SwizzledRows; the planes are padded, so no access needs a check.  With
+// X3 (bf16x3) a stage holds the hi and lo planes of both operands,
+// [A hi][A lo][B hi][B lo], and each step is lo*hi + hi*lo + hi*hi in the
+// order of the fused lowering, so the two give the same bits.
 // ---------------------------------------------------------------------------
-template <int TM, int TN, int TK, int WM, int WN, int NST>
+template <int TM, int TN, int TK, int WM, int WN, int NST, bool X3 = false>
 struct Bf16DmaShape {
   static constexpr int NW = (TM / WM) * (TN / WN), BM = WM / 32, BN = WN / 32;
   static constexpr int RB = 2 * TK;  // bytes of a row
-  static constexpr int kABytes = TM * RB, kStage = (TM + TN) * RB;
+  static constexpr int kPlanes = X3 ? 2 : 1;
+  static constexpr int kABytes = TM * RB, kBBytes = TN * RB;  // one plane
+  static constexpr int kBOff = kPlanes * kABytes;             // B hi within a stage
+  static constexpr int kStage = kPlanes * (TM + TN) * RB;
   static constexpr int64_t kLdsBytes = (int64_t)NST * kStage;
   static constexpr int kRowsPerDma = SwizzledRows<RB>::kRowsPerDma;
-  static constexpr int QA = TM / kRowsPerDma / NW, QB = TN / kRowsPerDma / NW, Q = QA + QB;
+  static constexpr int QA = TM / kRowsPerDma / NW, QB = TN / kRowsPerDma / NW, Q = kPlanes * (QA + QB);
   static constexpr int kMaxWaves = (163840 / (NST * kStage)) * NW / 4;
   static_assert(QA * NW * kRowsPerDma == TM && QB * NW * kRowsPerDma == TN && QA % 2 == 0 && QB % 2 == 0,
                 "even DMA split");
@@ -529,11 +535,12 @@ __device__ __forceinline__ void interleave_mfma_reads() {
 }
 
 // One output tile (number `tile` of the product p) on this workgroup.
-template <int TM, int TN, int TK, int WM, int WN, int NST, int EPI>
+template <int TM, int TN, int TK, int WM, int WN, int NST, int EPI, bool X3 = false>
 __device__ __forceinline__ void bf16_dma_tile(const StagedArgs& p, int tile, char* smem) {
-  using S = Bf16DmaShape<TM, TN, TK, WM, WN, NST>;
+  using S = Bf16DmaShape<TM, TN, TK, WM, WN, NST, X3>;
   using Lay = SwizzledRows<S::RB>;
   constexpr int BM = S::BM, BN = S::BN, QA = S::QA, QB = S::QB, KS = TK / 16, R = S::kRowsPerDma;
+  constexpr int P = S::kPlanes;
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -544,20 +551,30 @@ __device__ __forceinline__ void bf16_dma_tile(const StagedArgs& p, int tile, cha
   const int64_t rowb = p.kp * 2;
   const uint32_t lds0 = lds_addr(smem);
 
-  // This wave fills row slots [wave*QA*R, (wave+1)*QA*R) of the A stage and
-  // the same share of the B stage; instruction j's group parity is j's.
-  const char* asrc = reinterpret_cast<const char*>(p.ah) + (m0 + (int64_t)wave * QA * R) * rowb;
-  const char* bsrc = reinterpret_cast<const char*>(p.bh) + (n0 + (int64_t)wave * QB * R) * rowb;
+  // This wave fills row slots [wave*QA*R, (wave+1)*QA*R) of each A plane of
+  // the stage and the same share of each B plane; instruction j's group
+  // parity is j's.
+  const char* asrc[P];
+  const char* bsrc[P];
+  asrc[0] = reinterpret_cast<const char*>(p.ah) + (m0 + (int64_t)wave * QA * R) * rowb;
+  bsrc[0] = reinterpret_cast<const char*>(p.bh) + (n0 + (int64_t)wave * QB * R) * rowb;
+  if constexpr (X3) {
+    asrc[P - 1] = reinterpret_cast<const char*>(p.al) + (m0 + (int64_t)wave * QA * R) * rowb;
+    bsrc[P - 1] = reinterpret_cast<const char*>(p.bl) + (n0 + (int64_t)wave * QB * R) * rowb;
+  }
   const uint32_t voff[2] = {Lay::src(lane, 0, rowb), Lay::src(lane, 1, rowb)};
   auto dma_slab = [&](int slab, int st) {
-    const uint32_t la = lds0 + st * S::kStage + wave * QA * 1024;
-    const uint32_t lb = lds0 + st * S::kStage + S::kABytes + wave * QB * 1024;
-    const char* a = asrc + slab * S::RB;
-    const char* b = bsrc + slab * S::RB;
 #pragma unroll
-    for (int j = 0; j < QA; ++j) dma16(la + j * 1024, a + j * R * rowb, voff[j & 1]);
+    for (int q = 0; q < P; ++q) {
+      const uint32_t la = lds0 + st * S::kStage + q * S::kABytes + wave * QA * 1024;
+      const uint32_t lb = lds0 + st * S::kStage + S::kBOff + q * S::kBBytes + wave * QB * 1024;
+      const char* a = asrc[q] + slab * S::RB;
+      const char* b = bsrc[q] + slab * S::RB;
 #pragma unroll
-    for (int j = 0; j < QB; ++j) dma16(lb + j * 1024, b + j * R * rowb, voff[j & 1]);
+      for (int j = 0; j < QA; ++j) dma16(la + j * 1024, a + j * R * rowb, voff[j & 1]);
+#pragma unroll
+      for (int j = 0; j < QB; ++j) dma16(lb + j * 1024, b + j * R * rowb, voff[j & 1]);
+    }
   };
 
   int foff[KS];
@@ -565,23 +582,39 @@ __device__ __forceinline__ void bf16_dma_tile(const StagedArgs& p, int tile, cha
   for (int ks = 0; ks < KS; ++ks) foff[ks] = Lay::frag(lane, ks);
   f32x16 acc[BM][BN];
   zero_acc(acc);
-  bf16x8 fa[2][BM], fb[2][BN];
+  // [buffer][plane][block]; plane 1 (lo) only with X3.
+  bf16x8 fa[2][P][BM], fb[2][P][BN];
   // B first: a step's first MFMAs use A block 0 with every B block.
   auto read = [&](int buf, const char* st, int ks) {
 #pragma unroll
-    for (int bj = 0; bj < BN; ++bj)
-      fb[buf][bj] = *reinterpret_cast<const bf16x8*>(st + S::kABytes + (wn0 + 32 * bj) * S::RB + foff[ks]);
+    for (int q = 0; q < P; ++q)
 #pragma unroll
-    for (int bi = 0; bi < BM; ++bi)
-      fa[buf][bi] = *reinterpret_cast<const bf16x8*>(st + (wm0 + 32 * bi) * S::RB + foff[ks]);
+      for (int bj = 0; bj < BN; ++bj)
+        fb[buf][q][bj] = *reinterpret_cast<const bf16x8*>(st + S::kBOff + q * S::kBBytes + (wn0 + 32 * bj) * S::RB +
+                                                          foff[ks]);
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int bi = 0; bi < BM; ++bi)
+        fa[buf][q][bi] = *reinterpret_cast<const bf16x8*>(st + q * S::kABytes + (wm0 + 32 * bi) * S::RB + foff[ks]);
   };
   auto mfma = [&](int buf) {
+    if constexpr (X3) {
+#pragma unroll
+      for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BN; ++bj) {
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][1][bi], fb[buf][0][bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][0][bi], fb[buf][1][bj], acc[bi][bj], 0, 0, 0);
+        }
+    }
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
       for (int bj = 0; bj < BN; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][bi], fb[buf][bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][0][bi], fb[buf][0][bj], acc[bi][bj], 0, 0, 0);
   };
+  constexpr int kReads = P * (BM + BN), kMfmas = (X3 ? 3 : 1) * BM * BN;
 
   const int slabs = p.slabs;
   if (slabs > 0) {
@@ -597,7 +630,7 @@ __device__ __forceinline__ void bf16_dma_tile(const StagedArgs& p, int tile, cha
 #pragma unroll
     for (int ks = 0; ks + 1 < KS; ++ks) {
       read((ks + 1) & 1, cur, ks + 1);
-      interleave_mfma_reads<BM + BN, BM * BN>();
+      interleave_mfma_reads<kReads, kMfmas>();
       mfma(ks & 1);
     }
     // Slab s + 1 has landed everywhere and slab s is no longer read:
@@ -608,7 +641,7 @@ __device__ __forceinline__ void bf16_dma_tile(const StagedArgs& p, int tile, cha
     dma_wait_barrier<(NST - 2) * S::Q>();
     read(0, smem + nst * S::kStage, 0);
     dma_slab(s + NST < slabs ? s + NST : slabs - 1, st);
-    interleave_mfma_reads<BM + BN, BM * BN>();
+    interleave_mfma_reads<kReads, kMfmas>();
     mfma(1);
     st = nst;
   }
@@ -629,29 +662,29 @@ __device__ __forceinline__ void bf16_dma_tile(const StagedArgs& p, int tile, cha
   }
 }
 
-template <int TM, int TN, int TK, int WM, int WN, int NST, int EPI>
-__global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST>::NW * kWave))
-    __attribute__((amdgpu_waves_per_eu(1, (Bf16DmaShape<TM, TN, TK, WM, WN, NST>::kMaxWaves))))
+template <int TM, int TN, int TK, int WM, int WN, int NST, int EPI, bool X3>
+__global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST, X3>::NW * kWave))
+    __attribute__((amdgpu_waves_per_eu(1, (Bf16DmaShape<TM, TN, TK, WM, WN, NST, X3>::kMaxWaves))))
     sgemm_bf16_dma(StagedArgs p) {
   extern __shared__ __align__(16) char smem[];
-  bf16_dma_tile<TM, TN, TK, WM, WN, NST, EPI>(p, blockIdx.x, smem);
+  bf16_dma_tile<TM, TN, TK, WM, WN, NST, EPI, X3>(p, blockIdx.x, smem);
 }
 
 // Two independent products in one launch: the tiles of p1 (with the dalpha
 // epilogue when p1.partial is set), then those of p2.  Small products that
 // give one tile per CU each get two co-resident workgroups per CU this way.
-template <int TM, int TN, int TK, int WM, int WN, int NST>
-__global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST>::NW * kWave))
-    __attribute__((amdgpu_waves_per_eu(1, (Bf16DmaShape<TM, TN, TK, WM, WN, NST>::kMaxWaves))))
+template <int TM, int TN, int TK, int WM, int WN, int NST, bool X3>
+__global__ void __launch_bounds__((Bf16DmaShape<TM, TN, TK, WM, WN, NST, X3>::NW * kWave))
+    __attribute__((amdgpu_waves_per_eu(1, (Bf16DmaShape<TM, TN, TK, WM, WN, NST, X3>::kMaxWaves))))
     sgemm_bf16_dma_pair(StagedArgs p1, StagedArgs p2) {
   extern __shared__ __align__(16) char smem[];
   const int n1 = p1.tiles_m * p1.tiles_n;
   const int t = blockIdx.x;
   if (t < n1) {
-    if (p1.partial) bf16_dma_tile<TM, TN, TK, WM, WN, NST, 1>(p1, t, smem);
-    else bf16_dma_tile<TM, TN, TK, WM, WN, NST, 0>(p1, t, smem);
+    if (p1.partial) bf16_dma_tile<TM, TN, TK, WM, WN, NST, 1, X3>(p1, t, smem);
+    else bf16_dma_tile<TM, TN, TK, WM, WN, NST, 0, X3>(p1, t, smem);
   } else {
-    bf16_dma_tile<TM, TN, TK, WM, WN, NST, 0>(p2, t - n1, smem);
+    bf16_dma_tile<TM, TN, TK, WM, WN, NST, 0, X3>(p2, t - n1, smem);
   }
 }
 
@@ -783,10 +816,11 @@ struct StagedConfig {
    &StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::launch,                                                  \
    &StagedConfig<TM, TN, TK, WM, WN, X3, PIPE>::launch_planes}
 
-// BF16 on the DMA-fed kernel (NST LDS stages); same planes and workspace.
-template <int TM, int TN, int TK, int WM, int WN, int NST>
+// BF16 and bf16x3 on the DMA-fed kernel (NST LDS stages); same planes and
+// workspace as the other staged entries.
+template <int TM, int TN, int TK, int WM, int WN, int NST, bool X3>
 struct DmaConfig {
-  using S = Bf16DmaShape<TM, TN, TK, WM, WN, NST>;
+  using S = Bf16DmaShape<TM, TN, TK, WM, WN, NST, X3>;
   static constexpr int kThreads = S::NW * kWave;
   static_assert(kPadMN % TM == 0 && kPadMN % TN == 0 && kPadK % TK == 0, "padding covers the tile");
 
@@ -794,7 +828,7 @@ struct DmaConfig {
   static hipError_t gemm(const GemmArgs& a, const StagedPlanes& P, const float* aorig, int64_t lda_orig,
                          float* partial, hipStream_t s) {
     StagedArgs p = staged_args(a, P, TM, TN, TK, aorig, lda_orig, partial);
-    auto* fn = &sgemm_bf16_dma<TM, TN, TK, WM, WN, NST, EPI>;
+    auto* fn = &sgemm_bf16_dma<TM, TN, TK, WM, WN, NST, EPI, X3>;
     hipError_t e = allow_lds_staged(fn, (size_t)S::kLdsBytes);
     if (e != hipSuccess) return e;
     void* kargs[] = {&p};
@@ -802,11 +836,11 @@ struct DmaConfig {
                            dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
   }
   static hipError_t launch(const GemmArgs& a, void* workspace, hipStream_t s) {
-    const StagedLayout L = staged_layout(HPVM_PREC_BF16, a.m, a.n, a.k);
+    const StagedLayout L = staged_layout(X3 ? HPVM_PREC_BF16X3 : HPVM_PREC_BF16, a.m, a.n, a.k);
     char* ws = reinterpret_cast<char*>(workspace);
-    hipError_t e = stage_operands<false>(a, L, ws, s);
+    hipError_t e = stage_operands<X3>(a, L, ws, s);
     if (e != hipSuccess) return e;
-    return gemm<0>(a, planes_in<false>(L, ws), nullptr, 0, nullptr, s);
+    return gemm<0>(a, planes_in<X3>(L, ws), nullptr, 0, nullptr, s);
   }
   static hipError_t launch_planes(const GemmArgs& a, const StagedPlanes& P, const float* aorig, int64_t lda_orig,
                                   float* partial, hipStream_t s) {
@@ -816,7 +850,7 @@ struct DmaConfig {
                                 float* partial, const GemmArgs& a2, const StagedPlanes& P2, hipStream_t s) {
     StagedArgs p1 = staged_args(a1, P1, TM, TN, TK, aorig, lda_orig, partial);
     StagedArgs p2 = staged_args(a2, P2, TM, TN, TK, nullptr, 0, nullptr);
-    auto* fn = &sgemm_bf16_dma_pair<TM, TN, TK, WM, WN, NST>;
+    auto* fn = &sgemm_bf16_dma_pair<TM, TN, TK, WM, WN, NST, X3>;
     hipError_t e = allow_lds_staged(fn, (size_t)S::kLdsBytes);
     if (e != hipSuccess) return e;
     void* kargs[] = {&p1, &p2};
@@ -826,10 +860,12 @@ struct DmaConfig {
   }
 };
 
-#define HPVM_DMA_ENTRY(NST, TM, TN, TK, WM, WN)                                                          \
-  {{TM, TN, TK, WM, WN, 3}, HPVM_PREC_BF16, DmaConfig<TM, TN, TK, WM, WN, NST>::kThreads,               \
-   DmaConfig<TM, TN, TK, WM, WN, NST>::S::kLdsBytes, nullptr, &DmaConfig<TM, TN, TK, WM, WN, NST>::launch, \
-   &DmaConfig<TM, TN, TK, WM, WN, NST>::launch_planes, &DmaConfig<TM, TN, TK, WM, WN, NST>::launch_pair}
+#define HPVM_DMA_ENTRY_P(PREC, X3, NST, TM, TN, TK, WM, WN)                                               \
+  {{TM, TN, TK, WM, WN, 3}, PREC, DmaConfig<TM, TN, TK, WM, WN, NST, X3>::kThreads,                      \
+   DmaConfig<TM, TN, TK, WM, WN, NST, X3>::S::kLdsBytes, nullptr,                                          \
+   &DmaConfig<TM, TN, TK, WM, WN, NST, X3>::launch, &DmaConfig<TM, TN, TK, WM, WN, NST, X3>::launch_planes, \
+   &DmaConfig<TM, TN, TK, WM, WN, NST, X3>::launch_pair}
+#define HPVM_DMA_ENTRY(NST, TM, TN, TK, WM, WN) HPVM_DMA_ENTRY_P(HPVM_PREC_BF16, false, NST, TM, TN, TK, WM, WN)
 
 const MfmaEntry kStagedMenuBf16[] = {
     HPVM_DMA_ENTRY(2, 256, 256, 64, 128, 64),
@@ -839,9 +875,10 @@ const MfmaEntry kStagedMenuBf16[] = {
     HPVM_DMA_ENTRY(2, 128, 128, 64, 64, 32),
 };
 const MfmaEntry kStagedMenuBf16x3[] = {
-    HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, false, 256, 256, 32, 128, 64),
+    HPVM_DMA_ENTRY_P(HPVM_PREC_BF16X3, true, 2, 256, 256, 32, 128, 64),
     HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, true, 256, 128, 32, 128, 64),
     HPVM_STAGED_ENTRY(HPVM_PREC_BF16X3, true, true, 128, 128, 64, 64, 64),
+    HPVM_DMA_ENTRY_P(HPVM_PREC_BF16X3, true, 2, 128, 128, 64, 64, 32),
 };
 
 }  // namespace
