@@ -192,7 +192,9 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A,
  * workspace: device memory, 16-byte aligned, at least
  * hpvm_sgemm_workspace_bytes(m, n, k, prec, tile) bytes (may be NULL when
  * that is 0); its contents are scratch.  tile == NULL takes the autotuned
- * overall winner.  Every other argument and rule is hpvm_sgemm's.          */
+ * overall winner; with no autotuned entry, BF16 and bf16x3 products of at
+ * least 2^31 multiply-adds (m n k) take the first staged tile, others the
+ * menu's entry 0.  Every other argument and rule is hpvm_sgemm's.          */
 int hpvm_sgemm_ws(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
                   const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
                   const hpvm_tile* tile, void* workspace, int64_t workspace_bytes, void* stream);

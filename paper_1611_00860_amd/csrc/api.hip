@@ -152,6 +152,20 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
   return HPVM_OK;
 }
 
+// Built-in choice of hpvm_sgemm_ws (and of hpvm_sgemm_workspace_bytes) for
+// tile == NULL when the autotuner has no entry: BF16 and bf16x3 products of
+// at least 2^31 multiply-adds take the first staged tile, whose conversion
+// pass is then a small share of the time; everything else keeps the menu's
+// entry 0.  Returns false for the latter.
+bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
+  if (prec != HPVM_PREC_BF16 && prec != HPVM_PREC_BF16X3) return false;
+  if ((double)m * (double)n * (double)k < 2147483648.0 || !hpvm::staged_k_ok(k)) return false;
+  const hpvm::MfmaEntry* staged = nullptr;
+  if (hpvm::staged_menu(prec, &staged) == 0) return false;
+  *out = staged[0].tile;
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -270,6 +284,7 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 12: unknown precision %d", prec);
   hpvm_tile tuned;
   if (!tile && hpvm::tuned_tile(prec, m, n, k, ws_ok, &tuned)) tile = &tuned;
+  else if (!tile && ws_ok && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   rc = resolve(prec, tile, &entry, 13);
   if (rc != HPVM_OK) return rc;
@@ -341,6 +356,7 @@ int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, co
   if (!bytes) return fail(HPVM_INVALID_ARG, "argument 6: bytes is NULL");
   hpvm_tile tuned;
   if (!tile && hpvm::tuned_tile(prec, m, n, k, true, &tuned)) tile = &tuned;
+  else if (!tile && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   int rc = resolve(prec, tile, &entry, 5);
   if (rc != HPVM_OK) return rc;

@@ -363,6 +363,19 @@ def test_backward_validation(lib):
         del os.environ["HPVM_FAULT_INJECT"]
 
 
+def test_default_tile_with_a_workspace(lib):
+    """Without an autotuned entry, a workspace-capable BF16 / bf16x3 call with
+    no tile takes the first staged tile once m n k reaches 2^31, else the
+    menu's entry 0 (which needs no workspace); FP32 never needs one."""
+    hp.autotune_clear()
+    for prec in ("bf16", "bf16x3"):
+        staged = [t for t in hp.tile_menu(prec) if t[5] == 3]
+        big = (2048, 1024, 1024)  # 2^31 multiply-adds
+        assert hp.workspace_bytes(*big, prec, None) == hp.workspace_bytes(*big, prec, staged[0]) > 0
+        assert hp.workspace_bytes(2048, 1024, 1023, prec, None) == 0
+    assert hp.workspace_bytes(8192, 8192, 8192, "fp32", None) == 0
+
+
 def test_staged_workspace_rules(lib):
     BIG = 1 << 24  # far enough apart that no two matrices overlap
     for prec, planes in (("bf16", 1), ("bf16x3", 2)):

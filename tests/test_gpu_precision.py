@@ -121,3 +121,24 @@ def test_full_size_8192_sampled(gpu, dist):
         terms = 3 * n if prec == "bf16x3" else n
         bound = 2 * (terms + 2) * 2.0 ** -24 * ab * (1 + 2.0 ** -7)
         assert np.all(np.abs(got - split) <= bound), prec
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_default_tile_is_staged_for_large_products(gpu, prec):
+    """With no tile and no autotuned entry, a product of at least 2^31
+    multiply-adds runs the first staged tile (through a workspace): the same
+    bits as naming that tile, and within the precision's bound."""
+    import torch
+
+    gpu.autotune_clear()
+    m, n, k = 1536, 1536, 1024
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=37)
+    staged = [t for t in gpu.tile_menu(prec) if t[5] == 3][0]
+    print(f"case: default tile {prec} {m}x{n}x{k}", flush=True)
+    C1, C2 = to_dev(C), to_dev(C)
+    gpu.sgemm(to_dev(A), to_dev(B), C1, 1.0, 0.5, prec=prec)
+    gpu.sgemm(to_dev(A), to_dev(B), C2, 1.0, 0.5, prec=prec, tile=staged)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    ref = oracle.sgemm(A, B, C, 1.0, 0.5)
+    assert normwise(to_host(C1), ref) <= (1e-2 if prec == "bf16" else 1e-5)
