@@ -13,7 +13,14 @@
 // few outputs next to their long contractions (m x k and k x n against n and
 // m), so big tiles alone would leave most CUs idle.  Each slice writes its
 // raw partial tile to the workspace; one pass then sums the slices in order,
-// scales by alpha and forms dalpha's partials.
+// scales by alpha and forms dalpha's partials.  When both gradients are
+// wanted, their slices run in one launch and their sums with grad_c in
+// another.
+//
+// Staged (BF16, bf16x3) entries convert everything first, in one launch: a
+// single pass over G writes its bfloat16 planes for both products together
+// with dC_in and dbeta's partials, beside B's and A's conversions; both
+// products then run in one launch when the entry has the paired kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -261,8 +268,8 @@ namespace {
 
 // One candidate tile of the backward.  Fused entries run dA through
 // sgemm_grad_a and dB through the fused menu entry's launch; staged entries
-// run both through the staged lowering (conversion pass into the workspace,
-// with the transposition of each operand folded into it).
+// run both through the staged lowering (one conversion launch into the
+// workspace, with the transposition of each operand folded into it).
 struct BwdEntry {
   hpvm_tile tile;
   int32_t prec;

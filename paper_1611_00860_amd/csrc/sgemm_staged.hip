@@ -9,11 +9,13 @@
 //   B (k x n)  -> Bh[, Bl]  [n_pad][k_pad], k contiguous (B transposed);
 // zero-padded to whole 256 x 64 blocks, with hi = bf16(x) and, for bf16x3,
 // lo = bf16(x - hi).  The GEMM then moves 16-byte units with no edge checks:
-// for BF16 straight from HBM into a ring of LDS stages (sgemm_bf16_dma), for
-// bf16x3 through registers two K-slabs ahead of the LDS stage being
-// multiplied (sgemm_bf16_staged).  The hierarchy is the same as in the other
-// lowerings: one workgroup per SgemmInternal instance, the Allocation node as
-// LDS stages, SgemmLeaf outputs as MFMA accumulators.
+// straight from HBM into a ring of LDS stages (sgemm_bf16_dma, BF16 and
+// bf16x3), or for some bf16x3 tiles through registers two K-slabs ahead of
+// the LDS stage being multiplied (sgemm_bf16_staged).  The hierarchy is the
+// same as in the other lowerings: one workgroup per SgemmInternal instance,
+// the Allocation node as LDS stages, SgemmLeaf outputs as MFMA accumulators.
+// The backward's conversions (stage_backward) and its paired products
+// (sgemm_bf16_dma_pair) live here too.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
