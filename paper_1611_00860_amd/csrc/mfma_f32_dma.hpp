@@ -20,9 +20,13 @@
 //     32 V consecutive m (or n) as V phases, and a fragment is one read of V
 //     adjacent values at the k of step p (component t = phase t, which owns
 //     the values t, t + V, t + 2V, ...).
-// Whole tiles only: every access is in bounds because m, n and k are
-// multiples of the tile (the caller checks; other problems take the masked
-// loop of mfma_f32.hpp).
+// m and n need not be multiples of the tile when they are at least one tile
+// (and n a multiple of 4): a tile that would cross the edge is moved inward
+// to end at it, so every load stays inside the matrices, and it stores only
+// the rows and columns it owns (those of its place in the tile grid); the
+// rows and columns it overlaps belong to the neighbouring tile, which
+// computes them the same way.  k must be a multiple of the slab (the caller
+// checks; other problems take the masked loop of mfma_f32.hpp).
 #pragma once
 
 #include "device_common.hpp"
@@ -164,7 +168,10 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
   const int half = PAIR ? wcol / TN : 0;  // which output this wave's columns belong to
   const int wn0 = wcol - half * TN;
   const int splits = MODE == kDmaSplit ? o.splits : 1;
-  const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TN;
+  // The tile's own corner, and the corner it computes from (moved inward at
+  // the edges; the same for whole tiles).
+  const int64_t m_own = (int64_t)tm * TM, n_own = (int64_t)tn * TN;
+  const int64_t m0 = m_own + TM > p.m ? p.m - TM : m_own, n0 = n_own + TN > p.n ? p.n - TN : n_own;
   const int slabs_all = p.k / TK;
   const int per = (slabs_all + splits - 1) / splits;
   const int sbeg = z * per, slabs = (slabs_all - sbeg < per ? slabs_all - sbeg : per);
@@ -260,6 +267,7 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
     // access per row.  A group of 4 rows loads its C values first.
     using VB = typename OB::Frag;
     const int64_t col = n0 + OB::index(0, I, wn0);
+    const bool col_own = col >= n_own;  // the lane's NB columns are owned together (n % 4 == 0)
     VB bias{};
     if constexpr (MODE == kDmaConsume && kBias) {
 #pragma unroll
@@ -273,7 +281,7 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-          if (read_c) c[u] = *reinterpret_cast<const VB*>(cin + i * q.ldc + col);
+          if (read_c && col_own && i >= m_own) c[u] = *reinterpret_cast<const VB*>(cin + i * q.ldc + col);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -285,7 +293,7 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
             if (read_c) v[b] = fmaf(q.beta, c[u][b], v[b]);
             if constexpr (MODE == kDmaConsume) v[b] = consume<OP>(v[b], bias[b], o.lo, o.hi);
           }
-          *reinterpret_cast<VB*>(out + i * ldo + col) = v;
+          if (col_own && i >= m_own) *reinterpret_cast<VB*>(out + i * ldo + col) = v;
         }
       }
   } else {
@@ -300,14 +308,14 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-            c[u] = read_c ? cin[i * q.ldc + col] : 0.0f;
+            c[u] = (read_c && col >= n_own && i >= m_own) ? cin[i * q.ldc + col] : 0.0f;
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
             float v = alpha * acc[a][b][4 * g + u];
             if (read_c) v = fmaf(q.beta, c[u], v);
-            out[i * ldo + col] = v;
+            if (col >= n_own && i >= m_own) out[i * ldo + col] = v;
           }
         }
   }
@@ -335,6 +343,15 @@ template <int TM, int TN, int TK>
 inline bool f32_dma_fits(const GemmArgs& a, const void* out, int64_t ldo, int splits) {
   return a.vec_a && a.vec_b && a.m > 0 && a.n > 0 && a.k > 0 && a.m % TM == 0 && a.n % TN == 0 &&
          a.k % (TK * splits) == 0 && ldo % 4 == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+}
+
+// True when the DMA-fed loop covers the problem with edge tiles moved
+// inward (see the top of this file): at least one tile each way, n a
+// multiple of 4, k a multiple of the slab, alignment as f32_dma_fits.
+template <int TM, int TN, int TK>
+inline bool f32_dma_fits_edges(const GemmArgs& a, const void* out, int64_t ldo) {
+  return a.vec_a && a.vec_b && a.m >= TM && a.n >= TN && a.n % 4 == 0 && a.k > 0 && a.k % TK == 0 &&
+         ldo % 4 == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
 }
 
 }  // namespace hpvm

@@ -49,14 +49,15 @@ __device__ __forceinline__ void grouped_tile(const GemmArgs& p, int tm, int tn, 
                             tn * TN + (wave % (TN / WN)) * WN, lane);
 }
 
-// Interior 128 x 128 tiles of instances whose k is a multiple of 16 and
-// whose rows are 16-byte aligned take the DMA-fed loop: four waves of
-// 32 x 128, 16-deep slabs in two 16 KB stages.
+// 128 x 128 tiles of instances at least 128 x 128 with k a multiple of 16,
+// n a multiple of 4 and rows 16-byte aligned take the DMA-fed loop (edge
+// tiles moved inward, mfma_f32_dma.hpp): four waves of 32 x 128, 16-deep
+// slabs in two 16 KB stages.
 using GroupedDma = F32DmaShape<128, 128, 16, 32, 128, false, false, 2>;
 static_assert(GroupedDma::NW * kWave == kGroupedThreads && GroupedDma::kLdsBytes <= kGroupedLds, "DMA tile fits");
 
-__device__ __forceinline__ bool grouped_dma_ok(const GemmArgs& p, int tm, int tn) {
-  return p.vec_a && p.vec_b && p.k > 0 && p.k % 16 == 0 && (tm + 1) * 128 <= p.m && (tn + 1) * 128 <= p.n &&
+__device__ __forceinline__ bool grouped_dma_ok(const GemmArgs& p) {
+  return p.vec_a && p.vec_b && p.k > 0 && p.k % 16 == 0 && p.m >= 128 && p.n >= 128 && p.n % 4 == 0 &&
          p.ldc % 4 == 0 && (reinterpret_cast<uintptr_t>(p.C) & 15) == 0;
 }
 
@@ -67,7 +68,7 @@ __device__ __forceinline__ void run_shape_tile(int shape, const GemmArgs& p, int
   const int tm = local / tiles_n, tn = local - (local / tiles_n) * tiles_n;
   switch (shape) {
     case 0:
-      if (grouped_dma_ok(p, tm, tn)) {
+      if (grouped_dma_ok(p)) {
         F32DmaOut o{};
         o.splits = 1;
         f32_dma_tile<128, 128, 16, 32, 128, false, false, 2, kDmaUpdate>(p, p, o, tm, tn, 0,

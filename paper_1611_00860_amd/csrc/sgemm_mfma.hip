@@ -111,20 +111,21 @@ struct Bf16Config {
   {{TM, TN, TK, WM, WN, 2}, HPVM_PREC_FP32, F32Config<TM, TN, TK, WM, WN>::kThreads,     \
    F32Config<TM, TN, TK, WM, WN>::lds(false, false), &F32Config<TM, TN, TK, WM, WN>::launch}
 
-// Whole-tile FP32 problems (m, n, k multiples of the tile, every row
-// 16-byte aligned, no transposed operand) take the DMA-fed loop
-// (mfma_f32_dma.hpp) with 128-wide wave tiles; any other problem the
-// general 128 x 128 x 16 tile.
+// FP32 problems of at least one tile each way with k a multiple of the
+// slab, n a multiple of 4, every row 16-byte aligned and no transposed
+// operand take the DMA-fed loop (mfma_f32_dma.hpp; edge tiles moved inward)
+// with 128-wide wave tiles; any other problem the general 128 x 128 x 16
+// tile.
 template <int TM, int TN, int TK, int WM, int NST>
 struct F32DmaConfig {
   using S = F32DmaShape<TM, TN, TK, WM, 128, false, false, NST>;
   static constexpr int kThreads = S::NW * kWave;
   static hipError_t launch(const GemmArgs& args, bool at, bool bt, hipStream_t s) {
-    if (at || bt || !f32_dma_fits<TM, TN, TK>(args, args.C, args.ldc, 1))
+    if (at || bt || !f32_dma_fits_edges<TM, TN, TK>(args, args.C, args.ldc))
       return F32Config<128, 128, 16, 64, 64>::launch(args, at, bt, s);
     GemmArgs a = args;
-    a.tiles_m = a.m / TM;
-    a.tiles_n = a.n / TN;
+    a.tiles_m = (a.m + TM - 1) / TM;
+    a.tiles_n = (a.n + TN - 1) / TN;
     GemmArgs unused = a;
     F32DmaOut o{};
     o.splits = 1;

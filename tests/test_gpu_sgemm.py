@@ -168,3 +168,46 @@ def test_f32_full_size_sampled(gpu, m, n, k, beta):
     ab = np.abs(A[rows].astype(np.float64)) * np.abs(B[:, cols].T.astype(np.float64))
     bound = 2 * (k + 2) * 2.0 ** -24 * ab.sum(axis=1) + 4 * 2.0 ** -24 * abs(beta) * np.abs(C[rows, cols])
     assert np.all(np.abs(g - ref) <= bound)
+
+
+# ---------------------------------------------------------------------------
+# DMA-fed FP32 tiles on problems that are not whole tiles: a tile that would
+# cross the edge is moved inward and stores only the rows and columns it
+# owns, so overlapped outputs are neither computed from outside the
+# matrices nor given beta * C twice.
+# ---------------------------------------------------------------------------
+EDGE_SHAPES = [(300, 520, 96), (257, 260, 64), (511, 1000, 32), (256, 300, 2048), (1000, 256, 160)]
+
+
+@pytest.mark.parametrize("m,n,k", EDGE_SHAPES)
+def test_f32_dma_edge_tiles_integers(gpu, m, n, k):
+    """Integer inputs, beta = 2: exact, with NaN-filled row padding (a read
+    outside a matrix would poison the result) and, for beta = 0, a NaN-filled
+    C that must be overwritten, never read."""
+    dma = [t for t in gpu.tile_menu("fp32") if t[4] == 128]
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=41, dist="int")
+    ref = oracle.sgemm(A, B, C, 1.0, 2.0)
+    for tile in dma:
+        print(f"case: fp32 dma edge {m}x{n}x{k} tile {tile}", flush=True)
+        got = run(gpu, A, B, C, 1.0, 2.0, tile=tile, pad=4)
+        assert np.array_equal(got, ref), tile
+    nan_c = np.full_like(C, np.nan)
+    got0 = run(gpu, A, B, nan_c, 1.0, 0.0, tile=dma[0], pad=4)
+    assert np.array_equal(got0, oracle.sgemm(A, B, None, 1.0, 0.0))
+
+
+def test_f32_dma_edge_tiles_match_whole_tile_bits(gpu):
+    """Uniform inputs: every output of a ragged problem equals, bit for bit,
+    the same output computed inside a whole-tile problem that holds it (an
+    edge tile moved inward computes each of its outputs in the same order as
+    any tile)."""
+    import torch
+
+    m, n, k = 300, 520, 96
+    A, B, C = inputs.sgemm_operands(512, 768, k, seed=43)
+    tile = gpu.tile_menu("fp32")[0]
+    big = run(gpu, A, B, C, 1.0, 0.5, tile=tile)
+    small = run(gpu, np.ascontiguousarray(A[:m]), B[:, :n].copy(), C[:m, :n].copy(), 1.0, 0.5, tile=tile)
+    assert np.array_equal(small, big[:m, :n])
+    ref = oracle.sgemm(np.ascontiguousarray(A[:m]), B[:, :n].copy(), C[:m, :n].copy(), 1.0, 0.5)
+    assert normwise(small, ref) <= 1e-5
