@@ -174,9 +174,11 @@ typedef struct hpvm_edge {
  *                  when the matrix is not read or written.
  *   prec         : hpvm_precision.
  *   tile         : hierarchy shape, or NULL to take the autotuned choice for
- *                  this shape class (the built-in default until
- *                  hpvm_autotune has run).  Must be in hpvm_tile_menu for
- *                  prec and not need a workspace (stages != 3).
+ *                  this shape class (until hpvm_autotune has run, the
+ *                  built-in default: the menu's entry 0, or for FP32 entry 1
+ *                  when entry 0 would give fewer than 128 tiles).  Must be
+ *                  in hpvm_tile_menu for prec and not need a workspace
+ *                  (stages != 3).
  *   stream       : hipStream_t or NULL.
  * Returns HPVM_OK once the work is enqueued.  The MFMA lowerings use 16-byte
  * vector loads where A, B, C and their leading dimensions allow and scalar
@@ -237,7 +239,8 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec,
 int hpvm_dfg_edges(hpvm_edge* out, int32_t capacity, int32_t* count);
 
 /* Compiled tiles for `prec`: writes at most `capacity` entries, total count
- * to *count.  Entry 0 is the default when no tile is given.                */
+ * to *count.  Entry 0 is the default when no tile is given (see
+ * hpvm_sgemm for the exceptions).                                           */
 int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity,
                    int32_t* count);
 

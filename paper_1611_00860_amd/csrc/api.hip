@@ -157,6 +157,21 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
 // at least 2^31 multiply-adds take the first staged tile, whose conversion
 // pass is then a small share of the time; everything else keeps the menu's
 // entry 0.  Returns false for the latter.
+// Built-in FP32 choice for tile == NULL when the autotuner has no entry: the
+// menu's entry 0 (256 x 256 DMA-fed tiles) when it gives at least 128 tiles
+// (half a tile per CU of a 256-CU part), else entry 1 (128 x 128 x 16),
+// which gives four times as many.  Returns false for the former.
+bool default_fp32_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
+  if (prec != HPVM_PREC_FP32) return false;
+  const hpvm::MfmaEntry* e0 = hpvm::menu_entry_at(prec, 0);
+  const hpvm::MfmaEntry* e1 = hpvm::menu_entry_at(prec, 1);
+  if (!e0 || !e1) return false;
+  const int64_t tiles = ((m + e0->tile.tile_m - 1) / e0->tile.tile_m) * ((n + e0->tile.tile_n - 1) / e0->tile.tile_n);
+  if (tiles >= 128) return false;
+  *out = e1->tile;
+  return true;
+}
+
 bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
   if (prec != HPVM_PREC_BF16 && prec != HPVM_PREC_BF16X3) return false;
   if ((double)m * (double)n * (double)k < 2147483648.0 || !hpvm::staged_k_ok(k)) return false;
@@ -215,6 +230,8 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile
   if (k < 0) return fail(HPVM_INVALID_ARG, "argument 3: k = %lld < 0", (long long)k);
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
   if (!out) return fail(HPVM_INVALID_ARG, "argument 6: out is NULL");
+  hpvm_tile small;
+  if (!tile && default_fp32_tile(prec, m, n, &small)) tile = &small;
   const hpvm::MfmaEntry* e;
   int rc = resolve(prec, tile, &e, 5);
   if (rc != HPVM_OK) return rc;
@@ -285,6 +302,7 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   hpvm_tile tuned;
   if (!tile && hpvm::tuned_tile(prec, m, n, k, ws_ok, &tuned)) tile = &tuned;
   else if (!tile && ws_ok && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
+  else if (!tile && default_fp32_tile(prec, m, n, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   rc = resolve(prec, tile, &entry, 13);
   if (rc != HPVM_OK) return rc;

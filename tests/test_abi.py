@@ -376,6 +376,17 @@ def test_default_tile_with_a_workspace(lib):
     assert hp.workspace_bytes(8192, 8192, 8192, "fp32", None) == 0
 
 
+def test_default_fp32_tile_for_small_problems(lib):
+    """Without an autotuned entry the FP32 default is the menu's entry 0
+    unless that gives fewer than 128 tiles; then the 128 x 128 x 16 entry."""
+    hp.autotune_clear()
+    menu = hp.tile_menu("fp32")
+    big = hp.describe(4096, 4096, 1024, "fp32", None)
+    assert (big["grid_x"], big["grid_y"]) == (4096 // menu[0][1], 4096 // menu[0][0])
+    small = hp.describe(1000, 1000, 1024, "fp32", None)
+    assert (small["grid_x"], small["grid_y"]) == (-(-1000 // menu[1][1]), -(-1000 // menu[1][0]))
+
+
 def test_staged_workspace_rules(lib):
     BIG = 1 << 24  # far enough apart that no two matrices overlap
     for prec, planes in (("bf16", 1), ("bf16x3", 2)):
