@@ -265,8 +265,9 @@ struct PairConfig {
   }
 };
 
-// Whole, aligned tiles of the consumer on the DMA-fed loop (the consumer
-// applied in its epilogue); any other problem on the 128 x 128 x 16 tile.
+// Aligned problems of at least one tile each way (edge tiles moved inward)
+// of the consumer on the DMA-fed loop (the consumer applied in its
+// epilogue); any other problem on the 128 x 128 x 16 tile.
 template <int TM, int TN, int TK, int WM, int NST>
 struct ConsumerDmaConfig {
   using S = F32DmaShape<TM, TN, TK, WM, 128, false, false, NST>;
@@ -284,11 +285,11 @@ struct ConsumerDmaConfig {
   }
   static hipError_t launch(const GemmArgs& args, const ConsumerArgs& c, hipStream_t s) {
     const bool c_ok = args.beta == 0.0f || (args.ldc % 4 == 0 && (reinterpret_cast<uintptr_t>(args.C) & 15) == 0);
-    if (!c_ok || !f32_dma_fits<TM, TN, TK>(args, c.D, c.ldd, 1))
+    if (!c_ok || !f32_dma_fits_edges<TM, TN, TK>(args, c.D, c.ldd))
       return ConsumerConfig<128, 128, 16, 64, 64>::launch(args, c, s);
     GemmArgs a = args;
-    a.tiles_m = a.m / TM;
-    a.tiles_n = a.n / TN;
+    a.tiles_m = (a.m + TM - 1) / TM;
+    a.tiles_n = (a.n + TN - 1) / TN;
     F32DmaOut o{};
     o.splits = 1;
     o.D = c.D;
@@ -306,20 +307,20 @@ struct ConsumerDmaConfig {
   }
 };
 
-// Whole, aligned tiles of the pair on the DMA-fed loop: per stage one A slab
-// and both B slabs (B1's tile, then B2's); any other problem on the
-// 128 x 128 x 16 pair tile.
+// Aligned problems of at least one tile each way (edge tiles moved inward)
+// of the pair on the DMA-fed loop: per stage one A slab and both B slabs
+// (B1's tile, then B2's); any other problem on the 128 x 128 x 16 pair tile.
 template <int TM, int TN, int TK, int WM, int NST>
 struct PairDmaConfig {
   using S = F32DmaShape<TM, TN, TK, WM, 128, false, false, NST, true>;
   static constexpr int kThreads = S::NW * kWave;
   static hipError_t launch(const GemmArgs& a1, const GemmArgs& a2, hipStream_t s) {
-    const bool ok = f32_dma_fits<TM, TN, TK>(a1, a1.C, a1.ldc, 1) && a2.vec_b && a2.ldc % 4 == 0 &&
+    const bool ok = f32_dma_fits_edges<TM, TN, TK>(a1, a1.C, a1.ldc) && a2.vec_b && a2.ldc % 4 == 0 &&
                     (reinterpret_cast<uintptr_t>(a2.C) & 15) == 0;
     if (!ok) return PairConfig<128, 128, 16, 64, 64>::launch(a1, a2, s);
     GemmArgs p1 = a1, p2 = a2;
-    p1.tiles_m = p2.tiles_m = p1.m / TM;
-    p1.tiles_n = p2.tiles_n = p1.n / TN;
+    p1.tiles_m = p2.tiles_m = (p1.m + TM - 1) / TM;
+    p1.tiles_n = p2.tiles_n = (p1.n + TN - 1) / TN;
     F32DmaOut o{};
     o.splits = 1;
     void* kargs[] = {&p1, &p2, &o};

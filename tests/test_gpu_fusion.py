@@ -16,7 +16,7 @@ from gpu_util import normwise, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 OPS = ["none", "relu", "bias", "bias_relu", "clamp"]
-SHAPES = [(300, 260, 200), (129, 257, 77), (1, 1, 1), (256, 256, 64)]
+SHAPES = [(300, 260, 200), (129, 257, 77), (1, 1, 1), (256, 256, 64), (300, 520, 96)]
 
 
 def bias_for(n, seed):
