@@ -73,7 +73,7 @@ def fp32_kernel_name(tile, m, n, k):
     """The kernel an FP32 menu tile launches for a row-major problem with aligned operands."""
     tm, tn, tk, lm, ln, st = tile
     if ln == 128 and m % tm == 0 and n % tn == 0 and k % tk == 0:
-        return f"sgemm_f32_dma<{tm}, {tn}, {tk}, {lm}, 128, false, false, {st}, 0, 0, false>"
+        return f"sgemm_f32_dma<{tm}, {tn}, {tk}, {lm}, 128, false, false, {st}, 0, 0, false, false>"
     if ln == 128:
         tm, tn, tk, lm, ln = 128, 128, 16, 64, 64
     return f"sgemm_mfma_f32<{tm}, {tn}, {tk}, {lm}, {ln}, false, false>"

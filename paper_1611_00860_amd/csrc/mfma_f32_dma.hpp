@@ -20,13 +20,15 @@
 //     32 V consecutive m (or n) as V phases, and a fragment is one read of V
 //     adjacent values at the k of step p (component t = phase t, which owns
 //     the values t, t + V, t + 2V, ...).
-// m and n need not be multiples of the tile when they are at least one tile
-// (and n a multiple of 4): a tile that would cross the edge is moved inward
-// to end at it, so every load stays inside the matrices, and it stores only
-// the rows and columns it owns (those of its place in the tile grid); the
-// rows and columns it overlaps belong to the neighbouring tile, which
-// computes them the same way.  k must be a multiple of the slab (the caller
-// checks; other problems take the masked loop of mfma_f32.hpp).
+// With EDGES, m and n need not be multiples of the tile when they are at
+// least one tile (and n a multiple of 4): a tile that would cross the edge
+// is moved inward to end at it, so every load stays inside the matrices,
+// and it stores only the rows and columns it owns (those of its place in
+// the tile grid); the rows and columns it overlaps belong to the
+// neighbouring tile, which computes them the same way.  Without EDGES the
+// problem is whole tiles and the epilogue has no masks.  k must be a
+// multiple of the slab (the caller checks; other problems take the masked
+// loop of mfma_f32.hpp).
 #pragma once
 
 #include "device_common.hpp"
@@ -153,7 +155,7 @@ struct F32DmaOut {
 // beta2; the rest as p), ignored otherwise.  Ends with every transfer
 // drained and the workgroup past a barrier, so smem may be reused at once.
 template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, int NST, int MODE, int OP = 0,
-          bool PAIR = false>
+          bool PAIR = false, bool EDGES = false>
 __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& p2, const F32DmaOut& o, int tm,
                                              int tn, int z, char* smem) {
   using S = F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>;
@@ -168,10 +170,12 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
   const int half = PAIR ? wcol / TN : 0;  // which output this wave's columns belong to
   const int wn0 = wcol - half * TN;
   const int splits = MODE == kDmaSplit ? o.splits : 1;
-  // The tile's own corner, and the corner it computes from (moved inward at
-  // the edges; the same for whole tiles).
+  // The tile's own corner, and the corner it computes from: with EDGES, a
+  // tile that would cross the edge is moved inward; without, every tile is
+  // whole and the two are the same (no masks in the epilogue).
   const int64_t m_own = (int64_t)tm * TM, n_own = (int64_t)tn * TN;
-  const int64_t m0 = m_own + TM > p.m ? p.m - TM : m_own, n0 = n_own + TN > p.n ? p.n - TN : n_own;
+  const int64_t m0 = EDGES && m_own + TM > p.m ? p.m - TM : m_own;
+  const int64_t n0 = EDGES && n_own + TN > p.n ? p.n - TN : n_own;
   const int slabs_all = p.k / TK;
   const int per = (slabs_all + splits - 1) / splits;
   const int sbeg = z * per, slabs = (slabs_all - sbeg < per ? slabs_all - sbeg : per);
@@ -267,7 +271,7 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
     // access per row.  A group of 4 rows loads its C values first.
     using VB = typename OB::Frag;
     const int64_t col = n0 + OB::index(0, I, wn0);
-    const bool col_own = col >= n_own;  // the lane's NB columns are owned together (n % 4 == 0)
+    const bool col_own = !EDGES || col >= n_own;  // the lane's NB columns are owned together (n % 4 == 0)
     VB bias{};
     if constexpr (MODE == kDmaConsume && kBias) {
 #pragma unroll
@@ -281,7 +285,7 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-          if (read_c && col_own && i >= m_own) c[u] = *reinterpret_cast<const VB*>(cin + i * q.ldc + col);
+          if (read_c && col_own && (!EDGES || i >= m_own)) c[u] = *reinterpret_cast<const VB*>(cin + i * q.ldc + col);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -293,7 +297,7 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
             if (read_c) v[b] = fmaf(q.beta, c[u][b], v[b]);
             if constexpr (MODE == kDmaConsume) v[b] = consume<OP>(v[b], bias[b], o.lo, o.hi);
           }
-          if (col_own && i >= m_own) *reinterpret_cast<VB*>(out + i * ldo + col) = v;
+          if (col_own && (!EDGES || i >= m_own)) *reinterpret_cast<VB*>(out + i * ldo + col) = v;
         }
       }
   } else {
@@ -308,14 +312,14 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-            c[u] = (read_c && col >= n_own && i >= m_own) ? cin[i * q.ldc + col] : 0.0f;
+            c[u] = (read_c && (!EDGES || (col >= n_own && i >= m_own))) ? cin[i * q.ldc + col] : 0.0f;
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
             float v = alpha * acc[a][b][4 * g + u];
             if (read_c) v = fmaf(q.beta, c[u], v);
-            if (col >= n_own && i >= m_own) out[i * ldo + col] = v;
+            if (!EDGES || (col >= n_own && i >= m_own)) out[i * ldo + col] = v;
           }
         }
   }
@@ -324,7 +328,7 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
 // One launch: a workgroup per tile and contraction slice (slice-major, so
 // co-resident workgroups share a slice), XCD-aware tile order.
 template <int TM, int TN, int TK, int WM, int WN, bool AT, bool BT, int NST, int MODE, int OP = 0,
-          bool PAIR = false>
+          bool PAIR = false, bool EDGES = false>
 __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>::NW * kWave))
     __attribute__((amdgpu_waves_per_eu(1, (F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, PAIR>::kMaxWaves))))
     sgemm_f32_dma(GemmArgs p, GemmArgs p2, F32DmaOut o) {
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__((F32DmaShape<TM, TN, TK, WM, WN, AT, BT, NST, 
   const int z = blockIdx.x / tiles;
   int tm, tn;
   tile_coords(p.tiles_m, p.tiles_n, blockIdx.x - z * tiles, tm, tn);
-  f32_dma_tile<TM, TN, TK, WM, WN, AT, BT, NST, MODE, OP, PAIR>(p, p2, o, tm, tn, z, smem);
+  f32_dma_tile<TM, TN, TK, WM, WN, AT, BT, NST, MODE, OP, PAIR, EDGES>(p, p2, o, tm, tn, z, smem);
 }
 
 // True when the DMA-fed loop covers the problem in whole tiles: m, n and k

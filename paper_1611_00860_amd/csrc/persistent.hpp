@@ -71,8 +71,8 @@ __device__ __forceinline__ void run_shape_tile(int shape, const GemmArgs& p, int
       if (grouped_dma_ok(p)) {
         F32DmaOut o{};
         o.splits = 1;
-        f32_dma_tile<128, 128, 16, 32, 128, false, false, 2, kDmaUpdate>(p, p, o, tm, tn, 0,
-                                                                       reinterpret_cast<char*>(lds));
+        f32_dma_tile<128, 128, 16, 32, 128, false, false, 2, kDmaUpdate, 0, false, true>(
+            p, p, o, tm, tn, 0, reinterpret_cast<char*>(lds));
       } else {
         grouped_tile<128, 128, 16, 64, 64>(p, tm, tn, lds);
       }

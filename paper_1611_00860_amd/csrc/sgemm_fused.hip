@@ -274,7 +274,9 @@ struct ConsumerDmaConfig {
   static constexpr int kThreads = S::NW * kWave;
   template <int OP>
   static hipError_t run(const GemmArgs& a, const F32DmaOut& o, hipStream_t s) {
-    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaConsume, OP>;
+    auto* fn = f32_dma_fits<TM, TN, TK>(a, o.D, o.ldd, 1)
+                   ? &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaConsume, OP>
+                   : &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaConsume, OP, false, true>;
     hipError_t e = allow_lds_fused(fn, (size_t)S::kLdsBytes);
     if (e != hipSuccess) return e;
     GemmArgs a1 = a, a2 = a;
@@ -324,7 +326,9 @@ struct PairDmaConfig {
     F32DmaOut o{};
     o.splits = 1;
     void* kargs[] = {&p1, &p2, &o};
-    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaUpdate, 0, true>;
+    auto* fn = f32_dma_fits<TM, TN, TK>(a1, a1.C, a1.ldc, 1)
+                   ? &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaUpdate, 0, true>
+                   : &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaUpdate, 0, true, true>;
     hipError_t e = allow_lds_fused(fn, (size_t)S::kLdsBytes);
     if (e != hipSuccess) return e;
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(p1.tiles_m * p1.tiles_n)),

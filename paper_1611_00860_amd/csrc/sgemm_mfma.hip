@@ -130,7 +130,10 @@ struct F32DmaConfig {
     F32DmaOut o{};
     o.splits = 1;
     void* kargs[] = {&a, &unused, &o};
-    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaUpdate>;
+    // Whole tiles take the kernel without edge masks.
+    auto* fn = f32_dma_fits<TM, TN, TK>(args, args.C, args.ldc, 1)
+                   ? &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaUpdate>
+                   : &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaUpdate, 0, false, true>;
     hipError_t e = allow_lds(fn, (size_t)S::kLdsBytes);
     if (e != hipSuccess) return e;
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n)),
