@@ -12,6 +12,9 @@ and its error against the FP64 oracle:
   * BF16 and bf16x3 at M=N=K=8192 (uniform and log-uniform inputs, seed 2);
   * the grouped persistent launch of 512 uneven sgemms, replayed from a HIP
     graph (seed 3);
+  * FP32 problems whose tiles would not cover the CUs (1024 x 1024 x 4096 and
+    2048^3, seed 7): the contraction split into slices against the fastest
+    single launch over the tile menu;
   * forward + backward at M=N=4096, K=1024, alpha=0.7, beta=0.3 (seed 4), in
     FP32 and BF16.
 """
@@ -475,6 +478,46 @@ def variant_fusion(hp, inputs, dev, stream, reps):
     return out
 
 
+def variant_split(hp, inputs, dev, stream, reps):
+    """FP32 problems whose tiles would not cover the CUs: the contraction
+    split over DMA-fed 128 x 256 tiles (partial sums in a workspace, then
+    one summing launch) against the fastest single launch over the menu."""
+    import torch
+
+    import oracle
+
+    out = {}
+    split_tile = (128, 256, 32, 32, 128, 2)
+    for (m, n, k) in ((1024, 1024, 4096), (2048, 2048, 2048)):
+        A, B, C = inputs.sgemm_operands(m, n, k, seed=7)
+        dA, dB, dC = (torch.from_numpy(x).to(dev) for x in (A, B, C))
+        ws = torch.empty(hp.workspace_bytes(m, n, k, "fp32", split_tile), dtype=torch.uint8, device=dev)
+        with torch.cuda.stream(stream):
+            split_ms = event_time(lambda: hp.sgemm(dA, dB, dC, 1.0, 0.0, tile=split_tile, workspace=ws), reps,
+                                  stream)
+            single = {}
+            for tile in hp.tile_menu("fp32"):
+                single[tile] = event_time(lambda: hp.sgemm(dA, dB, dC, 1.0, 0.0, tile=tile, workspace=False),
+                                          reps, stream)
+            torch_ms = event_time(lambda: torch.matmul(dA, dB), reps, stream)
+            dC.copy_(torch.from_numpy(C))
+            hp.sgemm(dA, dB, dC, 0.5, 2.0, tile=split_tile, workspace=ws)
+        torch.cuda.synchronize()
+        best = min(single, key=single.get)
+        rs = np.random.default_rng(8)
+        rows, cols = rs.integers(0, m, 256), rs.integers(0, n, 256)
+        ref = oracle.sgemm_entries(A, B, C, 0.5, 2.0, rows, cols)
+        err = float(np.linalg.norm(gather(dC, rows, cols) - ref) / np.linalg.norm(ref))
+        flops = 2.0 * m * n * k
+        out[f"split_contraction_{m}x{n}x{k}"] = {
+            "split_tflops": round(flops / (split_ms / 1e3) / 1e12, 2), "split_ms": round(split_ms, 4),
+            "split_tile": list(split_tile), "slices": hp.workspace_bytes(m, n, k, "fp32", split_tile) // (4 * m * n),
+            "best_single_launch_ms": round(single[best], 4), "best_single_launch_tile": list(best),
+            "speedup": round(single[best] / split_ms, 3),
+            "torch_matmul_ms": round(torch_ms, 4), "normwise_rel_error_sampled": err, "bar": 1e-5}
+    return out
+
+
 def variant_tracked(hp, inputs, dev, reps):
     """4096^3 on tracked host arrays: copies in and out included, then resident."""
     import torch
@@ -605,7 +648,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--variants", default="precision,grouped,stream,fusion,tracked,backward",
+    ap.add_argument("--variants", default="precision,grouped,stream,fusion,split,tracked,backward",
                     help="comma-separated variants to run after the workload (a subset, e.g. for a counter run)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -617,7 +660,7 @@ def main():
     ap.add_argument("--traffic-table", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_LOG", "WRITE_LOG"),
                     help="build profiles/fp32_sgemm_tiles_traffic.txt from two --traffic-sweep counter runs and exit")
     args = ap.parse_args()
-    known = {"precision", "grouped", "stream", "fusion", "tracked", "backward"}
+    known = {"precision", "grouped", "stream", "fusion", "split", "tracked", "backward"}
     unknown = set(v.strip() for v in args.variants.split(",") if v.strip()) - known
     if unknown:
         print(f"bench.py: unknown variants {sorted(unknown)} (known: {sorted(known)})", file=sys.stderr)
@@ -761,6 +804,8 @@ def main():
             ("grouped", "grouped 512 from a HIP graph", lambda: variant_grouped(hp, inputs, dev, reps=10)),
             ("stream", "the 512 sgemms through a streaming graph", lambda: variant_stream(hp, inputs, dev, reps=5)),
             ("fusion", "node fusion", lambda: variant_fusion(hp, inputs, dev, stream, reps=10)),
+            ("split", "split contraction of small FP32 problems",
+             lambda: variant_split(hp, inputs, dev, stream, reps=20)),
             ("tracked", "tracked host arrays", lambda: variant_tracked(hp, inputs, dev, reps=5)),
             ("backward", "forward + backward 4096x4096x1024",
              lambda: variant_backward(hp, inputs, dev, stream, reps=20)),

@@ -175,8 +175,10 @@ typedef struct hpvm_edge {
  *   prec         : hpvm_precision.
  *   tile         : hierarchy shape, or NULL to take the autotuned choice for
  *                  this shape class (until hpvm_autotune has run, the
- *                  built-in default: the menu's entry 0, or for FP32 entry 1
- *                  when entry 0 would give fewer than 128 tiles).  Must be
+ *                  built-in default: the menu's entry 0, or for FP32, when
+ *                  entry 0 would give fewer than 128 tiles, entry 1
+ *                  (128 x 128 x 16) if that gives at least 256, else the
+ *                  64 x 64 x 16 tile).  Must be
  *                  in hpvm_tile_menu for prec and not need a workspace
  *                  (stages != 3).
  *   stream       : hipStream_t or NULL.
@@ -190,19 +192,32 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A,
 /* hpvm_sgemm with a workspace: the only way to run the staged BF16 / bf16x3
  * lowering (tiles with stages == 3), which first rewrites A and B as
  * zero-padded bfloat16 planes (B transposed so k is contiguous; hi and lo
- * planes for bf16x3) in `workspace` and then runs a GEMM over them.
+ * planes for bf16x3) in `workspace` and then runs a GEMM over them; and
+ * the split contraction of FP32 DMA-fed tiles (leaf_n == 128): a whole-tile
+ * problem (m, n multiples of the tile, A, B, C 16-byte aligned with leading
+ * dimensions that are multiples of 4) whose tiles would not cover 256 CUs
+ * runs as s contraction slices (s doubled from 1 while tiles * s < 256, at
+ * most 16, each slice a whole number of slabs and at least 256 deep; only
+ * when tiles * s reaches 256), each writing an m x n partial sum to
+ * `workspace`, then one launch forming C <- alpha * (sum of the partials,
+ * in slice order) + beta * C.  Results then differ from the single launch
+ * by rounding only.
  * workspace: device memory, 16-byte aligned, at least
  * hpvm_sgemm_workspace_bytes(m, n, k, prec, tile) bytes (may be NULL when
- * that is 0); its contents are scratch.  tile == NULL takes the autotuned
- * overall winner; with no autotuned entry, BF16 and bf16x3 products of at
- * least 2^31 multiply-adds (m n k) take the first staged tile, others the
- * menu's entry 0.  Every other argument and rule is hpvm_sgemm's.          */
+ * that is 0); its contents are scratch.  For a split FP32 tile it is
+ * optional: NULL or fewer bytes run the single launch.  tile == NULL takes
+ * the autotuned overall winner; with no autotuned entry, FP32 problems that
+ * a DMA-fed tile would split take the one with the fewest slices (the
+ * first in menu order on a tie), BF16 and bf16x3 products of at least 2^31
+ * multiply-adds (m n k) take the first staged tile, and others hpvm_sgemm's
+ * choice.  Every other argument and rule is hpvm_sgemm's.                  */
 int hpvm_sgemm_ws(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
                   const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
                   const hpvm_tile* tile, void* workspace, int64_t workspace_bytes, void* stream);
 
 /* Workspace bytes hpvm_sgemm_ws needs for these sizes and tile (NULL = the
- * tile it would pick); 0 for every lowering except the staged one.        */
+ * tile it would pick): the staged lowering's planes, or s * m * n * 4 for a
+ * split FP32 contraction of s slices; 0 otherwise.                         */
 int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec,
                                const hpvm_tile* tile, int64_t* bytes);
 
@@ -525,7 +540,10 @@ int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda
 typedef struct hpvm_stream_config {
   int32_t capacity;  /* ring slots = most items pushed and not yet popped,
                         1..4096                                           */
-  int32_t grid;      /* resident workgroups; 0 = one per compute unit     */
+  int32_t grid;      /* resident workgroups; 0 = one per compute unit.
+                        Above two per compute unit the kernel holds every
+                        SIMD's registers, so no other kernel (copies
+                        included) can start while the stream is open     */
   int32_t idle_ms;   /* the kernel ends the stream when nothing has been
                         pushed for this long, 1..60000                    */
   int32_t reserved;  /* 0                                                 */

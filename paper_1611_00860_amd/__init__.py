@@ -87,7 +87,8 @@ def _mat(t, name, rows=None, cols=None):
 
 
 def workspace_bytes(m: int, n: int, k: int, prec="fp32", tile=None) -> int:
-    """Workspace hpvm_sgemm_ws needs (0 except for the staged lowering)."""
+    """Workspace hpvm_sgemm_ws needs: the staged lowering's planes or a split
+    FP32 contraction's partial sums, else 0."""
     out = ctypes.c_int64(0)
     _check(load().hpvm_sgemm_workspace_bytes(m, n, k, _prec(prec), _tile(tile), ctypes.byref(out)))
     return out.value
@@ -100,9 +101,12 @@ def sgemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None
     A (m x k), B (k x n), C (m x n): float32 CUDA tensors, row-major, any
     leading dimension.  ``prec`` is 'fp32', 'bf16' or 'bf16x3'; ``tile`` is
     None (autotuned or default) or (tile_m, tile_n, tile_k, leaf_m, leaf_n,
-    stages).  Tiles of the staged lowering (stages = 3) need a workspace:
-    ``workspace`` (a CUDA tensor) is used when given, else one is allocated
-    from torch's caching allocator for the call (hpvm_sgemm_ws).
+    stages).  Tiles of the staged lowering (stages = 3) need a workspace,
+    and FP32 problems that a DMA-fed tile splits into contraction slices use
+    one: ``workspace`` (a CUDA tensor) is used when given and large enough,
+    else one is allocated from torch's caching allocator for the call
+    (hpvm_sgemm_ws).  ``workspace=False`` calls hpvm_sgemm, which takes none
+    (FP32 then runs as one launch; staged tiles are refused).
     """
     import torch
 
@@ -114,7 +118,7 @@ def sgemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(C, "C")
-    need = workspace_bytes(m, n, k, prec, tile)
+    need = 0 if workspace is False else workspace_bytes(m, n, k, prec, tile)
     if need == 0:
         _check(lib.hpvm_sgemm(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
                               _prec(prec), _tile(tile), _stream(stream)))

@@ -7,6 +7,7 @@
 // SgemmInternal / SgemmLeaf instance counts, and enqueues the kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -152,27 +153,49 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
   return HPVM_OK;
 }
 
-// Built-in choice of hpvm_sgemm_ws (and of hpvm_sgemm_workspace_bytes) for
-// tile == NULL when the autotuner has no entry: BF16 and bf16x3 products of
-// at least 2^31 multiply-adds take the first staged tile, whose conversion
-// pass is then a small share of the time; everything else keeps the menu's
-// entry 0.  Returns false for the latter.
-// Built-in FP32 choice for tile == NULL when the autotuner has no entry: the
-// menu's entry 0 (256 x 256 DMA-fed tiles) when it gives at least 128 tiles
-// (half a tile per CU of a 256-CU part), else entry 1 (128 x 128 x 16),
-// which gives four times as many.  Returns false for the former.
+// Built-in FP32 choice for tile == NULL when the autotuner has no entry and
+// no contraction split applies: the menu's entry 0 (256 x 256 DMA-fed
+// tiles) when it gives at least 128 tiles (half a tile per CU of a 256-CU
+// part), else entry 1 (128 x 128 x 16) when that gives a tile per CU, else
+// the 64 x 64 x 16 tile (at 1024 x 1024 x 4096, 64 tiles of 128 x 128 ran
+// at 28 TFLOP/s and 256 of 64 x 64 at 75).  Returns false for entry 0.
+int64_t tiles_of(const hpvm_tile& t, int64_t m, int64_t n) {
+  return ((m + t.tile_m - 1) / t.tile_m) * ((n + t.tile_n - 1) / t.tile_n);
+}
 bool default_fp32_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
   if (prec != HPVM_PREC_FP32) return false;
   const hpvm::MfmaEntry* e0 = hpvm::menu_entry_at(prec, 0);
   const hpvm::MfmaEntry* e1 = hpvm::menu_entry_at(prec, 1);
-  if (!e0 || !e1) return false;
-  const int64_t tiles = ((m + e0->tile.tile_m - 1) / e0->tile.tile_m) * ((n + e0->tile.tile_n - 1) / e0->tile.tile_n);
-  if (tiles >= 128) return false;
-  *out = e1->tile;
+  const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{64, 64, 16, 32, 32, 2});
+  if (!e0 || !e1 || !small) return false;
+  if (tiles_of(e0->tile, m, n) >= 128) return false;
+  *out = tiles_of(e1->tile, m, n) >= 256 ? e1->tile : small->tile;
   return true;
 }
 
+// Built-in choice of hpvm_sgemm_ws (and of hpvm_sgemm_workspace_bytes) for
+// tile == NULL when the autotuner has no entry: FP32 products whose tiles
+// would not cover the CUs take the DMA-fed entry that splits the contraction
+// into the deepest slices; BF16 and bf16x3 products of at least 2^31 multiply-adds take
+// the first staged tile, whose conversion pass is then a small share of the
+// time.  Returns false when neither applies (hpvm_sgemm's choice then).
 bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
+  if (prec == HPVM_PREC_FP32) {
+    // Deepest slices = fewest partial sums; the first in menu order on a tie.
+    const hpvm::MfmaEntry* best = nullptr;
+    int64_t best_bytes = 0;
+    for (int i = 0; i < hpvm::menu_size(prec); ++i) {
+      const hpvm::MfmaEntry* e = hpvm::menu_entry_at(prec, i);
+      const int64_t b = hpvm::entry_split_bytes(e, m, n, k);
+      if (b > 0 && (!best || b < best_bytes)) {
+        best = e;
+        best_bytes = b;
+      }
+    }
+    if (!best) return false;
+    *out = best->tile;
+    return true;
+  }
   if (prec != HPVM_PREC_BF16 && prec != HPVM_PREC_BF16X3) return false;
   if ((double)m * (double)n * (double)k < 2147483648.0 || !hpvm::staged_k_ok(k)) return false;
   const hpvm::MfmaEntry* staged = nullptr;
@@ -342,8 +365,11 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   a.beta = beta;
   a.vec_a = hpvm::vec16(A, lda);
   a.vec_b = hpvm::vec16(B, ldb);
+  const int64_t split = ws_ok ? hpvm::entry_split_bytes(entry, m, n, k) : 0;
   if (entry && entry->launch_staged)
     e = entry->launch_staged(a, workspace, s);
+  else if (split > 0 && workspace && (uintptr_t)workspace % 16 == 0 && workspace_bytes >= split)
+    e = entry->launch_split(a, workspace, s);
   else if (entry)
     e = entry->launch(a, false, false, s);
   else
@@ -378,7 +404,7 @@ int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, co
   const hpvm::MfmaEntry* entry;
   int rc = resolve(prec, tile, &entry, 5);
   if (rc != HPVM_OK) return rc;
-  *bytes = hpvm::entry_workspace_bytes(entry, m, n, k);
+  *bytes = std::max(hpvm::entry_workspace_bytes(entry, m, n, k), hpvm::entry_split_bytes(entry, m, n, k));
   return ok();
 }
 

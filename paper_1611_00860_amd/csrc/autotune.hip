@@ -132,11 +132,18 @@ int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A,
   if (e1) (void)hipEventDestroy(e1);
   if (rc != HPVM_OK) return rc;
   if (e != hipSuccess) return hip_error(e, "autotune timing");
+  // The fallback without a workspace is the fastest entry that ran without
+  // one: neither staged nor split into contraction slices.
+  auto used_workspace = [&](const MfmaEntry* me) {
+    const int64_t split = entry_split_bytes(me, m, n, k);
+    return me->launch_staged ||
+           (split > 0 && workspace && (uintptr_t)workspace % 16 == 0 && workspace_bytes >= split);
+  };
   int bi = -1, bf = -1;
   for (int i = 0; i < count; ++i) {
     if (best_of[i] < 0.0f) continue;
     if (bi < 0 || best_of[i] < best_of[bi]) bi = i;
-    if (!menu_entry_at(prec, i)->launch_staged && (bf < 0 || best_of[i] < best_of[bf])) bf = i;
+    if (!used_workspace(menu_entry_at(prec, i)) && (bf < 0 || best_of[i] < best_of[bf])) bf = i;
   }
   if (bi < 0 || bf < 0) return set_error(HPVM_INVALID_ARG, "no tile could be timed");
   Choice c{menu_entry_at(prec, bi)->tile, best_of[bi] / (float)reps, menu_entry_at(prec, bf)->tile,

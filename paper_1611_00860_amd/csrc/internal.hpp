@@ -49,7 +49,17 @@ struct MfmaEntry {
   hipError_t (*launch_staged_pair)(const GemmArgs& args1, const StagedPlanes& planes1, const float* aorig,
                                    int64_t lda_orig, float* partial, const GemmArgs& args2,
                                    const StagedPlanes& planes2, hipStream_t s) = nullptr;
+  // Split contraction (FP32 DMA-fed entries): workspace bytes that let an
+  // m x n x k product run as contraction slices whose partial sums go to the
+  // workspace (0 when the entry would not split it), and that launch
+  // (slices, then C <- alpha * sum + beta * C).  Null elsewhere.
+  int64_t (*split_bytes)(int64_t m, int64_t n, int64_t k) = nullptr;
+  hipError_t (*launch_split)(const GemmArgs& args, void* workspace, hipStream_t s) = nullptr;
 };
+
+inline int64_t entry_split_bytes(const MfmaEntry* e, int64_t m, int64_t n, int64_t k) {
+  return e && e->split_bytes ? e->split_bytes(m, n, k) : 0;
+}
 
 // The compiled fused menu for `prec` (FP32, BF16, BF16X3); returns the count.
 int mfma_menu(int32_t prec, const MfmaEntry** entries);

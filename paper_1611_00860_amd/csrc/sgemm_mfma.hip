@@ -5,6 +5,8 @@
 // The dynamic instances of SgemmInternal are independent (HPVM report,
 // Sec. 2.1), so the tiles may run in any order; the order chosen keeps the
 // tiles in flight on one XCD close together so that they share its L2.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 #include "mfma_f32_dma.hpp"
@@ -116,6 +118,32 @@ struct Bf16Config {
 // operand take the DMA-fed loop (mfma_f32_dma.hpp; edge tiles moved inward)
 // with 128-wide wave tiles; any other problem the general 128 x 128 x 16
 // tile.
+// C <- alpha * (slice 0 + ... + slice splits-1) + beta * C, the slices
+// summed in order, from partial sums [splits][m][n]; beta == 0 never reads
+// C.  Four adjacent outputs per lane (n, ldc multiples of 4, C 16-byte
+// aligned).
+constexpr int kSplitThreads = 256;
+__global__ void __launch_bounds__(kSplitThreads)
+    sgemm_split_finish(const float* __restrict__ part, int32_t splits, int64_t m, int64_t n, float alpha,
+                       float beta, float* __restrict__ C, int64_t ldc) {
+  const int64_t c4 = n / 4, units = m * c4, plane = m * n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += stride) {
+    const int64_t i = u / c4, j = (u - i * c4) * 4;
+    f32x4 v = *reinterpret_cast<const f32x4*>(part + i * n + j);
+    for (int z = 1; z < splits; ++z) v += *reinterpret_cast<const f32x4*>(part + z * plane + i * n + j);
+    f32x4* c = reinterpret_cast<f32x4*>(C + i * ldc + j);
+    if (beta != 0.0f) {
+      const f32x4 old = *c;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t] = fmaf(beta, old[t], alpha * v[t]);
+    } else {
+      v = alpha * v;
+    }
+    *c = v;
+  }
+}
+
 template <int TM, int TN, int TK, int WM, int NST>
 struct F32DmaConfig {
   using S = F32DmaShape<TM, TN, TK, WM, 128, false, false, NST>;
@@ -139,11 +167,69 @@ struct F32DmaConfig {
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n)),
                            dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
   }
+  // Contraction slices for a whole-tile problem whose tiles would not cover
+  // 256 CUs: doubled while they would not, each slice a whole number of
+  // slabs and at least 256 deep, at most 16; 1 (no split) when the slices
+  // still would not cover them.
+  static int splits(int64_t m, int64_t n, int64_t k) {
+    if (m <= 0 || n <= 0 || k <= 0 || m % TM || n % TN || k % TK) return 1;
+    const int64_t tiles = (m / TM) * (n / TN);
+    int sp = 1;
+    while (sp < 16 && tiles * sp < 256 && k % (2 * sp * TK) == 0 && k / (2 * sp) >= 256) sp *= 2;
+    return tiles * sp >= 256 ? sp : 1;
+  }
+  static int64_t split_bytes(int64_t m, int64_t n, int64_t k) {
+    const int sp = splits(m, n, k);
+    return sp > 1 ? (int64_t)sp * m * n * (int64_t)sizeof(float) : 0;
+  }
+  // The slices write raw partial tiles to `workspace` (split_bytes of it,
+  // 16-byte aligned), then sgemm_split_finish forms C.  Problems the split
+  // does not cover (operands or C not 16-byte units) take launch().
+  static hipError_t launch_split(const GemmArgs& args, void* workspace, hipStream_t s) {
+    const int sp = splits(args.m, args.n, args.k);
+    float* part = static_cast<float*>(workspace);
+    if (sp <= 1 || !f32_dma_fits<TM, TN, TK>(args, part, args.n, sp) ||
+        !f32_dma_fits<TM, TN, TK>(args, args.C, args.ldc, sp))
+      return launch(args, false, false, s);
+    GemmArgs a = args;
+    a.C = part;
+    a.ldc = a.n;
+    a.beta = 0.0f;
+    a.tiles_m = a.m / TM;
+    a.tiles_n = a.n / TN;
+    GemmArgs unused = a;
+    F32DmaOut o{};
+    o.splits = sp;
+    void* kargs[] = {&a, &unused, &o};
+    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaSplit>;
+    hipError_t e = allow_lds(fn, (size_t)S::kLdsBytes);
+    if (e != hipSuccess) return e;
+    e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n * sp)),
+                        dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
+    if (e != hipSuccess) return e;
+    const int64_t units = (int64_t)args.m * args.n / 4;
+    const unsigned blocks = (unsigned)std::min<int64_t>(2048, (units + kSplitThreads - 1) / kSplitThreads);
+    int32_t splits32 = sp;
+    int64_t m64 = args.m, n64 = args.n, ldc = args.ldc;
+    float alpha = args.alpha, beta = args.beta;
+    float* C = args.C;
+    void* fargs[] = {&part, &splits32, &m64, &n64, &alpha, &beta, &C, &ldc};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_finish), dim3(blocks), dim3(kSplitThreads),
+                           fargs, 0, s);
+  }
 };
 
 #define HPVM_F32_DMA_ENTRY(TM, TN, TK, WM, NST)                                                   \
-  {{TM, TN, TK, WM, 128, NST}, HPVM_PREC_FP32, F32DmaConfig<TM, TN, TK, WM, NST>::kThreads,       \
-   F32DmaConfig<TM, TN, TK, WM, NST>::S::kLdsBytes, &F32DmaConfig<TM, TN, TK, WM, NST>::launch}
+  {{TM, TN, TK, WM, 128, NST},                                                                    \
+   HPVM_PREC_FP32,                                                                                \
+   F32DmaConfig<TM, TN, TK, WM, NST>::kThreads,                                                   \
+   F32DmaConfig<TM, TN, TK, WM, NST>::S::kLdsBytes,                                               \
+   &F32DmaConfig<TM, TN, TK, WM, NST>::launch,                                                    \
+   nullptr,                                                                                       \
+   nullptr,                                                                                       \
+   nullptr,                                                                                       \
+   &F32DmaConfig<TM, TN, TK, WM, NST>::split_bytes,                                               \
+   &F32DmaConfig<TM, TN, TK, WM, NST>::launch_split}
 
 // Entry 0 is the default: DMA-fed for whole-tile problems, otherwise the
 // 128 x 128 x 16 tile.

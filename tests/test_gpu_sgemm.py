@@ -211,3 +211,76 @@ def test_f32_dma_edge_tiles_match_whole_tile_bits(gpu):
     assert np.array_equal(small, big[:m, :n])
     ref = oracle.sgemm(np.ascontiguousarray(A[:m]), B[:, :n].copy(), C[:m, :n].copy(), 1.0, 0.5)
     assert normwise(small, ref) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Split contraction (hpvm_sgemm_ws): FP32 DMA-fed tiles on whole-tile
+# problems whose tiles would not cover the CUs run as contraction slices
+# whose partial sums are added, in slice order, by a second launch.
+# ---------------------------------------------------------------------------
+T256 = (256, 256, 32, 64, 128, 2)
+T128X256 = (128, 256, 32, 32, 128, 2)
+SPLIT_CASES = [(1024, 1024, 4096, T256), (1024, 1024, 4096, T128X256), (512, 2048, 2048, T128X256),
+               (2048, 2048, 2048, None)]
+
+
+def sample_entries(m, n, count, seed):
+    rng = np.random.default_rng(seed)
+    rows = np.concatenate([rng.integers(0, m, count), [0, m - 1, m - 1, 0]])
+    cols = np.concatenate([rng.integers(0, n, count), [0, n - 1, 0, n - 1]])
+    return rows, cols
+
+
+@pytest.mark.parametrize("m,n,k,tile", SPLIT_CASES)
+def test_split_contraction_integers(gpu, m, n, k, tile):
+    """Integer inputs: every partial sum is an integer below 2^24, so the
+    result is exact whatever the slicing -- checked against the integer
+    product on all outputs and the oracle on sampled ones, with NaN-filled
+    row padding, and with beta = 0 on a NaN-filled C that is never read."""
+    assert gpu.workspace_bytes(m, n, k, "fp32", tile) > 0
+    print(f"case: fp32 split {m}x{n}x{k} tile {tile}", flush=True)
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=51, dist="int")
+    # integers of at most 8 * 8 * k < 2^53: exact in float64 in any order
+    product = A.astype(np.float64) @ B.astype(np.float64)
+    assert np.abs(product).max() < 2 ** 24
+    got = run(gpu, A, B, C, 1.0, 2.0, tile=tile, pad=4)
+    assert np.array_equal(got, product + 2.0 * C.astype(np.float64))
+    rows, cols = sample_entries(m, n, 300, 52)
+    assert np.array_equal(got[rows, cols], oracle.sgemm_entries(A, B, C, 1.0, 2.0, rows, cols))
+    got0 = run(gpu, A, B, np.full_like(C, np.nan), 1.0, 0.0, tile=tile)
+    assert np.array_equal(got0, product)
+
+
+@pytest.mark.parametrize("m,n,k,tile", SPLIT_CASES)
+def test_split_contraction_uniform_within_bound(gpu, m, n, k, tile):
+    print(f"case: fp32 split uniform {m}x{n}x{k} tile {tile}", flush=True)
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=53)
+    got = run(gpu, A, B, C, 0.75, -0.5, tile=tile)
+    rows, cols = sample_entries(m, n, 600, 54)
+    ref = oracle.sgemm_entries(A, B, C, 0.75, -0.5, rows, cols)
+    g = got[rows, cols].astype(np.float64)
+    assert normwise(g, ref) <= 1e-5
+    # each output: slices of k / s terms, then s partials, alpha and beta
+    ab = np.abs(A[rows].astype(np.float64)) * np.abs(B[:, cols].T.astype(np.float64))
+    bound = 0.75 * (k + 20) * 2.0 ** -24 * ab.sum(axis=1) + 4 * 2.0 ** -24 * 0.5 * np.abs(C[rows, cols])
+    assert np.all(np.abs(g - ref) <= bound)
+
+
+def test_split_contraction_without_workspace_runs_unsplit(gpu):
+    """hpvm_sgemm (no workspace) with a DMA-fed tile on a problem the split
+    would cover runs the single launch: the same result as the oracle."""
+    import ctypes
+
+    import torch
+
+    m, n, k = 1024, 1024, 4096
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=55, dist="int")
+    dA, dB, dC = (to_dev(x) for x in (A, B, C))
+    lib = gpu.load()
+    rc = lib.hpvm_sgemm(m, n, k, 1.0, ctypes.c_void_p(dA.data_ptr()), k, ctypes.c_void_p(dB.data_ptr()), n, 1.0,
+                        ctypes.c_void_p(dC.data_ptr()), n, gpu.PREC["fp32"], gpu._tile(T128X256),
+                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    torch.cuda.synchronize()
+    product = A.astype(np.float64) @ B.astype(np.float64)  # exact: integers below 2^53
+    assert np.array_equal(to_host(dC), product + C.astype(np.float64))
