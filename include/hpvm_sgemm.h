@@ -540,7 +540,7 @@ int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda
 typedef struct hpvm_stream_config {
   int32_t capacity;  /* ring slots = most items pushed and not yet popped,
                         1..4096                                           */
-  int32_t grid;      /* resident workgroups; 0 = one per compute unit.
+  int32_t grid;      /* resident workgroups; 0 = two per compute unit.
                         Above two per compute unit the kernel holds every
                         SIMD's registers, so no other kernel (copies
                         included) can start while the stream is open     */

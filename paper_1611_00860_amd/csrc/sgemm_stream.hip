@@ -380,7 +380,9 @@ int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
   if (e == hipSuccess && rate_khz <= 0) e = hipErrorInvalidValue;
-  s->grid = cfg->grid > 0 ? cfg->grid : std::max(cus, 1);
+  // Two resident workgroups per CU: a third would hold every SIMD's
+  // registers and keep other kernels off the device while the stream is open.
+  s->grid = cfg->grid > 0 ? cfg->grid : 2 * std::max(cus, 1);
   const int64_t hb = host_bytes(s->capacity);
   if (e == hipSuccess) {
     s->host = pool_take(hb, &s->host_size);  // a block of at least hb bytes

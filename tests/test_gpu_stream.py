@@ -43,6 +43,8 @@ def test_stream_items_bit_exact(gpu):
             assert np.array_equal(to_host(dC), ref), (seq, A.shape, B.shape)
         info = st.info()
         assert info["pushed"] == info["popped"] == len(cases) and info["running"] == 1
+        # default residency: two workgroups per CU
+        assert info["grid"] == 2 * torch.cuda.get_device_properties(0).multi_processor_count
 
 
 def test_stream_alpha_zero_null_operands_and_k_zero(gpu):
