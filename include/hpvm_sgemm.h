@@ -209,8 +209,9 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A,
  * the autotuned overall winner; with no autotuned entry, FP32 problems that
  * a DMA-fed tile would split take the one with the fewest slices (the
  * first in menu order on a tie), BF16 and bf16x3 products of at least 2^31
- * multiply-adds (m n k) take the first staged tile, and others hpvm_sgemm's
- * choice.  Every other argument and rule is hpvm_sgemm's.                  */
+ * multiply-adds (m n k) take the first staged tile, or 128 x 128 x 64 with
+ * 64 x 32 leaves when the first would give fewer than 256 tiles, and others
+ * hpvm_sgemm's choice.  Every other argument and rule is hpvm_sgemm's.     */
 int hpvm_sgemm_ws(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
                   const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
                   const hpvm_tile* tile, void* workspace, int64_t workspace_bytes, void* stream);

@@ -124,16 +124,21 @@ def test_full_size_8192_sampled(gpu, dist):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
-def test_default_tile_is_staged_for_large_products(gpu, prec):
+@pytest.mark.parametrize("m,n,k", [(1536, 1536, 1024), (4096, 4096, 256)])
+def test_default_tile_is_staged_for_large_products(gpu, prec, m, n, k):
     """With no tile and no autotuned entry, a product of at least 2^31
-    multiply-adds runs the first staged tile (through a workspace): the same
-    bits as naming that tile, and within the precision's bound."""
+    multiply-adds runs a staged tile (through a workspace): the first one
+    when it gives at least 256 tiles, else 128 x 128 x 64 with 64 x 32
+    leaves -- the same bits as naming that tile, and within the precision's
+    bound."""
     import torch
 
     gpu.autotune_clear()
-    m, n, k = 1536, 1536, 1024
     A, B, C = inputs.sgemm_operands(m, n, k, seed=37)
-    staged = [t for t in gpu.tile_menu(prec) if t[5] == 3][0]
+    first = [t for t in gpu.tile_menu(prec) if t[5] == 3][0]
+    whole = -(-m // first[0]) * -(-n // first[1]) >= 256
+    staged = first if whole else (128, 128, 64, 64, 32, 3)
+    assert whole == (m == 4096)
     print(f"case: default tile {prec} {m}x{n}x{k}", flush=True)
     C1, C2 = to_dev(C), to_dev(C)
     gpu.sgemm(to_dev(A), to_dev(B), C1, 1.0, 0.5, prec=prec)
