@@ -178,7 +178,8 @@ typedef struct hpvm_edge {
  *                  built-in default: the menu's entry 0, or for FP32, when
  *                  entry 0 would give fewer than 128 tiles, entry 1
  *                  (128 x 128 x 16) if that gives at least 256, else the
- *                  64 x 64 x 16 tile).  Must be
+ *                  64 x 64 x 16 tile; for BF16 and bf16x3, when entry 0
+ *                  would give fewer than 256 tiles, 64 x 64 x 32).  Must be
  *                  in hpvm_tile_menu for prec and not need a workspace
  *                  (stages != 3).
  *   stream       : hipStream_t or NULL.

@@ -153,23 +153,31 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
   return HPVM_OK;
 }
 
-// Built-in FP32 choice for tile == NULL when the autotuner has no entry and
-// no contraction split applies: the menu's entry 0 (256 x 256 DMA-fed
-// tiles) when it gives at least 128 tiles (half a tile per CU of a 256-CU
-// part), else entry 1 (128 x 128 x 16) when that gives a tile per CU, else
-// the 64 x 64 x 16 tile (at 1024 x 1024 x 4096, 64 tiles of 128 x 128 ran
-// at 28 TFLOP/s and 256 of 64 x 64 at 75).  Returns false for entry 0.
+// Built-in choice for tile == NULL when the autotuner has no entry and no
+// workspace lowering applies, for problems the menu's entry 0 would leave
+// CUs idle on.  FP32: entry 0 (256 x 256 DMA-fed tiles) when it gives at
+// least 128 tiles (half a tile per CU of a 256-CU part), else entry 1
+// (128 x 128 x 16) when that gives a tile per CU, else the 64 x 64 x 16 tile
+// (at 1024 x 1024 x 4096, 64 tiles of 128 x 128 ran at 28 TFLOP/s and 256
+// of 64 x 64 at 75).  BF16 and bf16x3: entry 0 (256 x 256 x 32) when it
+// gives at least 256 tiles, else the 64 x 64 x 32 tile (1024^3 BF16: 0.020
+// ms against 0.064).  Returns false for entry 0.
 int64_t tiles_of(const hpvm_tile& t, int64_t m, int64_t n) {
   return ((m + t.tile_m - 1) / t.tile_m) * ((n + t.tile_n - 1) / t.tile_n);
 }
-bool default_fp32_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
-  if (prec != HPVM_PREC_FP32) return false;
+bool default_small_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
   const hpvm::MfmaEntry* e0 = hpvm::menu_entry_at(prec, 0);
-  const hpvm::MfmaEntry* e1 = hpvm::menu_entry_at(prec, 1);
-  const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{64, 64, 16, 32, 32, 2});
-  if (!e0 || !e1 || !small) return false;
-  if (tiles_of(e0->tile, m, n) >= 128) return false;
-  *out = tiles_of(e1->tile, m, n) >= 256 ? e1->tile : small->tile;
+  if (!e0) return false;
+  if (prec == HPVM_PREC_FP32) {
+    const hpvm::MfmaEntry* e1 = hpvm::menu_entry_at(prec, 1);
+    const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{64, 64, 16, 32, 32, 2});
+    if (!e1 || !small || tiles_of(e0->tile, m, n) >= 128) return false;
+    *out = tiles_of(e1->tile, m, n) >= 256 ? e1->tile : small->tile;
+    return true;
+  }
+  const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{64, 64, 32, 32, 32, 2});
+  if (!small || tiles_of(e0->tile, m, n) >= 256) return false;
+  *out = small->tile;
   return true;
 }
 
@@ -260,7 +268,7 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
   if (!out) return fail(HPVM_INVALID_ARG, "argument 6: out is NULL");
   hpvm_tile small;
-  if (!tile && default_fp32_tile(prec, m, n, &small)) tile = &small;
+  if (!tile && default_small_tile(prec, m, n, &small)) tile = &small;
   const hpvm::MfmaEntry* e;
   int rc = resolve(prec, tile, &e, 5);
   if (rc != HPVM_OK) return rc;
@@ -331,7 +339,7 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   hpvm_tile tuned;
   if (!tile && hpvm::tuned_tile(prec, m, n, k, ws_ok, &tuned)) tile = &tuned;
   else if (!tile && ws_ok && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
-  else if (!tile && default_fp32_tile(prec, m, n, &tuned)) tile = &tuned;
+  else if (!tile && default_small_tile(prec, m, n, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   rc = resolve(prec, tile, &entry, 13);
   if (rc != HPVM_OK) return rc;

@@ -379,7 +379,8 @@ def test_default_tile_with_a_workspace(lib):
 def test_default_fp32_tile_for_small_problems(lib):
     """Without an autotuned entry the FP32 default is the menu's entry 0
     unless that gives fewer than 128 tiles; then the 128 x 128 x 16 entry
-    when it gives at least 256, else the 64 x 64 x 16 entry."""
+    when it gives at least 256, else the 64 x 64 x 16 entry.  BF16 and
+    bf16x3 keep entry 0 from 256 tiles up, else take 64 x 64 x 32."""
     hp.autotune_clear()
     menu = hp.tile_menu("fp32")
     assert menu[1] == (128, 128, 16, 64, 64, 2) and (64, 64, 16, 32, 32, 2) in menu
@@ -390,6 +391,14 @@ def test_default_fp32_tile_for_small_problems(lib):
     small = hp.describe(1000, 1000, 1024, "fp32", None)
     assert (small["grid_x"], small["grid_y"]) == (16, 16)
     assert small["waves"] == 4
+    # BF16 and bf16x3: entry 0 (256 x 256) from 256 tiles up, else 64 x 64 x 32
+    for prec in ("bf16", "bf16x3"):
+        menu = hp.tile_menu(prec)
+        assert menu[0][:2] == (256, 256) and (64, 64, 32, 32, 32, 2) in menu
+        big = hp.describe(4096, 4096, 512, prec, None)
+        assert (big["grid_x"], big["grid_y"]) == (16, 16)
+        small = hp.describe(1024, 1024, 1024, prec, None)
+        assert (small["grid_x"], small["grid_y"]) == (16, 16) and small["waves"] == 4
 
 
 def test_split_contraction_workspace_rules(lib):
