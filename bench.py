@@ -13,7 +13,7 @@ and its error against the FP64 oracle:
   * the grouped persistent launch of 512 uneven sgemms, replayed from a HIP
     graph (seed 3);
   * FP32 problems whose tiles would not cover the CUs (1024 x 1024 x 4096 and
-    2048^3, seed 7): the contraction split into slices against the fastest
+    1024^3, seed 7): the contraction split into slices against the fastest
     single launch over the tile menu;
   * forward + backward at M=N=4096, K=1024, alpha=0.7, beta=0.3 (seed 4), in
     FP32 and BF16.
@@ -479,16 +479,17 @@ def variant_fusion(hp, inputs, dev, stream, reps):
 
 
 def variant_split(hp, inputs, dev, stream, reps):
-    """FP32 problems whose tiles would not cover the CUs: the contraction
-    split over DMA-fed 128 x 256 tiles (partial sums in a workspace, then
-    one summing launch) against the fastest single launch over the menu."""
+    """FP32 problems that even 128 x 128 tiles would not cover the CUs with:
+    the contraction split over DMA-fed 128 x 128 x 32 tiles (partial sums in
+    a workspace, then one summing launch) against the fastest single launch
+    over the menu."""
     import torch
 
     import oracle
 
     out = {}
-    split_tile = (128, 256, 32, 32, 128, 2)
-    for (m, n, k) in ((1024, 1024, 4096), (2048, 2048, 2048)):
+    split_tile = (128, 128, 32, 32, 128, 2)
+    for (m, n, k) in ((1024, 1024, 4096), (1024, 1024, 1024)):
         A, B, C = inputs.sgemm_operands(m, n, k, seed=7)
         dA, dB, dC = (torch.from_numpy(x).to(dev) for x in (A, B, C))
         ws = torch.empty(hp.workspace_bytes(m, n, k, "fp32", split_tile), dtype=torch.uint8, device=dev)

@@ -175,11 +175,10 @@ typedef struct hpvm_edge {
  *   prec         : hpvm_precision.
  *   tile         : hierarchy shape, or NULL to take the autotuned choice for
  *                  this shape class (until hpvm_autotune has run, the
- *                  built-in default: the menu's entry 0, or for FP32, when
- *                  entry 0 would give fewer than 128 tiles, entry 1
- *                  (128 x 128 x 16) if that gives at least 256, else the
- *                  64 x 64 x 16 tile; for BF16 and bf16x3, when entry 0
- *                  would give fewer than 256 tiles, 64 x 64 x 32).  Must be
+ *                  built-in default: the menu's entry 0 when it gives at
+ *                  least 256 tiles; else for FP32 the DMA-fed
+ *                  128 x 128 x 32 tile if that does, else 64 x 64 x 16;
+ *                  for BF16 and bf16x3 64 x 64 x 32).  Must be
  *                  in hpvm_tile_menu for prec and not need a workspace
  *                  (stages != 3).
  *   stream       : hipStream_t or NULL.
@@ -208,8 +207,9 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A,
  * that is 0); its contents are scratch.  For a split FP32 tile it is
  * optional: NULL or fewer bytes run the single launch.  tile == NULL takes
  * the autotuned overall winner; with no autotuned entry, FP32 problems that
- * a DMA-fed tile would split take the one with the fewest slices (the
- * first in menu order on a tie), BF16 and bf16x3 products of at least 2^31
+ * even 128 x 128 tiles would not cover 256 CUs with take the DMA-fed tile
+ * with the fewest slices (the first in menu order on a tie), BF16 and
+ * bf16x3 products of at least 2^31
  * multiply-adds (m n k) take the first staged tile, or 128 x 128 x 64 with
  * 64 x 32 leaves when the first would give fewer than 256 tiles, and others
  * hpvm_sgemm's choice.  Every other argument and rule is hpvm_sgemm's.     */

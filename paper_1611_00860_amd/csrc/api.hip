@@ -156,23 +156,27 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
 // Built-in choice for tile == NULL when the autotuner has no entry and no
 // workspace lowering applies, for problems the menu's entry 0 would leave
 // CUs idle on.  FP32: entry 0 (256 x 256 DMA-fed tiles) when it gives at
-// least 128 tiles (half a tile per CU of a 256-CU part), else entry 1
-// (128 x 128 x 16) when that gives a tile per CU, else the 64 x 64 x 16 tile
-// (at 1024 x 1024 x 4096, 64 tiles of 128 x 128 ran at 28 TFLOP/s and 256
-// of 64 x 64 at 75).  BF16 and bf16x3: entry 0 (256 x 256 x 32) when it
-// gives at least 256 tiles, else the 64 x 64 x 32 tile (1024^3 BF16: 0.020
-// ms against 0.064).  Returns false for entry 0.
+// least 256 tiles (one per CU of a 256-CU part), else the DMA-fed
+// 128 x 128 x 32 tile when that does (2048^3: 0.128 ms against 0.166 for the
+// best register-staged tile and 0.457 for 64 tiles of 256 x 256), else the
+// 64 x 64 x 16 tile (at 1024 x 1024 x 4096, 64 tiles of 128 x 128 ran at 28
+// TFLOP/s and 256 of 64 x 64 at 75).  BF16 and bf16x3: entry 0
+// (256 x 256 x 32) when it gives at least 256 tiles, else the 64 x 64 x 32
+// tile (1024^3 BF16: 0.020 ms against 0.064).  Returns false for entry 0.
 int64_t tiles_of(const hpvm_tile& t, int64_t m, int64_t n) {
   return ((m + t.tile_m - 1) / t.tile_m) * ((n + t.tile_n - 1) / t.tile_n);
+}
+const hpvm::MfmaEntry* f32_mid_entry() {
+  return hpvm::find_menu_entry(HPVM_PREC_FP32, hpvm_tile{128, 128, 32, 32, 128, 2});
 }
 bool default_small_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
   const hpvm::MfmaEntry* e0 = hpvm::menu_entry_at(prec, 0);
   if (!e0) return false;
   if (prec == HPVM_PREC_FP32) {
-    const hpvm::MfmaEntry* e1 = hpvm::menu_entry_at(prec, 1);
+    const hpvm::MfmaEntry* mid = f32_mid_entry();
     const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{64, 64, 16, 32, 32, 2});
-    if (!e1 || !small || tiles_of(e0->tile, m, n) >= 128) return false;
-    *out = tiles_of(e1->tile, m, n) >= 256 ? e1->tile : small->tile;
+    if (!mid || !small || tiles_of(e0->tile, m, n) >= 256) return false;
+    *out = tiles_of(mid->tile, m, n) >= 256 ? mid->tile : small->tile;
     return true;
   }
   const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{64, 64, 32, 32, 32, 2});
@@ -182,16 +186,19 @@ bool default_small_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
 }
 
 // Built-in choice of hpvm_sgemm_ws (and of hpvm_sgemm_workspace_bytes) for
-// tile == NULL when the autotuner has no entry: FP32 products whose tiles
-// would not cover the CUs take the DMA-fed entry that splits the contraction
-// into the deepest slices; BF16 and bf16x3 products of at least 2^31 multiply-adds take
+// tile == NULL when the autotuner has no entry: FP32 products that even
+// 128 x 128 tiles would not cover the CUs with take the DMA-fed entry that
+// splits the contraction into the deepest slices; BF16 and bf16x3 products of at least 2^31 multiply-adds take
 // the first staged tile, whose conversion pass is then a small share of the
 // time (or, when that gives fewer than 256 tiles, the 128 x 128 x 64 tile
 // with 64 x 32 leaves).  Returns false when neither applies (hpvm_sgemm's
 // choice then).
 bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
   if (prec == HPVM_PREC_FP32) {
-    // Deepest slices = fewest partial sums; the first in menu order on a tie.
+    // Only when even 128 x 128 tiles would not cover the CUs; then the
+    // deepest slices = fewest partial sums, the first in menu order on a tie.
+    const hpvm::MfmaEntry* mid = f32_mid_entry();
+    if (mid && tiles_of(mid->tile, m, n) >= 256) return false;
     const hpvm::MfmaEntry* best = nullptr;
     int64_t best_bytes = 0;
     for (int i = 0; i < hpvm::menu_size(prec); ++i) {
@@ -415,6 +422,7 @@ int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, co
   hpvm_tile tuned;
   if (!tile && hpvm::tuned_tile(prec, m, n, k, true, &tuned)) tile = &tuned;
   else if (!tile && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
+  else if (!tile && default_small_tile(prec, m, n, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   int rc = resolve(prec, tile, &entry, 5);
   if (rc != HPVM_OK) return rc;

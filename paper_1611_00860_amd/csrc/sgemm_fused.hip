@@ -358,6 +358,7 @@ static const FusedEntry kConsumerMenu[] = {
     HPVM_CONSUMER_ENTRY(128, 64, 16, 64, 32), HPVM_CONSUMER_ENTRY(64, 128, 16, 32, 64),
     HPVM_CONSUMER_DMA_ENTRY(256, 256, 16, 64, 4),
     HPVM_CONSUMER_DMA_ENTRY(128, 256, 32, 32, 2),
+    HPVM_CONSUMER_DMA_ENTRY(128, 128, 32, 32, 2),
 };
 // Pair tiles: tile_m x tile_n of each output; 8, 8 and 4 waves.  The DMA-fed
 // entry's two stages of one A slab and two B slabs take all 160 KB of LDS.

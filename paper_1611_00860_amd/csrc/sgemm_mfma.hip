@@ -243,6 +243,7 @@ static const MfmaEntry kF32Menu[] = {
     HPVM_F32_ENTRY(64, 128, 16, 32, 64),
     HPVM_F32_DMA_ENTRY(256, 256, 16, 64, 4),
     HPVM_F32_DMA_ENTRY(128, 256, 32, 32, 2),
+    HPVM_F32_DMA_ENTRY(128, 128, 32, 32, 2),
 };
 
 #define HPVM_BF16_ENTRY(PREC, X3, TM, TN, TK, WM, WN)                                    \

@@ -378,19 +378,19 @@ def test_default_tile_with_a_workspace(lib):
 
 def test_default_fp32_tile_for_small_problems(lib):
     """Without an autotuned entry the FP32 default is the menu's entry 0
-    unless that gives fewer than 128 tiles; then the 128 x 128 x 16 entry
-    when it gives at least 256, else the 64 x 64 x 16 entry.  BF16 and
-    bf16x3 keep entry 0 from 256 tiles up, else take 64 x 64 x 32."""
+    when it gives at least 256 tiles, else the DMA-fed 128 x 128 x 32 tile
+    when that does, else the 64 x 64 x 16 tile.  BF16 and bf16x3 keep
+    entry 0 from 256 tiles up, else take 64 x 64 x 32."""
     hp.autotune_clear()
     menu = hp.tile_menu("fp32")
-    assert menu[1] == (128, 128, 16, 64, 64, 2) and (64, 64, 16, 32, 32, 2) in menu
+    mid_t, small_t = (128, 128, 32, 32, 128, 2), (64, 64, 16, 32, 32, 2)
+    assert mid_t in menu and small_t in menu
     big = hp.describe(4096, 4096, 1024, "fp32", None)
     assert (big["grid_x"], big["grid_y"]) == (4096 // menu[0][1], 4096 // menu[0][0])
-    mid = hp.describe(2048, 2048, 1024, "fp32", None)
-    assert (mid["grid_x"], mid["grid_y"]) == (16, 16)
-    small = hp.describe(1000, 1000, 1024, "fp32", None)
-    assert (small["grid_x"], small["grid_y"]) == (16, 16)
-    assert small["waves"] == 4
+    for m, n, tile in ((2048, 4096, mid_t), (2048, 2048, mid_t), (1000, 1000, small_t)):
+        d = hp.describe(m, n, 1024, "fp32", None)
+        assert (d["grid_x"], d["grid_y"]) == (-(-n // tile[1]), -(-m // tile[0])), (m, n)
+        assert d["alloc_bytes"] == hp.alloc_bytes(tile, "fp32"), (m, n)
     # BF16 and bf16x3: entry 0 (256 x 256) from 256 tiles up, else 64 x 64 x 32
     for prec in ("bf16", "bf16x3"):
         menu = hp.tile_menu(prec)
@@ -405,19 +405,23 @@ def test_split_contraction_workspace_rules(lib):
     """FP32 DMA-fed tiles split the contraction of whole-tile problems whose
     tiles would not cover 256 CUs, doubling the slices (each a whole number
     of slabs, at least 256 deep, at most 16) until they do; the workspace
-    holds one m x n float plane per slice.  With no tile, hpvm_sgemm_ws takes
-    the entry with the fewest slices."""
+    holds one m x n float plane per slice.  With no tile, hpvm_sgemm_ws
+    splits only when even 128 x 128 tiles would not cover the CUs, on the
+    entry with the fewest slices."""
     hp.autotune_clear()
     plane = lambda m, n: 4 * m * n
-    t256, t128x256 = (256, 256, 32, 64, 128, 2), (128, 256, 32, 32, 128, 2)
-    # 16 tiles of 256 x 256 -> 16 slices of 256; 32 of 128 x 256 -> 8 of 512
+    t256, t128x256, t128 = (256, 256, 32, 64, 128, 2), (128, 256, 32, 32, 128, 2), (128, 128, 32, 32, 128, 2)
+    # 16 tiles of 256 x 256 -> 16 slices of 256; 32 of 128 x 256 -> 8 of 512;
+    # 64 of 128 x 128 -> 4 of 1024
     assert hp.workspace_bytes(1024, 1024, 4096, "fp32", t256) == 16 * plane(1024, 1024)
     assert hp.workspace_bytes(1024, 1024, 4096, "fp32", t128x256) == 8 * plane(1024, 1024)
-    assert hp.workspace_bytes(1024, 1024, 4096, "fp32", None) == 8 * plane(1024, 1024)
+    assert hp.workspace_bytes(1024, 1024, 4096, "fp32", t128) == 4 * plane(1024, 1024)
+    assert hp.workspace_bytes(1024, 1024, 4096, "fp32", None) == 4 * plane(1024, 1024)
+    assert hp.workspace_bytes(1024, 1024, 1024, "fp32", None) == 4 * plane(1024, 1024)
     assert hp.workspace_bytes(2048, 2048, 2048, "fp32", t256) == 4 * plane(2048, 2048)
-    assert hp.workspace_bytes(2048, 2048, 2048, "fp32", None) == 2 * plane(2048, 2048)
     for m, n, k, tile in (
-            (1024, 1024, 1024, None),         # slices would stay under 256 workgroups
+            (2048, 2048, 2048, None),         # 256 tiles of 128 x 128: no split
+            (1024, 1024, 1024, t256),         # slices would stay under 256 workgroups
             (512, 512, 8192, t128x256),       # 8 tiles: 16 slices are not enough
             (4096, 4096, 4096, None),         # already 256 tiles
             (1000, 1024, 4096, t256),         # not whole tiles

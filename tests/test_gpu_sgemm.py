@@ -220,8 +220,9 @@ def test_f32_dma_edge_tiles_match_whole_tile_bits(gpu):
 # ---------------------------------------------------------------------------
 T256 = (256, 256, 32, 64, 128, 2)
 T128X256 = (128, 256, 32, 32, 128, 2)
-SPLIT_CASES = [(1024, 1024, 4096, T256), (1024, 1024, 4096, T128X256), (512, 2048, 2048, T128X256),
-               (2048, 2048, 2048, None)]
+T128 = (128, 128, 32, 32, 128, 2)
+SPLIT_CASES = [(1024, 1024, 4096, T256), (1024, 1024, 4096, T128X256), (1024, 1024, 4096, T128),
+               (512, 2048, 2048, T128X256), (2048, 2048, 2048, T256), (1024, 1024, 1024, None)]
 
 
 def sample_entries(m, n, count, seed):
