@@ -514,8 +514,9 @@ int hpvm_sgemm_consumer(int64_t m, int64_t n, int64_t k, float alpha, const floa
  * the output and the hpvm_sgemm argument position); C1 and C2 may not
  * overlap each other or the other output's B.  An output with k == 0 or
  * alpha == 0 shares nothing; the two outputs then take single launches.
- * tile: NULL = 128 x 128 per output when that gives 256 tiles or more, else
- * 64 x 64.                                                                  */
+ * tile: NULL = the first of the pair menu's 128 x 256 (DMA-fed),
+ * 128 x 128 and 64 x 64 tiles per output that gives at least 256 tiles,
+ * else 64 x 64.                                                             */
 int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, float alpha1,
                     const float* B1, int64_t ldb1, float beta1, float* C1, int64_t ldc1, float alpha2,
                     const float* B2, int64_t ldb2, float beta2, float* C2, int64_t ldc2,

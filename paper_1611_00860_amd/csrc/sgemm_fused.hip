@@ -491,12 +491,13 @@ int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda
     return set_error(HPVM_INVALID_ARG, "argument 10: C1 overlaps B2");
   if (r1 && ranges_meet(C2, m, n, ldc2, B1, k, n, ldb1))
     return set_error(HPVM_INVALID_ARG, "argument 16: C2 overlaps B1");
+  // Built-in choice: the largest tile per output that still gives a tile
+  // per CU of a 256-CU part -- the DMA-fed 128 x 256, else 128 x 128, else
+  // 64 x 64.
+  auto tiles = [&](const hpvm_tile& u) { return ((m + u.tile_m - 1) / u.tile_m) * ((n + u.tile_n - 1) / u.tile_n); };
   hpvm_tile t = kPairMenu[0].tile;
-  if (tile) {
-    t = *tile;
-  } else if ((m + 127) / 128 * ((n + 127) / 128) < 256) {
-    t = kPairMenu[1].tile;  // too few 128 x 128 tiles to fill the chip
-  }
+  if (tile) t = *tile;
+  else if (tiles(kPairMenu[0].tile) < 256) t = tiles(kPairMenu[1].tile) >= 256 ? kPairMenu[1].tile : kPairMenu[2].tile;
   const FusedEntry* e = find_fused(kPairMenu, kNumPair, t);
   if (!e)
     return set_error(HPVM_UNSUPPORTED, "argument 18: tile %dx%dx%d leaf %dx%d is not in the pair menu", t.tile_m,
