@@ -499,7 +499,7 @@ int hpvm_fusion_menu(int32_t which, hpvm_tile* out, int32_t capacity, int32_t* c
  * the consumer's output; it may be C itself (same pointer and leading
  * dimension) but may not otherwise overlap C, nor A, B or the bias vector.
  * tile: NULL = the autotuner's FP32 choice for the shape if it is in the
- * consumer menu, else the menu's first tile.  Errors as hpvm_sgemm, with
+ * consumer menu, else hpvm_sgemm's built-in FP32 choice.  Errors as hpvm_sgemm, with
  * argument 12 the consumer (unknown op, NULL bias, lo > hi), 13/14 D.     */
 int hpvm_sgemm_consumer(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
                         const float* B, int64_t ldb, float beta, const float* C, int64_t ldc,

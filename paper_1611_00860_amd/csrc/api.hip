@@ -169,6 +169,9 @@ int64_t tiles_of(const hpvm_tile& t, int64_t m, int64_t n) {
 const hpvm::MfmaEntry* f32_mid_entry() {
   return hpvm::find_menu_entry(HPVM_PREC_FP32, hpvm_tile{128, 128, 32, 32, 128, 2});
 }
+}  // namespace
+
+namespace hpvm {
 bool default_small_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
   const hpvm::MfmaEntry* e0 = hpvm::menu_entry_at(prec, 0);
   if (!e0) return false;
@@ -184,13 +187,16 @@ bool default_small_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
   *out = small->tile;
   return true;
 }
+}  // namespace hpvm
+
+namespace {
 
 // Built-in choice of hpvm_sgemm_ws (and of hpvm_sgemm_workspace_bytes) for
 // tile == NULL when the autotuner has no entry: FP32 products that even
 // 128 x 128 tiles would not cover the CUs with take the DMA-fed entry that
-// splits the contraction into the deepest slices; BF16 and bf16x3 products of at least 2^31 multiply-adds take
-// the first staged tile, whose conversion pass is then a small share of the
-// time (or, when that gives fewer than 256 tiles, the 128 x 128 x 64 tile
+// splits the contraction into the deepest slices; BF16 and bf16x3 products
+// of at least 2^31 multiply-adds take the first staged tile, whose
+// conversion pass is then a small share of the time (or, when that gives fewer than 256 tiles, the 128 x 128 x 64 tile
 // with 64 x 32 leaves).  Returns false when neither applies (hpvm_sgemm's
 // choice then).
 bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
@@ -275,7 +281,7 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
   if (!out) return fail(HPVM_INVALID_ARG, "argument 6: out is NULL");
   hpvm_tile small;
-  if (!tile && default_small_tile(prec, m, n, &small)) tile = &small;
+  if (!tile && hpvm::default_small_tile(prec, m, n, &small)) tile = &small;
   const hpvm::MfmaEntry* e;
   int rc = resolve(prec, tile, &e, 5);
   if (rc != HPVM_OK) return rc;
@@ -346,7 +352,7 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   hpvm_tile tuned;
   if (!tile && hpvm::tuned_tile(prec, m, n, k, ws_ok, &tuned)) tile = &tuned;
   else if (!tile && ws_ok && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
-  else if (!tile && default_small_tile(prec, m, n, &tuned)) tile = &tuned;
+  else if (!tile && hpvm::default_small_tile(prec, m, n, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   rc = resolve(prec, tile, &entry, 13);
   if (rc != HPVM_OK) return rc;
@@ -422,7 +428,7 @@ int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, co
   hpvm_tile tuned;
   if (!tile && hpvm::tuned_tile(prec, m, n, k, true, &tuned)) tile = &tuned;
   else if (!tile && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
-  else if (!tile && default_small_tile(prec, m, n, &tuned)) tile = &tuned;
+  else if (!tile && hpvm::default_small_tile(prec, m, n, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   int rc = resolve(prec, tile, &entry, 5);
   if (rc != HPVM_OK) return rc;

@@ -122,6 +122,10 @@ const MfmaEntry* menu_entry_at(int32_t prec, int index);
 int menu_size(int32_t prec);
 const MfmaEntry* find_menu_entry(int32_t prec, const hpvm_tile& tile);
 
+// Built-in tile for tile == NULL (no autotuned entry, no workspace) when the
+// menu's entry 0 would give fewer than 256 tiles; false otherwise.
+bool default_small_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out);
+
 // Workspace bytes an entry needs for m x n x k (0 for fused entries).
 int64_t entry_workspace_bytes(const MfmaEntry* e, int64_t m, int64_t n, int64_t k);
 

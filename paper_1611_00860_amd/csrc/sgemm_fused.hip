@@ -444,6 +444,8 @@ int hpvm_sgemm_consumer(int64_t m, int64_t n, int64_t k, float alpha, const floa
     hpvm_tile tuned;
     if (tuned_tile(HPVM_PREC_FP32, m, n, k, false, &tuned) && find_fused(kConsumerMenu, kNumConsumer, tuned))
       t = tuned;
+    else if (default_small_tile(HPVM_PREC_FP32, m, n, &tuned))
+      t = tuned;  // the single launch's choice for problems entry 0 leaves CUs idle on
   }
   const FusedEntry* e = find_fused(kConsumerMenu, kNumConsumer, t);
   if (!e)
