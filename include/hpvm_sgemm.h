@@ -330,7 +330,9 @@ int hpvm_autotune_backward(int64_t m, int64_t n, int64_t k, int32_t prec, const 
  * m x n, leading dimension ldc; overwritten with beta = 0, never read).
  * Tiles of the staged lowering (stages == 3) are timed only when
  * `workspace` (device, 16-byte aligned) holds at least
- * hpvm_sgemm_workspace_bytes for them; workspace may be NULL with 0 bytes.
+ * hpvm_sgemm_workspace_bytes for them; FP32 tiles that split the
+ * contraction run split when it holds their partial sums, and are then
+ * left out of the no-workspace choice.  workspace may be NULL with 0 bytes.
  * Two rounds over the menu; in each, a tile runs once to warm up, then
  * `reps` times, and it keeps its faster round.  The cache records the
  * fastest tile (used by hpvm_sgemm_ws with tile == NULL) and the fastest

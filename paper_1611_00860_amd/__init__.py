@@ -298,8 +298,9 @@ def autotune(A, B, prec="fp32", reps: int = 5, scratch=None, stream=None, allow_
     """Times every compiled tile for A @ B at `prec`; caches and returns (tile, ms).
 
     ``scratch`` (m x n float32, overwritten) is allocated when not given;
-    with ``allow_workspace`` the staged tiles are timed too, on a workspace
-    allocated for the call.
+    with ``allow_workspace`` the staged tiles are timed too, and FP32 tiles
+    that split the contraction run split, on a workspace allocated for the
+    call.
     """
     import torch
 

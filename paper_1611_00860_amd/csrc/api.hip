@@ -281,7 +281,8 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
   if (!out) return fail(HPVM_INVALID_ARG, "argument 6: out is NULL");
   hpvm_tile small;
-  if (!tile && hpvm::default_small_tile(prec, m, n, &small)) tile = &small;
+  if (!tile && hpvm::tuned_tile(prec, m, n, k, false, &small)) tile = &small;
+  else if (!tile && hpvm::default_small_tile(prec, m, n, &small)) tile = &small;
   const hpvm::MfmaEntry* e;
   int rc = resolve(prec, tile, &e, 5);
   if (rc != HPVM_OK) return rc;

@@ -401,6 +401,20 @@ def test_default_fp32_tile_for_small_problems(lib):
         assert (small["grid_x"], small["grid_y"]) == (16, 16) and small["waves"] == 4
 
 
+def test_describe_follows_the_autotuned_tile(lib):
+    """hpvm_describe reports the launch hpvm_sgemm would make: a recorded
+    autotuner entry for the shape takes precedence over the built-in rule."""
+    hp.autotune_clear()
+    tile = (64, 128, 16, 32, 64, 2)
+    hp.autotune_record(4096, 4096, 1024, tile, "fp32")
+    d = hp.describe(4096, 4096, 1024, "fp32", None)
+    assert (d["grid_x"], d["grid_y"]) == (4096 // 128, 4096 // 64)
+    assert d["alloc_bytes"] == hp.alloc_bytes(tile, "fp32")
+    hp.autotune_clear()
+    d = hp.describe(4096, 4096, 1024, "fp32", None)
+    assert (d["grid_x"], d["grid_y"]) == (16, 16)
+
+
 def test_split_contraction_workspace_rules(lib):
     """FP32 DMA-fed tiles split the contraction of whole-tile problems whose
     tiles would not cover 256 CUs, doubling the slices (each a whole number
