@@ -15,6 +15,8 @@ and its error against the FP64 oracle:
   * FP32 problems whose tiles would not cover the CUs (1024 x 1024 x 4096 and
     1024^3, seed 7): the contraction split into slices against the fastest
     single launch over the tile menu;
+  * the untiled one-level graph, the paper's two-level graph and the MFMA
+    lowering at 128^3 and 4096^3 (what tiling buys, beside the paper's ratios);
   * forward + backward at M=N=4096, K=1024, alpha=0.7, beta=0.3 (seed 4), in
     FP32 and BF16.
 """
@@ -191,30 +193,64 @@ def event_time(fn, reps, stream):
     return a.elapsed_time(b) / reps
 
 
-def cpu_baseline(host, target_s=30.0):
-    """The FP64 oracle over the FP32 step's products (all host threads).
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Times the first product (4096^3) in full; if the whole step would take
-    about `target_s` seconds or less, times all four products, otherwise
-    reports that first product alone.  Scaled to TFLOP/s.
+
+def cpu_baseline(host, target_s=30.0, runs=3):
+    """The FP64 oracle on the FP32 step's products, timed on the host.
+
+    All host threads: the median of `runs` passes over the whole step (four
+    products) when that fits in about `target_s` seconds, else over its
+    first product (4096^3).  One thread: the median of `runs` passes over a
+    row slice of the first product sized to about a second.  Each scaled to
+    TFLOP/s.
     """
     import oracle
 
     threads = oracle.default_threads()
-    t0 = time.perf_counter()
     (A, B, C), (m, n, k, beta) = host[0], WORKLOAD[0]
+    t0 = time.perf_counter()
     oracle.sgemm(A, B, C, 1.0, beta, threads=threads)
-    t1 = time.perf_counter() - t0
+    first = time.perf_counter() - t0
     step_flops = sum(2.0 * mm * nn * kk for (mm, nn, kk, _) in WORKLOAD)
-    if t1 * step_flops / (2.0 * m * n * k) <= target_s:
+    whole = runs * first * step_flops / (2.0 * m * n * k) <= target_s
+    times = []
+    for _ in range(runs):
         t0 = time.perf_counter()
-        for (A, B, C), (mm, nn, kk, beta) in zip(host, WORKLOAD):
+        if whole:
+            for (Ah, Bh, Ch), (mm, nn, kk, b) in zip(host, WORKLOAD):
+                oracle.sgemm(Ah, Bh, Ch, 1.0, b, threads=threads)
+        else:
             oracle.sgemm(A, B, C, 1.0, beta, threads=threads)
-        dt, flops, sample = time.perf_counter() - t0, step_flops, "the whole FP32 step (4 products)"
-    else:
-        dt, flops, sample = t1, 2.0 * m * n * k, f"the first product of the step ({m}x{n}x{k}, beta=0)"
+        times.append(time.perf_counter() - t0)
+    flops = step_flops if whole else 2.0 * m * n * k
+    sample = "the whole FP32 step (4 products)" if whole else f"the step's first product ({m}x{n}x{k}, beta=0)"
+    dt = float(np.median(times))
+    # one thread: rows of the first product, about a second of work
+    per_row_s = first * threads / m
+    rows = int(min(m, max(16, 1.0 / max(per_row_s, 1e-9))))
+    t1 = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.sgemm(A[:rows], B, C[:rows], 1.0, beta, threads=1)
+        t1.append(time.perf_counter() - t0)
+    d1 = float(np.median(t1))
+    f1 = 2.0 * rows * n * k
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample}: {flops / 1e9:.1f} GFLOP in {dt:.1f} s"}
+            "sample": f"{sample}: {flops / 1e9:.1f} GFLOP, median of {runs} runs {dt:.2f} s "
+                      f"(runs {', '.join(f'{t:.2f}' for t in times)} s)",
+            "cpu_model": cpu_model(),
+            "single_core": {"value": f1 / d1 / 1e12, "unit": "TFLOP/s", "cores": 1,
+                            "sample": f"rows 0..{rows - 1} of the first product ({rows}x{n}x{k}): "
+                                      f"{f1 / 1e9:.2f} GFLOP, median of {runs} runs {d1:.2f} s"}}
 
 
 def cpu_lowering(hp, host):
@@ -519,6 +555,46 @@ def variant_split(hp, inputs, dev, stream, reps):
     return out
 
 
+def variant_tiling(hp, inputs, dev, stream):
+    """What tiling buys, measured the way the paper compares its tiled and
+    untiled sgemm graphs: the untiled one-level graph (one lane per output,
+    A and B read from global memory), the paper's own two-level graph (32 x 32
+    internal instances, a B slab in the Allocation node's LDS, one output per
+    leaf lane), and this library's tiled MFMA lowering, at 128^3 (alpha 1,
+    beta 0.5, seed 0) and 4096^3 (seed 1, beta 0)."""
+    import torch
+
+    import oracle
+
+    flat, literal = (32, 32, 0, 1, 1, 0), (32, 32, 32, 1, 1, 1)
+    out = {}
+    for n, seed, beta, reps in ((128, 0, 0.5, 50), (4096, 1, 0.0, 3)):
+        A, B, C = inputs.sgemm_operands(n, n, n, seed=seed)
+        dA, dB, dC = (torch.from_numpy(x).to(dev) for x in (A, B, C))
+        tuned, _ = hp.autotune(dA, dB, prec="fp32", reps=3)
+        rec = {}
+        for name, tile in (("untiled", flat), ("paper_tiled", literal), ("mfma_tiled", None)):
+            ms = event_time(lambda: hp.sgemm(dA, dB, dC, 1.0, beta, tile=tile), reps, stream)
+            dC.copy_(torch.from_numpy(C))
+            hp.sgemm(dA, dB, dC, 1.0, beta, tile=tile)
+            torch.cuda.synchronize()
+            err = sampled_error(A, B, C, 1.0, beta, lambda r, c: gather(dC, r, c), n, n, count=128)
+            rec[name] = {"ms": round(ms, 5), "tflops": round(2.0 * n ** 3 / (ms / 1e3) / 1e12, 3),
+                         "tile": list(tile) if tile else list(tuned), "normwise_rel_error_sampled": err}
+        rec["paper_tiled_over_untiled"] = round(rec["untiled"]["ms"] / rec["paper_tiled"]["ms"], 2)
+        rec["mfma_tiled_over_untiled"] = round(rec["untiled"]["ms"] / rec["mfma_tiled"]["ms"], 2)
+        rec["mfma_tiled_over_paper_tiled"] = round(rec["paper_tiled"]["ms"] / rec["mfma_tiled"]["ms"], 2)
+        out[f"tiling_{n}^3"] = rec
+        del dA, dB, dC
+    out["tiling_paper_context"] = {
+        "sgemm_tiled_over_untiled": "up to 31x",
+        "hardware": "Intel Xeon, AVX vector backend, 3.6 GHz (Parboil sgemm, largest input, 10-run average)",
+        "mean_tiled_over_untiled_sgemm_tpacf_bfs": {"gpu": "19x on an NVIDIA GeForce GTX 680",
+                                                     "vector": "10x on the same Xeon with AVX"},
+        "note": "the paper's ratios, on its hardware and inputs; context, not targets"}
+    return out
+
+
 def variant_tracked(hp, inputs, dev, reps):
     """4096^3 on tracked host arrays: copies in and out included, then resident."""
     import torch
@@ -649,7 +725,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--variants", default="precision,grouped,stream,fusion,split,tracked,backward",
+    ap.add_argument("--variants", default="precision,grouped,stream,fusion,split,tiling,tracked,backward",
                     help="comma-separated variants to run after the workload (a subset, e.g. for a counter run)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -661,7 +737,7 @@ def main():
     ap.add_argument("--traffic-table", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_LOG", "WRITE_LOG"),
                     help="build profiles/fp32_sgemm_tiles_traffic.txt from two --traffic-sweep counter runs and exit")
     args = ap.parse_args()
-    known = {"precision", "grouped", "stream", "fusion", "split", "tracked", "backward"}
+    known = {"precision", "grouped", "stream", "fusion", "split", "tiling", "tracked", "backward"}
     unknown = set(v.strip() for v in args.variants.split(",") if v.strip()) - known
     if unknown:
         print(f"bench.py: unknown variants {sorted(unknown)} (known: {sorted(known)})", file=sys.stderr)
@@ -807,6 +883,7 @@ def main():
             ("fusion", "node fusion", lambda: variant_fusion(hp, inputs, dev, stream, reps=10)),
             ("split", "split contraction of small FP32 problems",
              lambda: variant_split(hp, inputs, dev, stream, reps=20)),
+            ("tiling", "tiled against untiled graphs", lambda: variant_tiling(hp, inputs, dev, stream)),
             ("tracked", "tracked host arrays", lambda: variant_tracked(hp, inputs, dev, reps=5)),
             ("backward", "forward + backward 4096x4096x1024",
              lambda: variant_backward(hp, inputs, dev, stream, reps=20)),

@@ -83,7 +83,12 @@ typedef enum hpvm_precision {
  *                   (= tile_m) x tile_n slab of B, as in Sec. 6.1-6.3.
  *                   Larger values select an MFMA lowering in which every
  *                   wavefront owns a leaf_m x leaf_n sub-tile of C.
- * stages          : the Allocation node's LDS stages.  1 = one buffer
+ * stages          : the Allocation node's LDS stages.  0 with tile_k = 0
+ *                   and leaf 1 x 1: no Allocation node and no SgemmInternal
+ *                   level -- the untiled one-level graph the paper compares
+ *                   tiling against (Sec. 3.4, 5.1): one lane per element of
+ *                   C reading A and B from global memory, tile_m x tile_n
+ *                   lanes per launch group; 1 = one buffer
  *                   (literal lowering); 2 = two stages filled through
  *                   registers, conversion to bfloat16 (if any) fused into
  *                   that copy; 3 = staged BF16 / bf16x3 lowering: operands
@@ -144,7 +149,12 @@ typedef struct hpvm_dfg {
   int64_t alloc_bytes;    /* LDS bytes the Allocation node provides        */
   int32_t k_slabs;        /* ceil(k / tile_k): trips of the staging loop   */
   int32_t lowering;       /* 0 literal, 1 FP32 MFMA, 2 BF16 MFMA,
-                             3 bf16x3 MFMA, 4 staged BF16, 5 staged bf16x3 */
+                             3 bf16x3 MFMA, 4 staged BF16, 5 staged bf16x3,
+                             6 untiled (one-level graph)                   */
+  int32_t splits;         /* contraction slices the launch runs (1 = the
+                             whole k in one pass; see hpvm_sgemm_ws)       */
+  int32_t reserved;       /* 0                                             */
+  hpvm_tile tile;         /* the tile the launch uses                      */
 } hpvm_dfg;
 
 /* One edge or binding of the static graph (Sec. 2.1, Table 1 createEdge,
@@ -246,9 +256,22 @@ int hpvm_wait(void* stream);
  * Sec. 6.1.                                                                 */
 int hpvm_alloc_bytes(const hpvm_tile* tile, int32_t prec, int64_t* bytes);
 
-/* Grid, block, LDS and lowering that hpvm_sgemm would use for these sizes. */
+/* The instance of the sgemm graph (Sec. 6.1) that hpvm_sgemm would launch
+ * for these sizes, as lowered by Sec. 3.4 and 6.3: the SgemmInternal grid
+ * (grid_x x grid_y workgroups), the SgemmLeaf lanes of one instance, the
+ * Allocation node's LDS bytes, the staging-loop trips and the lowering.
+ * tile == NULL describes the tile hpvm_sgemm picks (autotuned, else the
+ * built-in choice); splits is 1 (hpvm_sgemm never splits the contraction).
+ * Host only: reads no device state.                                        */
 int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec,
                   const hpvm_tile* tile, hpvm_dfg* out);
+
+/* The same for hpvm_sgemm_ws given a workspace of `workspace_bytes` (>= 0):
+ * the tile it picks for tile == NULL with that workspace, and in `splits`
+ * the contraction slices it runs (a split FP32 tile whose partial sums do
+ * not fit runs as one launch, splits = 1).                                 */
+int hpvm_describe_ws(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile,
+                     int64_t workspace_bytes, hpvm_dfg* out);
 
 /* The static edge and binding table of the sgemm graph.  Writes at most
  * `capacity` entries to `out` (which may be NULL when capacity is 0) and
@@ -545,10 +568,12 @@ int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda
 typedef struct hpvm_stream_config {
   int32_t capacity;  /* ring slots = most items pushed and not yet popped,
                         1..4096                                           */
-  int32_t grid;      /* resident workgroups; 0 = two per compute unit.
-                        Above two per compute unit the kernel holds every
-                        SIMD's registers, so no other kernel (copies
-                        included) can start while the stream is open     */
+  int32_t grid;      /* resident workgroups, 0..2 per compute unit of
+                        the device (at most 512); 0 = two per compute
+                        unit.  More is refused with HPVM_INVALID_ARG: a
+                        third per compute unit would hold every SIMD's
+                        registers, so no other kernel (a copy's included)
+                        could start while the stream is open            */
   int32_t idle_ms;   /* the kernel ends the stream when nothing has been
                         pushed for this long, 1..60000                    */
   int32_t reserved;  /* 0                                                 */

@@ -17,7 +17,7 @@ from . import _lib
 
 PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 LOWERINGS = {0: "literal", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_bf16x3", 4: "staged_bf16",
-             5: "staged_bf16x3"}
+             5: "staged_bf16x3", 6: "flat"}
 
 
 class HpvmError(RuntimeError):
@@ -68,6 +68,23 @@ def _stream(stream=None):
             return ctypes.c_void_p(None)  # host-only calls; a HIP call then fails loudly
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _empty(shape, dtype, device, stream=None):
+    """torch.empty on the stream the library will use the memory on.
+
+    Scratch memory a call hands to the library is used on ``stream`` (when
+    given, else torch's current stream).  Allocating it under that stream
+    makes torch's caching allocator order its reuse after the work queued
+    there: a block freed when this call returns is not handed to another
+    allocation until the stream's kernels have finished with it.
+    """
+    import torch
+
+    if stream is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    with torch.cuda.stream(stream):
+        return torch.empty(shape, dtype=dtype, device=device)
 
 
 def _mat(t, name, rows=None, cols=None):
@@ -124,7 +141,7 @@ def sgemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None
                               _prec(prec), _tile(tile), _stream(stream)))
         return C
     if workspace is None or workspace.numel() * workspace.element_size() < need:
-        workspace = torch.empty(need, dtype=torch.uint8, device=C.device)
+        workspace = _empty(need, torch.uint8, C.device, stream)
     _check(lib.hpvm_sgemm_ws(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
                              _prec(prec), _tile(tile), ctypes.c_void_p(workspace.data_ptr()),
                              workspace.numel() * workspace.element_size(), _stream(stream)))
@@ -168,11 +185,17 @@ def alloc_bytes(tile, prec="fp32") -> int:
     return out.value
 
 
-def describe(m: int, n: int, k: int, prec="fp32", tile=None) -> dict:
-    """Grid / block / LDS / lowering of one launch (hpvm_describe)."""
+def describe(m: int, n: int, k: int, prec="fp32", tile=None, workspace_bytes=None) -> dict:
+    """Grid / block / LDS / lowering / contraction slices of one launch:
+    hpvm_sgemm's (hpvm_describe), or with ``workspace_bytes`` hpvm_sgemm_ws's
+    given a workspace of that size (hpvm_describe_ws)."""
     d = _lib.Dfg()
-    _check(load().hpvm_describe(m, n, k, _prec(prec), _tile(tile), ctypes.byref(d)))
-    out = {f: getattr(d, f) for f, _ in _lib.Dfg._fields_}
+    if workspace_bytes is None:
+        _check(load().hpvm_describe(m, n, k, _prec(prec), _tile(tile), ctypes.byref(d)))
+    else:
+        _check(load().hpvm_describe_ws(m, n, k, _prec(prec), _tile(tile), int(workspace_bytes), ctypes.byref(d)))
+    out = {f: getattr(d, f) for f, _ in _lib.Dfg._fields_ if f not in ("reserved", "tile")}
+    out["tile"] = d.tile.as_tuple()
     out["lowering_name"] = LOWERINGS.get(d.lowering, "?")
     return out
 
@@ -231,14 +254,14 @@ def sgemm_backward(A, B, C_in, G, alpha: float, beta: float, prec="fp32", need=(
     dev = G.device
     out = {}
     if "dA" in need:
-        out["dA"] = torch.empty((m, k), dtype=torch.float32, device=dev)
+        out["dA"] = _empty((m, k), torch.float32, dev, stream)
     if "dB" in need:
-        out["dB"] = torch.empty((k, n), dtype=torch.float32, device=dev)
+        out["dB"] = _empty((k, n), torch.float32, dev, stream)
     if "dC_in" in need:
-        out["dC_in"] = torch.empty((m, n), dtype=torch.float32, device=dev)
-    scal = torch.empty(2, dtype=torch.float32, device=dev)  # the call writes each requested scalar
+        out["dC_in"] = _empty((m, n), torch.float32, dev, stream)
+    scal = _empty(2, torch.float32, dev, stream)  # the call writes each requested scalar
     nbytes = backward_workspace_bytes(m, n, k, prec, tile)
-    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=dev)
+    ws = _empty(max(nbytes, 16), torch.uint8, dev, stream)
 
     def mat(name, t, rows, cols):
         if t is None:
@@ -276,9 +299,9 @@ def autotune_backward(A, B, G, prec="fp32", reps: int = 3, stream=None):
     n = B.shape[1]
     dev = G.device
     need = max(backward_workspace_bytes(m, n, k, prec, t) for t in backward_menu(prec)) + 256
-    ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    dA = torch.empty((m, k), dtype=torch.float32, device=dev)
-    dB = torch.empty((k, n), dtype=torch.float32, device=dev)
+    ws = _empty(need, torch.uint8, dev, stream)
+    dA = _empty((m, k), torch.float32, dev, stream)
+    dB = _empty((k, n), torch.float32, dev, stream)
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pg, ldg = _mat(G, "G")
@@ -307,11 +330,11 @@ def autotune(A, B, prec="fp32", reps: int = 5, scratch=None, stream=None, allow_
     m, k = A.shape
     n = B.shape[1]
     if scratch is None:
-        scratch = torch.empty((m, n), dtype=torch.float32, device=A.device)
+        scratch = _empty((m, n), torch.float32, A.device, stream)
     need = 0
     if allow_workspace:
         need = max([workspace_bytes(m, n, k, prec, t) for t in tile_menu(prec)] + [0])
-    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    ws = _empty(max(need, 1), torch.uint8, A.device, stream)
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(scratch, "scratch")
@@ -418,20 +441,21 @@ class GroupedPlan:
         _check(load().hpvm_grouped_instance_tile(self._h, int(i), ctypes.byref(t)))
         return t.as_tuple()
 
-    def _ws(self):
+    def _ws(self, stream=None):
+        if stream is not None:  # freed with the plan: not before that stream's work is done
+            self.workspace.record_stream(stream)
         return ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel()
 
     def run(self, stream=None):
-        ws, nb = self._ws()
+        ws, nb = self._ws(stream)
         _check(load().hpvm_grouped_run(self._h, ws, nb, _stream(stream)))
 
     def autotune(self, reps: int = 3, stream=None) -> float:
         """Times candidate shape assignments on scratch outputs; keeps the fastest."""
         import torch
 
-        scratch = torch.empty(max(self.info()["scratch_bytes"] // 4, 1), dtype=torch.float32,
-                              device=self.workspace.device)
-        ws, nb = self._ws()
+        scratch = _empty(max(self.info()["scratch_bytes"] // 4, 1), torch.float32, self.workspace.device, stream)
+        ws, nb = self._ws(stream)
         best = ctypes.c_float(0.0)
         _check(load().hpvm_grouped_autotune(self._h, ws, nb, ctypes.c_void_p(scratch.data_ptr()),
                                             scratch.numel() * 4, int(reps), _stream(stream),
@@ -439,7 +463,7 @@ class GroupedPlan:
         return best.value
 
     def capture(self, stream=None) -> Graph:
-        ws, nb = self._ws()
+        ws, nb = self._ws(stream)
         g = ctypes.c_void_p()
         _check(load().hpvm_grouped_capture(self._h, ws, nb, _stream(stream), ctypes.byref(g)))
         return Graph(g, (self._keep, self.workspace))
@@ -483,7 +507,7 @@ def sgemm_consumer(A, B, C, alpha: float = 1.0, beta: float = 0.0, op="none", bi
     if k2 != k:
         raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}")
     if D is None:
-        D = C if C is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
+        D = C if C is not None else _empty((m, n), torch.float32, A.device, stream)
     if tuple(D.shape) != (m, n) or (C is not None and tuple(C.shape) != (m, n)):
         raise ValueError("C and D must be m x n")
     pa, lda = _mat(A, "A")

@@ -38,7 +38,8 @@ class RootIn(ctypes.Structure):
 class Dfg(ctypes.Structure):
     _fields_ = [("root_instances", i32), ("grid_x", i32), ("grid_y", i32),
                 ("block_x", i32), ("block_y", i32), ("waves", i32),
-                ("alloc_bytes", i64), ("k_slabs", i32), ("lowering", i32)]
+                ("alloc_bytes", i64), ("k_slabs", i32), ("lowering", i32),
+                ("splits", i32), ("reserved", i32), ("tile", Tile)]
 
 
 class Edge(ctypes.Structure):
@@ -90,6 +91,7 @@ SIGNATURES = {
     "hpvm_wait": (ctypes.c_int, [vp]),
     "hpvm_alloc_bytes": (ctypes.c_int, [ctypes.POINTER(Tile), i32, ctypes.POINTER(i64)]),
     "hpvm_describe": (ctypes.c_int, [i64, i64, i64, i32, ctypes.POINTER(Tile), ctypes.POINTER(Dfg)]),
+    "hpvm_describe_ws": (ctypes.c_int, [i64, i64, i64, i32, ctypes.POINTER(Tile), i64, ctypes.POINTER(Dfg)]),
     "hpvm_dfg_edges": (ctypes.c_int, [ctypes.POINTER(Edge), i32, ctypes.POINTER(i32)]),
     "hpvm_tile_menu": (ctypes.c_int, [i32, ctypes.POINTER(Tile), i32, ctypes.POINTER(i32)]),
     "hpvm_grouped_plan_create": (ctypes.c_int, [i32, ctypes.POINTER(SgemmDesc), i32, PTile, Pvp]),

@@ -117,11 +117,13 @@ bool is_literal(const hpvm_tile& t) { return t.leaf_m == 1 && t.leaf_n == 1; }
 
 // Literal lowering: tile_n x tile_m lanes (block_x = tile_n, block_y =
 // tile_m), a whole number of wavefronts, at most 1024 lanes; the staged B
-// slab is tile_m deep and one buffer.
+// slab is tile_m deep and one buffer.  The untiled one-level graph has the
+// same lanes, tile_k = 0 and stages = 0 (no Allocation node).
+bool is_flat(const hpvm_tile& t) { return t.stages == 0 && t.tile_k == 0; }
 bool literal_ok(const hpvm_tile& t) {
   const int64_t lanes = (int64_t)t.tile_m * t.tile_n;
   return t.tile_m > 0 && t.tile_n > 0 && lanes >= hpvm::kWave && lanes <= 1024 &&
-         lanes % hpvm::kWave == 0 && t.tile_k == t.tile_m && t.stages == 1;
+         lanes % hpvm::kWave == 0 && ((t.tile_k == t.tile_m && t.stages == 1) || is_flat(t));
 }
 
 const hpvm::MfmaEntry* find_entry(int32_t prec, const hpvm_tile* tile) {
@@ -138,7 +140,7 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
     if (!literal_ok(*tile))
       return fail(HPVM_UNSUPPORTED,
                   "argument %d: literal tile %dx%d (k %d, stages %d) needs 64..1024 lanes in whole "
-                  "wavefronts, tile_k == tile_m and one stage",
+                  "wavefronts, and tile_k == tile_m with one stage, or tile_k = 0 with none (untiled)",
                   argno, tile->tile_m, tile->tile_n, tile->tile_k, tile->stages);
     return HPVM_OK;
   }
@@ -194,12 +196,16 @@ namespace {
 // Built-in choice of hpvm_sgemm_ws (and of hpvm_sgemm_workspace_bytes) for
 // tile == NULL when the autotuner has no entry: FP32 products that even
 // 128 x 128 tiles would not cover the CUs with take the DMA-fed entry that
-// splits the contraction into the deepest slices; BF16 and bf16x3 products
-// of at least 2^31 multiply-adds take the first staged tile, whose
-// conversion pass is then a small share of the time (or, when that gives fewer than 256 tiles, the 128 x 128 x 64 tile
-// with 64 x 32 leaves).  Returns false when neither applies (hpvm_sgemm's
-// choice then).
-bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* out) {
+// splits the contraction into the deepest slices, provided `ws_bytes` (the
+// caller's workspace; -1 = as much as needed) holds its partial sums;
+// BF16 and bf16x3 products of at least 2^31 multiply-adds take the first
+// staged tile, whose conversion pass is then a small share of the time (or,
+// when that gives fewer than 256 tiles, the 128 x 128 x 64 tile with
+// 64 x 32 leaves).  Returns false when neither applies (hpvm_sgemm's choice
+// then): a split tile run as one launch would be the slowest choice there
+// is (64 tiles of 128 x 128 at 1024 x 1024 x 4096: 28 TFLOP/s against 75
+// for hpvm_sgemm's 64 x 64 tiles).
+bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, int64_t ws_bytes, hpvm_tile* out) {
   if (prec == HPVM_PREC_FP32) {
     // Only when even 128 x 128 tiles would not cover the CUs; then the
     // deepest slices = fewest partial sums, the first in menu order on a tie.
@@ -215,7 +221,7 @@ bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* o
         best_bytes = b;
       }
     }
-    if (!best) return false;
+    if (!best || (ws_bytes >= 0 && ws_bytes < best_bytes)) return false;
     *out = best->tile;
     return true;
   }
@@ -229,6 +235,28 @@ bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, hpvm_tile* o
   const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{128, 128, 64, 64, 32, 3});
   *out = tiles_of(staged[0].tile, m, n) >= 256 || !small ? staged[0].tile : small->tile;
   return true;
+}
+
+// The tile a call with tile == NULL runs.  ws_ok: the call has a workspace
+// argument (hpvm_sgemm_ws); ws_bytes: its size, or -1 for "as much as the
+// choice needs" (hpvm_sgemm_workspace_bytes asks which tile that is).  In
+// order: the autotuned winner (with a workspace the overall one, unless it
+// splits the contraction and the workspace cannot hold the partial sums:
+// then the winner that needs none), the built-in workspace choice, the
+// built-in small-problem choice; false = the menu's entry 0.
+int describe_impl(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile, bool ws_ok,
+                  int64_t ws_bytes, hpvm_dfg* out);
+
+bool choose_tile(int32_t prec, int64_t m, int64_t n, int64_t k, bool ws_ok, int64_t ws_bytes, hpvm_tile* out) {
+  if (hpvm::tuned_tile(prec, m, n, k, ws_ok, out)) {
+    if (!ws_ok || ws_bytes < 0) return true;
+    const hpvm::MfmaEntry* e = hpvm::find_menu_entry(prec, *out);
+    const int64_t split = hpvm::entry_split_bytes(e, m, n, k);
+    if (split == 0 || ws_bytes >= split) return true;
+    return hpvm::tuned_tile(prec, m, n, k, false, out) != 0;
+  }
+  if (ws_ok && default_ws_tile(prec, m, n, k, ws_bytes, out)) return true;
+  return hpvm::default_small_tile(prec, m, n, out);
 }
 
 }  // namespace
@@ -259,7 +287,7 @@ int hpvm_alloc_bytes(const hpvm_tile* tile, int32_t prec, int64_t* bytes) {
   const hpvm::MfmaEntry* e;
   int rc = resolve(prec, tile, &e, 1);
   if (rc != HPVM_OK) return rc;
-  *bytes = e ? e->lds_bytes : hpvm::literal_alloc_bytes(tile->tile_n, tile->tile_m);
+  *bytes = e ? e->lds_bytes : is_flat(*tile) ? 0 : hpvm::literal_alloc_bytes(tile->tile_n, tile->tile_m);
   return ok();
 }
 
@@ -280,17 +308,43 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile
   if (k < 0) return fail(HPVM_INVALID_ARG, "argument 3: k = %lld < 0", (long long)k);
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
   if (!out) return fail(HPVM_INVALID_ARG, "argument 6: out is NULL");
-  hpvm_tile small;
-  if (!tile && hpvm::tuned_tile(prec, m, n, k, false, &small)) tile = &small;
-  else if (!tile && hpvm::default_small_tile(prec, m, n, &small)) tile = &small;
+  return describe_impl(m, n, k, prec, tile, false, 0, out);
+}
+
+int hpvm_describe_ws(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile,
+                     int64_t workspace_bytes, hpvm_dfg* out) {
+  if (m < 0) return fail(HPVM_INVALID_ARG, "argument 1: m = %lld < 0", (long long)m);
+  if (n < 0) return fail(HPVM_INVALID_ARG, "argument 2: n = %lld < 0", (long long)n);
+  if (k < 0) return fail(HPVM_INVALID_ARG, "argument 3: k = %lld < 0", (long long)k);
+  if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
+  if (workspace_bytes < 0)
+    return fail(HPVM_INVALID_ARG, "argument 6: workspace_bytes = %lld < 0", (long long)workspace_bytes);
+  if (!out) return fail(HPVM_INVALID_ARG, "argument 7: out is NULL");
+  return describe_impl(m, n, k, prec, tile, true, workspace_bytes, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+int describe_impl(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile, bool ws_ok,
+                  int64_t ws_bytes, hpvm_dfg* out) {
+  hpvm_tile chosen;
+  if (!tile && choose_tile(prec, m, n, k, ws_ok, ws_bytes, &chosen)) tile = &chosen;
   const hpvm::MfmaEntry* e;
   int rc = resolve(prec, tile, &e, 5);
   if (rc != HPVM_OK) return rc;
   const hpvm_tile t = e ? e->tile : *tile;
+  std::memset(out, 0, sizeof *out);
   out->root_instances = 1;
+  out->splits = 1;
+  out->tile = t;
+  const int64_t split = ws_ok ? hpvm::entry_split_bytes(e, m, n, k) : 0;
+  if (split > 0 && ws_bytes >= split && m > 0 && n > 0 && k > 0)
+    out->splits = (int32_t)(split / (m * n * (int64_t)sizeof(float)));
   out->grid_x = (int32_t)((n + t.tile_n - 1) / t.tile_n);
   out->grid_y = (int32_t)((m + t.tile_m - 1) / t.tile_m);
-  out->k_slabs = (int32_t)((k + t.tile_k - 1) / t.tile_k);
+  out->k_slabs = t.tile_k > 0 ? (int32_t)((k + t.tile_k - 1) / t.tile_k) : 0;
   if (e) {
     out->block_x = e->threads;
     out->block_y = 1;
@@ -306,11 +360,16 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile
     out->block_x = t.tile_n;
     out->block_y = t.tile_m;
     out->waves = t.tile_m * t.tile_n / hpvm::kWave;
-    out->alloc_bytes = hpvm::literal_alloc_bytes(t.tile_n, t.tile_m);
-    out->lowering = hpvm::kLiteral;
+    out->alloc_bytes = is_flat(t) ? 0 : hpvm::literal_alloc_bytes(t.tile_n, t.tile_m);
+    out->lowering = is_flat(t) ? hpvm::kFlat : hpvm::kLiteral;
+    if (is_flat(t)) out->k_slabs = 0;
   }
   return ok();
 }
+
+}  // namespace
+
+extern "C" {
 
 // The sgemm graph of Sec. 6.1: SgemmRoot (0) creates a 2-D SgemmInternal (1)
 // and binds its inputs 0..13 through; SgemmInternal creates Allocation (2)
@@ -351,9 +410,7 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
   if (rc != HPVM_OK) return rc;
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 12: unknown precision %d", prec);
   hpvm_tile tuned;
-  if (!tile && hpvm::tuned_tile(prec, m, n, k, ws_ok, &tuned)) tile = &tuned;
-  else if (!tile && ws_ok && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
-  else if (!tile && hpvm::default_small_tile(prec, m, n, &tuned)) tile = &tuned;
+  if (!tile && choose_tile(prec, m, n, k, ws_ok, workspace ? workspace_bytes : 0, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   rc = resolve(prec, tile, &entry, 13);
   if (rc != HPVM_OK) return rc;
@@ -400,6 +457,8 @@ int sgemm_impl(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int
     e = entry->launch_split(a, workspace, s);
   else if (entry)
     e = entry->launch(a, false, false, s);
+  else if (is_flat(*tile))
+    e = hpvm::launch_flat(a, tile->tile_n, tile->tile_m, s);
   else
     e = hpvm::launch_literal(a, tile->tile_n, tile->tile_m, s);
   return e == hipSuccess ? ok() : hip_fail(e, "sgemm launch");
@@ -427,9 +486,7 @@ int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec, co
   if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 4: unknown precision %d", prec);
   if (!bytes) return fail(HPVM_INVALID_ARG, "argument 6: bytes is NULL");
   hpvm_tile tuned;
-  if (!tile && hpvm::tuned_tile(prec, m, n, k, true, &tuned)) tile = &tuned;
-  else if (!tile && default_ws_tile(prec, m, n, k, &tuned)) tile = &tuned;
-  else if (!tile && hpvm::default_small_tile(prec, m, n, &tuned)) tile = &tuned;
+  if (!tile && choose_tile(prec, m, n, k, true, -1, &tuned)) tile = &tuned;
   const hpvm::MfmaEntry* entry;
   int rc = resolve(prec, tile, &entry, 5);
   if (rc != HPVM_OK) return rc;

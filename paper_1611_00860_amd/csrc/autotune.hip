@@ -5,7 +5,9 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <map>
+#include <string>
 #include <mutex>
 #include <tuple>
 #include <vector>
@@ -13,6 +15,10 @@
 #include "device_common.hpp"
 #include "hpvm_sgemm.h"
 #include "internal.hpp"
+
+#ifndef HPVM_TARGET_ARCH
+#define HPVM_TARGET_ARCH "gfx950"
+#endif
 
 namespace hpvm {
 namespace {
@@ -62,6 +68,29 @@ Choice single_choice(int32_t prec, const hpvm_tile& t, float ms) {
     c.fused_ms = -1.0f;
   }
   return c;
+}
+
+// What a saved entry is valid for: the GPU architecture (the current
+// device's, without its feature suffix, else the one this library is
+// compiled for) and the HIP runtime version in use (else the one it was
+// built against).  Timings taken on another architecture or runtime say
+// nothing about this one, so loading skips entries with another tag.
+std::string cache_tag() {
+  std::string arch = HPVM_TARGET_ARCH;
+  int count = 0, dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceCount(&count) == hipSuccess && count > 0 && hipGetDevice(&dev) == hipSuccess &&
+      hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.gcnArchName[0]) {
+    arch.assign(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof prop.gcnArchName));
+    arch = arch.substr(0, arch.find(':'));
+  }
+  (void)hipGetLastError();  // a host without a device leaves an error behind
+  int runtime = 0;
+  if (hipRuntimeGetVersion(&runtime) != hipSuccess || runtime <= 0) runtime = HIP_VERSION;
+  (void)hipGetLastError();
+  char buf[96];
+  std::snprintf(buf, sizeof buf, "%s hip%d", arch.c_str(), runtime);
+  return buf;
 }
 
 }  // namespace
@@ -182,16 +211,18 @@ int hpvm_autotune_save(const char* path) {
   if (!path) return set_error(HPVM_INVALID_ARG, "argument 1: path is NULL");
   FILE* f = std::fopen(path, "w");
   if (!f) return set_error(HPVM_INVALID_ARG, "cannot open %s for writing", path);
+  const std::string tag = cache_tag();
   std::fprintf(f,
-               "# hpvm_sgemm autotune cache v2: prec m n k | best tile (m n k leaf_m leaf_n stages) ms | "
-               "best tile without workspace, ms\n");
+               "# hpvm_sgemm autotune cache v3: arch runtime | prec m n k | best tile (m n k leaf_m leaf_n "
+               "stages) ms | best tile without workspace, ms\n");
   {
     std::lock_guard<std::mutex> lk(g_mu);
     for (const auto& kv : g_cache) {
       if (std::get<4>(kv.first)) continue;  // class entries are rebuilt on load
       const hpvm_tile& t = kv.second.tile;
       const hpvm_tile& u = kv.second.fused;
-      std::fprintf(f, "%d %lld %lld %lld %d %d %d %d %d %d %.6f %d %d %d %d %d %d %.6f\n", std::get<0>(kv.first),
+      std::fprintf(f, "%s %d %lld %lld %lld %d %d %d %d %d %d %.6f %d %d %d %d %d %d %.6f\n", tag.c_str(),
+                   std::get<0>(kv.first),
                    (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
                    (long long)std::get<3>(kv.first), t.tile_m, t.tile_n, t.tile_k, t.leaf_m, t.leaf_n, t.stages,
                    kv.second.ms, u.tile_m, u.tile_n, u.tile_k, u.leaf_m, u.leaf_n, u.stages, kv.second.fused_ms);
@@ -205,17 +236,20 @@ int hpvm_autotune_load(const char* path) {
   if (!path) return set_error(HPVM_INVALID_ARG, "argument 1: path is NULL");
   FILE* f = std::fopen(path, "r");
   if (!f) return set_error(HPVM_INVALID_ARG, "cannot open %s", path);
+  const std::string tag = cache_tag();
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
+    char arch[64], runtime[32];
     int prec;
     long long m, n, k;
     hpvm_tile t, u;
     float ms, ums;
-    if (std::sscanf(line, "%d %lld %lld %lld %d %d %d %d %d %d %f %d %d %d %d %d %d %f", &prec, &m, &n, &k,
-                    &t.tile_m, &t.tile_n, &t.tile_k, &t.leaf_m, &t.leaf_n, &t.stages, &ms, &u.tile_m, &u.tile_n,
-                    &u.tile_k, &u.leaf_m, &u.leaf_n, &u.stages, &ums) != 18)
+    if (std::sscanf(line, "%63s %31s %d %lld %lld %lld %d %d %d %d %d %d %f %d %d %d %d %d %d %f", arch, runtime,
+                    &prec, &m, &n, &k, &t.tile_m, &t.tile_n, &t.tile_k, &t.leaf_m, &t.leaf_n, &t.stages, &ms,
+                    &u.tile_m, &u.tile_n, &u.tile_k, &u.leaf_m, &u.leaf_n, &u.stages, &ums) != 20)
       continue;
+    if (tag != std::string(arch) + " " + runtime) continue;  // timed on another device or runtime
     if (m < 0 || n < 0 || k < 0 || !in_menu(prec, t) || !in_menu(prec, u) || needs_workspace(prec, u)) continue;
     record(prec, m, n, k, Choice{t, ms, u, ums});
   }

@@ -13,7 +13,15 @@ namespace hpvm {
 struct GemmArgs;
 
 // Lowering ids (hpvm_dfg.lowering).
-enum Lowering { kLiteral = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kMfmaBf16x3 = 3, kStagedBf16 = 4, kStagedBf16x3 = 5 };
+enum Lowering {
+  kLiteral = 0,
+  kMfmaF32 = 1,
+  kMfmaBf16 = 2,
+  kMfmaBf16x3 = 3,
+  kStagedBf16 = 4,
+  kStagedBf16x3 = 5,
+  kFlat = 6,
+};
 
 // bfloat16 planes of one staged product, the contraction index contiguous:
 // the A side [round256(m)][kp], the B side [round256(n)][kp], kp =
@@ -135,6 +143,8 @@ void record_backward_tile(int32_t prec, int64_t m, int64_t n, int64_t k, const h
 
 // Literal lowering: block_x x block_y lanes, one output each.
 hipError_t launch_literal(const GemmArgs& args, int block_x, int block_y, hipStream_t s);
+// Untiled one-level graph: one lane per output, no Allocation node.
+hipError_t launch_flat(const GemmArgs& args, int block_x, int block_y, hipStream_t s);
 int64_t literal_alloc_bytes(int block_x, int block_y);
 
 // C <- beta * C (beta == 0 writes zeros without reading C).

@@ -38,6 +38,33 @@ __global__ void sgemm_leaf_literal(GemmArgs p) {
   }
 }
 
+// The untiled form of the same computation (the "non-tiled" version that
+// Sec. 3.4 and 5.1 compare the tiled graph with): a one-level graph whose
+// 2-D leaf grid covers C, one instance per element, reading its row of A
+// and column of B straight from global memory -- no SgemmInternal level and
+// no Allocation node.  The workgroup shape only groups leaf instances into
+// launches; nothing is shared between them.
+__global__ void sgemm_leaf_flat(GemmArgs p) {
+  const int64_t i = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.m || j >= p.n) return;
+  const float* a = p.A + i * p.lda;
+  const float* b = p.B + j;
+  float acc = 0.0f;
+  for (int64_t t = 0; t < p.k; ++t) acc = fmaf(a[t], b[t * p.ldb], acc);
+  float v = p.alpha * acc;
+  if (p.beta != 0.0f) v = fmaf(p.beta, p.C[i * p.ldc + j], v);
+  p.C[i * p.ldc + j] = v;
+}
+
+hipError_t launch_flat(const GemmArgs& args, int block_x, int block_y, hipStream_t s) {
+  dim3 block(block_x, block_y);
+  dim3 grid((unsigned)((args.n + block_x - 1) / block_x), (unsigned)((args.m + block_y - 1) / block_y));
+  GemmArgs a = args;
+  void* kargs[] = {&a};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_leaf_flat), grid, block, kargs, 0, s);
+}
+
 int64_t literal_alloc_bytes(int block_x, int block_y) {
   // The Allocation node function: (block_x * block_y) << 2 bytes.
   return ((int64_t)block_x * (int64_t)block_y) << 2;

@@ -233,6 +233,8 @@ namespace {
 constexpr uint64_t kStreamMagic = 0x48505653474d4d53ull;  // "HPVSGMMS"
 constexpr int kMaxCapacity = 4096;
 constexpr int kMaxIdleMs = 60000;
+constexpr int kMaxGridPerCu = 2;  // resident workgroups per CU (see hpvm_stream_open)
+constexpr int kMaxCus = 256;      // CUs of the largest gfx950 part
 
 struct Stream {
   uint64_t magic = kStreamMagic;
@@ -363,8 +365,14 @@ int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
   if (!cfg) return set_error(HPVM_INVALID_ARG, "argument 1: config is NULL");
   if (cfg->capacity < 1 || cfg->capacity > kMaxCapacity)
     return set_error(HPVM_INVALID_ARG, "argument 1: capacity = %d not in [1, %d]", cfg->capacity, kMaxCapacity);
-  if (cfg->grid < 0 || cfg->grid > 65536)
-    return set_error(HPVM_INVALID_ARG, "argument 1: grid = %d not in [0, 65536]", cfg->grid);
+  // Two resident workgroups per CU at most: a third takes every SIMD's
+  // registers, so no wave of another kernel (a copy's blit kernel included)
+  // could start while the stream is open; such work would wait until the
+  // stream idles out.  512 = two per CU of a 256-CU gfx950 part; the
+  // device's own CU count is checked again below.
+  if (cfg->grid < 0 || cfg->grid > kMaxGridPerCu * kMaxCus)
+    return set_error(HPVM_INVALID_ARG, "argument 1: grid = %d not in [0, %d] (at most %d workgroups per CU)",
+                     cfg->grid, kMaxGridPerCu * kMaxCus, kMaxGridPerCu);
   if (cfg->idle_ms < 1 || cfg->idle_ms > kMaxIdleMs)
     return set_error(HPVM_INVALID_ARG, "argument 1: idle_ms = %d not in [1, %d]", cfg->idle_ms, kMaxIdleMs);
   if (!handle) return set_error(HPVM_INVALID_ARG, "argument 2: handle is NULL");
@@ -380,9 +388,12 @@ int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
   if (e == hipSuccess && rate_khz <= 0) e = hipErrorInvalidValue;
-  // Two resident workgroups per CU: a third would hold every SIMD's
-  // registers and keep other kernels off the device while the stream is open.
-  s->grid = cfg->grid > 0 ? cfg->grid : 2 * std::max(cus, 1);
+  if (e == hipSuccess && cfg->grid > kMaxGridPerCu * std::max(cus, 1)) {
+    delete s;
+    return set_error(HPVM_INVALID_ARG, "argument 1: grid = %d is more than %d workgroups per CU on %d CUs",
+                     cfg->grid, kMaxGridPerCu, cus);
+  }
+  s->grid = cfg->grid > 0 ? cfg->grid : kMaxGridPerCu * std::max(cus, 1);
   const int64_t hb = host_bytes(s->capacity);
   if (e == hipSuccess) {
     s->host = pool_take(hb, &s->host_size);  // a block of at least hb bytes

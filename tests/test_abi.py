@@ -101,6 +101,19 @@ def test_describe_literal_config():
     assert d["waves"] == 16
 
 
+def test_describe_untiled_graph():
+    """tile_k = 0, stages = 0: the one-level graph with no Allocation node."""
+    d = hp.describe(128, 128, 128, "fp32", (32, 32, 0, 1, 1, 0))
+    assert (d["grid_x"], d["grid_y"], d["block_x"], d["block_y"]) == (4, 4, 32, 32)
+    assert d["alloc_bytes"] == 0 and d["lowering_name"] == "flat" and d["k_slabs"] == 0
+    assert hp.alloc_bytes((32, 32, 0, 1, 1, 0)) == 0
+    for bad in ((32, 32, 0, 1, 1, 2), (32, 32, 16, 1, 1, 0), (4, 4, 0, 1, 1, 0)):
+        with pytest.raises(hp.HpvmError):
+            hp.describe(128, 128, 128, "fp32", bad)
+    with pytest.raises(hp.HpvmError):
+        hp.describe(128, 128, 128, "bf16", (32, 32, 0, 1, 1, 0))
+
+
 def test_describe_mfma_grids():
     menu = hp.tile_menu("fp32")
     assert menu, "no FP32 MFMA tile compiled"
@@ -312,6 +325,54 @@ def test_autotune_cache_host_side(lib, tmp_path):
     hp.autotune_clear()
 
 
+def test_autotune_cache_keyed_by_arch_and_runtime(lib, tmp_path):
+    """Saved entries carry the GPU architecture and HIP runtime they were
+    timed on; loading skips entries whose tag differs from this process's."""
+    hp.autotune_clear()
+    menu = hp.tile_menu("fp32")
+    hp.autotune_record(2048, 2048, 2048, menu[1], "fp32", 0.5)
+    path = tmp_path / "cache.txt"
+    hp.autotune_save(path)
+    lines = [l for l in open(path) if not l.startswith("#")]
+    assert len(lines) == 1
+    arch, runtime = lines[0].split()[:2]
+    assert arch.startswith("gfx") and ":" not in arch and runtime.startswith("hip")
+    rest = " ".join(lines[0].split()[2:])
+    hp.autotune_clear()
+    hp.autotune_load(path)
+    assert hp.autotune_lookup(2048, 2048, 2048, "fp32") == (menu[1], 2)
+    for other in (f"gfx942 {runtime}", f"{arch} hip1", "0"):  # another arch, another runtime, untagged
+        hp.autotune_clear()
+        with open(path, "w") as f:
+            f.write(f"{other} {rest}\n")
+        hp.autotune_load(path)
+        assert hp.autotune_lookup(2048, 2048, 2048, "fp32")[1] == 0, other
+    hp.autotune_clear()
+
+
+def test_describe_ws_reports_the_split_only_when_the_workspace_holds_it(lib):
+    """hpvm_sgemm_ws with no tile splits the contraction of an FP32 problem
+    that even 128 x 128 tiles leave CUs idle on, only when the workspace
+    holds the partial sums; otherwise it takes hpvm_sgemm's tile."""
+    hp.autotune_clear()
+    m, n, k = 1024, 1024, 4096
+    need = hp.workspace_bytes(m, n, k, "fp32")
+    assert need > 0 and need % (4 * m * n) == 0
+    full = hp.describe(m, n, k, "fp32", workspace_bytes=need)
+    assert full["splits"] == need // (4 * m * n) > 1
+    plain = hp.describe(m, n, k, "fp32")
+    assert plain["splits"] == 1
+    for short in (0, need - 1):
+        d = hp.describe(m, n, k, "fp32", workspace_bytes=short)
+        assert d == plain, short  # the single launch's own choice, not the split tile unsplit
+    assert (full["grid_x"], full["grid_y"]) != (plain["grid_x"], plain["grid_y"])
+    # a problem 128 x 128 tiles cover never splits
+    assert hp.workspace_bytes(4096, 4096, 4096, "fp32") == 0
+    assert hp.describe(4096, 4096, 4096, "fp32", workspace_bytes=1 << 30)["splits"] == 1
+    with pytest.raises(hp.HpvmError):
+        hp.describe(m, n, k, "fp32", workspace_bytes=-1)
+
+
 def test_backward_validation(lib):
     ws = ctypes.c_int64()
     assert lib.hpvm_sgemm_backward_workspace_bytes(4096, 4096, 1024, 0, None, ctypes.byref(ws)) == 0
@@ -490,6 +551,14 @@ def test_stream_validation(lib, monkeypatch):
     assert open_(cap=0) == -1 and "capacity" in hp.last_error()
     assert open_(cap=4097) == -1
     assert open_(grid=-1) == -1 and "grid" in hp.last_error()
+    # more than two resident workgroups per CU would starve every other
+    # kernel while the stream is open: refused before any HIP call
+    for grid in (513, 768, 65536):
+        monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")  # a grid that passed would stop here with -3
+        assert open_(grid=grid) == -1 and "grid" in hp.last_error(), grid
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    assert open_(grid=512) == -3  # two per CU of 256 CUs passes the host check
+    monkeypatch.delenv("HPVM_FAULT_INJECT")
     assert open_(idle=0) == -1 and "idle_ms" in hp.last_error()
     assert open_(idle=60001) == -1
     assert open_(handle=False) == -1 and "argument 2" in hp.last_error()

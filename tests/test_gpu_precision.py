@@ -50,12 +50,78 @@ def test_random_against_exact_and_split_aware(gpu, prec, dist):
     exact = oracle.sgemm(A, B, C, alpha, beta)
     split = oracle.sgemm(A, B, C, alpha, beta, mode=prec)
     terms = 3 * k if prec == "bf16x3" else k
-    bound = componentwise_bound(A, B, C, alpha, beta, terms, extra=2.0 ** -7 if prec == "bf16" else 0)
+    bound = componentwise_bound(A, B, C, alpha, beta, terms)
     for tile in gpu.tile_menu(prec):
         print(f"case: {prec} {dist} tile {tile}", flush=True)
         got = run(gpu, A, B, C, alpha, beta, prec, tile=tile)
         assert normwise(got, exact) <= BAR[prec], tile
         assert np.all(np.abs(got - split) <= bound), tile
+
+
+# ---------------------------------------------------------------------------
+# The conversion itself, bit for bit.  With one nonzero column of A (or row
+# of B) meeting ones, every output is a single product x * 1, exact in FP32:
+# BF16 must give the oracle's round-to-nearest-even bf16(x), bf16x3 must give
+# hi + lo of the oracle's split (also exact in FP32).  Truncating instead of
+# rounding, rounding ties away from zero, or losing the lo part fails here.
+# ---------------------------------------------------------------------------
+def special_values(count, seed):
+    """float32 values that decide a conversion: ties (to an even and to an
+    odd neighbour), one bit either side of a tie, subnormals, the largest
+    finite values (some round to infinity), zeros, then random bit patterns
+    over the whole finite range, both signs."""
+    bits = [0x3F808000, 0x3F818000, 0x3F808001, 0x3F807FFF, 0x3F818001, 0x3F817FFF,  # ties near 1
+            0x40490FDB, 0x3EAAAAAB, 0x3DCCCCCD, 0x42F6E979, 0x4B7FFFFF, 0x4B800001,  # pi, 1/3, 0.1, 123.456, ...
+            0x00000001, 0x00008000, 0x00018000, 0x00017FFF, 0x007FFFFF, 0x00400000,  # subnormals
+            0x00808000, 0x00818000, 0x0080FFFF,                                       # smallest normals
+            0x7F7FFFFF, 0x7F7F7FFF, 0x7F7F8000, 0x7F7E8000, 0x7F7F0000,               # largest finite
+            0x00000000, 0x3F800000, 0x3F7FFFFF, 0x33800000, 0x33800001]
+    bits += [b | 0x80000000 for b in bits]
+    rng = np.random.default_rng(seed)
+    rnd = rng.integers(0, 0x7F800000, count - len(bits), dtype=np.int64)
+    rnd |= rng.integers(0, 2, rnd.shape[0], dtype=np.int64) << 31
+    return np.concatenate([np.array(bits, dtype=np.uint32), rnd.astype(np.uint32)]).view(np.float32)
+
+
+def conversion_expected(prec, x):
+    if prec == "bf16":
+        return oracle.bf16_round(x).astype(np.float64)
+    hi, lo = oracle.bf16_split(x)
+    return hi.astype(np.float64) + lo.astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("k,p", [(1, 0), (40, 0), (40, 39), (200, 131)])
+@pytest.mark.parametrize("side", ["A", "B"])
+def test_conversion_is_rne_bit_exact_all_tiles(gpu, prec, k, p, side):
+    import torch
+
+    vals = special_values(700, seed=k + p)
+    w = 72
+    if side == "A":  # column p of A holds the values, row p of B is ones
+        m, n = vals.shape[0], w
+        A = np.zeros((m, k), np.float32)
+        A[:, p] = vals
+        B = np.zeros((k, n), np.float32)
+        B[p, :] = 1.0
+        expect = np.repeat(conversion_expected(prec, vals)[:, None], n, axis=1)
+    else:  # row p of B holds the values, column p of A is ones
+        m, n = w, vals.shape[0]
+        A = np.zeros((m, k), np.float32)
+        A[:, p] = 1.0
+        B = np.zeros((k, n), np.float32)
+        B[p, :] = vals
+        expect = np.repeat(conversion_expected(prec, vals)[None, :], m, axis=0)
+    dA, dB = to_dev(A), to_dev(B)
+    for tile in gpu.tile_menu(prec):
+        print(f"case: {prec} conversion side {side} k {k} p {p} tile {tile}", flush=True)
+        dC = torch.full((m, n), float("nan"), device="cuda")
+        gpu.sgemm(dA, dB, dC, 1.0, 0.0, prec=prec, tile=tile)
+        torch.cuda.synchronize()
+        got = to_host(dC)
+        assert np.array_equal(np.isnan(got), np.isnan(expect)), tile
+        bad = ~np.isnan(expect) & (got != expect)
+        assert not bad.any(), (tile, vals[np.nonzero(bad.any(axis=1 if side == "A" else 0))[0][:5]])
 
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])

@@ -49,6 +49,23 @@ def test_literal_ragged(gpu, m, n, k, tile):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("m,n,k,tile", [(128, 128, 128, (32, 32, 0, 1, 1, 0)), (100, 70, 45, (16, 16, 0, 1, 1, 0)),
+                                        (33, 64, 17, (8, 32, 0, 1, 1, 0))])
+def test_untiled_graph_integers_bit_exact(gpu, m, n, k, tile):
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=2, dist="int")
+    ref = oracle.sgemm(A, B, C, 2.0, -1.0)
+    got = run(gpu, A, B, C, 2.0, -1.0, tile=tile, pad=3)
+    assert np.array_equal(got, ref)
+
+
+def test_untiled_graph_small_config(gpu):
+    A, B, C = inputs.sgemm_operands(128, 128, 128, seed=0)
+    ref = oracle.sgemm(A, B, C, 1.0, 0.5)
+    got = run(gpu, A, B, C, 1.0, 0.5, tile=(32, 32, 0, 1, 1, 0))
+    assert normwise(got, ref) <= 1e-5
+    assert np.all(np.abs(got - ref) <= componentwise_bound(A, B, C, 1.0, 0.5, 128))
+
+
 def test_root_launch_packed_args(gpu):
     """The paper's 88-byte root argument block drives the same lowering."""
     import torch
@@ -285,3 +302,94 @@ def test_split_contraction_without_workspace_runs_unsplit(gpu):
     torch.cuda.synchronize()
     product = A.astype(np.float64) @ B.astype(np.float64)  # exact: integers below 2^53
     assert np.array_equal(to_host(dC), product + C.astype(np.float64))
+
+
+# ---------------------------------------------------------------------------
+# 4096^3, beta = 1, in the launch configuration the benchmark times: every
+# output against the oracle (normwise and componentwise).
+# ---------------------------------------------------------------------------
+def test_f32_4096_beta1_all_outputs(gpu):
+    import torch
+
+    n = 4096
+    print("case: fp32 4096^3 beta 1, all outputs", flush=True)
+    A, B, C = inputs.sgemm_operands(n, n, n, seed=1)
+    dA, dB, dC = (to_dev(x) for x in (A, B, C))
+    gpu.sgemm(dA, dB, dC, 1.0, 1.0)
+    torch.cuda.synchronize()
+    got = to_host(dC)
+    del dA, dB, dC
+    ref = oracle.sgemm(A, B, C, 1.0, 1.0)
+    assert normwise(got, ref) <= 1e-5
+    assert np.all(np.abs(got - ref) <= componentwise_bound(A, B, C, 1.0, 1.0, n))
+
+
+# ---------------------------------------------------------------------------
+# A stream that is not torch's current one: the scratch memory a call
+# allocates for itself (here the split contraction's partial sums) must not
+# be handed to other work on the current stream while that stream still
+# uses it.
+# ---------------------------------------------------------------------------
+def test_split_on_a_side_stream_keeps_its_workspace(gpu):
+    import torch
+
+    m, n, k = 1024, 1024, 4096
+    need = gpu.workspace_bytes(m, n, k, "fp32")
+    assert need > 0  # the default tile splits this problem
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=57, dist="int")
+    dA, dB, dC = (to_dev(x) for x in (A, B, C))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # keep the side stream busy so the split runs late
+        x = torch.ones((4096, 4096), device="cuda")
+        for _ in range(4):
+            x = x @ x
+    gpu.sgemm(dA, dB, dC, 1.0, 2.0, stream=side)  # the side stream is not made current
+    # the current stream now allocates and fills memory of the workspace's size
+    junk = torch.full((need // 4,), float("nan"), device="cuda")
+    junk.add_(1.0)
+    side.synchronize()
+    torch.cuda.synchronize()
+    product = A.astype(np.float64) @ B.astype(np.float64)  # integers: exact
+    assert np.array_equal(to_host(dC), product + 2.0 * C.astype(np.float64))
+    del x, junk
+
+
+# ---------------------------------------------------------------------------
+# The single-launch autotuner: it reads A and B only, records a tile of the
+# menu, and a call with no tile then runs exactly that tile (with a
+# workspace) or the recorded tile that needs none (without).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,k", [(1024, 1024, 4096), (2048, 2048, 1024)])
+def test_autotune_records_a_menu_tile_and_uses_it(gpu, m, n, k):
+    import torch
+
+    print(f"case: autotune fp32 {m}x{n}x{k}", flush=True)
+    gpu.autotune_clear()
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=59)
+    dA, dB, dC = (to_dev(x) for x in (A, B, C))
+    a0, b0, c0 = dA.clone(), dB.clone(), dC.clone()
+    best, ms = gpu.autotune(dA, dB, "fp32", reps=2)
+    torch.cuda.synchronize()
+    assert torch.equal(dA, a0) and torch.equal(dB, b0) and torch.equal(dC, c0)
+    menu = gpu.tile_menu("fp32")
+    assert best in menu and ms > 0
+    assert gpu.autotune_lookup(m, n, k, "fp32") == (best, 2)
+    ws = gpu.workspace_bytes(m, n, k, "fp32")
+    assert ws == gpu.workspace_bytes(m, n, k, "fp32", best)
+    # the choice without a workspace never splits the contraction
+    plain = gpu.describe(m, n, k, "fp32")
+    assert plain["splits"] == 1 and plain["tile"] in menu
+    if gpu.workspace_bytes(m, n, k, "fp32", plain["tile"]) > 0:
+        assert plain["tile"] != best  # a split winner is not the no-workspace choice
+    with_ws = gpu.describe(m, n, k, "fp32", workspace_bytes=ws)
+    assert with_ws["tile"] == best
+    ref = oracle.sgemm(A, B, C, 1.0, 0.5)
+    for tile, wsarg in ((best, None), (plain["tile"], False)):
+        c1, c2 = to_dev(C), to_dev(C)
+        gpu.sgemm(dA, dB, c1, 1.0, 0.5, workspace=wsarg)
+        gpu.sgemm(dA, dB, c2, 1.0, 0.5, tile=tile, workspace=wsarg)
+        torch.cuda.synchronize()
+        assert torch.equal(c1, c2), (tile, wsarg)
+        assert normwise(to_host(c1), ref) <= 1e-5
+    gpu.autotune_clear()
