@@ -233,7 +233,10 @@ bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, int64_t ws_b
   // on 128 x 128 tiles then ran 1.8-3x faster (2048^3 BF16: 0.039 ms
   // against 0.070; at 4096^3 the first tile stays ahead, 0.150 against 0.159).
   const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{128, 128, 64, 64, 32, 3});
-  *out = tiles_of(staged[0].tile, m, n) >= 256 || !small ? staged[0].tile : small->tile;
+  const hpvm_tile pick = tiles_of(staged[0].tile, m, n) >= 256 || !small ? staged[0].tile : small->tile;
+  // A workspace too small for the planes: the choice without one.
+  if (ws_bytes >= 0 && ws_bytes < hpvm::staged_workspace_bytes(prec, m, n, k)) return false;
+  *out = pick;
   return true;
 }
 
@@ -251,8 +254,8 @@ bool choose_tile(int32_t prec, int64_t m, int64_t n, int64_t k, bool ws_ok, int6
   if (hpvm::tuned_tile(prec, m, n, k, ws_ok, out)) {
     if (!ws_ok || ws_bytes < 0) return true;
     const hpvm::MfmaEntry* e = hpvm::find_menu_entry(prec, *out);
-    const int64_t split = hpvm::entry_split_bytes(e, m, n, k);
-    if (split == 0 || ws_bytes >= split) return true;
+    const int64_t need = std::max(hpvm::entry_split_bytes(e, m, n, k), hpvm::entry_workspace_bytes(e, m, n, k));
+    if (need == 0 || ws_bytes >= need) return true;
     return hpvm::tuned_tile(prec, m, n, k, false, out) != 0;
   }
   if (ws_ok && default_ws_tile(prec, m, n, k, ws_bytes, out)) return true;

@@ -710,3 +710,19 @@ def test_staged_tiles_refuse_too_deep_a_contraction(lib):
         assert rc == -3
     finally:
         del os.environ["HPVM_FAULT_INJECT"]
+
+
+def test_workspace_choice_fits_the_workspace(lib):
+    """With no tile, hpvm_sgemm_ws takes the staged BF16 / bf16x3 planes only
+    when the workspace holds them; a smaller one gives the choice without a
+    workspace instead of a refusal."""
+    hp.autotune_clear()
+    for prec in ("bf16", "bf16x3"):
+        big = hp.describe(8192, 8192, 8192, prec, workspace_bytes=1 << 40)
+        assert big["lowering_name"] == f"staged_{prec}"
+        need = hp.workspace_bytes(8192, 8192, 8192, prec, big["tile"])
+        assert hp.describe(8192, 8192, 8192, prec, workspace_bytes=need)["lowering_name"] == f"staged_{prec}"
+        small = hp.describe(8192, 8192, 8192, prec, workspace_bytes=need - 1)
+        assert small["lowering_name"] != f"staged_{prec}"
+        assert small["tile"] == hp.describe(8192, 8192, 8192, prec)["tile"]
+
