@@ -233,6 +233,28 @@ int hpvm_sgemm_ws(int64_t m, int64_t n, int64_t k, float alpha, const float* A, 
 int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec,
                                const hpvm_tile* tile, int64_t* bytes);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * hpvm_sgemm_ws with, as its workspace, a fixed array of
+ * HPVM_NOALLOC_SCRATCH_BYTES bytes of device memory that the library holds
+ * on each device it runs on (from that device's first call until the
+ * process ends).  The call allocates and frees nothing.  Arguments, checks,
+ * results and errors are hpvm_sgemm_ws's for a workspace of that size: with
+ * tile == NULL the choice is the one that workspace allows (a split FP32
+ * contraction or the staged BF16 / bf16x3 planes only when they fit); an
+ * explicit tile of the staged lowering whose planes need more than
+ * HPVM_NOALLOC_SCRATCH_BYTES is refused with HPVM_WORKSPACE_TOO_SMALL
+ * before any device work, and an explicit split FP32 tile whose partial
+ * sums do not fit runs as one launch.  The array of the current device is
+ * used, so `stream` must belong to the current device.  Every call on a
+ * device shares that device's array: calls that overlap in time on one
+ * device (two streams, or two host threads) race on it and must be
+ * serialized by the caller; calls on one stream are ordered and safe.      */
+#define HPVM_NOALLOC_SCRATCH_BYTES ((int64_t)32 << 20)
+int hpvm_sgemm_noalloc(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
+                       const hpvm_tile* tile, void* stream);
+
 /* The paper's launch of the root node with its packed argument block
  * (Sec. 6.3, LaunchDataflowGraph unpacking the 88-byte block and calling the
  * generated SgemmRoot2).  Uses the literal lowering: block_x x block_y lanes

@@ -148,6 +148,29 @@ def sgemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None
     return C
 
 
+# Bytes of the device array hpvm_sgemm_noalloc uses as its workspace (the
+# header's HPVM_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def sgemm_noalloc(A, B, C, alpha: float = 1.0, beta: float = 0.0, prec="fp32", tile=None, stream=None):
+    """sgemm through hpvm_sgemm_noalloc: the library allocates nothing and its
+    fixed per-device array serves as the workspace (calls that overlap on one
+    device race on it).  Same arguments and results as ``sgemm`` with a
+    workspace of NOALLOC_SCRATCH_BYTES."""
+    lib = load()
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    _check(lib.hpvm_sgemm_noalloc(m, n, k, float(alpha), pa, lda, pb, ldb, float(beta), pc, ldc,
+                                  _prec(prec), _tile(tile), _stream(stream)))
+    return C
+
+
 def launch_root(A, B, C, k: int, alpha: float, beta: float, block, grid, stream=None,
                 bytes_override=None):
     """The root node's launch with the paper's packed 88-byte argument block.

@@ -110,6 +110,8 @@ SIGNATURES = {
     "hpvm_sgemm_ws": (ctypes.c_int, [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32, PTile, vp, i64,
                                      vp]),
     "hpvm_sgemm_workspace_bytes": (ctypes.c_int, [i64, i64, i64, i32, PTile, Pi64]),
+    "hpvm_sgemm_noalloc": (ctypes.c_int, [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32, PTile,
+                                          vp]),
     "hpvm_autotune_lookup": (ctypes.c_int, [i64, i64, i64, i32, PTile, ctypes.POINTER(i32)]),
     "hpvm_autotune_record": (ctypes.c_int, [i64, i64, i64, i32, PTile, f32]),
     "hpvm_autotune_clear": (ctypes.c_int, []),

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "device_common.hpp"
 #include "hpvm_sgemm.h"
@@ -533,3 +534,74 @@ int hpvm_wait(void* stream) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// hpvm_sgemm_noalloc: hpvm_sgemm_ws whose workspace is a fixed array of
+// device memory that the library's code object carries, so that the call
+// itself allocates nothing.  Each device that loads the library holds its
+// own copy of the array (at its own address) until the process ends.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Device-side storage.  On the host this name is only a stand-in for the
+// symbol: its device address, per device, comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[HPVM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kScratchDevices] = {};
+
+// The current device's copy of the array, looked up once per device with
+// that device current.
+int scratch_of_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(HPVM_UNSUPPORTED, "device %d: the no-allocation entry point supports devices 0..%d", dev,
+                kScratchDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || (uintptr_t)p % 256) return fail(HPVM_HIP_ERROR, "scratch symbol has no usable device address");
+    g_scratch_at[dev] = p;
+  }
+  *out = g_scratch_at[dev];
+  return HPVM_OK;
+}
+
+}  // namespace
+
+extern "C" int hpvm_sgemm_noalloc(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
+                                  const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
+                                  const hpvm_tile* tile, void* stream) {
+  // Checks in argument order, then the lowering hpvm_sgemm_ws would run with
+  // a workspace of HPVM_NOALLOC_SCRATCH_BYTES; nothing touches the device
+  // before all of them pass.
+  bool reads_ab = false;
+  int rc = hpvm::check_gemm_args("", m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, &reads_ab);
+  if (rc != HPVM_OK) return rc;
+  if (!valid_prec(prec)) return fail(HPVM_INVALID_ARG, "argument 12: unknown precision %d", prec);
+  const int64_t cap = HPVM_NOALLOC_SCRATCH_BYTES;
+  hpvm_tile chosen;
+  const hpvm_tile* t = tile;
+  if (!t && choose_tile(prec, m, n, k, true, cap, &chosen)) t = &chosen;
+  const hpvm::MfmaEntry* entry;
+  rc = resolve(prec, t, &entry, 13);
+  if (rc != HPVM_OK) return rc;
+  const int64_t need = hpvm::entry_workspace_bytes(entry, m, n, k);
+  if (need > cap && reads_ab && m > 0 && n > 0)
+    return fail(HPVM_WORKSPACE_TOO_SMALL,
+                "argument 13: this tile needs %lld bytes of scratch; the no-allocation entry point has %lld "
+                "(use hpvm_sgemm_ws with a workspace of that size)",
+                (long long)need, (long long)cap);
+  void* ws = nullptr;
+  if (reads_ab && m > 0 && n > 0 && (need > 0 || hpvm::entry_split_bytes(entry, m, n, k) > 0)) {
+    if (inject("launch")) return fail(HPVM_HIP_ERROR, "injected launch failure (HPVM_FAULT_INJECT)");
+    rc = scratch_of_current_device(&ws);
+    if (rc != HPVM_OK) return rc;
+  }
+  return sgemm_impl(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec, t, true, ws, ws ? cap : 0, stream);
+}

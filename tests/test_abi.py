@@ -726,3 +726,27 @@ def test_workspace_choice_fits_the_workspace(lib):
         assert small["lowering_name"] != f"staged_{prec}"
         assert small["tile"] == hp.describe(8192, 8192, 8192, prec)["tile"]
 
+
+def test_noalloc_checks_before_device_work(lib, monkeypatch):
+    """hpvm_sgemm_noalloc: argument checks, and the refusal of a staged tile
+    whose planes exceed the fixed array, happen before any HIP call."""
+    text = open(HEADER).read()
+    m = re.search(r"#define HPVM_NOALLOC_SCRATCH_BYTES \(\(int64_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == hp.NOALLOC_SCRATCH_BYTES
+    BIG = 1 << 28  # far enough apart that no two matrices overlap
+    bf16 = hp.PREC["bf16"]
+    staged = [t for t in hp.tile_menu("bf16") if t[5] == 3][0]
+    t = ctypes.byref(_lib.Tile(*staged))
+    assert hp.workspace_bytes(4096, 4096, 4096, "bf16", staged) > hp.NOALLOC_SCRATCH_BYTES
+    rc = lib.hpvm_sgemm_noalloc(4096, 4096, 4096, 1.0, BIG, 4096, BIG * 2, 4096, 0.0, BIG * 4, 4096, bf16, t, None)
+    assert rc == -4 and "scratch" in hp.last_error()
+    rc = lib.hpvm_sgemm_noalloc(-1, 4, 4, 1.0, BIG, 4, BIG * 2, 4, 0.0, BIG * 4, 4, bf16, None, None)
+    assert rc == -1 and "argument 1" in hp.last_error()
+    rc = lib.hpvm_sgemm_noalloc(4, 4, 4, 1.0, BIG, 4, BIG * 2, 4, 0.0, BIG * 4, 4, 9, None, None)
+    assert rc == -1 and "argument 12" in hp.last_error()
+    # calls that fit pass every check (the injected failure stops them)
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    for prec, size in (("bf16", 2048), ("bf16x3", 2048), ("fp32", 1024), ("bf16", 4096)):
+        rc = lib.hpvm_sgemm_noalloc(size, size, 4096, 1.0, BIG, 4096, BIG * 2, size, 0.0, BIG * 4, size,
+                                    hp.PREC[prec], None, None)
+        assert rc == -3, (prec, size, hp.last_error())
