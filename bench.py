@@ -298,10 +298,20 @@ def variant_precision(hp, inputs, dev, stream, reps):
                 ms = event_time(lambda: hp.sgemm(dA, dB, dC, 1.0, 0.0, prec=prec), reps, stream)
                 tf = 2.0 * n ** 3 / (ms / 1e3) / 1e12
                 peak = PEAK["bf16"] if prec == "bf16" else PEAK["bf16x3_fp32_equiv"]
+                ws = hp.workspace_bytes(n, n, n, prec)
                 rec = {"tflops": round(tf, 2), "ms": round(ms, 4), "tile": list(tile),
+                       "lowering": hp.describe(n, n, n, prec, workspace_bytes=ws)["lowering_name"],
                        "frac_of_peak": round(tf / peak, 4),
                        "peak": peak, "peak_note": "BF16 dense MFMA" if prec == "bf16" else
                        "BF16 dense MFMA / 3 (three bf16 products per FP32 product)"}
+                # The DMA-fed tile that converts in its own load path (no
+                # conversion pass, no workspace), whatever the tuner chose.
+                fused = hp.tile_menu(prec)[0]
+                ms_f = event_time(lambda: hp.sgemm(dA, dB, dC, 1.0, 0.0, prec=prec, tile=fused, workspace=False),
+                                  reps, stream)
+                tf_f = 2.0 * n ** 3 / (ms_f / 1e3) / 1e12
+                rec["no_conversion_pass"] = {"tile": list(fused), "ms": round(ms_f, 4), "tflops": round(tf_f, 2),
+                                             "frac_of_peak": round(tf_f / peak, 4)}
             else:
                 hp.sgemm(dA, dB, dC, 1.0, 0.0, prec=prec)
                 rec = {}

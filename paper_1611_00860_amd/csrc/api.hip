@@ -163,9 +163,11 @@ int resolve(int32_t prec, const hpvm_tile* tile, const hpvm::MfmaEntry** entry, 
 // 128 x 128 x 32 tile when that does (2048^3: 0.128 ms against 0.166 for the
 // best register-staged tile and 0.457 for 64 tiles of 256 x 256), else the
 // 64 x 64 x 16 tile (at 1024 x 1024 x 4096, 64 tiles of 128 x 128 ran at 28
-// TFLOP/s and 256 of 64 x 64 at 75).  BF16 and bf16x3: entry 0
-// (256 x 256 x 32) when it gives at least 256 tiles, else the 64 x 64 x 32
-// tile (1024^3 BF16: 0.020 ms against 0.064).  Returns false for entry 0.
+// TFLOP/s and 256 of 64 x 64 at 75).  BF16 and bf16x3: entry 0 (the
+// DMA-fed 256 x 256 tile) when it gives at least 256 tiles, else the
+// DMA-fed 128 x 128 tile when that does, else the register-staged
+// 64 x 64 x 32 tile (1024^3 BF16: 0.020 ms against 0.064 for 256 x 256).
+// Returns false for entry 0.
 int64_t tiles_of(const hpvm_tile& t, int64_t m, int64_t n) {
   return ((m + t.tile_m - 1) / t.tile_m) * ((n + t.tile_n - 1) / t.tile_n);
 }
@@ -185,9 +187,13 @@ bool default_small_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
     *out = tiles_of(mid->tile, m, n) >= 256 ? mid->tile : small->tile;
     return true;
   }
+  // BF16 / bf16x3: the DMA-fed 128 x 128 tile when it covers the CUs
+  // (2048^3 BF16: 0.055 ms against 0.084 for 64 tiles of 256 x 256), else
+  // the register-staged 64 x 64 x 32 tile.
+  const hpvm::MfmaEntry* mid = hpvm::find_menu_entry(prec, hpvm_tile{128, 128, 32, 64, 64, 4});
   const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{64, 64, 32, 32, 32, 2});
-  if (!small || tiles_of(e0->tile, m, n) >= 256) return false;
-  *out = small->tile;
+  if (!small || !mid || tiles_of(e0->tile, m, n) >= 256) return false;
+  *out = tiles_of(mid->tile, m, n) >= 256 ? mid->tile : small->tile;
   return true;
 }
 }  // namespace hpvm
@@ -199,10 +205,12 @@ namespace {
 // 128 x 128 tiles would not cover the CUs with take the DMA-fed entry that
 // splits the contraction into the deepest slices, provided `ws_bytes` (the
 // caller's workspace; -1 = as much as needed) holds its partial sums;
-// BF16 and bf16x3 products of at least 2^31 multiply-adds take the first
-// staged tile, whose conversion pass is then a small share of the time (or,
-// when that gives fewer than 256 tiles, the 128 x 128 x 64 tile with
-// 64 x 32 leaves).  Returns false when neither applies (hpvm_sgemm's choice
+// BF16 products of at least 2^31 multiply-adds take the first staged tile,
+// whose conversion pass is then a small share of the time (or, when that
+// gives fewer than 256 tiles, the 128 x 128 x 64 tile with 64 x 32 leaves);
+// bf16x3 products the same only when 256 x 256 tiles would not cover the
+// CUs (or k or n does not suit the DMA-fed tile).  Returns false when
+// neither applies (hpvm_sgemm's choice
 // then): a split tile run as one launch would be the slowest choice there
 // is (64 tiles of 128 x 128 at 1024 x 1024 x 4096: 28 TFLOP/s against 75
 // for hpvm_sgemm's 64 x 64 tiles).
@@ -234,7 +242,12 @@ bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, int64_t ws_b
   // on 128 x 128 tiles then ran 1.8-3x faster (2048^3 BF16: 0.039 ms
   // against 0.070; at 4096^3 the first tile stays ahead, 0.150 against 0.159).
   const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{128, 128, 64, 64, 32, 3});
-  const hpvm_tile pick = tiles_of(staged[0].tile, m, n) >= 256 || !small ? staged[0].tile : small->tile;
+  const bool big = tiles_of(staged[0].tile, m, n) >= 256;
+  // bf16x3 products that the DMA-fed 256 x 256 tile covers run faster on it,
+  // converting in the GEMM's own load path (8192^3: 2.71 ms against 2.82
+  // staged, 4096^3: 0.353 against 0.366), so they take no workspace.
+  if (prec == HPVM_PREC_BF16X3 && big && k % 32 == 0 && n % 4 == 0) return false;
+  const hpvm_tile pick = big || !small ? staged[0].tile : small->tile;
   // A workspace too small for the planes: the choice without one.
   if (ws_bytes >= 0 && ws_bytes < hpvm::staged_workspace_bytes(prec, m, n, k)) return false;
   *out = pick;

@@ -149,6 +149,81 @@ struct F32DmaOut {
   float lo, hi;       // CLAMP
 };
 
+// Epilogue of the DMA-fed loops: tile outputs from the accumulators (of
+// FP32 or BF16 MFMAs; both use the 32 x 32 block layout of acc_row /
+// acc_col).  q: the sgemm whose output this wave holds; m0, n0: the corner
+// the tile was computed from; m_own, n_own: its place in the tile grid
+// (EDGES stores only the outputs it owns); z: contraction slice (kDmaSplit).
+template <typename OA, typename OB, bool BT, int MODE, int OP, bool EDGES, int NA, int NB>
+__device__ __forceinline__ void dma_epilogue(const GemmArgs& q, const F32DmaOut& o, const f32x16 (&acc)[NA][NB],
+                                             int64_t m0, int64_t n0, int64_t m_own, int64_t n_own, int wm0,
+                                             int wn0, int lane, int z) {
+  const float* cin = q.C + (MODE == kDmaSplit ? (int64_t)z * q.m * q.ldc : 0);
+  float* out = MODE == kDmaConsume ? o.D : q.C + (MODE == kDmaSplit ? (int64_t)z * q.m * q.ldc : 0);
+  const int64_t ldo = MODE == kDmaConsume ? o.ldd : q.ldc;
+  const float alpha = MODE == kDmaSplit ? 1.0f : q.alpha;
+  const bool read_c = MODE != kDmaSplit && q.beta != 0.0f;
+  constexpr bool kBias = OP == HPVM_CONSUMER_BIAS || OP == HPVM_CONSUMER_BIAS_RELU;
+  const int I = lane & 31;
+  if constexpr (!BT) {
+    // The NB blocks give a lane NB adjacent outputs of a row: one vector
+    // access per row.  A group of 4 rows loads its C values first.
+    using VB = typename OB::Frag;
+    const int64_t col = n0 + OB::index(0, I, wn0);
+    const bool col_own = !EDGES || col >= n_own;  // the lane's NB columns are owned together (n % 4 == 0)
+    VB bias{};
+    if constexpr (MODE == kDmaConsume && kBias) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bias[b] = o.bias[col + b];
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        VB c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
+          if (read_c && col_own && (!EDGES || i >= m_own)) c[u] = *reinterpret_cast<const VB*>(cin + i * q.ldc + col);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
+          VB v;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            v[b] = alpha * acc[a][b][4 * g + u];
+            if (read_c) v[b] = fmaf(q.beta, c[u][b], v[b]);
+            if constexpr (MODE == kDmaConsume) v[b] = consume<OP>(v[b], bias[b], o.lo, o.hi);
+          }
+          if (col_own && (!EDGES || i >= m_own)) *reinterpret_cast<VB*>(out + i * ldo + col) = v;
+        }
+      }
+  } else {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int64_t col = n0 + OB::index(b, I, wn0);
+          float c[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
+            c[u] = (read_c && (!EDGES || (col >= n_own && i >= m_own))) ? cin[i * q.ldc + col] : 0.0f;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
+            float v = alpha * acc[a][b][4 * g + u];
+            if (read_c) v = fmaf(q.beta, c[u], v);
+            if (!EDGES || (col >= n_own && i >= m_own)) out[i * ldo + col] = v;
+          }
+        }
+  }
+}
+
 // One tile (tm, tn) of contraction slice z on the DMA-fed loop, by the
 // whole workgroup (S::NW waves), with the Allocation at smem (S::kLdsBytes).
 // p: the sgemm (for PAIR, output 1); p2: PAIR's output 2 (B2, C2, alpha2,
@@ -258,71 +333,7 @@ __device__ __forceinline__ void f32_dma_tile(const GemmArgs& p, const GemmArgs& 
   // No transfer may still be writing LDS when the workgroup ends.
   dma_wait_barrier<0>();
 
-  const GemmArgs& q = half ? p2 : p;
-  const float* cin = q.C + (MODE == kDmaSplit ? (int64_t)z * q.m * q.ldc : 0);
-  float* out = MODE == kDmaConsume ? o.D : q.C + (MODE == kDmaSplit ? (int64_t)z * q.m * q.ldc : 0);
-  const int64_t ldo = MODE == kDmaConsume ? o.ldd : q.ldc;
-  const float alpha = MODE == kDmaSplit ? 1.0f : q.alpha;
-  const bool read_c = MODE != kDmaSplit && q.beta != 0.0f;
-  constexpr bool kBias = OP == HPVM_CONSUMER_BIAS || OP == HPVM_CONSUMER_BIAS_RELU;
-  const int I = lane & 31;
-  if constexpr (!BT) {
-    // The NB blocks give a lane NB adjacent outputs of a row: one vector
-    // access per row.  A group of 4 rows loads its C values first.
-    using VB = typename OB::Frag;
-    const int64_t col = n0 + OB::index(0, I, wn0);
-    const bool col_own = !EDGES || col >= n_own;  // the lane's NB columns are owned together (n % 4 == 0)
-    VB bias{};
-    if constexpr (MODE == kDmaConsume && kBias) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b) bias[b] = o.bias[col + b];
-    }
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        VB c[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-          if (read_c && col_own && (!EDGES || i >= m_own)) c[u] = *reinterpret_cast<const VB*>(cin + i * q.ldc + col);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-          VB v;
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            v[b] = alpha * acc[a][b][4 * g + u];
-            if (read_c) v[b] = fmaf(q.beta, c[u][b], v[b]);
-            if constexpr (MODE == kDmaConsume) v[b] = consume<OP>(v[b], bias[b], o.lo, o.hi);
-          }
-          if (col_own && (!EDGES || i >= m_own)) *reinterpret_cast<VB*>(out + i * ldo + col) = v;
-        }
-      }
-  } else {
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const int64_t col = n0 + OB::index(b, I, wn0);
-          float c[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-            c[u] = (read_c && (!EDGES || (col >= n_own && i >= m_own))) ? cin[i * q.ldc + col] : 0.0f;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int64_t i = m0 + OA::index(a, acc_row(4 * g + u, lane), wm0);
-            float v = alpha * acc[a][b][4 * g + u];
-            if (read_c) v = fmaf(q.beta, c[u], v);
-            if (!EDGES || (col >= n_own && i >= m_own)) out[i * ldo + col] = v;
-          }
-        }
-  }
+  dma_epilogue<OA, OB, BT, MODE, OP, EDGES>(half ? p2 : p, o, acc, m0, n0, m_own, n_own, wm0, wn0, lane, z);
 }
 
 // One launch: a workgroup per tile and contraction slice (slice-major, so

@@ -11,6 +11,7 @@
 #include "internal.hpp"
 #include "mfma_f32_dma.hpp"
 #include "mfma_bf16.hpp"
+#include "mfma_bf16_dma.hpp"
 #include "mfma_f32.hpp"
 
 namespace hpvm {
@@ -250,7 +251,45 @@ static const MfmaEntry kF32Menu[] = {
   {{TM, TN, TK, WM, WN, 2}, PREC, Bf16Config<TM, TN, TK, WM, WN, X3>::kThreads,           \
    Bf16Config<TM, TN, TK, WM, WN, X3>::lds(false, false), &Bf16Config<TM, TN, TK, WM, WN, X3>::launch}
 
+// BF16 / bf16x3 products on the FP32 DMA-fed loop (mfma_bf16_dma.hpp):
+// problems of at least one tile each way with k a multiple of the slab, n a
+// multiple of 4 and 16-byte rows, no transposed operand (edge tiles moved
+// inward as in the FP32 loop); any other problem takes the register-staged
+// tile of the same size (FM x FN x 32 with FWM x FWN waves).
+template <int TM, int TN, int TK, int WM, int WN, int NST, bool X3, int FWM, int FWN>
+struct Bf16SrcConfig {
+  using S = Bf16SrcShape<TM, TN, TK, WM, WN, false, false, NST>;
+  static constexpr int kThreads = S::NW * kWave;
+  static hipError_t launch(const GemmArgs& args, bool at, bool bt, hipStream_t s) {
+    if (at || bt || !f32_dma_fits_edges<TM, TN, TK>(args, args.C, args.ldc))
+      return Bf16Config<TM, TN, 32, FWM, FWN, X3>::launch(args, at, bt, s);
+    GemmArgs a = args;
+    a.tiles_m = (a.m + TM - 1) / TM;
+    a.tiles_n = (a.n + TN - 1) / TN;
+    F32DmaOut o{};
+    o.splits = 1;
+    void* kargs[] = {&a, &o};
+    auto* fn = f32_dma_fits<TM, TN, TK>(args, args.C, args.ldc, 1)
+                   ? &sgemm_bf16src_dma<TM, TN, TK, WM, WN, false, false, NST, X3, kDmaUpdate>
+                   : &sgemm_bf16src_dma<TM, TN, TK, WM, WN, false, false, NST, X3, kDmaUpdate, true>;
+    hipError_t e = allow_lds(fn, (size_t)S::kLdsBytes);
+    if (e != hipSuccess) return e;
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n)),
+                           dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
+  }
+};
+
+#define HPVM_BF16SRC_ENTRY(PREC, X3, TM, TN, TK, WM, WN, NST, FWM, FWN)                                    \
+  {{TM, TN, TK, WM, WN, NST}, PREC, Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::kThreads,         \
+   Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::S::kLdsBytes,                                       \
+   &Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::launch}
+
+// Entry 0 is the default when no tile is given: BF16 and bf16x3 on the
+// DMA-fed loop, falling back to the register-staged 256 x 256 x 32 tile.
 static const MfmaEntry kBf16Menu[] = {
+    HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16, false, 256, 256, 16, 64, 128, 4, 128, 64),
+    HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16, false, 256, 256, 32, 64, 128, 2, 128, 64),
+    HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16, false, 128, 128, 32, 64, 64, 4, 64, 64),
     HPVM_BF16_ENTRY(HPVM_PREC_BF16, false, 256, 256, 32, 128, 64),
     HPVM_BF16_ENTRY(HPVM_PREC_BF16, false, 256, 128, 32, 128, 64),
     HPVM_BF16_ENTRY(HPVM_PREC_BF16, false, 128, 128, 32, 64, 64),
@@ -259,6 +298,9 @@ static const MfmaEntry kBf16Menu[] = {
 };
 
 static const MfmaEntry kBf16x3Menu[] = {
+    HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16X3, true, 256, 256, 32, 128, 128, 2, 128, 64),
+    HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16X3, true, 256, 256, 16, 128, 128, 4, 128, 64),
+    HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16X3, true, 128, 128, 32, 64, 64, 4, 64, 64),
     HPVM_BF16_ENTRY(HPVM_PREC_BF16X3, true, 256, 256, 32, 128, 64),
     HPVM_BF16_ENTRY(HPVM_PREC_BF16X3, true, 256, 128, 32, 128, 64),
     HPVM_BF16_ENTRY(HPVM_PREC_BF16X3, true, 128, 128, 32, 64, 64),

@@ -717,14 +717,19 @@ def test_workspace_choice_fits_the_workspace(lib):
     when the workspace holds them; a smaller one gives the choice without a
     workspace instead of a refusal."""
     hp.autotune_clear()
-    for prec in ("bf16", "bf16x3"):
-        big = hp.describe(8192, 8192, 8192, prec, workspace_bytes=1 << 40)
+    for prec, size in (("bf16", 8192), ("bf16x3", 2048)):
+        big = hp.describe(size, size, size, prec, workspace_bytes=1 << 40)
         assert big["lowering_name"] == f"staged_{prec}"
-        need = hp.workspace_bytes(8192, 8192, 8192, prec, big["tile"])
-        assert hp.describe(8192, 8192, 8192, prec, workspace_bytes=need)["lowering_name"] == f"staged_{prec}"
-        small = hp.describe(8192, 8192, 8192, prec, workspace_bytes=need - 1)
+        need = hp.workspace_bytes(size, size, size, prec, big["tile"])
+        assert hp.describe(size, size, size, prec, workspace_bytes=need)["lowering_name"] == f"staged_{prec}"
+        small = hp.describe(size, size, size, prec, workspace_bytes=need - 1)
         assert small["lowering_name"] != f"staged_{prec}"
-        assert small["tile"] == hp.describe(8192, 8192, 8192, prec)["tile"]
+        assert small["tile"] == hp.describe(size, size, size, prec)["tile"]
+    # bf16x3 products that 256 x 256 tiles cover take the DMA-fed tile,
+    # which converts in its own load path: no workspace
+    d = hp.describe(8192, 8192, 8192, "bf16x3", workspace_bytes=1 << 40)
+    assert d["lowering_name"] == "mfma_bf16x3" and d["tile"] == hp.tile_menu("bf16x3")[0]
+    assert hp.workspace_bytes(8192, 8192, 8192, "bf16x3") == 0
 
 
 def test_noalloc_checks_before_device_work(lib, monkeypatch):

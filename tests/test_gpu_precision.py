@@ -27,7 +27,9 @@ def run(hp, A, B, C, alpha, beta, prec, tile=None, pad=0, misalign=False):
     return to_host(dC)
 
 
-SHAPES = [(300, 260, 200), (257, 129, 77), (1, 1, 1), (64, 520, 48)]
+# The last two run the DMA-fed tiles (at least one tile each way, k a whole
+# number of slabs, n a multiple of 4): edge tiles moved inward, then whole.
+SHAPES = [(300, 260, 200), (257, 129, 77), (1, 1, 1), (64, 520, 48), (300, 260, 96), (512, 384, 64)]
 
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
@@ -91,13 +93,15 @@ def conversion_expected(prec, x):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
-@pytest.mark.parametrize("k,p", [(1, 0), (40, 0), (40, 39), (200, 131)])
+@pytest.mark.parametrize("k,p,w", [(1, 0, 72), (40, 0, 72), (40, 39, 72), (200, 131, 72), (32, 5, 260),
+                                   (64, 63, 260)])
 @pytest.mark.parametrize("side", ["A", "B"])
-def test_conversion_is_rne_bit_exact_all_tiles(gpu, prec, k, p, side):
+def test_conversion_is_rne_bit_exact_all_tiles(gpu, prec, k, p, w, side):
+    """w = 260 with k a whole number of slabs: the DMA-fed tiles convert
+    FP32 fragments read from LDS (the other sizes take their fallback)."""
     import torch
 
     vals = special_values(700, seed=k + p)
-    w = 72
     if side == "A":  # column p of A holds the values, row p of B is ones
         m, n = vals.shape[0], w
         A = np.zeros((m, k), np.float32)
@@ -152,6 +156,30 @@ def test_staged_equals_fused_bitwise(gpu, prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("m,n,k", [(768, 512, 320), (520, 300, 96)])
+def test_every_lowering_gives_the_same_bits(gpu, prec, m, n, k):
+    """Every lowering of a precision sums the same bf16 products of each
+    output in the same order (16-k steps in k order, bf16x3 as lo*hi, hi*lo,
+    hi*hi): converting in the DMA-fed loop's fragment reads, in the
+    register-staged copy into LDS, or in a pass before the GEMM gives the
+    same bits on random inputs."""
+    import torch
+
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=23)
+    dA, dB = to_dev(A), to_dev(B)
+    menu = gpu.tile_menu(prec)
+    ref = None
+    for tile in menu:
+        print(f"case: {prec} {m}x{n}x{k} tile {tile}", flush=True)
+        c = to_dev(C)
+        gpu.sgemm(dA, dB, c, 1.5, 0.5, prec=prec, tile=tile)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = c
+        assert torch.equal(c, ref), tile
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
 def test_beta_zero_ignores_nan_c(gpu, prec):
     A, B, C = inputs.sgemm_operands(100, 90, 80, seed=3)
     C[:] = np.nan
@@ -191,12 +219,14 @@ def test_full_size_8192_sampled(gpu, dist):
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
 @pytest.mark.parametrize("m,n,k", [(1536, 1536, 1024), (4096, 4096, 256)])
-def test_default_tile_is_staged_for_large_products(gpu, prec, m, n, k):
+def test_default_tile_for_large_products(gpu, prec, m, n, k):
     """With no tile and no autotuned entry, a product of at least 2^31
-    multiply-adds runs a staged tile (through a workspace): the first one
-    when it gives at least 256 tiles, else 128 x 128 x 64 with 64 x 32
-    leaves -- the same bits as naming that tile, and within the precision's
-    bound."""
+    multiply-adds runs, for BF16, a staged tile (through a workspace): the
+    first one when it gives at least 256 tiles, else 128 x 128 x 64 with
+    64 x 32 leaves; bf16x3 the same when 256 x 256 tiles would not cover the
+    CUs, else the menu's first (DMA-fed) tile, which converts in its own
+    load path.  The same bits as naming that tile, and within the
+    precision's bound."""
     import torch
 
     gpu.autotune_clear()
@@ -205,10 +235,12 @@ def test_default_tile_is_staged_for_large_products(gpu, prec, m, n, k):
     whole = -(-m // first[0]) * -(-n // first[1]) >= 256
     staged = first if whole else (128, 128, 64, 64, 32, 3)
     assert whole == (m == 4096)
+    expect = gpu.tile_menu(prec)[0] if (whole and prec == "bf16x3") else staged
+    assert gpu.describe(m, n, k, prec, workspace_bytes=1 << 40)["tile"] == expect
     print(f"case: default tile {prec} {m}x{n}x{k}", flush=True)
     C1, C2 = to_dev(C), to_dev(C)
     gpu.sgemm(to_dev(A), to_dev(B), C1, 1.0, 0.5, prec=prec)
-    gpu.sgemm(to_dev(A), to_dev(B), C2, 1.0, 0.5, prec=prec, tile=staged)
+    gpu.sgemm(to_dev(A), to_dev(B), C2, 1.0, 0.5, prec=prec, tile=expect)
     torch.cuda.synchronize()
     assert torch.equal(C1, C2)
     ref = oracle.sgemm(A, B, C, 1.0, 0.5)
