@@ -569,6 +569,35 @@ int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda
                     const float* B2, int64_t ldb2, float beta2, float* C2, int64_t ldc2,
                     const hpvm_tile* tile, void* stream);
 
+/* hpvm_sgemm_pair with a workspace: pairs whose per-output tiles of the
+ * first pair tile would not cover 256 CUs run on the DMA-fed 128 x 128
+ * pair tile with the contraction split into slices (the rule of
+ * hpvm_sgemm_ws: slices doubled while tiles * slices < 256, each a whole
+ * number of 32-deep slabs and at least 256 deep, at most 16), each
+ * workgroup computing one tile of both outputs over one slice from one A
+ * slab; the raw partial sums go to `workspace` ([slice][m][n] of output 1,
+ * then of output 2), then each output is formed as alpha * (sum of its
+ * slices, in order) + beta * C.  Requires whole tiles (m, n multiples of
+ * 128, k of 32 * slices), 16-byte aligned A, B1, B2, C1, C2 and leading
+ * dimensions that are multiples of 4; otherwise, or with NULL or fewer
+ * workspace bytes than hpvm_sgemm_pair_workspace_bytes gives, it runs as
+ * hpvm_sgemm_pair.  workspace: device memory, 16-byte aligned, contents
+ * are scratch.  tile: NULL = the choice above, else a pair menu tile
+ * (split when it is the splitting tile and the workspace holds the
+ * partial sums).  Every other argument and rule is hpvm_sgemm_pair's;
+ * workspace is argument 19, workspace_bytes (>= 0) argument 20.            */
+int hpvm_sgemm_pair_ws(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, float alpha1,
+                       const float* B1, int64_t ldb1, float beta1, float* C1, int64_t ldc1,
+                       float alpha2, const float* B2, int64_t ldb2, float beta2, float* C2,
+                       int64_t ldc2, const hpvm_tile* tile, void* workspace,
+                       int64_t workspace_bytes, void* stream);
+
+/* Workspace bytes hpvm_sgemm_pair_ws needs for these sizes and tile (NULL =
+ * the tile it would pick given enough): 2 * slices * m * n * 4 when it
+ * splits the contraction, else 0.                                           */
+int hpvm_sgemm_pair_workspace_bytes(int64_t m, int64_t n, int64_t k, const hpvm_tile* tile,
+                                    int64_t* bytes);
+
 /* ======================================================================== */
 /* Streaming graph (llvm.hpvm.launch with Stream = 1, push, pop)              */
 /* ======================================================================== */

@@ -550,9 +550,25 @@ def sgemm_consumer(A, B, C, alpha: float = 1.0, beta: float = 0.0, op="none", bi
     return D
 
 
+def pair_workspace_bytes(m: int, n: int, k: int, tile=None) -> int:
+    """Workspace hpvm_sgemm_pair_ws needs: the split pair's partial sums, else 0."""
+    out = ctypes.c_int64(0)
+    _check(load().hpvm_sgemm_pair_workspace_bytes(m, n, k, _tile(tile), ctypes.byref(out)))
+    return out.value
+
+
 def sgemm_pair(A, B1, C1, B2, C2, alpha1: float = 1.0, beta1: float = 0.0, alpha2: float = 1.0,
-               beta2: float = 0.0, tile=None, stream=None):
-    """C1 <- alpha1 A B1 + beta1 C1 and C2 <- alpha2 A B2 + beta2 C2 in one launch."""
+               beta2: float = 0.0, tile=None, stream=None, workspace=None):
+    """C1 <- alpha1 A B1 + beta1 C1 and C2 <- alpha2 A B2 + beta2 C2 in one launch.
+
+    Pairs whose tiles would not cover the CUs split the contraction into
+    slices when a workspace holds the partial sums (hpvm_sgemm_pair_ws):
+    ``workspace`` (a CUDA tensor) is used when given and large enough, else
+    one is allocated on the call's stream; ``workspace=False`` calls
+    hpvm_sgemm_pair, which takes none.
+    """
+    import torch
+
     lib = load()
     m, k = A.shape
     n = B1.shape[1]
@@ -564,8 +580,17 @@ def sgemm_pair(A, B1, C1, B2, C2, alpha1: float = 1.0, beta1: float = 0.0, alpha
     q1, m1 = _mat(C1, "C1")
     p2, l2 = _mat(B2, "B2")
     q2, m2 = _mat(C2, "C2")
-    _check(lib.hpvm_sgemm_pair(m, n, k, pa, lda, float(alpha1), p1, l1, float(beta1), q1, m1,
-                               float(alpha2), p2, l2, float(beta2), q2, m2, _tile(tile), _stream(stream)))
+    need = 0 if workspace is False else pair_workspace_bytes(m, n, k, tile)
+    if need == 0:
+        _check(lib.hpvm_sgemm_pair(m, n, k, pa, lda, float(alpha1), p1, l1, float(beta1), q1, m1,
+                                   float(alpha2), p2, l2, float(beta2), q2, m2, _tile(tile), _stream(stream)))
+        return C1, C2
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = _empty(need, torch.uint8, C1.device, stream)
+    _check(lib.hpvm_sgemm_pair_ws(m, n, k, pa, lda, float(alpha1), p1, l1, float(beta1), q1, m1,
+                                  float(alpha2), p2, l2, float(beta2), q2, m2, _tile(tile),
+                                  ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                                  _stream(stream)))
     return C1, C2
 
 

@@ -130,6 +130,9 @@ SIGNATURES = {
                                            ctypes.POINTER(Consumer), vp, i64, ctypes.POINTER(Tile), vp]),
     "hpvm_sgemm_pair": (ctypes.c_int, [i64, i64, i64, vp, i64, f32, vp, i64, f32, vp, i64,
                                        f32, vp, i64, f32, vp, i64, ctypes.POINTER(Tile), vp]),
+    "hpvm_sgemm_pair_ws": (ctypes.c_int, [i64, i64, i64, vp, i64, f32, vp, i64, f32, vp, i64,
+                                          f32, vp, i64, f32, vp, i64, ctypes.POINTER(Tile), vp, i64, vp]),
+    "hpvm_sgemm_pair_workspace_bytes": (ctypes.c_int, [i64, i64, i64, ctypes.POINTER(Tile), Pi64]),
     "hpvm_track_mem": (ctypes.c_int, [vp, i64]),
     "hpvm_request_mem": (ctypes.c_int, [vp, i64, vp]),
     "hpvm_untrack_mem": (ctypes.c_int, [vp, vp]),

@@ -69,6 +69,22 @@ inline int64_t entry_split_bytes(const MfmaEntry* e, int64_t m, int64_t n, int64
   return e && e->split_bytes ? e->split_bytes(m, n, k) : 0;
 }
 
+// Contraction slices for a whole-tile problem of `tiles` tiles of depth-TK
+// slabs whose tiles would not cover 256 CUs: doubled while they would not,
+// each slice a whole number of slabs and at least 256 deep, at most 16; 1
+// (no split) when the slices still would not cover them.
+inline int dma_split_count(int64_t tiles, int64_t k, int tk) {
+  int sp = 1;
+  while (sp < 16 && tiles * sp < 256 && k % (2 * sp * tk) == 0 && k / (2 * sp) >= 256) sp *= 2;
+  return tiles * sp >= 256 ? sp : 1;
+}
+
+// C <- alpha * (part[0] + ... + part[splits-1]) + beta * C, the slices
+// summed in order, from partial sums [splits][m][n] (n, ldc multiples of 4,
+// part and C 16-byte aligned); beta == 0 never reads C.
+hipError_t launch_split_finish(const float* part, int32_t splits, int64_t m, int64_t n, float alpha, float beta,
+                               float* C, int64_t ldc, hipStream_t s);
+
 // The compiled fused menu for `prec` (FP32, BF16, BF16X3); returns the count.
 int mfma_menu(int32_t prec, const MfmaEntry** entries);
 

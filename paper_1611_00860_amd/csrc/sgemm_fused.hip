@@ -225,8 +225,13 @@ struct FusedEntry {
   hpvm_tile tile;
   int32_t threads;
   int64_t lds_bytes;
-  hipError_t (*consumer)(const GemmArgs&, const ConsumerArgs&, hipStream_t);
-  hipError_t (*pair)(const GemmArgs&, const GemmArgs&, hipStream_t);
+  hipError_t (*consumer)(const GemmArgs&, const ConsumerArgs&, hipStream_t) = nullptr;
+  hipError_t (*pair)(const GemmArgs&, const GemmArgs&, hipStream_t) = nullptr;
+  // Pair with the contraction split into slices (DMA-fed pair tiles): the
+  // workspace bytes that let an m x n x k pair run split (0 when the entry
+  // would not split it), and that launch.
+  int64_t (*pair_split_bytes)(int64_t m, int64_t n, int64_t k) = nullptr;
+  hipError_t (*pair_split)(const GemmArgs&, const GemmArgs&, void* workspace, hipStream_t) = nullptr;
 };
 
 template <int TM, int TN, int TK, int WM, int WN>
@@ -334,6 +339,46 @@ struct PairDmaConfig {
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(p1.tiles_m * p1.tiles_n)),
                            dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
   }
+  // Split contraction (the rule of the single launch's split): each
+  // workgroup computes one tile of both outputs over one slice, writing raw
+  // partial sums [slice][m][n] of output 1 and then of output 2 to the
+  // workspace; then each output is formed from its slices, in order.
+  static int splits(int64_t m, int64_t n, int64_t k) {
+    if (m <= 0 || n <= 0 || k <= 0 || m % TM || n % TN || k % TK) return 1;
+    return dma_split_count((m / TM) * (n / TN), k, TK);
+  }
+  static int64_t split_bytes(int64_t m, int64_t n, int64_t k) {
+    const int sp = splits(m, n, k);
+    return sp > 1 ? 2 * (int64_t)sp * m * n * (int64_t)sizeof(float) : 0;
+  }
+  static hipError_t launch_split(const GemmArgs& a1, const GemmArgs& a2, void* workspace, hipStream_t s) {
+    const int sp = splits(a1.m, a1.n, a1.k);
+    float* part1 = static_cast<float*>(workspace);
+    float* part2 = part1 + (int64_t)sp * a1.m * a1.n;
+    GemmArgs b2 = a2;
+    b2.vec_a = a1.vec_a;
+    if (sp <= 1 || !f32_dma_fits<TM, TN, TK>(a1, part1, a1.n, sp) || !f32_dma_fits<TM, TN, TK>(a1, a1.C, a1.ldc, sp) ||
+        !f32_dma_fits<TM, TN, TK>(b2, a2.C, a2.ldc, sp))
+      return launch(a1, a2, s);
+    GemmArgs p1 = a1, p2 = a2;
+    p1.C = part1;
+    p2.C = part2;
+    p1.ldc = p2.ldc = a1.n;
+    p1.beta = p2.beta = 0.0f;
+    p1.tiles_m = p2.tiles_m = a1.m / TM;
+    p1.tiles_n = p2.tiles_n = a1.n / TN;
+    F32DmaOut o{};
+    o.splits = sp;
+    void* kargs[] = {&p1, &p2, &o};
+    auto* fn = &sgemm_f32_dma<TM, TN, TK, WM, 128, false, false, NST, kDmaSplit, 0, true>;
+    hipError_t e = allow_lds_fused(fn, (size_t)S::kLdsBytes);
+    if (e != hipSuccess) return e;
+    e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(p1.tiles_m * p1.tiles_n * sp)),
+                        dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
+    if (e == hipSuccess) e = launch_split_finish(part1, sp, a1.m, a1.n, a1.alpha, a1.beta, a1.C, a1.ldc, s);
+    if (e == hipSuccess) e = launch_split_finish(part2, sp, a2.m, a2.n, a2.alpha, a2.beta, a2.C, a2.ldc, s);
+    return e;
+  }
 };
 
 #define HPVM_CONSUMER_DMA_ENTRY(TM, TN, TK, WM, NST)                                                 \
@@ -341,7 +386,8 @@ struct PairDmaConfig {
    ConsumerDmaConfig<TM, TN, TK, WM, NST>::S::kLdsBytes, &ConsumerDmaConfig<TM, TN, TK, WM, NST>::launch, nullptr}
 #define HPVM_PAIR_DMA_ENTRY(TM, TN, TK, WM, NST)                                                     \
   {{TM, TN, TK, WM, 128, NST}, PairDmaConfig<TM, TN, TK, WM, NST>::kThreads,                           \
-   PairDmaConfig<TM, TN, TK, WM, NST>::S::kLdsBytes, nullptr, &PairDmaConfig<TM, TN, TK, WM, NST>::launch}
+   PairDmaConfig<TM, TN, TK, WM, NST>::S::kLdsBytes, nullptr, &PairDmaConfig<TM, TN, TK, WM, NST>::launch, \
+   &PairDmaConfig<TM, TN, TK, WM, NST>::split_bytes, &PairDmaConfig<TM, TN, TK, WM, NST>::launch_split}
 #define HPVM_CONSUMER_ENTRY(TM, TN, TK, WM, WN)                                                   \
   {{TM, TN, TK, WM, WN, 2}, ConsumerConfig<TM, TN, TK, WM, WN>::kThreads,                           \
    ConsumerConfig<TM, TN, TK, WM, WN>::kLds, &ConsumerConfig<TM, TN, TK, WM, WN>::launch, nullptr}
@@ -360,12 +406,15 @@ static const FusedEntry kConsumerMenu[] = {
     HPVM_CONSUMER_DMA_ENTRY(128, 256, 32, 32, 2),
     HPVM_CONSUMER_DMA_ENTRY(128, 128, 32, 32, 2),
 };
-// Pair tiles: tile_m x tile_n of each output; 8, 8 and 4 waves.  The DMA-fed
-// entry's two stages of one A slab and two B slabs take all 160 KB of LDS.
+// Pair tiles: tile_m x tile_n of each output; 8, 8, 4 and 8 waves.  The
+// first DMA-fed entry's two stages of one A slab and two B slabs take all
+// 160 KB of LDS; the last (96 KB) is the one that splits the contraction of
+// pairs whose tiles would not cover the CUs.
 static const FusedEntry kPairMenu[] = {
     HPVM_PAIR_DMA_ENTRY(128, 256, 32, 64, 2),
     HPVM_PAIR_ENTRY(128, 128, 16, 64, 64),
     HPVM_PAIR_ENTRY(64, 64, 16, 32, 64),
+    HPVM_PAIR_DMA_ENTRY(128, 128, 32, 32, 2),
 };
 constexpr int kNumConsumer = (int)(sizeof(kConsumerMenu) / sizeof(kConsumerMenu[0]));
 constexpr int kNumPair = (int)(sizeof(kPairMenu) / sizeof(kPairMenu[0]));
@@ -478,9 +527,33 @@ int hpvm_sgemm_consumer(int64_t m, int64_t n, int64_t k, float alpha, const floa
   return he == hipSuccess ? clear_error() : hip_error(he, "consumer launch");
 }
 
-int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, float alpha1, const float* B1,
-                    int64_t ldb1, float beta1, float* C1, int64_t ldc1, float alpha2, const float* B2, int64_t ldb2,
-                    float beta2, float* C2, int64_t ldc2, const hpvm_tile* tile, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The pair tile that splits the contraction when a pair's tiles would not
+// cover the CUs.
+const FusedEntry* pair_split_entry() { return find_fused(kPairMenu, kNumPair, hpvm_tile{128, 128, 32, 32, 128, 2}); }
+
+// Built-in choice: the largest tile per output that still gives a tile per
+// CU of a 256-CU part -- the DMA-fed 128 x 256, else (with a workspace
+// argument that holds its partial sums; -1 = as much as needed) the
+// DMA-fed 128 x 128 in contraction slices, else 128 x 128, else 64 x 64.
+hpvm_tile pair_choice(int64_t m, int64_t n, int64_t k, bool ws_ok, int64_t ws_bytes) {
+  auto tiles = [&](const hpvm_tile& u) { return ((m + u.tile_m - 1) / u.tile_m) * ((n + u.tile_n - 1) / u.tile_n); };
+  if (tiles(kPairMenu[0].tile) >= 256) return kPairMenu[0].tile;
+  const FusedEntry* sp = pair_split_entry();
+  if (ws_ok && sp) {
+    const int64_t need = sp->pair_split_bytes(m, n, k);
+    if (need > 0 && (ws_bytes < 0 || ws_bytes >= need)) return sp->tile;
+  }
+  return tiles(kPairMenu[1].tile) >= 256 ? kPairMenu[1].tile : kPairMenu[2].tile;
+}
+
+int pair_impl(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, float alpha1, const float* B1,
+              int64_t ldb1, float beta1, float* C1, int64_t ldc1, float alpha2, const float* B2, int64_t ldb2,
+              float beta2, float* C2, int64_t ldc2, const hpvm_tile* tile, bool ws_ok, void* workspace,
+              int64_t workspace_bytes, void* stream) {
   bool r1, r2;
   int rc = check_gemm_args("output 1: ", m, n, k, alpha1, A, lda, B1, ldb1, beta1, C1, ldc1, &r1);
   if (rc != HPVM_OK) return rc;
@@ -493,17 +566,13 @@ int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda
     return set_error(HPVM_INVALID_ARG, "argument 10: C1 overlaps B2");
   if (r1 && ranges_meet(C2, m, n, ldc2, B1, k, n, ldb1))
     return set_error(HPVM_INVALID_ARG, "argument 16: C2 overlaps B1");
-  // Built-in choice: the largest tile per output that still gives a tile
-  // per CU of a 256-CU part -- the DMA-fed 128 x 256, else 128 x 128, else
-  // 64 x 64.
-  auto tiles = [&](const hpvm_tile& u) { return ((m + u.tile_m - 1) / u.tile_m) * ((n + u.tile_n - 1) / u.tile_n); };
-  hpvm_tile t = kPairMenu[0].tile;
-  if (tile) t = *tile;
-  else if (tiles(kPairMenu[0].tile) < 256) t = tiles(kPairMenu[1].tile) >= 256 ? kPairMenu[1].tile : kPairMenu[2].tile;
+  const hpvm_tile t = tile ? *tile : pair_choice(m, n, k, ws_ok, workspace ? workspace_bytes : 0);
   const FusedEntry* e = find_fused(kPairMenu, kNumPair, t);
   if (!e)
     return set_error(HPVM_UNSUPPORTED, "argument 18: tile %dx%dx%d leaf %dx%d is not in the pair menu", t.tile_m,
                      t.tile_n, t.tile_k, t.leaf_m, t.leaf_n);
+  if (ws_ok && workspace && (uintptr_t)workspace % 16)
+    return set_error(HPVM_INVALID_ARG, "argument 19: workspace is not 16-byte aligned");
   if (empty) return clear_error();
   if (!r1 || !r2) {
     // A scale-only output (k == 0 or alpha == 0) reads neither A nor its B:
@@ -534,8 +603,45 @@ int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda
   g2.alpha = alpha2;
   g2.beta = beta2;
   g2.vec_b = vec16(B2, ldb2);
-  const hipError_t he = e->pair(g1, g2, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t need = e->pair_split_bytes ? e->pair_split_bytes(m, n, k) : 0;
+  const hipError_t he = (ws_ok && need > 0 && workspace && workspace_bytes >= need)
+                            ? e->pair_split(g1, g2, workspace, s)
+                            : e->pair(g1, g2, s);
   return he == hipSuccess ? clear_error() : hip_error(he, "pair launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpvm_sgemm_pair(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, float alpha1, const float* B1,
+                    int64_t ldb1, float beta1, float* C1, int64_t ldc1, float alpha2, const float* B2, int64_t ldb2,
+                    float beta2, float* C2, int64_t ldc2, const hpvm_tile* tile, void* stream) {
+  return pair_impl(m, n, k, A, lda, alpha1, B1, ldb1, beta1, C1, ldc1, alpha2, B2, ldb2, beta2, C2, ldc2, tile,
+                   false, nullptr, 0, stream);
+}
+
+int hpvm_sgemm_pair_ws(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, float alpha1, const float* B1,
+                       int64_t ldb1, float beta1, float* C1, int64_t ldc1, float alpha2, const float* B2,
+                       int64_t ldb2, float beta2, float* C2, int64_t ldc2, const hpvm_tile* tile, void* workspace,
+                       int64_t workspace_bytes, void* stream) {
+  if (workspace_bytes < 0)
+    return set_error(HPVM_INVALID_ARG, "argument 20: workspace_bytes = %lld < 0", (long long)workspace_bytes);
+  return pair_impl(m, n, k, A, lda, alpha1, B1, ldb1, beta1, C1, ldc1, alpha2, B2, ldb2, beta2, C2, ldc2, tile,
+                   true, workspace, workspace_bytes, stream);
+}
+
+int hpvm_sgemm_pair_workspace_bytes(int64_t m, int64_t n, int64_t k, const hpvm_tile* tile, int64_t* bytes) {
+  if (m < 0 || n < 0 || k < 0) return set_error(HPVM_INVALID_ARG, "sizes must be >= 0");
+  if (!bytes) return set_error(HPVM_INVALID_ARG, "argument 5: bytes is NULL");
+  const hpvm_tile t = tile ? *tile : pair_choice(m, n, k, true, -1);
+  const FusedEntry* e = find_fused(kPairMenu, kNumPair, t);
+  if (!e)
+    return set_error(HPVM_UNSUPPORTED, "argument 4: tile %dx%dx%d leaf %dx%d is not in the pair menu", t.tile_m,
+                     t.tile_n, t.tile_k, t.leaf_m, t.leaf_n);
+  *bytes = e->pair_split_bytes ? e->pair_split_bytes(m, n, k) : 0;
+  return clear_error();
 }
 
 }  // extern "C"

@@ -145,6 +145,15 @@ __global__ void __launch_bounds__(kSplitThreads)
   }
 }
 
+hipError_t launch_split_finish(const float* part, int32_t splits, int64_t m, int64_t n, float alpha, float beta,
+                               float* C, int64_t ldc, hipStream_t s) {
+  const int64_t units = m * n / 4;
+  const unsigned blocks = (unsigned)std::min<int64_t>(2048, (units + kSplitThreads - 1) / kSplitThreads);
+  void* fargs[] = {&part, &splits, &m, &n, &alpha, &beta, &C, &ldc};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_finish), dim3(blocks), dim3(kSplitThreads),
+                         fargs, 0, s);
+}
+
 template <int TM, int TN, int TK, int WM, int NST>
 struct F32DmaConfig {
   using S = F32DmaShape<TM, TN, TK, WM, 128, false, false, NST>;
@@ -174,10 +183,7 @@ struct F32DmaConfig {
   // still would not cover them.
   static int splits(int64_t m, int64_t n, int64_t k) {
     if (m <= 0 || n <= 0 || k <= 0 || m % TM || n % TN || k % TK) return 1;
-    const int64_t tiles = (m / TM) * (n / TN);
-    int sp = 1;
-    while (sp < 16 && tiles * sp < 256 && k % (2 * sp * TK) == 0 && k / (2 * sp) >= 256) sp *= 2;
-    return tiles * sp >= 256 ? sp : 1;
+    return dma_split_count((m / TM) * (n / TN), k, TK);
   }
   static int64_t split_bytes(int64_t m, int64_t n, int64_t k) {
     const int sp = splits(m, n, k);
@@ -208,15 +214,7 @@ struct F32DmaConfig {
     e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n * sp)),
                         dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
     if (e != hipSuccess) return e;
-    const int64_t units = (int64_t)args.m * args.n / 4;
-    const unsigned blocks = (unsigned)std::min<int64_t>(2048, (units + kSplitThreads - 1) / kSplitThreads);
-    int32_t splits32 = sp;
-    int64_t m64 = args.m, n64 = args.n, ldc = args.ldc;
-    float alpha = args.alpha, beta = args.beta;
-    float* C = args.C;
-    void* fargs[] = {&part, &splits32, &m64, &n64, &alpha, &beta, &C, &ldc};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&sgemm_split_finish), dim3(blocks), dim3(kSplitThreads),
-                           fargs, 0, s);
+    return launch_split_finish(part, sp, args.m, args.n, args.alpha, args.beta, args.C, args.ldc, s);
   }
 };
 

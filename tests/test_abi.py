@@ -585,7 +585,8 @@ def test_fusion_menus(lib):
     # the consumer kernel takes the FP32 single-launch tiles, in order
     assert hp.fusion_menu("consumer") == hp.tile_menu("fp32")
     pair = hp.fusion_menu("pair")
-    assert len(pair) == 3 and all(t[5] == 2 for t in pair) and pair[0][4] == 128
+    assert len(pair) == 4 and all(t[5] == 2 for t in pair) and pair[0][4] == 128
+    assert pair[3] == (128, 128, 32, 32, 128, 2)  # the tile that splits the contraction
     cnt = ctypes.c_int32()
     assert lib.hpvm_fusion_menu(2, None, 0, ctypes.byref(cnt)) == -1
 
@@ -755,3 +756,28 @@ def test_noalloc_checks_before_device_work(lib, monkeypatch):
         rc = lib.hpvm_sgemm_noalloc(size, size, 4096, 1.0, BIG, 4096, BIG * 2, size, 0.0, BIG * 4, size,
                                     hp.PREC[prec], None, None)
         assert rc == -3, (prec, size, hp.last_error())
+
+
+def test_pair_split_workspace_rules(lib, monkeypatch):
+    """hpvm_sgemm_pair_ws splits the contraction of pairs whose tiles would
+    not cover 256 CUs (the single launch's slice rule, on 128 x 128 tiles
+    per output); the workspace holds both outputs' partial sums."""
+    plane = lambda m, n: 4 * m * n
+    split = (128, 128, 32, 32, 128, 2)
+    # 64 tiles of 128 x 128 per output -> 4 slices of 1024
+    assert hp.pair_workspace_bytes(1024, 1024, 4096) == 2 * 4 * plane(1024, 1024)
+    assert hp.pair_workspace_bytes(1024, 1024, 4096, split) == 2 * 4 * plane(1024, 1024)
+    assert hp.pair_workspace_bytes(512, 512, 4096) == 2 * 16 * plane(512, 512)
+    for m, n, k, tile in ((4096, 4096, 4096, None),    # the first pair tile covers the CUs
+                          (1024, 1024, 4096, (128, 128, 16, 64, 64, 2)),  # not a splitting tile
+                          (1000, 1024, 4096, split),     # not whole tiles
+                          (1024, 1024, 256, split)):     # slices would be under 256 deep
+        assert hp.pair_workspace_bytes(m, n, k, tile) == 0, (m, n, k, tile)
+    BIG = 1 << 28
+    A, B1, C1, B2, C2 = BIG, 2 * BIG, 3 * BIG, 4 * BIG, 5 * BIG
+    args = (1024, 1024, 4096, A, 4096, 1.0, B1, 1024, 0.0, C1, 1024, 1.0, B2, 1024, 0.0, C2, 1024, None)
+    assert lib.hpvm_sgemm_pair_ws(*args, 6 * BIG, -1, None) == -1 and "argument 20" in hp.last_error()
+    assert lib.hpvm_sgemm_pair_ws(*args, 6 * BIG + 4, 1 << 30, None) == -1 and "argument 19" in hp.last_error()
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
+    assert lib.hpvm_sgemm_pair_ws(*args, 6 * BIG, 1 << 30, None) == -3
+    assert lib.hpvm_sgemm_pair_ws(*args, None, 0, None) == -3  # no workspace: the unsplit pair

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_1611_00860_amd import inputs
-from gpu_util import normwise, to_dev, to_host
+from gpu_util import componentwise_bound, normwise, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -130,6 +130,43 @@ def test_pair_random_matches_single_launches_bitwise(gpu, m, n, k):
         torch.cuda.synchronize()
         assert torch.equal(c1, s1) and torch.equal(c2, s2), (tile, single)
         assert normwise(to_host(c1), oracle.sgemm(A, B1, C1, 0.75, 0.5)) <= 1e-5
+
+
+@pytest.mark.parametrize("dist", ["int", "uniform"])
+def test_pair_split_matches_split_single_launches(gpu, dist):
+    """1024 x 1024 x 4096: the pair's tiles would not cover the CUs, so with a
+    workspace it splits the contraction (4 slices of 1024) -- the same slices,
+    wave tiles and ordered sums as the single launch's split, so each output
+    agrees with it bit for bit (integers: with the oracle too)."""
+    import torch
+
+    m, n, k = 1024, 1024, 4096
+    split = (128, 128, 32, 32, 128, 2)
+    assert gpu.pair_workspace_bytes(m, n, k) == 2 * 4 * m * n * 4
+    assert gpu.workspace_bytes(m, n, k, "fp32", split) == 4 * m * n * 4
+    A, B1, C1 = inputs.sgemm_operands(m, n, k, seed=31, dist=dist)
+    _, B2, C2 = inputs.sgemm_operands(m, n, k, seed=32, dist=dist)
+    dA, dB1, dB2 = to_dev(A), to_dev(B1), to_dev(B2)
+    print(f"case: split pair {dist}", flush=True)
+    c1, c2 = to_dev(C1), to_dev(C2)
+    ws = torch.full((gpu.pair_workspace_bytes(m, n, k) // 4,), float("nan"), device="cuda")
+    gpu.sgemm_pair(dA, dB1, c1, dB2, c2, 0.75, 0.5, 1.25, -1.0, workspace=ws)
+    s1, s2 = to_dev(C1), to_dev(C2)
+    gpu.sgemm(dA, dB1, s1, 0.75, 0.5, tile=split)
+    gpu.sgemm(dA, dB2, s2, 1.25, -1.0, tile=split)
+    torch.cuda.synchronize()
+    assert torch.equal(c1, s1) and torch.equal(c2, s2)
+    ref1, ref2 = oracle.sgemm(A, B1, C1, 0.75, 0.5), oracle.sgemm(A, B2, C2, 1.25, -1.0)
+    if dist == "int":
+        assert np.array_equal(to_host(c1), ref1) and np.array_equal(to_host(c2), ref2)
+    else:
+        assert normwise(to_host(c1), ref1) <= 1e-5 and normwise(to_host(c2), ref2) <= 1e-5
+        assert np.all(np.abs(to_host(c1) - ref1) <= componentwise_bound(A, B1, C1, 0.75, 0.5, k))
+    # without a workspace the same call runs unsplit, within the same bound
+    u1, u2 = to_dev(C1), to_dev(C2)
+    gpu.sgemm_pair(dA, dB1, u1, dB2, u2, 0.75, 0.5, 1.25, -1.0, workspace=False)
+    torch.cuda.synchronize()
+    assert normwise(to_host(u2), ref2) <= 1e-5
 
 
 def test_pair_scale_only_output(gpu):
