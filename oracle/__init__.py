@@ -38,10 +38,15 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    src_m = os.path.getmtime(_build.SRC)
-    if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < src_m:
-        _build.build()
-    lib = ctypes.CDLL(_build.LIB)
+    # HPVM_ORACLE_LIB names another build of the oracle (the tests'
+    # sanitizer build); otherwise the default one, rebuilt when stale.
+    path = os.environ.get("HPVM_ORACLE_LIB")
+    if not path:
+        src_m = os.path.getmtime(_build.SRC)
+        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < src_m:
+            _build.build()
+        path = _build.LIB
+    lib = ctypes.CDLL(path)
     lib.oracle_bf16_round.restype = ctypes.c_float
     lib.oracle_bf16_round.argtypes = [ctypes.c_float]
     lib.oracle_bf16_round_array.argtypes = [_ptr, _ptr, _i64]

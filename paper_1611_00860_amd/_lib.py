@@ -161,7 +161,9 @@ def load(path: str | None = None):
         return _lib
     import torch  # noqa: F401  -- binds the library to torch's HIP runtime
 
-    path = path or LIB_PATH
+    # HPVM_SGEMM_LIB names another build of the same library (the tests'
+    # sanitizer build of the host code).
+    path = path or os.environ.get("HPVM_SGEMM_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")

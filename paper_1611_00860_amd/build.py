@@ -31,9 +31,30 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+# The sanitizer build (tests only): AddressSanitizer on the host code of
+# every source (argument checks, handle registries, plan and tracker
+# bookkeeping); device code is built as usual.  The ASan runtime is the one
+# of the ROCm clang that compiles the host code; the library is loaded into
+# a process that preloads it.
+ASAN_DIR = os.path.join(OBJDIR, "asan")
+ASAN_LIB = os.path.join(ASAN_DIR, "libhpvm_sgemm_asan.so")
+ASAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+CLANGXX = "/opt/rocm/llvm/bin/clang++"
+
+
+def asan_runtime() -> str:
+    """Path of the ASan runtime the sanitizer build needs preloaded."""
+    out = subprocess.run([CLANGXX, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = out.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        found = glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+        path = found[0] if found else ""
+    return path
+
+
+def _compile(src: str, verbose: bool, objdir: str = OBJDIR, extra=()) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,10 +71,11 @@ CXX = os.environ.get("CXX", "g++")
 CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 
 
-def _compile_host(src: str, verbose: bool) -> str:
+def _compile_host(src: str, verbose: bool, objdir: str = OBJDIR, sanitize: bool = False) -> str:
     """Host-only C++ (the CPU lowering): compiled by the host compiler."""
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [CXX, *CXXFLAGS, "-c", src, "-o", obj]
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = [CLANGXX, *CXXFLAGS, "-fsanitize=address", "-fno-omit-frame-pointer"] if sanitize else [CXX, *CXXFLAGS]
+    cmd += ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -62,21 +84,34 @@ def _compile_host(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every kernel source for gfx950 and link the library; returns its path."""
-    os.makedirs(OBJDIR, exist_ok=True)
-    os.makedirs(LIBDIR, exist_ok=True)
-    sources = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
-    jobs = jobs or min(len(sources), max(1, (os.cpu_count() or 2) // 2))
+def sources() -> list:
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
+
+
+def build(verbose: bool = False, jobs: int | None = None, sanitize: bool = False) -> str:
+    """Compile every kernel source for gfx950 and link the library; returns its
+    path.  sanitize: the AddressSanitizer build of the host code, as ASAN_LIB."""
+    objdir = ASAN_DIR if sanitize else OBJDIR
+    lib = ASAN_LIB if sanitize else LIB
+    os.makedirs(objdir, exist_ok=True)
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2) // 2))
+
+    def one(src):
+        if src.endswith(".cpp"):
+            return _compile_host(src, verbose, objdir, sanitize)
+        return _compile(src, verbose, objdir, ASAN_HOST if sanitize else ())
+
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: (_compile_host if s.endswith(".cpp") else _compile)(s, verbose), sources))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        objs = list(ex.map(one, srcs))
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *(ASAN_HOST if sanitize else ()), "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
