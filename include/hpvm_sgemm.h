@@ -490,9 +490,11 @@ int hpvm_grouped_plan_destroy(void* plan);
 /* Autotuner of the grouped plan: times candidate shape assignments (one
  * shape for all instances, and cost-model assignments) with the real
  * kernel, keeps the fastest in the plan and returns its time per launch in
- * *best_ms.  Timing runs write their outputs to `scratch` (device memory of
- * hpvm_grouped_info.scratch_bytes, with beta = 0), never to the instances'
- * C.  Each candidate is launched `reps` times after one warm-up.           */
+ * *best_ms.  Timing runs use `scratch` (device memory of
+ * hpvm_grouped_info.scratch_bytes, zeroed first) as every instance's C, with
+ * the instance's own beta, so they read C where the replays do; the
+ * instances' C are never touched.  Each candidate is launched `reps` times
+ * after one warm-up.                                                       */
 int hpvm_grouped_autotune(void* plan, void* workspace, int64_t workspace_bytes, float* scratch,
                           int64_t scratch_bytes, int32_t reps, void* stream, float* best_ms);
 

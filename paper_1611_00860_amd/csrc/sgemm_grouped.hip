@@ -132,8 +132,9 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int64_t tiles_of(const hpvm_sgemm_desc& d, int shape) { return shape_tiles(d.m, d.n, shape); }
 
 // Rebuilds the device schedule from plan->user and plan->shape.  With
-// `scratch`, every instance writes to its own slice of scratch (ldc = n,
-// beta = 0) instead of its C.
+// `scratch`, every instance reads and writes its own slice of scratch
+// (ldc = n) instead of its C, with its own beta, so that timing runs do the
+// replays' work (C read when beta != 0) without touching C.
 void build_schedule(Plan* p, float* scratch) {
   const int count = (int)p->user.size();
   std::vector<int> order(count);
@@ -169,7 +170,7 @@ void build_schedule(Plan* p, float* scratch) {
     d.n = (int32_t)u.n;
     d.k = u.alpha != 0.0f ? (int32_t)u.k : 0;  // alpha == 0: A and B are not read
     d.alpha = u.alpha;
-    d.beta = scratch ? 0.0f : u.beta;
+    d.beta = u.beta;
     d.shape = p->shape[i];
     d.tiles_n = (int32_t)ceil_div(u.n, kGroupedShapes[d.shape].tile.tile_n);
     d.tile_start = (int32_t)p->tile_inst.size();
@@ -520,6 +521,12 @@ int hpvm_grouped_autotune(void* plan, void* workspace, int64_t workspace_bytes_,
   if (reps < 1) return set_error(HPVM_INVALID_ARG, "argument 6: reps = %d < 1", reps);
   if (!best_ms) return set_error(HPVM_INVALID_ARG, "argument 8: best_ms is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // The timing runs read the scratch as C: clear it first (a fill kernel,
+  // so the values read are finite and the same every time).
+  if (need > 0) {
+    hipError_t ze = launch_scale(scratch, 1, 1, need / (int64_t)sizeof(float), 0.0f, s);
+    if (ze != hipSuccess) return hip_error(ze, "grouped autotune (clear scratch)");
+  }
 
   // Candidates: one shape for all instances, and the cost model at several
   // weights of the per-shape cost factors.
