@@ -323,6 +323,14 @@ int hpvm_tile_menu(int32_t prec, hpvm_tile* out, int32_t capacity,
  * dB) in transposed form; the staged one (tiles with stages == 3) folds
  * that transposition into its conversion passes, and converts G for both
  * products in one pass that also writes dC_in and the partials of dbeta.
+ * The first menu entry of FP32 and of BF16 (256 x 256 x 32, leaf 64 x 128)
+ * runs both products on the DMA-fed loop with their contractions split into
+ * slices (partial sums in the workspace, then one ordered summing pass that
+ * also writes dC_in and dbeta's partials); BF16 there rounds the FP32 slabs
+ * in the fragment reads, with no conversion pass.  Passes that are not
+ * whole, 16-byte aligned tiles take another entry (FP32: per pass; BF16:
+ * the whole call takes the staged 128 x 128 x 64 entry).  The built-in
+ * choice takes the DMA entry for FP32 only.
  * The two scalars are reduced
  * in FP32 with fixed-order tree sums, so repeated calls give identical bits.
  * Any of dA, dB, dC_in, dalpha, dbeta may be NULL to skip that output.

@@ -32,6 +32,7 @@
 #include "hpvm_sgemm.h"
 #include "internal.hpp"
 #include "mfma_bf16.hpp"
+#include "mfma_bf16_dma.hpp"
 #include "mfma_f32.hpp"
 #include "mfma_f32_dma.hpp"
 
@@ -276,7 +277,10 @@ struct BwdEntry {
   int32_t threads;
   int64_t lds;
   void (*grad_a)(GemmArgs, const float*, int64_t, float*);  // null for staged entries
-  bool dma = false;  // split-contraction DMA-fed FP32 entry (falls back to kBwd[1])
+  bool dma = false;  // split-contraction DMA-fed entry
+  // DMA entries: the entry for what the DMA-fed loop does not cover (FP32:
+  // the passes that are not whole aligned tiles; BF16: the whole call).
+  int fallback = 1;
 };
 
 template <int TM, int TN, int TK, int WM, int WN, int PREC>
@@ -305,16 +309,29 @@ constexpr BwdEntry dma_entry() {
   e.dma = true;
   return e;
 }
+// The same tiles with BF16 products converted from the FP32 slabs in the
+// fragment reads (mfma_bf16_dma.hpp): no conversion pass at all.  A call it
+// does not cover in whole aligned tiles takes the staged entry `fallback`.
+using Bf16DmaA = Bf16SrcShape<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, false, true, kDmaStages>;
+using Bf16DmaB = Bf16SrcShape<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, true, false, kDmaStages>;
+constexpr BwdEntry bf16_dma_entry(int fallback) {
+  BwdEntry e{{kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, kDmaStages}, HPVM_PREC_BF16, Bf16DmaA::NW * kWave,
+             Bf16DmaA::kLdsBytes > Bf16DmaB::kLdsBytes ? Bf16DmaA::kLdsBytes : Bf16DmaB::kLdsBytes, nullptr};
+  e.dma = true;
+  e.fallback = fallback;
+  return e;
+}
 
 // Per precision, in the order the built-in choice tries them.  kBwd[1] is
 // the DMA entry's fallback for problems that are not whole tiles.
-const BwdEntry kBwd[] = {
+constexpr BwdEntry kBwd[] = {
     dma_entry(),
     fused_entry<128, 128, 32, 64, 64, HPVM_PREC_FP32>(),
     fused_entry<128, 128, 16, 64, 64, HPVM_PREC_FP32>(),
     fused_entry<128, 64, 16, 64, 32, HPVM_PREC_FP32>(),
     fused_entry<64, 128, 16, 32, 64, HPVM_PREC_FP32>(),
     fused_entry<64, 64, 16, 32, 32, HPVM_PREC_FP32>(),
+    bf16_dma_entry(7),
     staged_entry(128, 128, 64, 64, 32, HPVM_PREC_BF16),
     staged_entry(128, 128, 64, 64, 64, HPVM_PREC_BF16),
     staged_entry(256, 256, 64, 128, 64, HPVM_PREC_BF16),
@@ -329,6 +346,8 @@ const BwdEntry kBwd[] = {
     fused_entry<64, 64, 32, 32, 32, HPVM_PREC_BF16X3>(),
 };
 constexpr int kNumBwd = sizeof(kBwd) / sizeof(kBwd[0]);
+static_assert(kBwd[6].dma && kBwd[6].prec == HPVM_PREC_BF16 && !kBwd[7].grad_a && kBwd[7].prec == HPVM_PREC_BF16,
+              "the BF16 DMA entry falls back to the staged entry after it");
 
 int64_t tiles_for(const hpvm_tile& t, int64_t rows, int64_t cols) {
   return ((rows + t.tile_m - 1) / t.tile_m) * ((cols + t.tile_n - 1) / t.tile_n);
@@ -411,7 +430,10 @@ const BwdEntry* pick(int32_t prec, int64_t m, int64_t n, int64_t k) {
   for (int i = 0; i < kNumBwd; ++i) {
     if (kBwd[i].prec != prec) continue;
     if (kBwd[i].dma) {
-      if (dma_splits(m, k, n)) return &kBwd[i];
+      // FP32 only: the BF16 DMA entry reads FP32 slabs where the staged
+      // products read bfloat16 planes, twice the bytes (4096 x 4096 x 1024:
+      // 0.181 ms against 0.131 for the staged 128 x 128 x 64 tile).
+      if (prec == HPVM_PREC_FP32 && dma_splits(m, k, n)) return &kBwd[i];
       continue;
     }
     if (!kBwd[i].grad_a && !staged_ok) continue;
@@ -475,7 +497,7 @@ BwdPlanes bwd_planes(int32_t prec, void* stage, int64_t m, int64_t n, int64_t k)
 BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
   BwdLayout L;
-  L.na = (m > 0 && k > 0) ? tiles_for(e->dma ? kBwd[1].tile : e->tile, m, k) : 0;
+  L.na = (m > 0 && k > 0) ? tiles_for(e->dma ? kBwd[e->fallback].tile : e->tile, m, k) : 0;
   const DmaPlan d = dma_plan(e, m, n, k);
   if (d.sa) L.na = std::max(L.na, split_sum_blocks(m, k));
   L.nb = elem_blocks(m, n);
@@ -489,6 +511,9 @@ BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
   }
   if (e->dma) stage = 4 * std::max<int64_t>(std::max<int64_t>(d.sa * m * k, d.sb * k * n), d.sp * (m * k + k * n));
   L.total = L.stage_off + stage;
+  // A call the BF16 DMA entry does not cover takes its fallback entry, in
+  // the same workspace.
+  if (e->dma && e->prec != HPVM_PREC_FP32) L.total = std::max(L.total, bwd_layout(&kBwd[e->fallback], m, n, k).total);
   return L;
 }
 
@@ -496,13 +521,16 @@ BwdLayout bwd_layout(const BwdEntry* e, int64_t m, int64_t n, int64_t k) {
 // partial tiles to part ([splits][a.m][a.n]), then sgemm_split_sum adds
 // them, writes out = alpha * sum (when out is given) and dalpha's partials
 // (when aorig is given).
-template <bool AT, bool BT>
+template <int PREC, bool AT, bool BT>
 hipError_t launch_split(const GemmArgs& args, int splits, float* part, float* out, int64_t ldo, const float* aorig,
                         int64_t ldao, float* dpart, hipStream_t s) {
   using S = F32DmaShape<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, AT, BT, kDmaStages>;
-  auto* fn = &sgemm_f32_dma<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, AT, BT, kDmaStages, kDmaSplit>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLdsBytes);
+  const void* fn = PREC == HPVM_PREC_FP32
+                       ? reinterpret_cast<const void*>(
+                             &sgemm_f32_dma<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, AT, BT, kDmaStages, kDmaSplit>)
+                       : reinterpret_cast<const void*>(&sgemm_bf16src_dma<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN,
+                                                                          AT, BT, kDmaStages, false, kDmaSplit>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLdsBytes);
   if (e != hipSuccess) return e;
   GemmArgs a = args;
   a.C = part;
@@ -513,9 +541,10 @@ hipError_t launch_split(const GemmArgs& args, int splits, float* part, float* ou
   F32DmaOut o{};
   o.splits = splits;
   int32_t sp = splits;
-  void* kargs[] = {&a, &unused, &o};
-  e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n * splits)),
-                      dim3(S::NW * kWave), kargs, (size_t)S::kLdsBytes, s);
+  void* kargs_f32[] = {&a, &unused, &o};
+  void* kargs_bf16[] = {&a, &o};
+  e = hipLaunchKernel(fn, dim3((unsigned)(a.tiles_m * a.tiles_n * splits)), dim3(S::NW * kWave),
+                      PREC == HPVM_PREC_FP32 ? kargs_f32 : kargs_bf16, (size_t)S::kLdsBytes, s);
   if (e != hipSuccess || (!out && !dpart)) return e;
   SumJob j{part, sp, a.m, a.n, args.alpha, out, ldo, aorig, ldao, dpart, split_sum_blocks(a.m, a.n)};
   void* sargs[] = {&j};
@@ -549,15 +578,44 @@ __global__ void __launch_bounds__(DmaA::NW * kWave) __attribute__((amdgpu_waves_
   }
 }
 
+// The same with BF16 products (the FP32 slabs converted in the fragment
+// reads).
+constexpr int64_t kBf16DmaPairLds = Bf16DmaA::kLdsBytes > Bf16DmaB::kLdsBytes ? Bf16DmaA::kLdsBytes
+                                                                                : Bf16DmaB::kLdsBytes;
+constexpr int kBf16DmaPairWaves = Bf16DmaA::kMaxWaves < Bf16DmaB::kMaxWaves ? Bf16DmaA::kMaxWaves
+                                                                             : Bf16DmaB::kMaxWaves;
+static_assert(Bf16DmaA::NW == DmaA::NW && Bf16DmaB::NW == DmaA::NW, "one workgroup size");
+
+__global__ void __launch_bounds__(Bf16DmaA::NW * kWave) __attribute__((amdgpu_waves_per_eu(1, kBf16DmaPairWaves)))
+    sgemm_grad_pair_bf16src(GemmArgs pa, F32DmaOut oa, GemmArgs pb, F32DmaOut ob) {
+  extern __shared__ __align__(16) char smem[];
+  const int ta = pa.tiles_m * pa.tiles_n, na = ta * oa.splits;
+  int t = blockIdx.x, tm, tn;
+  if (t < na) {
+    const int z = t / ta;
+    tile_coords(pa.tiles_m, pa.tiles_n, t - z * ta, tm, tn);
+    bf16src_dma_tile<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, false, true, kDmaStages, false, kDmaSplit, false,
+                     kBf16SrcCvb<kDmaWM, kDmaWN, false>>(pa, oa, tm, tn, z, smem);
+  } else {
+    t -= na;
+    const int tb = pb.tiles_m * pb.tiles_n, z = t / tb;
+    tile_coords(pb.tiles_m, pb.tiles_n, t - z * tb, tm, tn);
+    bf16src_dma_tile<kDmaTile, kDmaTile, kDmaK, kDmaWM, kDmaWN, true, false, kDmaStages, false, kDmaSplit, false,
+                     kBf16SrcCvb<kDmaWM, kDmaWN, false>>(pb, ob, tm, tn, z, smem);
+  }
+}
+
 // dA and dB with `splits` slices each in one launch (partials [splits][m][k]
 // at part_a, [splits][k][n] at part_b), then one launch of both slice sums
 // and the grad_c job gc (absent when gc.blocks == 0).
-hipError_t launch_split_pair(const GemmArgs& ga, const GemmArgs& gb, int splits, float* part_a, float* part_b,
-                             float* dA, int64_t ldda, float* dB, int64_t lddb, const float* aorig, int64_t ldao,
-                             float* dpart, GradCJob gc, hipStream_t s) {
-  auto* fn = &sgemm_grad_pair_dma;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDmaPairLds);
+hipError_t launch_split_pair(int32_t prec, const GemmArgs& ga, const GemmArgs& gb, int splits, float* part_a,
+                             float* part_b, float* dA, int64_t ldda, float* dB, int64_t lddb, const float* aorig,
+                             int64_t ldao, float* dpart, GradCJob gc, hipStream_t s) {
+  const bool f32 = prec == HPVM_PREC_FP32;
+  const void* fn = f32 ? reinterpret_cast<const void*>(&sgemm_grad_pair_dma)
+                       : reinterpret_cast<const void*>(&sgemm_grad_pair_bf16src);
+  const int64_t lds = f32 ? kDmaPairLds : kBf16DmaPairLds;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   GemmArgs a = ga, b = gb;
   a.C = part_a;
@@ -572,8 +630,7 @@ hipError_t launch_split_pair(const GemmArgs& ga, const GemmArgs& gb, int splits,
   oa.splits = ob.splits = splits;
   void* kargs[] = {&a, &oa, &b, &ob};
   const int64_t wgs = ((int64_t)a.tiles_m * a.tiles_n + (int64_t)b.tiles_m * b.tiles_n) * splits;
-  e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)wgs), dim3(DmaA::NW * kWave), kargs,
-                      (size_t)kDmaPairLds, s);
+  e = hipLaunchKernel(fn, dim3((unsigned)wgs), dim3(DmaA::NW * kWave), kargs, (size_t)lds, s);
   if (e != hipSuccess) return e;
   SumJob ja{part_a, splits, a.m, a.n, ga.alpha, dA, ldda, aorig, ldao, dpart,
             (dA || dpart) ? split_sum_blocks(a.m, a.n) : 0};
@@ -594,7 +651,7 @@ int resolve_bwd(int32_t prec, const hpvm_tile* tile, int64_t m, int64_t n, int64
   if (!*out)
     return set_error(HPVM_UNSUPPORTED, "argument %d: tile not in the backward menu for precision %d", argno,
                      prec);
-  if (!(*out)->grad_a && !(staged_k_ok(n) && staged_k_ok(m)))
+  if (!(*out)->grad_a && !(*out)->dma && !(staged_k_ok(n) && staged_k_ok(m)))
     return set_error(HPVM_UNSUPPORTED, "argument %d: m or n too deep a contraction for a staged tile", argno);
   return HPVM_OK;
 }
@@ -675,8 +732,20 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   const BwdEntry* cfg;
   int rc = resolve_bwd(prec, tile, m, n, k, &cfg, 23);
   if (rc != HPVM_OK) return rc;
-  const BwdLayout L = bwd_layout(cfg, m, n, k);
-  const bool staged = cfg->grad_a == nullptr;
+  // The BF16 DMA entry runs a call only when every pass it makes is whole,
+  // aligned tiles; otherwise the whole call takes its staged fallback (the
+  // workspace it asks for covers that entry too).
+  const BwdLayout L0 = bwd_layout(cfg, m, n, k);
+  if (cfg->dma && prec != HPVM_PREC_FP32) {
+    const DmaPlan d = dma_plan(cfg, m, n, k);
+    const bool ok_a = !run_a || (d.sa && vec16(G, ldg) && vec16(B, ldb) && (!dA || vec16(dA, ldda)) &&
+                                 (!dalpha || vec16(A, lda)));
+    const bool ok_b = !run_b || (d.sb && vec16(A, lda) && vec16(G, ldg) && vec16(dB, lddb));
+    if (!ok_a || !ok_b) cfg = &kBwd[cfg->fallback];
+  }
+  BwdLayout L = bwd_layout(cfg, m, n, k);
+  L.total = L0.total;
+  const bool staged = cfg->grad_a == nullptr && !cfg->dma;
   const DmaPlan plan = dma_plan(cfg, m, n, k);
   const bool need_ws = dalpha || dbeta || (staged && (run_a || run_b)) || (cfg->dma && (run_a || run_b));
   if (need_ws && !workspace) return set_error(HPVM_INVALID_ARG, "argument 24: workspace is NULL");
@@ -694,7 +763,7 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
   void* stage = ws ? ws + L.stage_off : nullptr;
   // A DMA entry runs a pass it does not cover in whole, aligned tiles on
   // its fallback entry.
-  const BwdEntry* fb = cfg->dma ? &kBwd[1] : cfg;
+  const BwdEntry* fb = cfg->dma ? &kBwd[cfg->fallback] : cfg;
   const MfmaEntry* me = find_menu_entry(prec, fb->tile);
   const bool dma_a = plan.sa && vec16(G, ldg) && vec16(B, ldb) && (!dA || vec16(dA, ldda)) &&
                      (!dalpha || vec16(A, lda));
@@ -786,8 +855,11 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
       if (dma_pair)
         a_pair = a;  // launched with dB below
       else
-        e = launch_split<false, true>(a, plan.sa, reinterpret_cast<float*>(stage), dA, ldda, dalpha ? A : nullptr,
-                                      lda, dalpha ? pa : nullptr, s);
+        e = prec == HPVM_PREC_FP32
+                ? launch_split<HPVM_PREC_FP32, false, true>(a, plan.sa, reinterpret_cast<float*>(stage), dA, ldda,
+                                                            dalpha ? A : nullptr, lda, dalpha ? pa : nullptr, s)
+                : launch_split<HPVM_PREC_BF16, false, true>(a, plan.sa, reinterpret_cast<float*>(stage), dA, ldda,
+                                                            dalpha ? A : nullptr, lda, dalpha ? pa : nullptr, s);
       na = dalpha ? split_sum_blocks(m, k) : 0;
     } else if (staged) {
       if (pair)
@@ -835,13 +907,17 @@ int hpvm_sgemm_backward(int64_t m, int64_t n, int64_t k, float alpha, float beta
     b.vec_a = vec16(A, lda);
     b.vec_b = vec16(G, ldg);
     if (dma_pair) {
-      e = launch_split_pair(a_pair, b, plan.sp, reinterpret_cast<float*>(stage),
+      e = launch_split_pair(prec, a_pair, b, plan.sp, reinterpret_cast<float*>(stage),
                             reinterpret_cast<float*>(stage) + plan.sp * m * k, dA, ldda, dB, lddb,
                             dalpha ? A : nullptr, lda, dalpha ? pa : nullptr, gc, s);
       gc_done = true;
     }
     else if (dma_b)
-      e = launch_split<true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb, nullptr, 0, nullptr, s);
+      e = prec == HPVM_PREC_FP32
+              ? launch_split<HPVM_PREC_FP32, true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb,
+                                                          nullptr, 0, nullptr, s)
+              : launch_split<HPVM_PREC_BF16, true, false>(b, plan.sb, reinterpret_cast<float*>(stage), dB, lddb,
+                                                          nullptr, 0, nullptr, s);
     else if (!me) e = hipErrorInvalidValue;
     else if (staged && pair)
       e = me->launch_staged_pair(a_pair, StagedPlanes{P.gh, P.gl, P.bh, P.bl}, A, lda, dalpha ? pa : nullptr, b,

@@ -101,22 +101,24 @@ def test_backward_edge_cases(gpu):
     del A0, B0
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("m,n,k", [(512, 512, 256), (256, 1024, 512)])
-def test_backward_dma_split_integers(gpu, m, n, k):
-    """FP32 whole tiles take the DMA-fed loop with the contraction split into
-    slices (dA over n, dB over m) and one ordered pass summing the slices:
-    integer inputs stay exact, and the DMA tile named explicitly or chosen
-    by default gives the same bits."""
+def test_backward_dma_split_integers(gpu, prec, m, n, k):
+    """Whole tiles take the DMA-fed loop with the contraction split into
+    slices (dA over n, dB over m) and one ordered pass summing the slices --
+    BF16 converting the FP32 slabs in the fragment reads, with no conversion
+    pass: integer inputs stay exact, and the DMA tile named explicitly or
+    chosen by default gives the same bits."""
     import torch
 
-    print(f"case: backward dma split {m}x{n}x{k}", flush=True)
+    print(f"case: backward dma split {prec} {m}x{n}x{k}", flush=True)
     A, B, C, G = inputs.backward_operands(m, n, k, seed=m + n + k, dist="int")
     ref = oracle.sgemm_grad(A, B, C, G, 1.0, 2.0)
     d = dev_all(A, B, C, G)
-    dma_tile = gpu.backward_menu("fp32")[0]
+    dma_tile = gpu.backward_menu(prec)[0]
     assert dma_tile[4] == 128
-    g = gpu.sgemm_backward(*d, 1.0, 2.0, prec="fp32", tile=dma_tile)
-    g0 = gpu.sgemm_backward(*d, 1.0, 2.0, prec="fp32")
+    g = gpu.sgemm_backward(*d, 1.0, 2.0, prec=prec, tile=dma_tile)
+    g0 = gpu.sgemm_backward(*d, 1.0, 2.0, prec=prec)
     torch.cuda.synchronize()
     for key in ("dA", "dB", "dC_in"):
         assert np.array_equal(to_host(g[key]), ref[key]), key
