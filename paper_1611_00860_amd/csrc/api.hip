@@ -243,10 +243,13 @@ bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, int64_t ws_b
   // against 0.070; at 4096^3 the first tile stays ahead, 0.150 against 0.159).
   const hpvm::MfmaEntry* small = hpvm::find_menu_entry(prec, hpvm_tile{128, 128, 64, 64, 32, 3});
   const bool big = tiles_of(staged[0].tile, m, n) >= 256;
-  // bf16x3 products that the DMA-fed 256 x 256 tile covers run faster on it,
-  // converting in the GEMM's own load path (8192^3: 2.71 ms against 2.82
-  // staged, 4096^3: 0.353 against 0.366), so they take no workspace.
-  if (prec == HPVM_PREC_BF16X3 && big && k % 32 == 0 && n % 4 == 0) return false;
+  // bf16x3 products that the DMA-fed 256 x 256 tile (menu entry 0) covers
+  // run faster on it, converting in the GEMM's own fragment reads (8192^3:
+  // 2.71 ms against 2.82 staged, 4096^3: 0.353 against 0.366), so they take
+  // no workspace.
+  const hpvm::MfmaEntry* e0 = hpvm::menu_entry_at(prec, 0);
+  if (prec == HPVM_PREC_BF16X3 && e0 && tiles_of(e0->tile, m, n) >= 256 && k % e0->tile.tile_k == 0 && n % 4 == 0)
+    return false;
   const hpvm_tile pick = big || !small ? staged[0].tile : small->tile;
   // A workspace too small for the planes: the choice without one.
   if (ws_bytes >= 0 && ws_bytes < hpvm::staged_workspace_bytes(prec, m, n, k)) return false;
