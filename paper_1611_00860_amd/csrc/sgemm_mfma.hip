@@ -284,11 +284,13 @@ struct Bf16SrcConfig {
 
 // Entry 0 is the default when no tile is given: BF16 and bf16x3 on the
 // DMA-fed loop, falling back to the register-staged 256 x 256 x 32 tile.
-// 16-deep slabs in 4 stages come first for both (8192^3 bf16x3: 2.71 ms
-// against 2.90 for 32-deep slabs in 2 stages).
+// bf16x3 takes 16-deep slabs in 4 stages first (8192^3: 2.65 ms against
+// 2.87 for 32-deep slabs in 2 stages), BF16 32-deep slabs in 2 stages
+// (8192^3: 1.46 ms against 1.51, 4096^3: 0.167 against 0.176; a fifth
+// 16-deep stage, all 160 KB of LDS, gave 1.45).
 static const MfmaEntry kBf16Menu[] = {
-    HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16, false, 256, 256, 16, 64, 128, 4, 128, 64),
     HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16, false, 256, 256, 32, 64, 128, 2, 128, 64),
+    HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16, false, 256, 256, 16, 64, 128, 4, 128, 64),
     HPVM_BF16SRC_ENTRY(HPVM_PREC_BF16, false, 128, 128, 32, 64, 64, 4, 64, 64),
     HPVM_BF16_ENTRY(HPVM_PREC_BF16, false, 256, 256, 32, 128, 64),
     HPVM_BF16_ENTRY(HPVM_PREC_BF16, false, 256, 128, 32, 128, 64),
