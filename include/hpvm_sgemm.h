@@ -203,7 +203,8 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A,
  * lowering (tiles with stages == 3), which first rewrites A and B as
  * zero-padded bfloat16 planes (B transposed so k is contiguous; hi and lo
  * planes for bf16x3) in `workspace` and then runs a GEMM over them; and
- * the split contraction of FP32 DMA-fed tiles (leaf_n == 128): a whole-tile
+ * the split contraction of the DMA-fed tiles (FP32: leaf_n == 128; BF16 and
+ * bf16x3: stages 2 and 4): a whole-tile
  * problem (m, n multiples of the tile, A, B, C 16-byte aligned with leading
  * dimensions that are multiples of 4) whose tiles would not cover 256 CUs
  * runs as s contraction slices (s doubled from 1 while tiles * s < 256, at
@@ -214,14 +215,16 @@ int hpvm_sgemm(int64_t m, int64_t n, int64_t k, float alpha, const float* A,
  * by rounding only.
  * workspace: device memory, 16-byte aligned, at least
  * hpvm_sgemm_workspace_bytes(m, n, k, prec, tile) bytes (may be NULL when
- * that is 0); its contents are scratch.  For a split FP32 tile it is
+ * that is 0); its contents are scratch.  For a split tile it is
  * optional: NULL or fewer bytes run the single launch.  tile == NULL takes
- * the autotuned overall winner; with no autotuned entry, FP32 problems that
- * even 128 x 128 tiles would not cover 256 CUs with take the DMA-fed tile
- * with the fewest slices (the first in menu order on a tie), BF16 and
- * bf16x3 products of at least 2^31
- * multiply-adds (m n k) take the first staged tile, or 128 x 128 x 64 with
- * 64 x 32 leaves when the first would give fewer than 256 tiles, and others
+ * the autotuned overall winner; with no autotuned entry, problems that
+ * even 128 x 128 tiles would not cover 256 CUs with (BF16 and bf16x3: with
+ * k >= 2048) take the DMA-fed tile with the fewest slices (the first in
+ * menu order on a tie) when the workspace holds the partial sums; other
+ * BF16 products of at least 2^31 multiply-adds (m n k) take the first
+ * staged tile, or 128 x 128 x 64 with 64 x 32 leaves when the first would
+ * give fewer than 256 tiles (bf16x3 only when the DMA-fed 256 x 256 tile
+ * would not cover the CUs or does not suit k and n), and others
  * hpvm_sgemm's choice.  Every other argument and rule is hpvm_sgemm's.     */
 int hpvm_sgemm_ws(int64_t m, int64_t n, int64_t k, float alpha, const float* A, int64_t lda,
                   const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int32_t prec,
@@ -229,7 +232,7 @@ int hpvm_sgemm_ws(int64_t m, int64_t n, int64_t k, float alpha, const float* A, 
 
 /* Workspace bytes hpvm_sgemm_ws needs for these sizes and tile (NULL = the
  * tile it would pick): the staged lowering's planes, or s * m * n * 4 for a
- * split FP32 contraction of s slices; 0 otherwise.                         */
+ * split contraction of s slices; 0 otherwise.                              */
 int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec,
                                const hpvm_tile* tile, int64_t* bytes);
 
@@ -240,11 +243,11 @@ int hpvm_sgemm_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t prec,
  * on each device it runs on (from that device's first call until the
  * process ends).  The call allocates and frees nothing.  Arguments, checks,
  * results and errors are hpvm_sgemm_ws's for a workspace of that size: with
- * tile == NULL the choice is the one that workspace allows (a split FP32
+ * tile == NULL the choice is the one that workspace allows (a split
  * contraction or the staged BF16 / bf16x3 planes only when they fit); an
  * explicit tile of the staged lowering whose planes need more than
  * HPVM_NOALLOC_SCRATCH_BYTES is refused with HPVM_WORKSPACE_TOO_SMALL
- * before any device work, and an explicit split FP32 tile whose partial
+ * before any device work, and an explicit split tile whose partial
  * sums do not fit runs as one launch.  The array of the current device is
  * used, so `stream` must belong to the current device.  Every call on a
  * device shares that device's array: calls that overlap in time on one
@@ -290,7 +293,7 @@ int hpvm_describe(int64_t m, int64_t n, int64_t k, int32_t prec,
 
 /* The same for hpvm_sgemm_ws given a workspace of `workspace_bytes` (>= 0):
  * the tile it picks for tile == NULL with that workspace, and in `splits`
- * the contraction slices it runs (a split FP32 tile whose partial sums do
+ * the contraction slices it runs (a split tile whose partial sums do
  * not fit runs as one launch, splits = 1).                                 */
 int hpvm_describe_ws(int64_t m, int64_t n, int64_t k, int32_t prec, const hpvm_tile* tile,
                      int64_t workspace_bytes, hpvm_dfg* out);

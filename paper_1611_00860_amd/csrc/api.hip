@@ -200,39 +200,52 @@ bool default_small_tile(int32_t prec, int64_t m, int64_t n, hpvm_tile* out) {
 
 namespace {
 
+// The DMA-fed entry whose split contraction needs the fewest partial sums
+// (the deepest slices; the first in menu order on a tie), or null.
+const hpvm::MfmaEntry* fewest_slices(int32_t prec, int64_t m, int64_t n, int64_t k, int64_t* bytes) {
+  const hpvm::MfmaEntry* best = nullptr;
+  int64_t best_bytes = 0;
+  for (int i = 0; i < hpvm::menu_size(prec); ++i) {
+    const hpvm::MfmaEntry* e = hpvm::menu_entry_at(prec, i);
+    const int64_t b = hpvm::entry_split_bytes(e, m, n, k);
+    if (b > 0 && (!best || b < best_bytes)) {
+      best = e;
+      best_bytes = b;
+    }
+  }
+  *bytes = best_bytes;
+  return best;
+}
+
 // Built-in choice of hpvm_sgemm_ws (and of hpvm_sgemm_workspace_bytes) for
-// tile == NULL when the autotuner has no entry: FP32 products that even
-// 128 x 128 tiles would not cover the CUs with take the DMA-fed entry that
-// splits the contraction into the deepest slices, provided `ws_bytes` (the
-// caller's workspace; -1 = as much as needed) holds its partial sums;
+// tile == NULL when the autotuner has no entry: products that even 128 x 128
+// tiles would not cover the CUs with (BF16 and bf16x3: with k >= 2048) take
+// the DMA-fed entry that splits the contraction into the deepest slices,
+// provided `ws_bytes` (the caller's workspace; -1 = as much as needed)
+// holds its partial sums (BF16 512 x 512 x 4096: 0.035 ms against 0.095 on
+// 64 x 64 tiles, 1024 x 1024 x 4096: 0.047 against 0.069 staged); other
 // BF16 products of at least 2^31 multiply-adds take the first staged tile,
 // whose conversion pass is then a small share of the time (or, when that
 // gives fewer than 256 tiles, the 128 x 128 x 64 tile with 64 x 32 leaves);
 // bf16x3 products the same only when 256 x 256 tiles would not cover the
 // CUs (or k or n does not suit the DMA-fed tile).  Returns false when
-// neither applies (hpvm_sgemm's choice
-// then): a split tile run as one launch would be the slowest choice there
-// is (64 tiles of 128 x 128 at 1024 x 1024 x 4096: 28 TFLOP/s against 75
-// for hpvm_sgemm's 64 x 64 tiles).
+// neither applies (hpvm_sgemm's choice then): a split tile run as one
+// launch would be the slowest choice there is (64 tiles of 128 x 128 at
+// 1024 x 1024 x 4096 FP32: 28 TFLOP/s against 75 for hpvm_sgemm's 64 x 64
+// tiles).
 bool default_ws_tile(int32_t prec, int64_t m, int64_t n, int64_t k, int64_t ws_bytes, hpvm_tile* out) {
-  if (prec == HPVM_PREC_FP32) {
-    // Only when even 128 x 128 tiles would not cover the CUs; then the
-    // deepest slices = fewest partial sums, the first in menu order on a tie.
-    const hpvm::MfmaEntry* mid = f32_mid_entry();
-    if (mid && tiles_of(mid->tile, m, n) >= 256) return false;
-    const hpvm::MfmaEntry* best = nullptr;
-    int64_t best_bytes = 0;
-    for (int i = 0; i < hpvm::menu_size(prec); ++i) {
-      const hpvm::MfmaEntry* e = hpvm::menu_entry_at(prec, i);
-      const int64_t b = hpvm::entry_split_bytes(e, m, n, k);
-      if (b > 0 && (!best || b < best_bytes)) {
-        best = e;
-        best_bytes = b;
-      }
+  // The split contraction, only when even 128 x 128 tiles would not cover
+  // the CUs (BF16 / bf16x3: and k >= 2048; at 1024^3 the 64 x 64 tiles were
+  // as fast, 0.031 ms against 0.033), on the entry with the deepest slices.
+  const hpvm::MfmaEntry* mid =
+      prec == HPVM_PREC_FP32 ? f32_mid_entry() : hpvm::find_menu_entry(prec, hpvm_tile{128, 128, 32, 64, 64, 4});
+  if (mid && tiles_of(mid->tile, m, n) < 256 && (prec == HPVM_PREC_FP32 || k >= 2048)) {
+    int64_t need = 0;
+    const hpvm::MfmaEntry* best = fewest_slices(prec, m, n, k, &need);
+    if (best && (ws_bytes < 0 || ws_bytes >= need)) {
+      *out = best->tile;
+      return true;
     }
-    if (!best || (ws_bytes >= 0 && ws_bytes < best_bytes)) return false;
-    *out = best->tile;
-    return true;
   }
   if (prec != HPVM_PREC_BF16 && prec != HPVM_PREC_BF16X3) return false;
   if ((double)m * (double)n * (double)k < 2147483648.0 || !hpvm::staged_k_ok(k)) return false;

@@ -253,7 +253,8 @@ static const MfmaEntry kF32Menu[] = {
 // problems of at least one tile each way with k a multiple of the slab, n a
 // multiple of 4 and 16-byte rows, no transposed operand (edge tiles moved
 // inward as in the FP32 loop); any other problem takes the register-staged
-// tile of the same size (FM x FN x 32 with FWM x FWN waves).
+// tile of the same size (FM x FN x 32 with FWM x FWN waves).  The split
+// contraction is the FP32 entries' (same slice rule, same ordered sum).
 template <int TM, int TN, int TK, int WM, int WN, int NST, bool X3, int FWM, int FWN>
 struct Bf16SrcConfig {
   using S = Bf16SrcShape<TM, TN, TK, WM, WN, false, false, NST>;
@@ -275,12 +276,48 @@ struct Bf16SrcConfig {
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n)),
                            dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
   }
+  static int splits(int64_t m, int64_t n, int64_t k) {
+    if (m <= 0 || n <= 0 || k <= 0 || m % TM || n % TN || k % TK) return 1;
+    return dma_split_count((m / TM) * (n / TN), k, TK);
+  }
+  static int64_t split_bytes(int64_t m, int64_t n, int64_t k) {
+    const int sp = splits(m, n, k);
+    return sp > 1 ? (int64_t)sp * m * n * (int64_t)sizeof(float) : 0;
+  }
+  static hipError_t launch_split(const GemmArgs& args, void* workspace, hipStream_t s) {
+    const int sp = splits(args.m, args.n, args.k);
+    float* part = static_cast<float*>(workspace);
+    if (sp <= 1 || !f32_dma_fits<TM, TN, TK>(args, part, args.n, sp) ||
+        !f32_dma_fits<TM, TN, TK>(args, args.C, args.ldc, sp))
+      return launch(args, false, false, s);
+    GemmArgs a = args;
+    a.C = part;
+    a.ldc = a.n;
+    a.beta = 0.0f;
+    a.tiles_m = a.m / TM;
+    a.tiles_n = a.n / TN;
+    F32DmaOut o{};
+    o.splits = sp;
+    void* kargs[] = {&a, &o};
+    auto* fn = &sgemm_bf16src_dma<TM, TN, TK, WM, WN, false, false, NST, X3, kDmaSplit>;
+    hipError_t e = allow_lds(fn, (size_t)S::kLdsBytes);
+    if (e != hipSuccess) return e;
+    e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)(a.tiles_m * a.tiles_n * sp)),
+                        dim3(kThreads), kargs, (size_t)S::kLdsBytes, s);
+    if (e != hipSuccess) return e;
+    return launch_split_finish(part, sp, args.m, args.n, args.alpha, args.beta, args.C, args.ldc, s);
+  }
 };
 
 #define HPVM_BF16SRC_ENTRY(PREC, X3, TM, TN, TK, WM, WN, NST, FWM, FWN)                                    \
   {{TM, TN, TK, WM, WN, NST}, PREC, Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::kThreads,         \
    Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::S::kLdsBytes,                                       \
-   &Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::launch}
+   &Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::launch,                                            \
+   nullptr,                                                                                                   \
+   nullptr,                                                                                                   \
+   nullptr,                                                                                                   \
+   &Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::split_bytes,                                       \
+   &Bf16SrcConfig<TM, TN, TK, WM, WN, NST, X3, FWM, FWN>::launch_split}
 
 // Entry 0 is the default when no tile is given: BF16 and bf16x3 on the
 // DMA-fed loop, falling back to the register-staged 256 x 256 x 32 tile.

@@ -506,6 +506,35 @@ def test_split_contraction_workspace_rules(lib):
         assert hp.workspace_bytes(m, n, k, "fp32", tile) == 0, (m, n, k, tile)
 
 
+def test_bf16_split_contraction_workspace_rules(lib):
+    """The DMA-fed BF16 and bf16x3 tiles split the contraction by the FP32
+    rule; with no tile, hpvm_sgemm_ws splits when even 128 x 128 tiles would
+    not cover the CUs and k >= 2048, only when the workspace holds the
+    partial sums, else it keeps its other choices."""
+    hp.autotune_clear()
+    plane = lambda m, n: 4 * m * n
+    t128 = (128, 128, 32, 64, 64, 4)
+    for prec in ("bf16", "bf16x3"):
+        big = hp.tile_menu(prec)[0]
+        assert big[:2] == (256, 256) and t128 in hp.tile_menu(prec)
+        # 16 tiles of 128 x 128 -> 16 slices of 256; 4 of 256 x 256: not enough
+        assert hp.workspace_bytes(512, 512, 4096, prec, t128) == 16 * plane(512, 512)
+        assert hp.workspace_bytes(512, 512, 4096, prec, big) == 0
+        assert hp.workspace_bytes(1024, 1024, 4096, prec, t128) == 4 * plane(1024, 1024)
+        need = hp.workspace_bytes(512, 512, 4096, prec)
+        assert need == 16 * plane(512, 512)
+        d = hp.describe(512, 512, 4096, prec, workspace_bytes=need)
+        assert d["tile"] == t128 and d["splits"] == 16
+        short = hp.describe(512, 512, 4096, prec, workspace_bytes=need - 1)
+        assert short["splits"] == 1 and short == hp.describe(512, 512, 4096, prec)
+        assert hp.describe(1024, 1024, 4096, prec, workspace_bytes=1 << 30)["splits"] == 4
+        # k < 2048, or 128 x 128 tiles that cover the CUs: no split
+        assert hp.describe(1024, 1024, 1024, prec, workspace_bytes=1 << 30)["splits"] == 1
+        assert hp.describe(2048, 2048, 4096, prec, workspace_bytes=1 << 30)["splits"] == 1
+        # not whole tiles: no split, whatever the tile
+        assert hp.workspace_bytes(1000, 1024, 4096, prec, t128) == 0
+
+
 def test_staged_workspace_rules(lib):
     BIG = 1 << 24  # far enough apart that no two matrices overlap
     for prec, planes in (("bf16", 1), ("bf16x3", 2)):

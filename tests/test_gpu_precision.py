@@ -60,6 +60,28 @@ def test_random_against_exact_and_split_aware(gpu, prec, dist):
         assert np.all(np.abs(got - split) <= bound), tile
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("m,n,k", [(512, 512, 4096), (1024, 512, 2048)])
+def test_split_contraction(gpu, prec, m, n, k):
+    """Products that 128 x 128 tiles leave CUs idle on take the DMA-fed
+    tile's split contraction by default (with a workspace): integers exact,
+    random inputs within the bound of the split-aware oracle, and the same
+    bits as naming the tile."""
+    d = gpu.describe(m, n, k, prec, workspace_bytes=1 << 30)
+    assert d["splits"] > 1, d
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=31, dist="int")
+    print(f"case: {prec} split {m}x{n}x{k} int, {d['splits']} slices", flush=True)
+    assert np.array_equal(run(gpu, A, B, C, 2.0, -1.0, prec), oracle.sgemm(A, B, C, 2.0, -1.0))
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=32)
+    print(f"case: {prec} split {m}x{n}x{k} uniform", flush=True)
+    got = run(gpu, A, B, C, 1.0, 0.5, prec)
+    assert np.array_equal(got, run(gpu, A, B, C, 1.0, 0.5, prec, tile=d["tile"]))
+    assert normwise(got, oracle.sgemm(A, B, C, 1.0, 0.5)) <= BAR[prec]
+    split = oracle.sgemm(A, B, C, 1.0, 0.5, mode=prec)
+    bound = componentwise_bound(A, B, C, 1.0, 0.5, 3 * k if prec == "bf16x3" else k)
+    assert np.all(np.abs(got - split) <= bound)
+
+
 # ---------------------------------------------------------------------------
 # The conversion itself, bit for bit.  With one nonzero column of A (or row
 # of B) meeting ones, every output is a single product x * 1, exact in FP32:
