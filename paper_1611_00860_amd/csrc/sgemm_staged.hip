@@ -98,7 +98,7 @@ struct StageJob {
 
 // Copy form: -> [rows_pad][cols_pad] bfloat16, zero outside rows x cols.
 // 8-element units are dealt to the job's workgroups in turn; each thread
-// loads two units before storing either.
+// loads four units before storing any.
 template <bool X3>
 __device__ __forceinline__ void stage_rows_part(const StageJob& j, int64_t block) {
   const int64_t per_row = j.cols_pad / 8;
@@ -128,14 +128,14 @@ __device__ __forceinline__ void stage_rows_part(const StageJob& j, int64_t block
     if constexpr (X3) *reinterpret_cast<u32x4*>(j.lo + r * j.cols_pad + c) = lv;
   };
   int64_t u = block * blockDim.x + threadIdx.x;
-  for (; u + stride < units; u += 2 * stride) {
-    float v0[8], v1[8];
-    load(u, v0);
-    load(u + stride, v1);
-    store(u, v0);
-    store(u + stride, v1);
+  for (; u + 3 * stride < units; u += 4 * stride) {
+    float v[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) load(u + i * stride, v[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) store(u + i * stride, v[i]);
   }
-  if (u < units) {
+  for (; u < units; u += stride) {
     float v0[8];
     load(u, v0);
     store(u, v0);
@@ -143,52 +143,81 @@ __device__ __forceinline__ void stage_rows_part(const StageJob& j, int64_t block
 }
 
 // Transposing form: -> [cols_pad][rows_pad] bfloat16, so that the
-// contraction index is contiguous.  One workgroup moves a 64 x 64 block
-// through LDS; blocks are numbered row-major, cols_pad / 64 per block row.
+// contraction index is contiguous.  The 64 x 64 blocks (numbered row-major,
+// cols_pad / 64 per block row) go through LDS; the job's workgroups take
+// blocks wg, wg + blocks, ... and load the next block's rows while they
+// write out the current one.
 constexpr int kTB = 64;
 // A block reads its rows in 16-byte units when the whole 64 x 64 block is
 // inside the matrix and the rows allow them (vec), element by element
 // otherwise; LDS rows are 65 floats, so both the row-wise writes and the
 // column-wise reads of a wavefront fall on distinct banks.
 template <bool X3>
-__device__ __forceinline__ void stage_cols_block(const StageJob& j, int64_t block, float (*t)[kTB + 1]) {
+__device__ __forceinline__ void stage_cols_part(const StageJob& j, int64_t wg, float (*t)[kTB + 1]) {
+  constexpr int kV = kTB * kTB / 4 / 256;  // 16-byte loads per thread and block
   const int64_t col_blocks = j.cols_pad / kTB;
-  const int64_t r0 = (block / col_blocks) * kTB, c0 = (block % col_blocks) * kTB;
+  const int64_t total = col_blocks * (j.rows_pad / kTB);
   const int tid = threadIdx.x;
-  if (j.vec && r0 + kTB <= j.rows && c0 + kTB <= j.cols) {
-    f32x4 v[kTB * kTB / 4 / 256];
+  auto corner = [&](int64_t b, int64_t& r0, int64_t& c0) {
+    r0 = (b / col_blocks) * kTB;
+    c0 = (b % col_blocks) * kTB;
+  };
+  auto whole = [&](int64_t b) {
+    int64_t r0, c0;
+    corner(b, r0, c0);
+    return j.vec && r0 + kTB <= j.rows && c0 + kTB <= j.cols;
+  };
+  auto load = [&](int64_t b, f32x4 (&v)[kV]) {
+    int64_t r0, c0;
+    corner(b, r0, c0);
 #pragma unroll
-    for (int i = 0; i < kTB * kTB / 4 / 256; ++i) {
+    for (int i = 0; i < kV; ++i) {
       const int r = i * (256 / (kTB / 4)) + tid / (kTB / 4), c = (tid % (kTB / 4)) * 4;
       v[i] = *reinterpret_cast<const f32x4*>(j.src + (r0 + r) * j.ld + c0 + c);
     }
+  };
+  f32x4 v[kV];
+  int64_t b = wg;
+  bool fast = b < total && whole(b);
+  if (fast) load(b, v);
+  for (; b < total; b += j.blocks) {
+    int64_t r0, c0;
+    corner(b, r0, c0);
+    if (fast) {
 #pragma unroll
-    for (int i = 0; i < kTB * kTB / 4 / 256; ++i) {
-      const int r = i * (256 / (kTB / 4)) + tid / (kTB / 4), c = (tid % (kTB / 4)) * 4;
+      for (int i = 0; i < kV; ++i) {
+        const int r = i * (256 / (kTB / 4)) + tid / (kTB / 4), c = (tid % (kTB / 4)) * 4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) t[r][c + e] = v[i][e];
+        for (int e = 0; e < 4; ++e) t[r][c + e] = v[i][e];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTB * kTB / 256; ++i) {
+        const int r = i * (256 / kTB) + tid / kTB, c = tid % kTB;
+        const int64_t gr = r0 + r, gc = c0 + c;
+        t[r][c] = (gr < j.rows && gc < j.cols) ? j.src[gr * j.ld + gc] : 0.0f;
+      }
     }
-  } else {
+    __syncthreads();
+    // The next block's rows are requested before this block is written out.
+    const int64_t nb = b + j.blocks;
+    const bool nfast = nb < total && whole(nb);
+    if (nfast) load(nb, v);
 #pragma unroll
-    for (int i = 0; i < kTB * kTB / 256; ++i) {
-      const int r = i * (256 / kTB) + tid / kTB, c = tid % kTB;
-      const int64_t gr = r0 + r, gc = c0 + c;
-      t[r][c] = (gr < j.rows && gc < j.cols) ? j.src[gr * j.ld + gc] : 0.0f;
+    for (int q = 0; q < kTB * kTB / 8 / 256; ++q) {
+      const int u = tid + q * 256;
+      const int cc = u / (kTB / 8), kc = (u % (kTB / 8)) * 8;
+      float w[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[e] = t[kc + e][cc];
+      u32x4 hv, lv;
+      pack8<X3>(w, hv, lv);
+      const int64_t off = (c0 + cc) * j.rows_pad + r0 + kc;
+      *reinterpret_cast<u32x4*>(j.hi + off) = hv;
+      if constexpr (X3) *reinterpret_cast<u32x4*>(j.lo + off) = lv;
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kTB * kTB / 8 / 256; ++q) {
-    const int u = tid + q * 256;
-    const int cc = u / (kTB / 8), kc = (u % (kTB / 8)) * 8;
-    float v[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = t[kc + e][cc];
-    u32x4 hv, lv;
-    pack8<X3>(v, hv, lv);
-    const int64_t off = (c0 + cc) * j.rows_pad + r0 + kc;
-    *reinterpret_cast<u32x4*>(j.hi + off) = hv;
-    if constexpr (X3) *reinterpret_cast<u32x4*>(j.lo + off) = lv;
+    __syncthreads();  // LDS is rewritten by the next block
+    fast = nfast;
   }
 }
 
@@ -199,13 +228,13 @@ template <bool X3>
 __global__ void __launch_bounds__(256) stage_pair(StageJob a, StageJob b) {
   __shared__ float t[kTB][kTB + 1];
   if ((int64_t)blockIdx.x < a.blocks) stage_rows_part<X3>(a, blockIdx.x);
-  else stage_cols_block<X3>(b, blockIdx.x - a.blocks, t);
+  else stage_cols_part<X3>(b, blockIdx.x - a.blocks, t);
 }
 
 // The backward's pass over G (see stage_backward in internal.hpp): one
 // workgroup per 64 x 64 block of the round256(m) x round256(n) padded
 // matrix, row-major over blocks (col_blocks per block row).
-// The block goes through LDS as in stage_cols_block; the row plane is written
+// The block goes through LDS as in stage_cols_part; the row plane is written
 // when the block's columns lie within round64(n), the transposed plane when
 // its rows lie within round64(m).  Each thread's share of <G, Cin> follows a
 // fixed element order, so the partials repeat bit for bit.
@@ -332,7 +361,7 @@ __global__ void __launch_bounds__(256) stage_backward_k(GradJob g, StageJob b, S
   }
   blk -= g.blocks;
   if (blk < b.blocks) stage_rows_part<X3>(b, blk);
-  else stage_cols_block<X3>(a, blk - b.blocks, t);
+  else stage_cols_part<X3>(a, blk - b.blocks, t);
 }
 
 struct StagedArgs {
@@ -703,11 +732,13 @@ StageJob rows_job(const float* src, int64_t ld, int64_t rows, int64_t cols, int6
                   uint16_t* hi, uint16_t* lo, int32_t vec) {
   const int64_t units = rows_pad * cols_pad / 8;
   return StageJob{src, ld, rows, cols, rows_pad, cols_pad, hi, lo, vec,
-                  std::max<int64_t>(1, std::min<int64_t>((units + 511) / 512, 8192))};
+                  std::max<int64_t>(1, std::min<int64_t>((units + 1023) / 1024, 8192))};
 }
 StageJob cols_job(const float* src, int64_t ld, int64_t rows, int64_t cols, int64_t rows_pad, int64_t cols_pad,
                   uint16_t* hi, uint16_t* lo, int32_t vec) {
-  return StageJob{src, ld, rows, cols, rows_pad, cols_pad, hi, lo, vec, (cols_pad / kTB) * (rows_pad / kTB)};
+  // Up to 2048 workgroups (eight per CU), each looping over its blocks.
+  return StageJob{src, ld, rows, cols, rows_pad, cols_pad, hi, lo, vec,
+                  std::min<int64_t>((cols_pad / kTB) * (rows_pad / kTB), 2048)};
 }
 
 
