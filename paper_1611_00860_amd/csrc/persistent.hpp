@@ -26,11 +26,17 @@ struct GroupedShape {
 };
 
 // The shapes a persistent kernel can run: all use 256 lanes (4 waves).
+// Relative costs per useful flop, from the grouped autotuner's timings of
+// batches of 512 sgemms with log-uniform sizes: the 128 x 128 tiles,
+// DMA-fed for most instances, run well ahead of the register-staged smaller
+// ones (factors of 1.12 and 1.35 gave 9626 tiles and 1.32 ms where the tuned
+// assignments, these factors or their squares, gave 8762 or 8398 tiles and
+// 1.20-1.22 ms).
 static const GroupedShape kGroupedShapes[] = {
     {{128, 128, 16, 64, 64, 2}, 1.00},
-    {{128, 64, 16, 64, 32, 2}, 1.12},
-    {{64, 128, 16, 32, 64, 2}, 1.12},
-    {{64, 64, 16, 32, 32, 2}, 1.35},
+    {{128, 64, 16, 64, 32, 2}, 1.25},
+    {{64, 128, 16, 32, 64, 2}, 1.25},
+    {{64, 64, 16, 32, 32, 2}, 1.82},
 };
 constexpr int kNumGroupedShapes = 4;
 constexpr int kGroupedThreads = 256;
