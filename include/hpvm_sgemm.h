@@ -93,14 +93,23 @@ typedef enum hpvm_precision {
  *                   registers, conversion to bfloat16 (if any) fused into
  *                   that copy; 3 = staged BF16 / bf16x3 lowering: operands
  *                   converted into a workspace by a separate pass, then
- *                   moved straight from HBM into a ring of LDS stages (BF16)
- *                   or through registers into two (bf16x3); hpvm_sgemm_ws
- *                   only.  FP32 tiles with leaf_n = 128 are DMA-fed: a ring
- *                   of `stages` LDS stages filled straight from HBM, for
- *                   whole-tile problems (m, n, k multiples of the tile, A, B
- *                   and C 16-byte aligned with leading dimensions that are
- *                   multiples of 4); any other problem given such a tile
- *                   runs the 128 x 128 x 16 tile.
+ *                   moved into LDS stages: straight from HBM for every BF16
+ *                   tile and for bf16x3's 256 x 256 tile and 128 x 128 x 64
+ *                   tile with 64 x 32 leaves, through registers for
+ *                   bf16x3's others; hpvm_sgemm_ws only.
+ *                   DMA-fed tiles: FP32 tiles with leaf_n = 128, and BF16 /
+ *                   bf16x3 tiles of 256 x 256 with 64 x 128 or 128 x 128
+ *                   leaves or with stages = 4 have a ring of `stages` LDS
+ *                   stages filled straight from HBM (BF16: FP32 slabs,
+ *                   rounded to bfloat16 as each MFMA fragment is read).
+ *                   They run problems with m, n at least the tile, n a
+ *                   multiple of 4, k a multiple of tile_k, A, B and C
+ *                   16-byte aligned with leading dimensions that are
+ *                   multiples of 4 (edge tiles computed from a corner moved
+ *                   inward, storing only the outputs they own); any other
+ *                   problem given such a tile runs FP32's 128 x 128 x 16
+ *                   tile, or the register-staged BF16 / bf16x3 tile of the
+ *                   same size with tile_k = 32.
  * hpvm_tile_menu lists the combinations compiled into this library.       */
 typedef struct hpvm_tile {
   int32_t tile_m;
@@ -186,9 +195,9 @@ typedef struct hpvm_edge {
  *   tile         : hierarchy shape, or NULL to take the autotuned choice for
  *                  this shape class (until hpvm_autotune has run, the
  *                  built-in default: the menu's entry 0 when it gives at
- *                  least 256 tiles; else for FP32 the DMA-fed
- *                  128 x 128 x 32 tile if that does, else 64 x 64 x 16;
- *                  for BF16 and bf16x3 64 x 64 x 32).  Must be
+ *                  least 256 tiles; else the DMA-fed 128 x 128 x 32 tile
+ *                  if that does, else FP32 64 x 64 x 16, BF16 and bf16x3
+ *                  64 x 64 x 32).  Must be
  *                  in hpvm_tile_menu for prec and not need a workspace
  *                  (stages != 3).
  *   stream       : hipStream_t or NULL.
