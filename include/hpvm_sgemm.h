@@ -395,7 +395,7 @@ int hpvm_autotune_backward(int64_t m, int64_t n, int64_t k, int32_t prec, const 
  * m x n, leading dimension ldc; overwritten with beta = 0, never read).
  * Tiles of the staged lowering (stages == 3) are timed only when
  * `workspace` (device, 16-byte aligned) holds at least
- * hpvm_sgemm_workspace_bytes for them; FP32 tiles that split the
+ * hpvm_sgemm_workspace_bytes for them; DMA-fed tiles that split the
  * contraction run split when it holds their partial sums, and are then
  * left out of the no-workspace choice.  workspace may be NULL with 0 bytes.
  * Two rounds over the menu; in each, a tile runs once to warm up, then
@@ -422,10 +422,12 @@ int hpvm_autotune_record(int64_t m, int64_t n, int64_t k, int32_t prec, const hp
 /* Empties the cache. */
 int hpvm_autotune_clear(void);
 
-/* Writes / merges the cache as text, one entry per line: "prec m n k", the
- * overall winner (tile_m tile_n tile_k leaf_m leaf_n stages ms), then the
- * no-workspace winner in the same form.  Loading skips entries whose tiles
- * are not compiled into this library.                                       */
+/* Writes / merges the cache as text, one entry per line: the GPU
+ * architecture and HIP runtime version it was timed with ("gfx950
+ * hip<version>"), "prec m n k", the overall winner (tile_m tile_n tile_k
+ * leaf_m leaf_n stages ms), then the no-workspace winner in the same form.
+ * Loading skips entries timed on another architecture or runtime and
+ * entries whose tiles are not compiled into this library.                  */
 int hpvm_autotune_save(const char* path);
 int hpvm_autotune_load(const char* path);
 
