@@ -393,3 +393,36 @@ def test_autotune_records_a_menu_tile_and_uses_it(gpu, m, n, k):
         assert torch.equal(c1, c2), (tile, wsarg)
         assert normwise(to_host(c1), ref) <= 1e-5
     gpu.autotune_clear()
+
+
+# ---------------------------------------------------------------------------
+# A C of more than 2^31 elements (8.6 GB): every lowering addresses it with
+# 64-bit offsets.  Integer inputs keep every product and sum exact, so the
+# rows around element 2^31 and the last rows must match the oracle bit for
+# bit; beta = 0 leaves C unread (it is never filled).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,tile,workspace", [
+    ("fp32", None, None),                       # DMA-fed 256 x 256, ragged n
+    ("fp32", (128, 128, 16, 64, 64, 2), None),  # register-staged
+    ("bf16", None, None),                       # staged planes (workspace)
+    ("bf16", None, False),                      # DMA-fed, converting in the fragment reads
+])
+def test_offsets_past_2_31_elements(gpu, prec, tile, workspace):
+    import torch
+
+    m, n, k = (1 << 21) + 64, 1032, 32
+    assert m * n > 2 ** 31
+    rng = np.random.default_rng(41)
+    A = inputs.draw(rng, (m, k), "int")
+    B = inputs.draw(rng, (k, n), "int")
+    dA, dB = to_dev(A), to_dev(B)
+    dC = torch.empty((m, n), device="cuda")
+    print(f"case: {prec} {m}x{n}x{k} tile {tile} workspace {workspace}", flush=True)
+    gpu.sgemm(dA, dB, dC, 2.0, 0.0, prec=prec, tile=tile, workspace=workspace)
+    torch.cuda.synchronize()
+    rows = np.array([0, 1, 2 ** 31 // n - 1, 2 ** 31 // n, 2 ** 31 // n + 1, m - 65, m - 1])
+    got = dC[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    ref = oracle.sgemm(A[rows], B, None, 2.0, 0.0)
+    assert np.array_equal(got, ref)
+    del dC
+    torch.cuda.empty_cache()
