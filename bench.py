@@ -740,6 +740,57 @@ def traffic_sweep(hp, devs, outs, dev):
     print(json.dumps({"traffic_sweep": seq}), flush=True)
 
 
+def sustained_clock(step, step_ms, seconds=0.4):
+    """The GPU core clock while the FP32 step runs back to back (outside the
+    timed region): the current sclk the driver reports in sysfs (pp_dpm_sclk,
+    the line marked '*'), read every 2 ms from a host thread while the GPU
+    works through ~`seconds` of steps.  None when there is not exactly one
+    such file or it cannot be read."""
+    import glob
+    import threading
+
+    import torch
+
+    files = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+    if len(files) != 1:
+        return None
+
+    def read():
+        try:
+            with open(files[0]) as f:
+                for line in f:
+                    if line.rstrip().endswith("*"):
+                        return float(line.split(":", 1)[1].strip().rstrip("*").strip().lower().rstrip("mhz"))
+        except (OSError, ValueError, IndexError):
+            return None
+        return None
+
+    if read() is None:
+        return None
+    samples, stop = [], threading.Event()
+
+    def poll():
+        while not stop.is_set():
+            v = read()
+            if v is not None:
+                samples.append(v)
+            time.sleep(0.002)
+
+    steps = max(1, int(seconds * 1e3 / max(step_ms, 1e-3)))
+    torch.cuda.synchronize()
+    th = threading.Thread(target=poll)
+    th.start()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    stop.set()
+    th.join()
+    if not samples:
+        return None
+    return {"mhz_median": float(np.median(samples)), "samples": len(samples),
+            "source": f"{files[0]} (current sclk), read every 2 ms while {steps} FP32 steps ran back to back"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -856,6 +907,8 @@ def main():
                           "median_ms": round(float(np.median(ms)), 4),
                           "tile": list(hp.autotune_lookup(m, n, k, "fp32")[0])}
 
+    clock = sustained_clock(step, total_ms / args.steps)
+
     traffic = None
     table = load_traffic_table()
     if table is not None:
@@ -892,7 +945,12 @@ def main():
                      "kernel": sorted(set(fp32_kernel_name(per_shape[f"{m}x{n}x{k}_beta{beta:g}"]["tile"], m, n, k)
                                           for (m, n, k, beta) in WORKLOAD)),
                      "avg_launch_ms": round(kernel_ms / len(launch_ms), 5),
-                     "flops_per_launch_avg": flops_step / len(WORKLOAD)},
+                     "flops_per_launch_avg": flops_step / len(WORKLOAD),
+                     # the same fraction against the FP32 peak at the clock the kernel ran at
+                     "sustained_clock_mhz": clock["mhz_median"] if clock else None,
+                     "frac_at_sustained_clock": (round(achieved / (PEAK["fp32"] * clock["mhz_median"] / 2400.0), 4)
+                                                 if clock else None),
+                     "clock_source": clock["source"] if clock else None},
     }
 
     if not args.no_variants:
