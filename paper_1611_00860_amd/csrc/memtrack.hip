@@ -53,7 +53,8 @@ Region* find_region(const void* p, int64_t bytes, uintptr_t* start) {
 hipError_t to_device(Region& r, uintptr_t start, const void* p, bool read, hipStream_t s, void** dptr) {
   hipError_t e = hipSuccess;
   if (!r.dev) {
-    e = hipMallocAsync(&r.dev, (size_t)r.bytes, s);
+    // HPVM_FAULT_INJECT=alloc: the device copy's allocation fails.
+    e = fault_injected("alloc") ? hipErrorOutOfMemory : hipMallocAsync(&r.dev, (size_t)r.bytes, s);
     if (e != hipSuccess) {
       r.dev = nullptr;
       return e;

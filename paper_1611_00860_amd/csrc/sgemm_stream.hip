@@ -414,7 +414,9 @@ int hpvm_stream_open(const hpvm_stream_config* cfg, void** handle) {
   const size_t db = 256 + (size_t)s->capacity * 4;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s->finished, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMallocAsync(&s->dev, db, s->stream);
+  // HPVM_FAULT_INJECT=alloc: the device counters' allocation fails (the
+  // host ring, stream and event exist by then and are released below).
+  if (e == hipSuccess) e = fault_injected("alloc") ? hipErrorOutOfMemory : hipMallocAsync(&s->dev, db, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->dev, 0, db, s->stream);  // ordered before the kernel
   StreamCtl* dctl = nullptr;
   StreamSlot* dslots = nullptr;

@@ -709,8 +709,17 @@ def test_tracker_table_host_side(lib, monkeypatch):
     monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
     assert lib.hpvm_sgemm_tracked(8, 8, 8, 1.0, ctypes.c_void_p(A.ctypes.data), 8, ctypes.c_void_p(B.ctypes.data),
                                   8, 0.0, ctypes.c_void_p(C.ctypes.data), 8, 0, None, None) == -3
+    # the first device copy's allocation fails: an error, and the table is as before
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "alloc")
+    assert lib.hpvm_sgemm_tracked(8, 8, 8, 1.0, ctypes.c_void_p(A.ctypes.data), 8, ctypes.c_void_p(B.ctypes.data),
+                                  8, 0.0, ctypes.c_void_p(C.ctypes.data), 8, 0, None, None) == -3
+    assert "tracked copy" in hp.last_error()
+    for x in (A, B, C):
+        st = hp.tracked_state(x)
+        assert st["on_host"] and not st["on_device"] and st["device"] == 0
     monkeypatch.delenv("HPVM_FAULT_INJECT")
     assert hp.tracker_counters()["regions"] == base["regions"] + 3
+    assert hp.tracker_counters()["h2d_copies"] == base["h2d_copies"]
     for x in (A, B, C):
         hp.untrack(x)
     after = hp.tracker_counters()

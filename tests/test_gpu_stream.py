@@ -184,3 +184,24 @@ def test_stream_refuses_an_item_larger_than_the_ticket_window(gpu):
         rc = gpu.load().hpvm_stream_push(st._h, ctypes.byref(d), None)
         assert rc == -2 and "tiles" in gpu.last_error()
         assert st.info()["pushed"] == 0
+
+
+def test_open_after_an_injected_allocation_failure(gpu, monkeypatch):
+    """HPVM_FAULT_INJECT=alloc fails the stream's device counters after its
+    host ring, stream and event exist: the open reports a HIP error, releases
+    them, and the next open works."""
+    import torch
+
+    monkeypatch.setenv("HPVM_FAULT_INJECT", "alloc")
+    print("case: stream open with an injected allocation failure", flush=True)
+    with pytest.raises(gpu.HpvmError) as ei:
+        gpu.SgemmStream(capacity=8, idle_ms=2000)
+    assert ei.value.status == -3 and "stream open" in gpu.last_error()
+    monkeypatch.delenv("HPVM_FAULT_INJECT")
+    A, B, C = item(64, 96, 32, seed=77)
+    with gpu.SgemmStream(capacity=8, idle_ms=10000) as st:
+        dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+        st.push(dA, dB, dC, 1.0, 1.0)
+        _, out = st.pop()
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out), oracle.sgemm(A, B, C, 1.0, 1.0))

@@ -119,3 +119,32 @@ def test_tracked_pinned_torch_tensors(gpu):
         for x in (tA, tB, tC):
             gpu.untrack(x)
         torch.cuda.synchronize()
+
+
+def test_tracked_launch_after_an_injected_allocation_failure(gpu, monkeypatch):
+    """HPVM_FAULT_INJECT=alloc fails the first device copy's allocation: the
+    launch reports a HIP error and leaves the table as it was; the next launch
+    copies and computes as usual."""
+    import torch
+
+    A, B, C = inputs.sgemm_operands(70, 90, 50, seed=43, dist="int")
+    C0 = C.copy()
+    for x in (A, B, C):
+        gpu.track(x)
+    try:
+        c0 = gpu.tracker_counters()
+        monkeypatch.setenv("HPVM_FAULT_INJECT", "alloc")
+        print("case: tracked launch with an injected allocation failure", flush=True)
+        with pytest.raises(gpu.HpvmError) as ei:
+            gpu.sgemm_tracked(A, B, C, 2.0, -1.0)
+        assert ei.value.status == -3
+        monkeypatch.delenv("HPVM_FAULT_INJECT")
+        assert delta(c0, gpu.tracker_counters())["h2d_copies"] == 0
+        assert all(gpu.tracked_state(x)["on_host"] and not gpu.tracked_state(x)["on_device"] for x in (A, B, C))
+        gpu.sgemm_tracked(A, B, C, 2.0, -1.0)
+        gpu.request(C)
+        assert np.array_equal(C, oracle.sgemm(A, B, C0, 2.0, -1.0))
+    finally:
+        for x in (A, B, C):
+            gpu.untrack(x)
+        torch.cuda.synchronize()
