@@ -427,7 +427,12 @@ int hpvm_autotune_clear(void);
  * hip<version>"), "prec m n k", the overall winner (tile_m tile_n tile_k
  * leaf_m leaf_n stages ms), then the no-workspace winner in the same form.
  * Loading skips entries timed on another architecture or runtime and
- * entries whose tiles are not compiled into this library.                  */
+ * entries whose tiles are not compiled into this library.  With the
+ * environment variable HPVM_AUTOTUNE_CACHE set to a path, the cache
+ * persists there across processes: the file is merged in at the first use
+ * of the cache (a missing file is an empty cache) and rewritten after every
+ * hpvm_autotune and hpvm_autotune_record (processes sharing the file: the
+ * last writer's entries win).                                              */
 int hpvm_autotune_save(const char* path);
 int hpvm_autotune_load(const char* path);
 

@@ -5,10 +5,11 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
-#include <string>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -93,11 +94,81 @@ std::string cache_tag() {
   return buf;
 }
 
+// The cache as text, one entry per line (see hpvm_autotune_save).
+bool save_file(const char* path) {
+  FILE* f = std::fopen(path, "w");
+  if (!f) return false;
+  const std::string tag = cache_tag();
+  std::fprintf(f,
+               "# hpvm_sgemm autotune cache v3: arch runtime | prec m n k | best tile (m n k leaf_m leaf_n "
+               "stages) ms | best tile without workspace, ms\n");
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : g_cache) {
+      if (std::get<4>(kv.first)) continue;  // class entries are rebuilt on load
+      const hpvm_tile& t = kv.second.tile;
+      const hpvm_tile& u = kv.second.fused;
+      std::fprintf(f, "%s %d %lld %lld %lld %d %d %d %d %d %d %.6f %d %d %d %d %d %d %.6f\n", tag.c_str(),
+                   std::get<0>(kv.first),
+                   (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
+                   (long long)std::get<3>(kv.first), t.tile_m, t.tile_n, t.tile_k, t.leaf_m, t.leaf_n, t.stages,
+                   kv.second.ms, u.tile_m, u.tile_n, u.tile_k, u.leaf_m, u.leaf_n, u.stages, kv.second.fused_ms);
+    }
+  }
+  return std::fclose(f) == 0;
+}
+
+// Merges a saved cache: entries timed on another architecture or runtime,
+// and entries whose tiles this library does not hold, are skipped.
+bool load_file(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  const std::string tag = cache_tag();
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    char arch[64], runtime[32];
+    int prec;
+    long long m, n, k;
+    hpvm_tile t, u;
+    float ms, ums;
+    if (std::sscanf(line, "%63s %31s %d %lld %lld %lld %d %d %d %d %d %d %f %d %d %d %d %d %d %f", arch, runtime,
+                    &prec, &m, &n, &k, &t.tile_m, &t.tile_n, &t.tile_k, &t.leaf_m, &t.leaf_n, &t.stages, &ms,
+                    &u.tile_m, &u.tile_n, &u.tile_k, &u.leaf_m, &u.leaf_n, &u.stages, &ums) != 20)
+      continue;
+    if (tag != std::string(arch) + " " + runtime) continue;  // timed on another device or runtime
+    if (m < 0 || n < 0 || k < 0 || !in_menu(prec, t) || !in_menu(prec, u) || needs_workspace(prec, u)) continue;
+    record(prec, m, n, k, Choice{t, ms, u, ums});
+  }
+  std::fclose(f);
+  return true;
+}
+
+// HPVM_AUTOTUNE_CACHE names a file the cache persists in across processes:
+// merged in at the library's first use of the cache (a missing file is an
+// empty cache), written back after every tuning or record.
+const char* env_path() {
+  const char* p = std::getenv("HPVM_AUTOTUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+void env_cache() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    if (const char* p = env_path()) (void)load_file(p);
+  });
+}
+
+void env_save() {
+  if (const char* p = env_path()) (void)save_file(p);
+}
+
 }  // namespace
 
 // Used by hpvm_sgemm / hpvm_sgemm_ws when no tile is given: 2 exact, 1
 // class, 0 none.
 int tuned_tile(int32_t prec, int64_t m, int64_t n, int64_t k, bool allow_workspace, hpvm_tile* out) {
+  env_cache();
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_cache.find(exact_key(prec, m, n, k));
   int found = 2;
@@ -177,7 +248,9 @@ int hpvm_autotune(int64_t m, int64_t n, int64_t k, int32_t prec, const float* A,
   if (bi < 0 || bf < 0) return set_error(HPVM_INVALID_ARG, "no tile could be timed");
   Choice c{menu_entry_at(prec, bi)->tile, best_of[bi] / (float)reps, menu_entry_at(prec, bf)->tile,
            best_of[bf] / (float)reps};
+  env_cache();
   record(prec, m, n, k, c);
+  env_save();
   if (best) *best = c.tile;
   if (best_ms) *best_ms = c.ms;
   return clear_error();
@@ -197,11 +270,14 @@ int hpvm_autotune_record(int64_t m, int64_t n, int64_t k, int32_t prec, const hp
   if (m < 0 || n < 0 || k < 0) return set_error(HPVM_INVALID_ARG, "sizes must be >= 0");
   if (!tile) return set_error(HPVM_INVALID_ARG, "argument 5: tile is NULL");
   if (!in_menu(prec, *tile)) return set_error(HPVM_UNSUPPORTED, "argument 5: tile not compiled for precision %d", prec);
+  env_cache();
   record(prec, m, n, k, single_choice(prec, *tile, ms));
+  env_save();
   return clear_error();
 }
 
 int hpvm_autotune_clear(void) {
+  env_cache();  // a cache file merged later would bring the entries back
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache.clear();
   return clear_error();
@@ -209,51 +285,14 @@ int hpvm_autotune_clear(void) {
 
 int hpvm_autotune_save(const char* path) {
   if (!path) return set_error(HPVM_INVALID_ARG, "argument 1: path is NULL");
-  FILE* f = std::fopen(path, "w");
-  if (!f) return set_error(HPVM_INVALID_ARG, "cannot open %s for writing", path);
-  const std::string tag = cache_tag();
-  std::fprintf(f,
-               "# hpvm_sgemm autotune cache v3: arch runtime | prec m n k | best tile (m n k leaf_m leaf_n "
-               "stages) ms | best tile without workspace, ms\n");
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (const auto& kv : g_cache) {
-      if (std::get<4>(kv.first)) continue;  // class entries are rebuilt on load
-      const hpvm_tile& t = kv.second.tile;
-      const hpvm_tile& u = kv.second.fused;
-      std::fprintf(f, "%s %d %lld %lld %lld %d %d %d %d %d %d %.6f %d %d %d %d %d %d %.6f\n", tag.c_str(),
-                   std::get<0>(kv.first),
-                   (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
-                   (long long)std::get<3>(kv.first), t.tile_m, t.tile_n, t.tile_k, t.leaf_m, t.leaf_n, t.stages,
-                   kv.second.ms, u.tile_m, u.tile_n, u.tile_k, u.leaf_m, u.leaf_n, u.stages, kv.second.fused_ms);
-    }
-  }
-  const bool ok = std::fclose(f) == 0;
-  return ok ? clear_error() : set_error(HPVM_INVALID_ARG, "write to %s failed", path);
+  if (!save_file(path)) return set_error(HPVM_INVALID_ARG, "cannot write %s", path);
+  return clear_error();
 }
 
 int hpvm_autotune_load(const char* path) {
   if (!path) return set_error(HPVM_INVALID_ARG, "argument 1: path is NULL");
-  FILE* f = std::fopen(path, "r");
-  if (!f) return set_error(HPVM_INVALID_ARG, "cannot open %s", path);
-  const std::string tag = cache_tag();
-  char line[512];
-  while (std::fgets(line, sizeof line, f)) {
-    if (line[0] == '#') continue;
-    char arch[64], runtime[32];
-    int prec;
-    long long m, n, k;
-    hpvm_tile t, u;
-    float ms, ums;
-    if (std::sscanf(line, "%63s %31s %d %lld %lld %lld %d %d %d %d %d %d %f %d %d %d %d %d %d %f", arch, runtime,
-                    &prec, &m, &n, &k, &t.tile_m, &t.tile_n, &t.tile_k, &t.leaf_m, &t.leaf_n, &t.stages, &ms,
-                    &u.tile_m, &u.tile_n, &u.tile_k, &u.leaf_m, &u.leaf_n, &u.stages, &ums) != 20)
-      continue;
-    if (tag != std::string(arch) + " " + runtime) continue;  // timed on another device or runtime
-    if (m < 0 || n < 0 || k < 0 || !in_menu(prec, t) || !in_menu(prec, u) || needs_workspace(prec, u)) continue;
-    record(prec, m, n, k, Choice{t, ms, u, ums});
-  }
-  std::fclose(f);
+  env_cache();
+  if (!load_file(path)) return set_error(HPVM_INVALID_ARG, "cannot open %s", path);
   return clear_error();
 }
 

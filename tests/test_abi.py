@@ -819,3 +819,30 @@ def test_pair_split_workspace_rules(lib, monkeypatch):
     monkeypatch.setenv("HPVM_FAULT_INJECT", "launch")
     assert lib.hpvm_sgemm_pair_ws(*args, 6 * BIG, 1 << 30, None) == -3
     assert lib.hpvm_sgemm_pair_ws(*args, None, 0, None) == -3  # no workspace: the unsplit pair
+
+
+def test_autotune_cache_persists_through_the_environment(tmp_path):
+    """HPVM_AUTOTUNE_CACHE: a choice recorded in one process is written to the
+    file and found by the next process that names it; without it, nothing
+    carries over."""
+    import sys
+
+    path = tmp_path / "tune.txt"
+
+    def run(code, cache):
+        env = dict(os.environ)
+        env.pop("HPVM_AUTOTUNE_CACHE", None)
+        if cache:
+            env["HPVM_AUTOTUNE_CACHE"] = str(path)
+        out = subprocess.run([sys.executable, "-c", "import paper_1611_00860_amd as hp\n" + code], cwd=ROOT, env=env,
+                             capture_output=True, text=True, timeout=300)
+        assert out.returncode == 0, out.stderr[-2000:]
+        return out.stdout.strip()
+
+    menu = hp.tile_menu("fp32")
+    run(f"hp.autotune_record(4096, 4096, 4096, {tuple(menu[2])}, 'fp32', 1.25)", cache=True)
+    assert path.exists() and "4096 4096 4096" in path.read_text()
+    got = run("t, f = hp.autotune_lookup(4096, 4096, 4096, 'fp32'); print(list(t), f, "
+              "list(hp.describe(4096, 4096, 4096, 'fp32')['tile']))", cache=True)
+    assert got == f"{list(menu[2])} 2 {list(menu[2])}"
+    assert run("print(hp.autotune_lookup(4096, 4096, 4096, 'fp32')[1])", cache=False) == "0"
