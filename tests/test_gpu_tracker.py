@@ -148,3 +148,51 @@ def test_tracked_launch_after_an_injected_allocation_failure(gpu, monkeypatch):
         for x in (A, B, C):
             gpu.untrack(x)
         torch.cuda.synchronize()
+
+
+def test_tracked_padded_a_region_goes_over_whole(gpu):
+    """A is a view of a padded tracked region (lda > k): the region goes over
+    once, gaps included, so a later launch that reads the padded rows whole
+    sees the gap values; the result matches the oracle bit for bit."""
+    import torch
+
+    m, n, k = 1300, 260, 200
+    A, B, C = inputs.sgemm_operands(m, n, k, seed=47, dist="int")
+    Afull = np.full((m, k + 8), 7.0, dtype=np.float32)
+    Afull[:, :k] = A
+    Av = Afull[:, :k]
+    C0 = C.copy()
+    for x in (Afull, B, C):
+        gpu.track(x)
+    try:
+        c0 = gpu.tracker_counters()
+        print("case: tracked launch on a padded A", (m, n, k), flush=True)
+        gpu.sgemm_tracked(Av, B, C, 1.0, -1.0)
+        d = delta(c0, gpu.tracker_counters())
+        assert d["h2d_copies"] == 3 and d["h2d_bytes"] == Afull.nbytes + B.nbytes + C.nbytes
+        st = gpu.tracked_state(Afull)
+        assert st["on_device"] and st["on_host"]
+        gpu.sgemm_tracked(Av, B, C, 1.0, -1.0)  # everything resident: no copy
+        assert delta(c0, gpu.tracker_counters())["h2d_copies"] == 3
+        gpu.request(C)
+        once = oracle.sgemm(A, B, C0, 1.0, -1.0)
+        assert np.array_equal(C, oracle.sgemm(A, B, once.astype(np.float32), 1.0, -1.0))
+        # the gap columns went over with the region: a product that reads the
+        # padded rows whole sees them
+        Cw = np.zeros((m, 4), dtype=np.float32)
+        Bw = np.zeros((k + 8, 4), dtype=np.float32)
+        Bw[k:, :] = 1.0
+        for x in (Bw, Cw):
+            gpu.track(x)
+        try:
+            gpu.sgemm_tracked(Afull, Bw, Cw, 1.0, 0.0)
+            assert delta(c0, gpu.tracker_counters())["h2d_copies"] == 4  # Bw only
+            gpu.request(Cw)
+            assert np.all(Cw == 56.0)
+        finally:
+            for x in (Bw, Cw):
+                gpu.untrack(x)
+    finally:
+        for x in (Afull, B, C):
+            gpu.untrack(x)
+        torch.cuda.synchronize()
