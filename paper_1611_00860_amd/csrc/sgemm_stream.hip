@@ -9,10 +9,10 @@
 // memory; the host publishes each with a release store of the ring's tail.
 // The resident workgroups take tickets from a device counter; the tiles of
 // item i are tickets [first_i, end_i), handed out in push order.  At push
-// the host also writes, for every ticket of the item, the item's sequence
-// number into a ticket map (a window of kTicketWindow entries, tagged with
-// the ticket), so a workgroup finds the item that holds its ticket with one
-// read.  The workgroup that finishes an item's last tile raises the item's
+// the host also writes, for every ticket of the item, the item's slot into a
+// ticket map (a window of kTicketWindow words, each tagged with its ticket),
+// so a workgroup finds the item that holds its ticket with one read of host
+// memory and then reads the item's argument pack with a second.  The workgroup that finishes an item's last tile raises the item's
 // completion flag in host memory, which pop waits on.
 //
 // Every wait in the kernel is bounded: a workgroup with nothing to do leaves
@@ -46,7 +46,7 @@ constexpr uint64_t kTicketWindow = 1ull << 18;
 
 // One argument pack as the kernel reads it (host memory).
 struct alignas(128) StreamSlot {
-  uint64_t seq;    // sequence number of the item held (for inspection)
+  uint64_t seq;    // sequence number of the item held
   uint64_t first;  // first ticket of the item
   uint64_t end;    // one past its last ticket
   const float* A;
@@ -64,7 +64,8 @@ struct alignas(128) StreamCtl {
   uint32_t closed;  // host: no more pushes; drain and leave
   uint32_t status;  // kernel: 0 running, else why it ended the stream
 };
-constexpr uint32_t kStreamIdle = 2;  // nothing pushed for the idle limit
+constexpr uint32_t kStreamIdle = 2;     // nothing pushed for the idle limit
+constexpr uint32_t kStreamBadSlot = 3;  // a ticket map word named a slot past the ring
 
 
 __device__ __forceinline__ uint64_t ld_acquire(const uint64_t* p) {
@@ -85,11 +86,14 @@ struct StreamTask {
   uint64_t seq;
 };
 
-// Ticket map entry: the ticket + 1 (0 = never written) and the item.
+// Ticket map entry, one word written with a release store: the ticket + 1
+// in the high bits (0 = never written) and the slot of the item holding the
+// ticket in the low kSlotBits, so the tag and the slot arrive in one read.
 struct TicketEntry {
-  uint64_t tag;  // ticket + 1, written last (release)
-  uint64_t seq;  // sequence number of the item holding the ticket
+  uint64_t word;
 };
+constexpr int kSlotBits = 12;
+constexpr uint64_t kSlotMask = (1ull << kSlotBits) - 1;
 
 // Thread 0: find the item that holds ticket t.  Returns false when the
 // workgroup must leave.  The idle clock restarts whenever the tail moves:
@@ -98,17 +102,22 @@ struct TicketEntry {
 __device__ bool stream_find(StreamCtl* ctl, const StreamSlot* slots, const TicketEntry* tmap, int cap,
                             uint64_t t, uint64_t idle_ticks, StreamTask* task) {
   const TicketEntry* e = tmap + (t & (kTicketWindow - 1));
-  uint64_t last_tail = ld_acquire(&ctl->tail);
+  const uint64_t want = (t + 1) << kSlotBits;
+  uint64_t last_tail = ~0ull;  // read with the other control words when polling
   uint64_t since = wall_clock64();
   int backoff = 1;
   uint32_t polls = 0;
   for (;;) {
-    if (ld_acquire(&e->tag) == t + 1) {
+    const uint64_t w = ld_acquire(&e->word);
+    if ((w & ~kSlotMask) == want) {
       // The item holding t stays in its slot until this tile is done, and
       // the acquire above orders these plain loads after the host's writes
       // of the slot, which is read as eight 16-byte loads issued together.
-      const uint64_t seq = e->seq;
-      const int s = (int)(seq % (uint64_t)cap);
+      const int s = (int)(w & kSlotMask);
+      if (s >= cap) {  // never written so by the host: end the stream rather than read past the ring
+        __hip_atomic_store(&ctl->status, kStreamBadSlot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        return false;
+      }
       StreamSlot slot;
       {
         const u32x4* src = reinterpret_cast<const u32x4*>(slots + s);
@@ -140,7 +149,7 @@ __device__ bool stream_find(StreamCtl* ctl, const StreamSlot* slots, const Ticke
       task->slot = s;
       task->local = (int32_t)(t - q->first);
       task->tiles = (uint32_t)(q->end - q->first);
-      task->seq = seq;
+      task->seq = q->seq;
       return true;
     }
     // Nothing pushed for this ticket yet: the entry is polled every time,
@@ -151,7 +160,7 @@ __device__ bool stream_find(StreamCtl* ctl, const StreamSlot* slots, const Ticke
     }
     if (ld_acquire32(&ctl->closed)) {
       // A push before the close is visible now: look once more.
-      if (ld_acquire(&e->tag) == t + 1) continue;
+      if ((ld_acquire(&e->word) & ~kSlotMask) == want) continue;
       return false;
     }
     if (ld_acquire32(&ctl->status) != 0) return false;
@@ -232,6 +241,7 @@ namespace {
 
 constexpr uint64_t kStreamMagic = 0x48505653474d4d53ull;  // "HPVSGMMS"
 constexpr int kMaxCapacity = 4096;
+static_assert(kMaxCapacity <= (1 << kSlotBits), "a slot index must fit the ticket map's slot bits");
 constexpr int kMaxIdleMs = 60000;
 constexpr int kMaxGridPerCu = 2;  // resident workgroups per CU (see hpvm_stream_open)
 constexpr int kMaxCus = 256;      // CUs of the largest gfx950 part
@@ -517,11 +527,8 @@ int hpvm_stream_push(void* handle, const hpvm_sgemm_desc* item, int64_t* seq) {
   q->vec_b = vec16(d.B, d.ldb);
   q->seq = sq;
   s->first_ticket[slot] = s->next_ticket;
-  for (uint64_t t = s->next_ticket; t < s->next_ticket + tiles; ++t) {
-    TicketEntry* te = s->tmap + (t & (kTicketWindow - 1));
-    te->seq = sq;
-    host_store(&te->tag, t + 1);
-  }
+  for (uint64_t t = s->next_ticket; t < s->next_ticket + tiles; ++t)
+    host_store(&s->tmap[t & (kTicketWindow - 1)].word, ((t + 1) << kSlotBits) | (uint64_t)slot);
   if (tiles == 0) host_store(s->done + slot, sq + 1);  // nothing for the kernel to do
   s->next_ticket += tiles;
   s->tiles += (int64_t)tiles;
