@@ -432,7 +432,9 @@ int hpvm_autotune_clear(void);
  * persists there across processes: the file is merged in at the first use
  * of the cache (a missing file is an empty cache) and rewritten after every
  * hpvm_autotune and hpvm_autotune_record (processes sharing the file: the
- * last writer's entries win).                                              */
+ * last writer's entries win).  A save writes "<path>.tmp<pid>" and renames
+ * it over the path, so a reader never sees a half-written file; a failed
+ * save leaves the old file in place.                                       */
 int hpvm_autotune_save(const char* path);
 int hpvm_autotune_load(const char* path);
 

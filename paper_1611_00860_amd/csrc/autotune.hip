@@ -13,6 +13,8 @@
 #include <tuple>
 #include <vector>
 
+#include <unistd.h>
+
 #include "device_common.hpp"
 #include "hpvm_sgemm.h"
 #include "internal.hpp"
@@ -94,9 +96,12 @@ std::string cache_tag() {
   return buf;
 }
 
-// The cache as text, one entry per line (see hpvm_autotune_save).
+// The cache as text, one entry per line (see hpvm_autotune_save), written
+// to a file of its own and renamed over `path`, so that a reader (or another
+// process saving the same cache) never sees a half-written file.
 bool save_file(const char* path) {
-  FILE* f = std::fopen(path, "w");
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return false;
   const std::string tag = cache_tag();
   std::fprintf(f,
@@ -115,7 +120,12 @@ bool save_file(const char* path) {
                    kv.second.ms, u.tile_m, u.tile_n, u.tile_k, u.leaf_m, u.leaf_n, u.stages, kv.second.fused_ms);
     }
   }
-  return std::fclose(f) == 0;
+  const bool written = !std::ferror(f);
+  if (std::fclose(f) != 0 || !written || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return false;
+  }
+  return true;
 }
 
 // Merges a saved cache: entries timed on another architecture or runtime,

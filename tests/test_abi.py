@@ -842,6 +842,7 @@ def test_autotune_cache_persists_through_the_environment(tmp_path):
     menu = hp.tile_menu("fp32")
     run(f"hp.autotune_record(4096, 4096, 4096, {tuple(menu[2])}, 'fp32', 1.25)", cache=True)
     assert path.exists() and "4096 4096 4096" in path.read_text()
+    assert [p.name for p in tmp_path.iterdir()] == ["tune.txt"]  # written aside, then renamed over
     got = run("t, f = hp.autotune_lookup(4096, 4096, 4096, 'fp32'); print(list(t), f, "
               "list(hp.describe(4096, 4096, 4096, 'fp32')['tile']))", cache=True)
     assert got == f"{list(menu[2])} 2 {list(menu[2])}"
