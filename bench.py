@@ -177,14 +177,22 @@ def gather(t, rows, cols):
     return t[torch.from_numpy(rows).to(t.device), torch.from_numpy(cols).to(t.device)].cpu().numpy()
 
 
-def event_time(fn, reps, stream):
-    """Milliseconds per call of fn() from HIP events recorded on `stream`
-    (after one untimed call, which loads whatever code it needs)."""
+def event_time(fn, reps, stream, warm_ms=25.0):
+    """Milliseconds per call of fn() from HIP events recorded on `stream`:
+    one untimed call (which loads whatever code it needs and sizes the
+    warm-up), then untimed calls worth about `warm_ms` queued right before
+    the timed ones, so the GPU runs at its steady clock when timing starts
+    instead of ramping up from the idle gap a synchronization leaves."""
     import torch
 
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
     fn()
+    b.record(stream)
     torch.cuda.synchronize()
+    first = max(a.elapsed_time(b), 1e-3)
+    for _ in range(min(int(warm_ms / first) + 1, 200)):
+        fn()
     a.record(stream)
     for _ in range(reps):
         fn()
