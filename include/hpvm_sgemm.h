@@ -696,8 +696,10 @@ int hpvm_stream_push(void* handle, const hpvm_sgemm_desc* item, int64_t* seq);
  * be NULL).  Its C is then final and visible to later work on any stream.
  * Waits at most timeout_ms (0 = just test): HPVM_TIMEOUT leaves the item in
  * flight.  HPVM_INVALID_ARG if nothing is in flight; HPVM_STREAM_ENDED if
- * the kernel exited (idle limit) before the item completed; HPVM_HIP_ERROR
- * if it failed.                                                             */
+ * the kernel exited before the item completed (its idle limit, or a ticket
+ * map entry naming a slot past the ring, which the library never writes:
+ * the kernel then ends the stream instead of reading past the ring);
+ * HPVM_HIP_ERROR if it failed.                                              */
 int hpvm_stream_pop(void* handle, int32_t timeout_ms, int64_t* seq, float** C);
 
 /* Counters and state of a stream.                                          */
