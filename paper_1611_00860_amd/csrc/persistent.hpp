@@ -97,16 +97,19 @@ inline int64_t shape_tiles(int64_t m, int64_t n, int shape) {
   return ((m + t.tile_m - 1) / t.tile_m) * ((n + t.tile_n - 1) / t.tile_n);
 }
 
-// Cost model: padded flops of the tiles an instance needs, weighted by the
-// shape's relative cost per flop raised to `lambda`, plus a fixed per-tile
-// cost (prologue / epilogue) worth 32 steps of k.
-inline int cost_model_shape(int64_t m, int64_t n, int64_t k, double lambda) {
+// Cost model: padded flops of the tiles an instance needs (each tile k + 32
+// deep, for its epilogue), weighted by the shape's relative cost per flop
+// raised to `lambda`, plus `overhead` steps of k of a 128 x 128 tile per tile
+// whatever its shape (the latency of a tile's start and end, which favours
+// fewer, larger tiles for shallow instances).
+inline int cost_model_shape(int64_t m, int64_t n, int64_t k, double lambda, double overhead = 0.0) {
   int best = 0;
   double best_cost = 0.0;
   for (int s = 0; s < kNumGroupedShapes; ++s) {
     const hpvm_tile& t = kGroupedShapes[s].tile;
     const double per_tile = (double)t.tile_m * t.tile_n * (double)((k > 0 ? k : 0) + 32);
-    const double cost = (double)shape_tiles(m, n, s) * per_tile * std::pow(kGroupedShapes[s].cost_per_flop, lambda);
+    const double cost = (double)shape_tiles(m, n, s) *
+                        (per_tile * std::pow(kGroupedShapes[s].cost_per_flop, lambda) + overhead * 128.0 * 128.0);
     if (s == 0 || cost < best_cost) {
       best = s;
       best_cost = cost;

@@ -529,14 +529,17 @@ int hpvm_grouped_autotune(void* plan, void* workspace, int64_t workspace_bytes_,
   }
 
   // Candidates: one shape for all instances, and the cost model at several
-  // weights of the per-shape cost factors.
+  // weights of the per-shape cost factors and of the per-tile overhead
+  // (each distinct assignment timed once).
   std::vector<std::vector<int>> cands;
   for (int sh = 0; sh < kNumGroupedShapes; ++sh) cands.emplace_back(p->user.size(), sh);
-  for (double lambda : {0.0, 0.5, 1.0, 2.0, 4.0}) {
-    std::vector<int> c(p->user.size());
-    for (size_t i = 0; i < p->user.size(); ++i) c[i] = cost_model_shape(p->user[i].m, p->user[i].n, p->user[i].k, lambda);
-    cands.push_back(c);
-  }
+  for (double overhead : {0.0, 32.0, 64.0, 128.0, 256.0})
+    for (double lambda : {0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0}) {
+      std::vector<int> c(p->user.size());
+      for (size_t i = 0; i < p->user.size(); ++i)
+        c[i] = cost_model_shape(p->user[i].m, p->user[i].n, p->user[i].k, lambda, overhead);
+      if (std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(std::move(c));
+    }
   const std::vector<int> original = p->shape;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipError_t e = hipEventCreate(&ev0);
