@@ -172,6 +172,32 @@ def test_stream_many_random_items(gpu):
     assert worst <= 1e-5, worst
 
 
+def test_stream_full_ring_of_slots_wraps(gpu):
+    """The largest ring (4096 slots, whose indices fill the ticket map's slot
+    bits) held full, then wrapped: 4296 one-tile items sharing A and B, each
+    with its own C, all bit-exact, popped in push order."""
+    import torch
+
+    cap, count, m, n, k = 4096, 4296, 32, 32, 16
+    A, B, _ = inputs.sgemm_operands(m, n, k, seed=60, dist="int")
+    dA, dB = to_dev(A), to_dev(B)
+    Cs = torch.arange(count, dtype=torch.float32, device="cuda").view(count, 1, 1).repeat(1, m, n)
+    done = []
+    print(f"case: stream of {count} items through {cap} slots", flush=True)
+    with gpu.SgemmStream(capacity=cap, idle_ms=10000) as st:
+        for i in range(count):
+            if st.in_flight == cap:
+                done.append(st.pop()[0])
+            assert st.push(dA, dB, Cs[i], 1.0, 1.0) == i
+        while st.in_flight:
+            done.append(st.pop()[0])
+    assert done == list(range(count))
+    ab = oracle.sgemm(A, B, None, 1.0, 0.0)
+    got = to_host(Cs)
+    for i in range(count):
+        assert np.array_equal(got[i], ab + np.float32(i)), i
+
+
 def test_stream_refuses_an_item_larger_than_the_ticket_window(gpu):
     """An item needing more tiles than the stream can hold in flight is refused
     at push (its pointers are never used: the check comes first)."""
