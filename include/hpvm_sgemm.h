@@ -474,7 +474,9 @@ typedef struct hpvm_grouped_info {
  * instances' C ranges may overlap) and builds a plan.  prec must be
  * HPVM_PREC_FP32.  tile == NULL picks a shape per instance from
  * hpvm_grouped_menu with the built-in cost model; otherwise `tile` (from
- * that menu) is used for every instance.  *plan receives an opaque handle
+ * that menu) is used for every instance.  Tuning the shapes is the separate
+ * call hpvm_grouped_autotune rather than a flag here, so that creating a
+ * plan never launches device work.  *plan receives an opaque handle
  * owned by the library until hpvm_grouped_plan_destroy.  The descriptors
  * are copied: the caller's array may be freed afterwards; the matrices
  * themselves must stay valid while the plan is run.                       */
