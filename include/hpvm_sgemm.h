@@ -519,8 +519,10 @@ int hpvm_graph_destroy(void* graph);
 int hpvm_grouped_plan_destroy(void* plan);
 
 /* Autotuner of the grouped plan: times candidate shape assignments (one
- * shape for all instances, and cost-model assignments) with the real
- * kernel, keeps the fastest in the plan and returns its time per launch in
+ * shape for all instances, and the cost model's assignments over a range of
+ * weights of the shapes' relative costs and of a fixed per-tile overhead,
+ * each distinct assignment once) with the real kernel, keeps the fastest in
+ * the plan and returns its time per launch in
  * *best_ms.  Timing runs use `scratch` (device memory of
  * hpvm_grouped_info.scratch_bytes, zeroed first) as every instance's C, with
  * the instance's own beta, so they read C where the replays do; the
